@@ -1,0 +1,185 @@
+/*
+ * rpq.h - single-source two-way regular path queries on one MI355X (gfx950).
+ *
+ * The library evaluates the single-source reachability map of a two-way
+ * regular path query (Sec. 2, Def. 2.6 and the SSR set): given an
+ * edge-labelled graph (Def. 2.1), an epsilon-free NFA over labels and inverse
+ * labels (Def. 2.4) and a source vertex, it returns every vertex u such that
+ * some two-way walk from the source to u spells a word the NFA accepts.
+ *
+ * It does so by the level-synchronous traversal of Alg. 1 (Sec. 4): each level
+ * computes M' = (sum over shared symbols a of (N^a)^T M G^a) masked by the
+ * complement of P, then P = P + M', until M' is empty, and returns F P. Inverse
+ * symbols use the transposed adjacency, G^{a^-} = (G^a)^T (Sec. 3). All work
+ * after the graph is loaded runs in HIP kernels on the GPU.
+ *
+ * Conventions for every entry point:
+ *  - Every call returns an rpq_status; no exception or abort crosses this
+ *    interface. On failure rpq_last_error() describes the cause.
+ *  - All input arrays are host memory unless a flag says otherwise; they are
+ *    copied and the caller keeps ownership.
+ *  - Vertex ids are 0-based int32 in [0, num_vertices). Bitmaps are
+ *    rpq_bitmap_words(V) = ceil(V/64) uint64 words; vertex v is bit (v & 63) of
+ *    word (v >> 6) (least significant bit first); pad bits are zero.
+ *  - Handles are owned by the library until the matching *_free call.
+ *  - Calls on one graph handle are serialized internally; different graph
+ *    handles may be used from different threads.
+ */
+#ifndef RPQ_H
+#define RPQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RPQ_OK = 0,
+    RPQ_PENDING = 1,     /* rpq_poll: not finished yet */
+    RPQ_EINVAL = -1,     /* invalid argument; nothing was done */
+    RPQ_ENOMEM = -2,     /* host or device allocation failed */
+    RPQ_EDEVICE = -3,    /* a HIP call failed; the handle may need to be freed */
+    RPQ_EAGAIN = -4,     /* resource busy (e.g. graph freed with pending tickets) */
+    RPQ_ENOTFOUND = -5,  /* unknown ticket or option */
+    RPQ_ETIMEDOUT = -6   /* rpq_poll: timeout elapsed before completion */
+} rpq_status;
+
+typedef struct rpq_graph rpq_graph; /* device-resident graph store + query state */
+typedef struct rpq_nfa rpq_nfa;     /* host-side NFA tables */
+typedef uint64_t rpq_ticket;
+
+/* Flags for the query entry points. */
+#define RPQ_OUT_DEVICE 1u   /* out_bitmap(s) is device memory on the graph's GPU */
+#define RPQ_COUNTERS 2u     /* fill the algorithmic work counters in rpq_stats */
+#define RPQ_KERNEL_TIMING 4u /* time the expansion kernels with HIP events */
+#define RPQ_FORCE_PUSH 8u   /* never use the pull direction (testing / tuning) */
+#define RPQ_FORCE_PULL 16u  /* use the pull direction from level 1 on (testing / tuning) */
+#define RPQ_HOST_LOOP 32u   /* drive levels from the host instead of one persistent launch */
+
+/*
+ * Statistics of one query (or one batch). Input fields: level_counts may point
+ * to a caller buffer of level_cap int64 that receives |M_n|, the number of
+ * (state, vertex) pairs first reached at level n (the frontier sizes of
+ * Alg. 1), for n < level_cap; it may be NULL.
+ */
+typedef struct {
+    int64_t *level_counts;   /* in: optional buffer, level_cap entries */
+    int32_t level_cap;       /* in */
+    int32_t levels;          /* out: number of non-empty frontiers M_0..M_{levels-1} */
+    int32_t push_levels;     /* out: levels expanded in the push direction */
+    int32_t pull_levels;     /* out: levels expanded in the pull direction */
+    int64_t visited_pairs;   /* out: |P|, reached (state, vertex) pairs */
+    /* out, only with RPQ_COUNTERS (algorithmic work, independent of direction):
+       product_edges = sum over reached (q,v) and symbols a of |succ_a(q)|*deg_a(v);
+       scans = (level, vertex, symbol) triples with a non-empty successor set
+       and at least one neighbour; scanned_edges = their neighbours;
+       alg_bytes = sum over levels of (2w+8)*active + (8+(4+w)*deg) per scan,
+       plus ceil(V/8), w the state-word bytes (1, 2, 4 for <= 8, 16, 32 states);
+       active = (level, vertex) pairs with a non-empty frontier word. */
+    int64_t product_edges, scans, scanned_edges, alg_bytes, active;
+    double device_ms;        /* out: GPU time of the whole call (events) */
+    double expand_ms;        /* out, with RPQ_KERNEL_TIMING: summed expansion-kernel time */
+    int32_t expand_launches; /* out, with RPQ_KERNEL_TIMING */
+    int32_t batch;           /* out: sources evaluated together */
+} rpq_stats;
+
+/* Number of uint64 words of a reachable-vertex bitmap over V vertices. */
+int64_t rpq_bitmap_words(int32_t num_vertices);
+
+/*
+ * Build the device graph store from per-label COO edges (the Boolean
+ * decomposition {G^a} of Sec. 3, Defs 3.7-3.8). Edges of label l are
+ * (src[i] -> dst[i]) for i in [label_ptr[l], label_ptr[l+1]); label_ptr has
+ * num_labels+1 entries with label_ptr[0] = 0. An edge with several labels
+ * appears once per label. Duplicate entries are merged; self-loops are kept.
+ * Both directions are stored (adjacency and transpose), as the two-way walks
+ * need G^a and (G^a)^T.
+ * Errors: RPQ_EINVAL for num_vertices < 1, num_labels < 1, a decreasing or
+ * non-zero-based label_ptr, an id outside [0, num_vertices), more than
+ * 2^31-1 distinct edges, or a NULL pointer with edges; RPQ_ENOMEM; RPQ_EDEVICE
+ * when no usable GPU is present.
+ */
+rpq_status rpq_graph_load(int32_t num_vertices, int32_t num_labels, const int64_t *label_ptr,
+                          const int32_t *src, const int32_t *dst, rpq_graph **out);
+rpq_status rpq_graph_free(rpq_graph *g);
+/* Graph facts: "num_vertices", "num_labels", "num_edges" (distinct), "device_bytes". */
+rpq_status rpq_graph_info(const rpq_graph *g, const char *key, int64_t *value);
+
+/*
+ * Options on a graph handle (key, value):
+ *  "stream"      hipStream_t (as an integer) the queries run on; 0 = the
+ *                library's own stream. The stream must outlive its use.
+ *  "pull_alpha"  push->pull switch: pull when the frontier's push edges exceed
+ *                (edges of the query's symbols) / alpha; 0 disables pull.
+ *  "pull_beta"   pull->push switch: back to push when the frontier has fewer
+ *                than num_vertices / beta vertices.
+ *  "max_batch"   largest number of sources stacked in one launch (<= 1024).
+ *  "mem_budget"  device bytes the served path may use for query state.
+ *  "max_slots"   concurrent queries in the served path.
+ * Errors: RPQ_ENOTFOUND for an unknown key, RPQ_EINVAL for a bad value.
+ */
+rpq_status rpq_set_option(rpq_graph *g, const char *key, int64_t value);
+rpq_status rpq_get_option(const rpq_graph *g, const char *key, int64_t *value);
+
+/*
+ * Build an NFA (Sec. 2, Def. 2.4) from its per-symbol Boolean transition
+ * matrices N^a in coordinate form (Sec. 4, Alg. 1 input). Symbol s <
+ * num_labels is label s; s >= num_labels is the inverse of label
+ * s - num_labels. Transitions of symbol s are (from[i] -> to[i]) for i in
+ * [sym_ptr[s], sym_ptr[s+1]); sym_ptr has 2*num_labels+1 entries. start and
+ * final_states list state ids (duplicates allowed). Symbols whose label the
+ * graph lacks contribute nothing at query time (the shared-alphabet rule of
+ * Alg. 1), which is not an error.
+ * Errors: RPQ_EINVAL for num_states outside [1, 32], num_labels < 0, a state
+ * id out of range, a decreasing sym_ptr, or NULL arrays with entries.
+ */
+rpq_status rpq_nfa_load(int32_t num_states, int32_t num_labels, const int64_t *sym_ptr,
+                        const int32_t *from, const int32_t *to, const int32_t *start,
+                        int32_t n_start, const int32_t *final_states, int32_t n_final,
+                        rpq_nfa **out);
+rpq_status rpq_nfa_free(rpq_nfa *n);
+
+/*
+ * One single-source query (Alg. 1 with the visited set initialised to the
+ * start pairs, i.e. counting the zero-length walk). Blocking. out_bitmap
+ * receives rpq_bitmap_words(V) words (host memory, or device memory with
+ * RPQ_OUT_DEVICE). stats may be NULL.
+ * Errors: RPQ_EINVAL for a NULL handle/output or a source outside
+ * [0, num_vertices); RPQ_EDEVICE on a HIP failure.
+ */
+rpq_status rpq_single_source(rpq_graph *g, const rpq_nfa *n, int32_t source,
+                             uint64_t *out_bitmap, uint32_t flags, rpq_stats *stats);
+
+/*
+ * Many sources under one NFA, stacked into one traversal (the multiple-source
+ * direction of Sec. 6): every vertex carries one bit per (state, source). The
+ * result of source i is identical to rpq_single_source's and is written to
+ * out_bitmaps + i * rpq_bitmap_words(V). Sources may repeat. Blocking.
+ * Errors: as rpq_single_source, plus RPQ_EINVAL for n_sources < 1.
+ */
+rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sources,
+                            int32_t n_sources, uint64_t *out_bitmaps, uint32_t flags,
+                            rpq_stats *stats);
+
+/*
+ * Served path. rpq_submit copies what it needs (the NFA may be freed after it
+ * returns) and queues the query; a scheduler thread admits queued queries into
+ * free slots while memory allows, advances all admitted queries level by level
+ * in shared launches, and retires finished ones. Thread-safe.
+ * rpq_poll waits up to timeout_us microseconds (0 = just check, < 0 = forever):
+ * RPQ_OK when finished (bitmap copied to out_bitmap, host memory, and the
+ * ticket retired), RPQ_PENDING if not finished and timeout_us == 0,
+ * RPQ_ETIMEDOUT if the wait elapsed, RPQ_ENOTFOUND for an unknown ticket.
+ */
+rpq_status rpq_submit(rpq_graph *g, const rpq_nfa *n, int32_t source, rpq_ticket *out);
+rpq_status rpq_poll(rpq_graph *g, rpq_ticket t, uint64_t *out_bitmap, rpq_stats *stats,
+                    int64_t timeout_us);
+
+/* Thread-local description of the last failure on this thread. */
+const char *rpq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RPQ_H */

@@ -1,0 +1,492 @@
+// C-ABI entry points of librpq (declared in include/rpq.h) and the host
+// runtime behind them: graph upload, per-query NFA tables, the single-query
+// executor (one persistent launch, or a host-driven level loop).
+#include "api_internal.h"
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+
+using namespace rpq;
+
+// ------------------------------------------------------------------ errors
+static thread_local char g_err[512] = "";
+
+const char *rpq_last_error(void) { return g_err; }
+
+rpq_status rpq::fail(rpq_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+rpq_status rpq::hip_fail(hipError_t e, const char *what) {
+    return fail(RPQ_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+int64_t rpq_bitmap_words(int32_t num_vertices) {
+    return num_vertices > 0 ? (static_cast<int64_t>(num_vertices) + 63) / 64 : 0;
+}
+
+// ------------------------------------------------------------------ NFA
+rpq_status rpq_nfa_load(int32_t num_states, int32_t num_labels, const int64_t *sym_ptr,
+                        const int32_t *from, const int32_t *to, const int32_t *start, int32_t n_start,
+                        const int32_t *final_states, int32_t n_final, rpq_nfa **out) {
+    if (!out) return fail(RPQ_EINVAL, "rpq_nfa_load: out is NULL");
+    *out = nullptr;
+    if (num_states < 1 || num_states > MAX_STATES)
+        return fail(RPQ_EINVAL, "rpq_nfa_load: num_states %d outside [1, %d]", num_states, MAX_STATES);
+    if (num_labels < 0) return fail(RPQ_EINVAL, "rpq_nfa_load: num_labels < 0");
+    if (!sym_ptr) return fail(RPQ_EINVAL, "rpq_nfa_load: sym_ptr is NULL");
+    if (n_start < 0 || n_final < 0) return fail(RPQ_EINVAL, "rpq_nfa_load: negative count");
+    if ((n_start && !start) || (n_final && !final_states))
+        return fail(RPQ_EINVAL, "rpq_nfa_load: NULL start/final array");
+    const int64_t nsym = 2 * static_cast<int64_t>(num_labels);
+    if (sym_ptr[0] != 0) return fail(RPQ_EINVAL, "rpq_nfa_load: sym_ptr[0] != 0");
+    for (int64_t s = 0; s < nsym; s++)
+        if (sym_ptr[s + 1] < sym_ptr[s]) return fail(RPQ_EINVAL, "rpq_nfa_load: sym_ptr decreases at %lld", (long long)s);
+    const int64_t nt = sym_ptr[nsym];
+    if (nt && (!from || !to)) return fail(RPQ_EINVAL, "rpq_nfa_load: NULL transition arrays");
+    for (int64_t i = 0; i < nt; i++)
+        if (from[i] < 0 || from[i] >= num_states || to[i] < 0 || to[i] >= num_states)
+            return fail(RPQ_EINVAL, "rpq_nfa_load: transition %lld has a state out of range", (long long)i);
+    uint32_t sm = 0, fm = 0;
+    for (int32_t i = 0; i < n_start; i++) {
+        if (start[i] < 0 || start[i] >= num_states) return fail(RPQ_EINVAL, "rpq_nfa_load: start state out of range");
+        sm |= 1u << start[i];
+    }
+    for (int32_t i = 0; i < n_final; i++) {
+        if (final_states[i] < 0 || final_states[i] >= num_states)
+            return fail(RPQ_EINVAL, "rpq_nfa_load: final state out of range");
+        fm |= 1u << final_states[i];
+    }
+    rpq_nfa *n = new (std::nothrow) rpq_nfa;
+    if (!n) return fail(RPQ_ENOMEM, "rpq_nfa_load: out of host memory");
+    n->Q = num_states;
+    n->NL = num_labels;
+    n->smask = sm;
+    n->fmask = fm;
+    static std::atomic<uint64_t> serial{1};
+    n->serial = serial.fetch_add(1);
+    for (int64_t s = 0; s < nsym; s++)
+        for (int64_t i = sym_ptr[s]; i < sym_ptr[s + 1]; i++)
+            n->trans.push_back({static_cast<int32_t>(s), from[i], to[i]});
+    *out = n;
+    return RPQ_OK;
+}
+
+rpq_status rpq_nfa_free(rpq_nfa *n) {
+    delete n;
+    return RPQ_OK;
+}
+
+// Builds the query-constant block (QHeader, succ, pred, label->symbol maps)
+// for NFA n on graph g into `buf`; returns its size in bytes.
+size_t rpq::build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, uint32_t counters,
+                         std::vector<uint8_t> &buf, int32_t *nsym_out) {
+    const int32_t L = g->L;
+    // used symbols: label within the graph, with edges, with transitions
+    std::vector<int32_t> symidx(2 * static_cast<size_t>(n->NL), -1);
+    std::vector<int32_t> used;
+    for (const auto &t : n->trans) {
+        const int32_t lab = t.sym >= n->NL ? t.sym - n->NL : t.sym;
+        if (lab >= L || g->label_edges[lab] == 0) continue;
+        if (symidx[t.sym] < 0) {
+            symidx[t.sym] = static_cast<int32_t>(used.size());
+            used.push_back(t.sym);
+        }
+    }
+    const int32_t ns = static_cast<int32_t>(used.size());
+    *nsym_out = ns;
+    const size_t tab = static_cast<size_t>(ns) * MAX_STATES * sizeof(uint32_t);
+    const size_t sz = sizeof(QHeader) + 2 * tab + 2 * static_cast<size_t>(L) * sizeof(int16_t);
+    buf.assign(sz, 0);
+    QHeader *h = reinterpret_cast<QHeader *>(buf.data());
+    uint32_t *succ = reinterpret_cast<uint32_t *>(buf.data() + sizeof(QHeader));
+    uint32_t *pred = succ + static_cast<size_t>(ns) * MAX_STATES;
+    int16_t *l2s = reinterpret_cast<int16_t *>(buf.data() + sizeof(QHeader) + 2 * tab);
+    for (int32_t i = 0; i < 2 * L; i++) l2s[i] = -1;
+    h->Q = n->Q;
+    h->nsym = ns;
+    h->smask = n->smask;
+    h->fmask = n->fmask;
+    h->alpha = static_cast<float>(g->pull_alpha);
+    h->beta = static_cast<float>(g->pull_beta);
+    h->force = force;
+    h->counters = counters;
+    uint64_t erel = 0;
+    for (int32_t u = 0; u < ns; u++) {
+        const int32_t s = used[u];
+        const bool inv = s >= n->NL;
+        const int32_t lab = inv ? s - n->NL : s;
+        l2s[(inv ? L : 0) + lab] = static_cast<int16_t>(u);
+        erel += static_cast<uint64_t>(g->label_edges[lab]);
+    }
+    for (const auto &t : n->trans) {
+        const int32_t u = symidx[t.sym];
+        if (u < 0) continue;
+        succ[u * MAX_STATES + t.from] |= 1u << t.to;
+        pred[u * MAX_STATES + t.to] |= 1u << t.from;
+        h->inmask |= 1u << t.to;
+        h->succ_any[t.from] |= 1u << t.to;
+    }
+    h->e_rel = erel;
+    return sz;
+}
+
+// ------------------------------------------------------------------ graph
+static rpq_status dev_alloc(rpq_graph *g, void **p, size_t bytes, const char *what) {
+    hipError_t e = hipMalloc(p, bytes ? bytes : 64);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(RPQ_ENOMEM, "hipMalloc(%s, %zu bytes): %s", what, bytes, hipGetErrorString(e));
+    }
+    g->allocs.push_back(*p);
+    g->device_bytes += static_cast<int64_t>(bytes);
+    return RPQ_OK;
+}
+
+template <typename T>
+static rpq_status upload(rpq_graph *g, T **dst, const std::vector<T> &src, const char *what) {
+    rpq_status st = dev_alloc(g, reinterpret_cast<void **>(dst), src.size() * sizeof(T), what);
+    if (st != RPQ_OK) return st;
+    if (!src.empty()) HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return RPQ_OK;
+}
+
+static void destroy(rpq_graph *g) {
+    if (!g) return;
+    serve_shutdown(g);
+    if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
+    for (hipEvent_t e : g->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (g->pinned) (void)hipHostFree(g->pinned);
+    for (void *p : g->allocs) (void)hipFree(p);
+    batch_free(g);
+    delete g;
+}
+
+rpq_status rpq_graph_load(int32_t V, int32_t L, const int64_t *label_ptr, const int32_t *src,
+                          const int32_t *dst, rpq_graph **out) {
+    if (!out) return fail(RPQ_EINVAL, "rpq_graph_load: out is NULL");
+    *out = nullptr;
+    if (V < 1) return fail(RPQ_EINVAL, "rpq_graph_load: num_vertices < 1");
+    if (L < 1) return fail(RPQ_EINVAL, "rpq_graph_load: num_labels < 1");
+    if (!label_ptr) return fail(RPQ_EINVAL, "rpq_graph_load: label_ptr is NULL");
+    if (label_ptr[0] != 0) return fail(RPQ_EINVAL, "rpq_graph_load: label_ptr[0] != 0");
+    for (int32_t l = 0; l < L; l++)
+        if (label_ptr[l + 1] < label_ptr[l]) return fail(RPQ_EINVAL, "rpq_graph_load: label_ptr decreases at %d", l);
+    const int64_t E = label_ptr[L];
+    if (E > 0 && (!src || !dst)) return fail(RPQ_EINVAL, "rpq_graph_load: NULL edge arrays");
+    if (E > MAX_EDGES) return fail(RPQ_EINVAL, "rpq_graph_load: %lld edges exceed the limit %lld",
+                                   (long long)E, (long long)MAX_EDGES);
+    for (int64_t i = 0; i < E; i++)
+        if (src[i] < 0 || src[i] >= V || dst[i] < 0 || dst[i] >= V)
+            return fail(RPQ_EINVAL, "rpq_graph_load: edge %lld has a vertex id out of range", (long long)i);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(RPQ_EDEVICE, "rpq_graph_load: no HIP device is available");
+
+    rpq_graph *g = new (std::nothrow) rpq_graph;
+    if (!g) return fail(RPQ_ENOMEM, "rpq_graph_load: out of host memory");
+    g->V = V;
+    g->L = L;
+    rpq_status st = graph_upload(g, label_ptr, src, dst);
+    if (st != RPQ_OK) {
+        destroy(g);
+        return st;
+    }
+    *out = g;
+    return RPQ_OK;
+}
+
+rpq_status rpq::graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32_t *src, const int32_t *dst) {
+    const int32_t V = g->V, L = g->L;
+    const int64_t Ein = label_ptr[L];
+    HIP_TRY(hipGetDevice(&g->device));
+    HostDir d[2];
+    build_direction(V, Ein, src, dst, label_ptr, L, d[OUT]);
+    build_direction(V, Ein, dst, src, label_ptr, L, d[IN]);
+    const int64_t E = d[OUT].E;
+    g->E = E;
+    g->label_edges = d[OUT].label_edges;
+    g->nseg[OUT] = d[OUT].seg_lab.size();
+    g->nseg[IN] = d[IN].seg_lab.size();
+    for (auto &x : d[IN].seg_beg) x += static_cast<uint32_t>(E);  // IN neighbours follow the OUT ones
+    rpq_status st;
+    uint32_t *col = nullptr;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&col), 2 * E * sizeof(uint32_t), "col")) != RPQ_OK) return st;
+    if (E) {
+        HIP_TRY(hipMemcpy(col, d[OUT].col.data(), E * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(col + E, d[IN].col.data(), E * sizeof(uint32_t), hipMemcpyHostToDevice));
+    }
+    g->gv.col = col;
+    g->gv.V = V;
+    g->gv.L = L;
+    for (int k = 0; k < 2; k++) {
+        uint32_t *p;
+        if ((st = upload(g, &p, d[k].vseg, "vseg")) != RPQ_OK) return st;
+        g->gv.vseg[k] = p;
+        if ((st = upload(g, &p, d[k].seg_lab, "seg_lab")) != RPQ_OK) return st;
+        g->gv.seg_lab[k] = p;
+        if ((st = upload(g, &p, d[k].seg_beg, "seg_beg")) != RPQ_OK) return st;
+        g->gv.seg_beg[k] = p;
+        d[k].col.clear();
+        d[k].col.shrink_to_fit();
+    }
+    // single-query state, sized for 4-byte state words
+    StateView &sv = g->sv;
+    const size_t wbytes = 4 * static_cast<size_t>(V) + 256;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.P), wbytes, "P")) != RPQ_OK) return st;
+    for (int k = 0; k < 2; k++) {
+        if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.M[k]), wbytes, "M")) != RPQ_OK) return st;
+        if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.q[k]), 4 * static_cast<size_t>(V), "queue")) != RPQ_OK)
+            return st;
+    }
+    const size_t items = g->nseg[OUT] + g->nseg[IN] + 1;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.it_ebase), 4 * items, "items")) != RPQ_OK) return st;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.it_beg), 4 * items, "items")) != RPQ_OK) return st;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.it_mask), 4 * items, "items")) != RPQ_OK) return st;
+    const size_t tiles = (2 * static_cast<size_t>(E)) / TILE + 2;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.tile_first), 4 * tiles, "tiles")) != RPQ_OK) return st;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.rec), sizeof(LevelRec) * REC_RING, "rec")) != RPQ_OK) return st;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.lvl_pairs), 8 * LVL_COUNT_CAP, "lvl")) != RPQ_OK) return st;
+    g->nwords = rpq_bitmap_words(V);
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&g->dev_out), 8 * g->nwords, "out")) != RPQ_OK) return st;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.status), 64, "status")) != RPQ_OK) return st;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.cnt), 64, "cnt")) != RPQ_OK) return st;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.bar), 64, "barrier")) != RPQ_OK) return st;
+    g->qconst_cap = sizeof(QHeader) + 2 * MAX_SYMS * MAX_STATES * sizeof(uint32_t) + 4 * static_cast<size_t>(L) + 64;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&g->qconst_dev), g->qconst_cap, "qconst")) != RPQ_OK) return st;
+    g->pinned_cap = g->qconst_cap + 4096 + 8 * LVL_COUNT_CAP;
+    HIP_TRY(hipHostMalloc(&g->pinned, g->pinned_cap, hipHostMallocDefault));
+    HIP_TRY(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+    g->own_stream = true;
+    for (int k = 0; k < 4; k++) HIP_TRY(hipEventCreate(&g->ev[k]));
+    // zero the query state once; every query leaves it zero again
+    HIP_TRY(launch_fill(sv.P, wbytes / 4, 0, g->stream));
+    HIP_TRY(launch_fill(sv.M[0], wbytes / 4, 0, g->stream));
+    HIP_TRY(launch_fill(sv.M[1], wbytes / 4, 0, g->stream));
+    HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(sv.bar), 16, 0, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    for (int W : {1, 2, 4}) g->pgrid[W] = persistent_grid(W);
+    return RPQ_OK;
+}
+
+rpq_status rpq_graph_free(rpq_graph *g) {
+    if (!g) return RPQ_OK;
+    if (serve_pending(g)) return fail(RPQ_EAGAIN, "rpq_graph_free: tickets are still pending");
+    destroy(g);
+    return RPQ_OK;
+}
+
+rpq_status rpq_graph_info(const rpq_graph *g, const char *key, int64_t *value) {
+    if (!g || !key || !value) return fail(RPQ_EINVAL, "rpq_graph_info: NULL argument");
+    if (!strcmp(key, "num_vertices")) *value = g->V;
+    else if (!strcmp(key, "num_labels")) *value = g->L;
+    else if (!strcmp(key, "num_edges")) *value = g->E;
+    else if (!strcmp(key, "device_bytes")) *value = g->device_bytes;
+    else if (!strcmp(key, "num_segments_out")) *value = static_cast<int64_t>(g->nseg[OUT]);
+    else if (!strcmp(key, "num_segments_in")) *value = static_cast<int64_t>(g->nseg[IN]);
+    else if (!strcmp(key, "persistent_grid")) *value = g->pgrid[1];
+    else if (!strcmp(key, "occupancy_blocks_per_cu")) *value = occupancy_blocks_per_cu(1);
+    else return fail(RPQ_ENOTFOUND, "rpq_graph_info: unknown key '%s'", key);
+    return RPQ_OK;
+}
+
+rpq_status rpq_set_option(rpq_graph *g, const char *key, int64_t value) {
+    if (!g || !key) return fail(RPQ_EINVAL, "rpq_set_option: NULL argument");
+    std::lock_guard<std::recursive_mutex> lk(g->mu);
+    if (!strcmp(key, "stream")) {
+        hipStream_t s = reinterpret_cast<hipStream_t>(static_cast<intptr_t>(value));
+        g->user_stream = s;
+    } else if (!strcmp(key, "pull_alpha")) {
+        if (value < 0) return fail(RPQ_EINVAL, "rpq_set_option: pull_alpha < 0");
+        g->pull_alpha = static_cast<double>(value);
+    } else if (!strcmp(key, "pull_beta")) {
+        if (value < 1) return fail(RPQ_EINVAL, "rpq_set_option: pull_beta < 1");
+        g->pull_beta = static_cast<double>(value);
+    } else if (!strcmp(key, "max_batch")) {
+        if (value < 1 || value > MAX_BATCH) return fail(RPQ_EINVAL, "rpq_set_option: max_batch outside [1, %d]", MAX_BATCH);
+        g->max_batch = static_cast<int32_t>(value);
+    } else if (!strcmp(key, "mem_budget")) {
+        if (value < 0) return fail(RPQ_EINVAL, "rpq_set_option: mem_budget < 0");
+        g->mem_budget = value;
+    } else if (!strcmp(key, "max_slots")) {
+        if (value < 1 || value > MAX_SLOTS) return fail(RPQ_EINVAL, "rpq_set_option: max_slots outside [1, %d]", MAX_SLOTS);
+        g->max_slots = static_cast<int32_t>(value);
+    } else if (!strcmp(key, "grid")) {
+        if (value < 0) return fail(RPQ_EINVAL, "rpq_set_option: grid < 0");
+        g->grid_override = static_cast<int32_t>(value);
+    } else {
+        return fail(RPQ_ENOTFOUND, "rpq_set_option: unknown key '%s'", key);
+    }
+    return RPQ_OK;
+}
+
+rpq_status rpq_get_option(const rpq_graph *g, const char *key, int64_t *value) {
+    if (!g || !key || !value) return fail(RPQ_EINVAL, "rpq_get_option: NULL argument");
+    if (!strcmp(key, "stream")) *value = static_cast<int64_t>(reinterpret_cast<intptr_t>(g->user_stream));
+    else if (!strcmp(key, "pull_alpha")) *value = static_cast<int64_t>(g->pull_alpha);
+    else if (!strcmp(key, "pull_beta")) *value = static_cast<int64_t>(g->pull_beta);
+    else if (!strcmp(key, "max_batch")) *value = g->max_batch;
+    else if (!strcmp(key, "mem_budget")) *value = g->mem_budget;
+    else if (!strcmp(key, "max_slots")) *value = g->max_slots;
+    else if (!strcmp(key, "grid")) *value = g->grid_override;
+    else return fail(RPQ_ENOTFOUND, "rpq_get_option: unknown key '%s'", key);
+    return RPQ_OK;
+}
+
+// ------------------------------------------------------------------ plain query
+static int word_width(int32_t Q) { return Q <= 8 ? 1 : Q <= 16 ? 2 : 4; }
+
+rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint64_t *out, uint32_t flags,
+                           rpq_stats *stats) {
+    hipStream_t s = g->user_stream ? g->user_stream : g->stream;
+    const int W = word_width(n->Q);
+    if (g->dirty) {
+        const size_t words = (4 * static_cast<size_t>(g->V) + 256) / 4;
+        HIP_TRY(launch_fill(g->sv.P, words, 0, s));
+        HIP_TRY(launch_fill(g->sv.M[0], words, 0, s));
+        HIP_TRY(launch_fill(g->sv.M[1], words, 0, s));
+        HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(g->sv.bar), 16, 0, s));
+        g->dirty = false;
+    }
+    g->dirty = true;  // until this query completes
+    const uint32_t force = (flags & RPQ_FORCE_PUSH) ? 1u : (flags & RPQ_FORCE_PULL) ? 2u : 0u;
+    const uint32_t counters = (flags & RPQ_COUNTERS) ? 1u : 0u;
+    // query constants: rebuilt when the NFA or the settings change
+    if (g->q_serial != n->serial || g->q_force != force || g->q_counters != counters ||
+        g->q_alpha != g->pull_alpha || g->q_beta != g->pull_beta) {
+        int32_t nsym = 0;
+        const size_t sz = build_qconst(g, n, force, counters, g->qbuf, &nsym);
+        if (nsym > MAX_SYMS) return fail(RPQ_EINVAL, "query uses %d symbols; the limit is %d", nsym, MAX_SYMS);
+        if (sz > g->qconst_cap) return fail(RPQ_EINVAL, "query constants too large");
+        memcpy(g->pinned, g->qbuf.data(), sz);
+        HIP_TRY(hipMemcpyAsync(g->qconst_dev, g->pinned, sz, hipMemcpyHostToDevice, s));
+        const size_t tab = static_cast<size_t>(nsym) * MAX_STATES * sizeof(uint32_t);
+        g->qv.h = reinterpret_cast<const QHeader *>(g->qconst_dev);
+        g->qv.succ = reinterpret_cast<const uint32_t *>(g->qconst_dev + sizeof(QHeader));
+        g->qv.pred = reinterpret_cast<const uint32_t *>(g->qconst_dev + sizeof(QHeader) + tab);
+        const int16_t *l2s = reinterpret_cast<const int16_t *>(g->qconst_dev + sizeof(QHeader) + 2 * tab);
+        g->qv.l2s[0] = l2s;
+        g->qv.l2s[1] = l2s + g->L;
+        g->q_serial = n->serial;
+        g->q_force = force;
+        g->q_counters = counters;
+        g->q_alpha = g->pull_alpha;
+        g->q_beta = g->pull_beta;
+        HIP_TRY(hipStreamSynchronize(s));  // the pinned staging buffer is reused below
+    }
+    Params p;
+    p.g = g->gv;
+    p.qv = g->qv;
+    p.st = g->sv;
+    p.st.out = (flags & RPQ_OUT_DEVICE) ? out : g->dev_out;
+    p.source = source;
+    const bool timing = (flags & RPQ_KERNEL_TIMING) != 0;
+    HIP_TRY(hipEventRecord(g->ev[0], s));
+    uint32_t nlev = 0;
+    float expand_ms = 0.f;
+    int32_t launches = 0;
+    const int grid_p = g->grid_override ? std::min(g->grid_override, g->pgrid[W]) : g->pgrid[W];
+    if (!(flags & RPQ_HOST_LOOP) && grid_p > 0) {
+        if (timing) HIP_TRY(hipEventRecord(g->ev[2], s));
+        HIP_TRY(launch_persistent(W, p, grid_p, s));
+        if (timing) HIP_TRY(hipEventRecord(g->ev[3], s));
+        launches = 1;
+    } else {
+        const int grid = g->grid_override ? g->grid_override : 1024;
+        HIP_TRY(launch_init(W, p, s));
+        uint32_t *nq_host = reinterpret_cast<uint32_t *>(g->pinned + g->qconst_cap);
+        nlev = (n->smask != 0) ? 1u : 0u;
+        for (uint32_t lev = 0; nlev > lev; lev++) {
+            HIP_TRY(launch_select(W, p, lev, grid, s));
+            if (timing) HIP_TRY(hipEventRecord(g->ev[2], s));
+            HIP_TRY(launch_expand(W, p, lev, grid, s));
+            if (timing) HIP_TRY(hipEventRecord(g->ev[3], s));
+            HIP_TRY(hipMemcpyAsync(nq_host, &p.st.rec[(lev + 1) % REC_RING].nq, 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (timing) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, g->ev[2], g->ev[3]));
+                expand_ms += ms;
+                launches++;
+            }
+            if (*nq_host) nlev = lev + 2;
+        }
+        HIP_TRY(launch_final(W, p, nlev, grid, s));
+    }
+    HIP_TRY(hipEventRecord(g->ev[1], s));
+    // results
+    uint8_t *stage = g->pinned + g->qconst_cap;
+    uint32_t *status = reinterpret_cast<uint32_t *>(stage);
+    uint64_t *cnt = reinterpret_cast<uint64_t *>(stage + 64);
+    HIP_TRY(hipMemcpyAsync(status, p.st.status, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(status + 4, p.st.bar, 16, hipMemcpyDeviceToHost, s));
+    if (counters) HIP_TRY(hipMemcpyAsync(cnt, p.st.cnt, 32, hipMemcpyDeviceToHost, s));
+    if (!(flags & RPQ_OUT_DEVICE))
+        HIP_TRY(hipMemcpyAsync(out, g->dev_out, 8 * g->nwords, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (status[4 + 2]) return fail(RPQ_EDEVICE, "persistent traversal aborted: grid barrier timed out");
+    const uint32_t levels = (flags & RPQ_HOST_LOOP || grid_p <= 0) ? nlev : status[0];
+    if (stats) {
+        stats->levels = static_cast<int32_t>(levels);
+        stats->push_levels = static_cast<int32_t>(status[1]);
+        stats->pull_levels = static_cast<int32_t>(status[2]);
+        stats->batch = 1;
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, g->ev[0], g->ev[1]));
+        stats->device_ms = ms;
+        if (timing && launches == 1 && !(flags & RPQ_HOST_LOOP)) {
+            HIP_TRY(hipEventElapsedTime(&expand_ms, g->ev[2], g->ev[3]));
+        }
+        stats->expand_ms = timing ? expand_ms : 0.0;
+        stats->expand_launches = timing ? launches : 0;
+        int64_t *lp = reinterpret_cast<int64_t *>(stage + 128);
+        const uint32_t ncopy = std::min<uint32_t>(levels, LVL_COUNT_CAP);
+        int64_t visited = 0;
+        if (ncopy) {
+            HIP_TRY(hipMemcpy(lp, p.st.lvl_pairs, 8 * ncopy, hipMemcpyDeviceToHost));
+            for (uint32_t i = 0; i < ncopy; i++) visited += lp[i];
+        }
+        stats->visited_pairs = visited;
+        if (stats->level_counts && stats->level_cap > 0)
+            for (int32_t i = 0; i < stats->level_cap; i++)
+                stats->level_counts[i] = static_cast<uint32_t>(i) < ncopy ? lp[i] : 0;
+        if (counters) {
+            const int64_t w = W;
+            stats->product_edges = static_cast<int64_t>(cnt[0]);
+            stats->scans = static_cast<int64_t>(cnt[1]);
+            stats->scanned_edges = static_cast<int64_t>(cnt[2]);
+            stats->active = static_cast<int64_t>(cnt[3]);
+            stats->alg_bytes = (2 * w + 8) * stats->active + 8 * stats->scans + (4 + w) * stats->scanned_edges +
+                               (static_cast<int64_t>(g->V) + 7) / 8;
+        }
+    }
+    g->dirty = false;
+    return RPQ_OK;
+}
+
+rpq_status rpq_single_source(rpq_graph *g, const rpq_nfa *n, int32_t source, uint64_t *out_bitmap,
+                             uint32_t flags, rpq_stats *stats) {
+    if (!g || !n || !out_bitmap) return fail(RPQ_EINVAL, "rpq_single_source: NULL argument");
+    if (source < 0 || source >= g->V)
+        return fail(RPQ_EINVAL, "rpq_single_source: source %d outside [0, %d)", source, g->V);
+    if ((flags & RPQ_FORCE_PUSH) && (flags & RPQ_FORCE_PULL))
+        return fail(RPQ_EINVAL, "rpq_single_source: RPQ_FORCE_PUSH and RPQ_FORCE_PULL together");
+    std::lock_guard<std::recursive_mutex> lk(g->mu);
+    HIP_TRY(hipSetDevice(g->device));
+    return run_single(g, n, source, out_bitmap, flags, stats);
+}

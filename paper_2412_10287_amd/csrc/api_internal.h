@@ -1,0 +1,89 @@
+// Host-side handle structures of librpq.
+#pragma once
+
+#include <atomic>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/rpq.h"
+#include "graph_build.h"
+#include "rpq_internal.h"
+
+namespace rpq {
+
+constexpr int64_t MAX_EDGES = (1ll << 31) - (1ll << 16);  // distinct edges per direction
+constexpr int32_t MAX_BATCH = 1024;
+constexpr int32_t MAX_SLOTS = 256;
+
+struct Trans {
+    int32_t sym, from, to;
+};
+
+struct ServeState;  // serve.cpp
+struct BatchState;  // batch.cpp
+
+}  // namespace rpq
+
+struct rpq_nfa {
+    int32_t Q = 0, NL = 0;
+    uint32_t smask = 0, fmask = 0;
+    uint64_t serial = 0;
+    std::vector<rpq::Trans> trans;
+};
+
+struct rpq_graph {
+    int32_t V = 0, L = 0;
+    int64_t E = 0;
+    int device = 0;
+    rpq::GraphView gv{};
+    rpq::StateView sv{};
+    std::vector<int64_t> label_edges;
+    size_t nseg[2] = {0, 0};
+    std::vector<void *> allocs;
+    int64_t device_bytes = 0;
+    int64_t nwords = 0;
+    uint64_t *dev_out = nullptr;
+    uint8_t *qconst_dev = nullptr;
+    size_t qconst_cap = 0;
+    uint8_t *pinned = nullptr;
+    size_t pinned_cap = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t user_stream = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    int pgrid[5] = {0, 0, 0, 0, 0};
+    bool dirty = false;
+    // options
+    double pull_alpha = 15.0;
+    double pull_beta = 24.0;
+    int32_t max_batch = 256;
+    int64_t mem_budget = 0;  // 0 = a quarter of the free device memory at first use
+    int32_t max_slots = 64;
+    int32_t grid_override = 0;
+    std::recursive_mutex mu;
+    // cached query constants of the single-query path
+    rpq::QueryView qv{};
+    std::vector<uint8_t> qbuf;
+    uint64_t q_serial = 0;
+    uint32_t q_force = ~0u, q_counters = ~0u;
+    double q_alpha = -1, q_beta = -1;
+    // batched and served paths
+    rpq::BatchState *batch = nullptr;
+    rpq::ServeState *serve = nullptr;
+};
+
+namespace rpq {
+
+rpq_status fail(rpq_status st, const char *fmt, ...);
+rpq_status hip_fail(hipError_t e, const char *what);
+size_t build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, uint32_t counters,
+                    std::vector<uint8_t> &buf, int32_t *nsym_out);
+rpq_status graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32_t *src, const int32_t *dst);
+rpq_status run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint64_t *out, uint32_t flags,
+                      rpq_stats *stats);
+void serve_shutdown(rpq_graph *g);
+bool serve_pending(rpq_graph *g);
+void batch_free(rpq_graph *g);
+
+}  // namespace rpq

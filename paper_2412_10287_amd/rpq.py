@@ -1,0 +1,243 @@
+"""ctypes binding of librpq (include/rpq.h). Argument marshalling only: every
+step of a query runs in the library's HIP kernels.
+
+The library must have been built (``paper_2412_10287_amd.build.build()``); if
+``librpq.so`` is missing, importing this module raises, so nothing can fall
+back to another implementation.
+
+Two layers:
+* the raw entry points under their C names (``rpq_graph_load``, ...), with
+  ctypes argument types set, in ``lib``;
+* thin helpers ``Graph`` / ``NFA`` that hold handles and convert numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librpq.so")
+
+RPQ_OK, RPQ_PENDING = 0, 1
+RPQ_EINVAL, RPQ_ENOMEM, RPQ_EDEVICE, RPQ_EAGAIN, RPQ_ENOTFOUND, RPQ_ETIMEDOUT = -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "RPQ_OK", 1: "RPQ_PENDING", -1: "RPQ_EINVAL", -2: "RPQ_ENOMEM", -3: "RPQ_EDEVICE",
+                -4: "RPQ_EAGAIN", -5: "RPQ_ENOTFOUND", -6: "RPQ_ETIMEDOUT"}
+
+OUT_DEVICE, COUNTERS, KERNEL_TIMING, FORCE_PUSH, FORCE_PULL, HOST_LOOP = 1, 2, 4, 8, 16, 32
+
+EXPORTS = ("rpq_bitmap_words", "rpq_graph_load", "rpq_graph_free", "rpq_graph_info", "rpq_set_option",
+           "rpq_get_option", "rpq_nfa_load", "rpq_nfa_free", "rpq_single_source", "rpq_multi_source",
+           "rpq_submit", "rpq_poll", "rpq_last_error")
+
+
+class rpq_stats(ctypes.Structure):
+    _fields_ = [
+        ("level_counts", ctypes.POINTER(ctypes.c_int64)),
+        ("level_cap", ctypes.c_int32),
+        ("levels", ctypes.c_int32),
+        ("push_levels", ctypes.c_int32),
+        ("pull_levels", ctypes.c_int32),
+        ("visited_pairs", ctypes.c_int64),
+        ("product_edges", ctypes.c_int64),
+        ("scans", ctypes.c_int64),
+        ("scanned_edges", ctypes.c_int64),
+        ("alg_bytes", ctypes.c_int64),
+        ("active", ctypes.c_int64),
+        ("device_ms", ctypes.c_double),
+        ("expand_ms", ctypes.c_double),
+        ("expand_launches", ctypes.c_int32),
+        ("batch", ctypes.c_int32),
+    ]
+
+
+class RPQError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError("librpq.so is not built (%s); run paper_2412_10287_amd.build.build()" % path)
+    L = ctypes.CDLL(path)
+    P, i32, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+    sig = {
+        "rpq_bitmap_words": (i64, [i32]),
+        "rpq_graph_load": (ctypes.c_int, [i32, i32, P, P, P, ctypes.POINTER(P)]),
+        "rpq_graph_free": (ctypes.c_int, [P]),
+        "rpq_graph_info": (ctypes.c_int, [P, ctypes.c_char_p, ctypes.POINTER(i64)]),
+        "rpq_set_option": (ctypes.c_int, [P, ctypes.c_char_p, i64]),
+        "rpq_get_option": (ctypes.c_int, [P, ctypes.c_char_p, ctypes.POINTER(i64)]),
+        "rpq_nfa_load": (ctypes.c_int, [i32, i32, P, P, P, P, i32, P, i32, ctypes.POINTER(P)]),
+        "rpq_nfa_free": (ctypes.c_int, [P]),
+        "rpq_single_source": (ctypes.c_int, [P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
+        "rpq_multi_source": (ctypes.c_int, [P, P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
+        "rpq_submit": (ctypes.c_int, [P, P, i32, ctypes.POINTER(u64)]),
+        "rpq_poll": (ctypes.c_int, [P, u64, P, ctypes.POINTER(rpq_stats), i64]),
+        "rpq_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+lib = load_library()
+
+
+def last_error() -> str:
+    return lib.rpq_last_error().decode(errors="replace")
+
+
+def check(status: int) -> int:
+    if status < 0:
+        raise RPQError(status, last_error())
+    return status
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def bitmap_words(num_vertices: int) -> int:
+    return int(lib.rpq_bitmap_words(num_vertices))
+
+
+@dataclass
+class Stats:
+    levels: int = 0
+    push_levels: int = 0
+    pull_levels: int = 0
+    visited_pairs: int = 0
+    product_edges: int = 0
+    scans: int = 0
+    scanned_edges: int = 0
+    alg_bytes: int = 0
+    active: int = 0
+    device_ms: float = 0.0
+    expand_ms: float = 0.0
+    expand_launches: int = 0
+    batch: int = 0
+    level_counts: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
+
+    @classmethod
+    def from_c(cls, s: rpq_stats, lc: Optional[np.ndarray]):
+        out = cls(**{k: getattr(s, k) for k, _ in rpq_stats._fields_
+                     if k not in ("level_counts", "level_cap")})
+        if lc is not None:
+            out.level_counts = lc[:min(lc.size, max(s.levels, 0))].copy()
+        return out
+
+
+def _stats_struct(level_cap: int):
+    st = rpq_stats()
+    lc = None
+    if level_cap > 0:
+        lc = np.zeros(level_cap, dtype=np.int64)
+        st.level_counts = lc.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        st.level_cap = level_cap
+    return st, lc
+
+
+class NFA:
+    """Handle on rpq_nfa_load's tables. ``nfa`` is any object with the fields
+    num_states, num_labels, sym_ptr, frm, to, start, final (per-symbol COO)."""
+
+    def __init__(self, nfa):
+        self.num_states = int(nfa.num_states)
+        sp = np.ascontiguousarray(nfa.sym_ptr, dtype=np.int64)
+        fr = np.ascontiguousarray(nfa.frm, dtype=np.int32)
+        to = np.ascontiguousarray(nfa.to, dtype=np.int32)
+        st = np.ascontiguousarray(nfa.start, dtype=np.int32)
+        fi = np.ascontiguousarray(nfa.final, dtype=np.int32)
+        h = ctypes.c_void_p()
+        check(lib.rpq_nfa_load(self.num_states, int(nfa.num_labels), _p(sp), _p(fr), _p(to), _p(st),
+                               int(st.size), _p(fi), int(fi.size), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib.rpq_nfa_free(self.h)
+            self.h = None
+
+    __del__ = close
+
+
+class Graph:
+    """Handle on a device-resident graph store built by rpq_graph_load."""
+
+    def __init__(self, g):
+        self.num_vertices = int(g.num_vertices)
+        self.num_labels = int(g.num_labels)
+        lp = np.ascontiguousarray(g.label_ptr, dtype=np.int64)
+        s = np.ascontiguousarray(g.src, dtype=np.int32)
+        d = np.ascontiguousarray(g.dst, dtype=np.int32)
+        h = ctypes.c_void_p()
+        check(lib.rpq_graph_load(self.num_vertices, self.num_labels, _p(lp), _p(s), _p(d), ctypes.byref(h)))
+        self.h = h
+        self.words = bitmap_words(self.num_vertices)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            check(lib.rpq_graph_free(self.h))
+            self.h = None
+
+    __del__ = close
+
+    def info(self, key: str) -> int:
+        v = ctypes.c_int64()
+        check(lib.rpq_graph_info(self.h, key.encode(), ctypes.byref(v)))
+        return v.value
+
+    def set_option(self, key: str, value: int):
+        check(lib.rpq_set_option(self.h, key.encode(), int(value)))
+
+    def get_option(self, key: str) -> int:
+        v = ctypes.c_int64()
+        check(lib.rpq_get_option(self.h, key.encode(), ctypes.byref(v)))
+        return v.value
+
+    def single_source(self, nfa: NFA, source: int, flags: int = 0, level_cap: int = 0,
+                      out: Optional[np.ndarray] = None, out_device_ptr: Optional[int] = None):
+        """Returns (bitmap or None, Stats). With out_device_ptr the bitmap goes
+        to that device address (RPQ_OUT_DEVICE) and None is returned."""
+        st, lc = _stats_struct(level_cap)
+        if out_device_ptr is not None:
+            check(lib.rpq_single_source(self.h, nfa.h, int(source), ctypes.c_void_p(out_device_ptr),
+                                        flags | OUT_DEVICE, ctypes.byref(st)))
+            return None, Stats.from_c(st, lc)
+        bm = out if out is not None else np.zeros(self.words, dtype=np.uint64)
+        check(lib.rpq_single_source(self.h, nfa.h, int(source), _p(bm), flags, ctypes.byref(st)))
+        return bm, Stats.from_c(st, lc)
+
+    def multi_source(self, nfa: NFA, sources: Sequence[int], flags: int = 0,
+                     out_device_ptr: Optional[int] = None, level_cap: int = 0):
+        src = np.ascontiguousarray(sources, dtype=np.int32)
+        st, lc = _stats_struct(level_cap)
+        if out_device_ptr is not None:
+            check(lib.rpq_multi_source(self.h, nfa.h, _p(src), int(src.size), ctypes.c_void_p(out_device_ptr),
+                                       flags | OUT_DEVICE, ctypes.byref(st)))
+            return None, Stats.from_c(st, lc)
+        bm = np.zeros((src.size, self.words), dtype=np.uint64)
+        check(lib.rpq_multi_source(self.h, nfa.h, _p(src), int(src.size), _p(bm), flags, ctypes.byref(st)))
+        return bm, Stats.from_c(st, lc)
+
+    def submit(self, nfa: NFA, source: int) -> int:
+        t = ctypes.c_uint64()
+        check(lib.rpq_submit(self.h, nfa.h, int(source), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, timeout_us: int = 0):
+        """Returns (bitmap, Stats) when finished, None while pending."""
+        bm = np.zeros(self.words, dtype=np.uint64)
+        st, lc = _stats_struct(0)
+        r = lib.rpq_poll(self.h, ctypes.c_uint64(ticket), _p(bm), ctypes.byref(st), int(timeout_us))
+        if r in (RPQ_PENDING, RPQ_ETIMEDOUT):
+            return None
+        check(r)
+        return bm, Stats.from_c(st, lc)

@@ -1,0 +1,186 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle, bit-exact,
+on the same seeded inputs. Results are sets, so the tolerance is zero bits;
+per-level frontier sizes |M_n| and the algorithmic counters must match too."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle
+from workloads import configs as C
+from workloads import graphs as G
+from workloads import regex as R
+import oracle_cases as OC
+
+
+@pytest.fixture(scope="module")
+def rpq():
+    from paper_2412_10287_amd import rpq as mod
+    return mod
+
+
+MODES = {"auto": 0, "push": 8, "pull": 16, "hostloop": 32, "hostloop-pull": 32 | 16}
+
+
+def _run(rpq, gg, nfa_h, src, flags=0, level_cap=0):
+    bm, st = gg.single_source(nfa_h, src, flags=flags, level_cap=level_cap)
+    return bm, st
+
+
+def test_first_light(rpq):
+    # a few tiny cases per mode, host-driven levels first; prints each case
+    rng = np.random.default_rng(5)
+    for case in range(4):
+        g = OC.tiny_graph(rng)
+        text = OC.tiny_expr(rng, g.num_labels)
+        nfa = R.compile_regex(text, g.num_labels)
+        src = int(rng.integers(0, g.num_vertices))
+        want = oracle.ssr(g, nfa, src)
+        gg = rpq.Graph(g)
+        print("persistent grid", gg.info("persistent_grid"), "occupancy api blocks/CU",
+              gg.info("occupancy_blocks_per_cu"), flush=True)
+        nh = rpq.NFA(nfa)
+        for name in ("hostloop", "hostloop-pull", "auto", "push", "pull"):
+            print("case", case, text, "source", src, "mode", name, flush=True)
+            bm, st = _run(rpq, gg, nh, src, MODES[name], level_cap=64)
+            assert np.array_equal(bm, want.bitmap), (case, text, src, name)
+
+
+def test_tiny_graphs_all_modes(rpq):
+    rng = np.random.default_rng(99)
+    for case in range(60):
+        g = OC.tiny_graph(rng)
+        text = OC.tiny_expr(rng, g.num_labels)
+        nfa = R.compile_regex(text, g.num_labels)
+        src = int(rng.integers(0, g.num_vertices))
+        want = oracle.ssr(g, nfa, src)
+        gg = rpq.Graph(g)
+        nh = rpq.NFA(nfa)
+        for name, fl in MODES.items():
+            bm, st = _run(rpq, gg, nh, src, fl, level_cap=64)
+            assert np.array_equal(bm, want.bitmap), (case, text, src, name)
+            assert st.levels == want.levels, (case, text, name)
+            assert np.array_equal(st.level_counts, want.level_counts), (case, text, name)
+
+
+def test_er_workload(rpq):
+    w = C.er_workload()
+    og = oracle.Graph(w.graph)
+    gg = rpq.Graph(w.graph)
+    for text, nfa, s in zip(w.queries, w.nfas, w.sources):
+        want = og.ssr(nfa, int(s))
+        nh = rpq.NFA(nfa)
+        for name, fl in MODES.items():
+            bm, st = _run(rpq, gg, nh, int(s), fl | rpq.COUNTERS, level_cap=4096)
+            assert np.array_equal(bm, want.bitmap), (text, name)
+            assert np.array_equal(st.level_counts, want.level_counts), (text, name)
+            assert st.visited_pairs == int(want.level_counts.sum())
+            assert (st.product_edges, st.scans, st.scanned_edges, st.active, st.alg_bytes) == \
+                (want.product_edges, want.scans, want.scanned_edges, want.active, want.alg_bytes), (text, name)
+
+
+def test_rmat_small_templates(rpq):
+    w = C.rmat_workload(scale=14, edge_factor=16, num_labels=16, n_per_template=6)
+    og = oracle.Graph(w.graph)
+    gg = rpq.Graph(w.graph)
+    for text, nfa, s in zip(w.queries, w.nfas, w.sources):
+        want = og.ssr(nfa, int(s))
+        nh = rpq.NFA(nfa)
+        for name, fl in MODES.items():
+            bm, st = _run(rpq, gg, nh, int(s), fl, level_cap=4096)
+            assert np.array_equal(bm, want.bitmap), (text, name)
+            assert np.array_equal(st.level_counts, want.level_counts), (text, name)
+
+
+def test_wide_state_words(rpq):
+    # 9..16 states use 2-byte words, 17..32 states 4-byte words
+    rng = np.random.default_rng(4)
+    g = G.rmat(12, 8, 6, 1.1, 21)
+    og = oracle.Graph(g)
+    gg = rpq.Graph(g)
+    for leaves in (9, 12, 15, 20, 26, 31):
+        ast = R.random_ast(rng, leaves, lambda r: r.integers(0, 6), 0.3)
+        nfa = R.glushkov(ast, 6)
+        assert nfa.num_states == leaves + 1
+        nh = rpq.NFA(nfa)
+        for s in rng.integers(0, g.num_vertices, size=3):
+            want = og.ssr(nfa, int(s))
+            for name, fl in MODES.items():
+                bm, st = _run(rpq, gg, nh, int(s), fl, level_cap=4096)
+                assert np.array_equal(bm, want.bitmap), (leaves, name)
+                assert np.array_equal(st.level_counts, want.level_counts), (leaves, name)
+
+
+def test_grid_closed_forms_gpu(rpq):
+    side = 48
+    g = G.grid(side, 0.0, 0)
+    gg = rpq.Graph(g)
+
+    def fn(graph, nfa, s):
+        bm, st = gg.single_source(rpq.NFA(nfa), s)
+        return bm, None, st.levels
+
+    OC.check_grid(fn, side, np.random.default_rng(3), n=4)
+
+
+def test_special_cases_gpu(rpq):
+    g = G.erdos_renyi(3000, 9000, 5, 3)
+    gg = rpq.Graph(g)
+
+    def fn(graph, nfa, s):
+        bm, st = gg.single_source(rpq.NFA(nfa), s)
+        return bm, None, st.levels
+
+    OC.check_special(fn, np.random.default_rng(17), g)
+
+
+def test_edge_cases(rpq):
+    # isolated source, empty start set, no final states, labels missing from the
+    # graph, self-loops, a single vertex
+    g = G.from_triples(5, 2, [0, 1, 1, 3], [1, 1, 2, 3], [0, 0, 1, 0])
+    gg = rpq.Graph(g)
+    og = oracle.Graph(g)
+    cases = [R.compile_regex(t, 4) for t in ["0*", "0+", "(0|^0)*", "3*", "3", "^3 0", "1 ^1", "0 0 0 0"]]
+    cases.append(R.nfa_from_triples(2, 2, [(0, 0, 1)], [], [1]))
+    cases.append(R.nfa_from_triples(2, 2, [(0, 0, 1)], [0], []))
+    for nfa in cases:
+        nh = rpq.NFA(nfa)
+        for s in range(5):
+            want = og.ssr(nfa, s)
+            for name, fl in MODES.items():
+                bm, st = _run(rpq, gg, nh, s, fl, level_cap=64)
+                assert np.array_equal(bm, want.bitmap), (nfa.text, s, name)
+                assert st.levels == want.levels
+    one = rpq.Graph(G.from_triples(1, 1, [], [], []))
+    bm, _ = one.single_source(rpq.NFA(R.compile_regex("0*", 1)), 0)
+    assert bm.tolist() == [1]
+
+
+def test_errors(rpq):
+    g = G.erdos_renyi(100, 300, 2, 1)
+    gg = rpq.Graph(g)
+    nh = rpq.NFA(R.compile_regex("0*", 2))
+    with pytest.raises(rpq.RPQError) as e:
+        gg.single_source(nh, 100)
+    assert e.value.status == rpq.RPQ_EINVAL
+    with pytest.raises(rpq.RPQError):
+        gg.single_source(nh, 0, flags=rpq.FORCE_PUSH | rpq.FORCE_PULL)
+    with pytest.raises(rpq.RPQError):
+        gg.set_option("no_such_option", 1)
+    # still usable after errors
+    bm, _ = gg.single_source(nh, 0)
+    assert np.array_equal(bm, oracle.ssr(g, R.compile_regex("0*", 2), 0).bitmap)
+
+
+def test_repeat_is_stable(rpq):
+    # all device updates are idempotent ORs; repeated runs (different atomic
+    # interleavings) must give identical sets and level counts
+    w = C.rmat_workload(scale=13, edge_factor=16, num_labels=8, n_per_template=2)
+    gg = rpq.Graph(w.graph)
+    for nfa, s in zip(w.nfas, w.sources):
+        nh = rpq.NFA(nfa)
+        first, st0 = gg.single_source(nh, int(s), level_cap=1024)
+        for _ in range(5):
+            bm, st = gg.single_source(nh, int(s), level_cap=1024)
+            assert np.array_equal(bm, first)
+            assert np.array_equal(st.level_counts, st0.level_counts)
