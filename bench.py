@@ -1,0 +1,176 @@
+"""Benchmark: single-source 2-RPQ throughput on one MI355X.
+
+Default workload (one "step" = every query of the set, each through the whole
+hot path): R-MAT scale 20 (2^20 vertices, 2^24 generated edges, a,b,c,d =
+0.57/0.19/0.19/0.05), 64 labels Zipf(1.1), 100 queries (20 each of a*, a b*,
+(a|b)+, ^a b*, a ^b c*), sources drawn in proportion to out-degree; queries run
+one at a time through rpq_single_source (the plain path).
+
+Prints one JSON line. ``value`` is product-graph GTEPS: product edges out of
+every reached (state, vertex) pair, summed over the step's queries, divided by
+the step's wall time, with the graph resident in HBM and results written to a
+device buffer. The roofline object reports the persistent traversal kernel:
+algorithmic bytes per launch (one launch = one query) over its mean launch
+duration, timed with HIP events on its own stream inside the timed region.
+The cpu_baseline object times the oracle (single-threaded C) on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(name: str, scale: int):
+    from workloads import configs as C
+    if name == "rmat":
+        return C.rmat_workload(scale=scale)
+    if name == "er":
+        return C.er_workload()
+    raise SystemExit("unknown workload %r" % name)
+
+
+def percentile(xs, p):
+    return float(np.percentile(np.asarray(xs), p)) if len(xs) else 0.0
+
+
+def cpu_baseline(w, budget_s: float):
+    """Oracle (test infrastructure) on the host: single-threaded, one query at
+    a time, over as many of the step's queries as fit in the time budget."""
+    import oracle
+    og = oracle.Graph(w.graph)
+    done, pe, t_total = 0, 0, 0.0
+    for nfa, s in zip(w.nfas, w.sources):
+        t0 = time.perf_counter()
+        r = og.ssr(nfa, int(s))
+        t_total += time.perf_counter() - t0
+        done += 1
+        pe += r.product_edges
+        if t_total > budget_s:
+            break
+    og.close()
+    return {"value": pe / t_total / 1e9 if t_total > 0 else 0.0, "unit": "GTEPS", "cores": 1,
+            "kind": "oracle", "qps": done / t_total if t_total > 0 else 0.0,
+            "sample": "first %d of the %d queries of the step, one at a time, single thread; "
+                      "product edges from the oracle's own counters" % (done, len(w.nfas))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat")
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--host-loop", action="store_true", help="drive levels from the host")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this engine runs on one GPU; --gpus %d is not supported (use --gpus 1)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    t0 = time.time()
+    w = build_workload(args.workload, args.scale)
+    log("workload %s: V=%d E=%d queries=%d (%.1fs)" % (w.name, w.graph.num_vertices, w.graph.num_edges,
+                                                      len(w.queries), time.time() - t0))
+    import torch
+    from paper_2412_10287_amd import rpq
+
+    t0 = time.time()
+    g = rpq.Graph(w.graph)
+    nfas = [rpq.NFA(n) for n in w.nfas]
+    log("graph store loaded (%.1fs), %d MB on device" % (time.time() - t0, g.info("device_bytes") >> 20))
+    words = g.words
+    out = torch.zeros((len(nfas), words), dtype=torch.int64, device="cuda")
+    base_ptr = out.data_ptr()
+    row_bytes = words * 8
+    mode = rpq.HOST_LOOP if args.host_loop else 0
+
+    # algorithmic work per query (deterministic; the GPU counters match the oracle's)
+    pe = np.zeros(len(nfas), np.int64)
+    ab = np.zeros(len(nfas), np.int64)
+    levels = np.zeros(len(nfas), np.int64)
+    for i, (nh, s) in enumerate(zip(nfas, w.sources)):
+        _, st = g.single_source(nh, int(s), flags=mode | rpq.COUNTERS, out_device_ptr=base_ptr + i * row_bytes)
+        pe[i], ab[i], levels[i] = st.product_edges, st.alg_bytes, st.levels
+    log("counters: product edges %d, algorithmic bytes %d, levels max %d" % (pe.sum(), ab.sum(), levels.max()))
+
+    def step(timing: bool, lat=None, kern=None):
+        fl = mode | (rpq.KERNEL_TIMING if timing else 0)
+        for i, (nh, s) in enumerate(zip(nfas, w.sources)):
+            t = time.perf_counter()
+            _, st = g.single_source(nh, int(s), flags=fl, out_device_ptr=base_ptr + i * row_bytes)
+            if lat is not None:
+                lat.append(time.perf_counter() - t)
+            if kern is not None:
+                kern.append((st.expand_ms, st.expand_launches))
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    lat, kern = [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(True, lat, kern)
+        log("step %d done" % k)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+    gteps = pe.sum() * args.steps / dt / 1e9
+    kern_ms = np.array([k[0] for k in kern])
+    n_launch = int(sum(k[1] for k in kern))
+    bytes_total = int(ab.sum()) * args.steps
+    achieved = bytes_total / (kern_ms.sum() * 1e-3) / 1e9 if kern_ms.sum() > 0 else 0.0
+    # correctness spot check against itself across steps is in the tests; here
+    # just make sure the device results are present
+    reached = int(torch.count_nonzero(out).item())
+
+    res = {
+        "metric": "product-graph GTEPS (plain one-query-at-a-time path)",
+        "value": round(gteps, 4),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": w.name + " plain, %d queries per step" % len(nfas),
+                   "queries": len(nfas), "vertices": w.graph.num_vertices,
+                   "edges": w.graph.num_edges, "labels": w.graph.num_labels,
+                   "levels": "host" if args.host_loop else "persistent"},
+        "qps": round(len(nfas) * args.steps / dt, 2),
+        "latency_ms_p50": round(percentile(lat, 50) * 1e3, 4),
+        "latency_ms_p99": round(percentile(lat, 99) * 1e3, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": "rpq::k_persistent<1>", "launches": n_launch,
+                     "mean_launch_us": round(kern_ms.sum() * 1e3 / max(n_launch, 1), 3),
+                     "alg_bytes_per_launch": round(bytes_total / max(n_launch, 1), 1)},
+        "nonzero_result_words": reached,
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -109,14 +109,17 @@ size_t rpq::build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, u
     }
     const int32_t ns = static_cast<int32_t>(used.size());
     *nsym_out = ns;
+    if (ns > MAX_SYMS) return 0;
     const size_t tab = static_cast<size_t>(ns) * MAX_STATES * sizeof(uint32_t);
-    const size_t sz = sizeof(QHeader) + 2 * tab + 2 * static_cast<size_t>(L) * sizeof(int16_t);
+    const size_t sz = sizeof(QHeader) + 2 * tab + 2 * static_cast<size_t>(ns) * 8 + 2 * static_cast<size_t>(ns) * 4;
     buf.assign(sz, 0);
     QHeader *h = reinterpret_cast<QHeader *>(buf.data());
     uint32_t *succ = reinterpret_cast<uint32_t *>(buf.data() + sizeof(QHeader));
     uint32_t *pred = succ + static_cast<size_t>(ns) * MAX_STATES;
-    int16_t *l2s = reinterpret_cast<int16_t *>(buf.data() + sizeof(QHeader) + 2 * tab);
-    for (int32_t i = 0; i < 2 * L; i++) l2s[i] = -1;
+    uint64_t *push_w = reinterpret_cast<uint64_t *>(buf.data() + sizeof(QHeader) + 2 * tab);
+    uint64_t *pull_w = push_w + ns;
+    uint32_t *push_r = reinterpret_cast<uint32_t *>(pull_w + ns);
+    uint32_t *pull_r = push_r + ns;
     h->Q = n->Q;
     h->nsym = ns;
     h->smask = n->smask;
@@ -130,7 +133,13 @@ size_t rpq::build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, u
         const int32_t s = used[u];
         const bool inv = s >= n->NL;
         const int32_t lab = inv ? s - n->NL : s;
-        l2s[(inv ? L : 0) + lab] = static_cast<int16_t>(u);
+        // a forward symbol follows G^a (OUT rows) when pushing and (G^a)^T when
+        // pulling; an inverse symbol the other way round (G^{a^-} = (G^a)^T)
+        const int dpush = inv ? IN : OUT, dpull = inv ? OUT : IN;
+        push_w[u] = (static_cast<uint64_t>(dpush) * L + lab) * static_cast<uint64_t>(g->nwords);
+        pull_w[u] = (static_cast<uint64_t>(dpull) * L + lab) * static_cast<uint64_t>(g->nwords);
+        push_r[u] = static_cast<uint32_t>(g->rbase[static_cast<size_t>(dpush) * L + lab]);
+        pull_r[u] = static_cast<uint32_t>(g->rbase[static_cast<size_t>(dpull) * L + lab]);
         erel += static_cast<uint64_t>(g->label_edges[lab]);
     }
     for (const auto &t : n->trans) {
@@ -143,6 +152,20 @@ size_t rpq::build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, u
     }
     h->e_rel = erel;
     return sz;
+}
+
+// Device addresses of the tables inside a query-constant block at `base`.
+QueryView rpq::query_view(uint8_t *base, int32_t nsym) {
+    QueryView qv;
+    const size_t tab = static_cast<size_t>(nsym) * MAX_STATES * sizeof(uint32_t);
+    qv.h = reinterpret_cast<const QHeader *>(base);
+    qv.succ = reinterpret_cast<const uint32_t *>(base + sizeof(QHeader));
+    qv.pred = reinterpret_cast<const uint32_t *>(base + sizeof(QHeader) + tab);
+    qv.push_w = reinterpret_cast<const uint64_t *>(base + sizeof(QHeader) + 2 * tab);
+    qv.pull_w = qv.push_w + nsym;
+    qv.push_r = reinterpret_cast<const uint32_t *>(qv.pull_w + nsym);
+    qv.pull_r = qv.push_r + nsym;
+    return qv;
 }
 
 // ------------------------------------------------------------------ graph
@@ -213,38 +236,53 @@ rpq_status rpq_graph_load(int32_t V, int32_t L, const int64_t *label_ptr, const 
 
 rpq_status rpq::graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32_t *src, const int32_t *dst) {
     const int32_t V = g->V, L = g->L;
-    const int64_t Ein = label_ptr[L];
     HIP_TRY(hipGetDevice(&g->device));
+    rpq_status st;
     HostDir d[2];
-    build_direction(V, Ein, src, dst, label_ptr, L, d[OUT]);
-    build_direction(V, Ein, dst, src, label_ptr, L, d[IN]);
+    build_direction(V, src, dst, label_ptr, L, 0, d[OUT]);
     const int64_t E = d[OUT].E;
+    build_direction(V, dst, src, label_ptr, L, static_cast<uint32_t>(E), d[IN]);
     g->E = E;
     g->label_edges = d[OUT].label_edges;
-    g->nseg[OUT] = d[OUT].seg_lab.size();
-    g->nseg[IN] = d[IN].seg_lab.size();
-    for (auto &x : d[IN].seg_beg) x += static_cast<uint32_t>(E);  // IN neighbours follow the OUT ones
-    rpq_status st;
-    uint32_t *col = nullptr;
+    g->nwords = rpq_bitmap_words(V);
+    g->rows[OUT] = g->rows[IN] = 0;
+    for (int32_t l = 0; l < L; l++) {
+        g->rows[OUT] += d[OUT].label_rows[l];
+        g->rows[IN] += d[IN].label_rows[l];
+    }
+    // one array per kind, OUT part first
+    const uint64_t nrp_out = d[OUT].rowptr.size();
+    g->rbase.assign(2 * static_cast<size_t>(L), 0);
+    for (int32_t l = 0; l < L; l++) {
+        g->rbase[l] = d[OUT].rbase[l];
+        g->rbase[L + l] = nrp_out + d[IN].rbase[l];
+    }
+    uint32_t *col = nullptr, *rowptr = nullptr;
+    RankWordD *rankw = nullptr;
+    const size_t nrank = static_cast<size_t>(L) * g->nwords;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&col), 2 * E * sizeof(uint32_t), "col")) != RPQ_OK) return st;
-    if (E) {
-        HIP_TRY(hipMemcpy(col, d[OUT].col.data(), E * sizeof(uint32_t), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(col + E, d[IN].col.data(), E * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&rowptr),
+                        (nrp_out + d[IN].rowptr.size()) * sizeof(uint32_t), "rowptr")) != RPQ_OK)
+        return st;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&rankw), 2 * nrank * sizeof(RankWordD), "rank")) != RPQ_OK)
+        return st;
+    static_assert(sizeof(RankWord) == sizeof(RankWordD), "rank word layout");
+    for (int k = 0; k < 2; k++) {
+        if (d[k].E)
+            HIP_TRY(hipMemcpy(col + (k ? E : 0), d[k].col.data(), d[k].E * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(rowptr + (k ? nrp_out : 0), d[k].rowptr.data(), d[k].rowptr.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(rankw + (k ? nrank : 0), d[k].rankw.data(), nrank * sizeof(RankWordD),
+                          hipMemcpyHostToDevice));
+        HostDir().col.swap(d[k].col);
     }
     g->gv.col = col;
+    g->gv.rowptr = rowptr;
+    g->gv.rankw = rankw;
+    g->gv.ncol = 2 * static_cast<uint64_t>(E);
+    g->gv.nwords = g->nwords;
     g->gv.V = V;
     g->gv.L = L;
-    for (int k = 0; k < 2; k++) {
-        uint32_t *p;
-        if ((st = upload(g, &p, d[k].vseg, "vseg")) != RPQ_OK) return st;
-        g->gv.vseg[k] = p;
-        if ((st = upload(g, &p, d[k].seg_lab, "seg_lab")) != RPQ_OK) return st;
-        g->gv.seg_lab[k] = p;
-        if ((st = upload(g, &p, d[k].seg_beg, "seg_beg")) != RPQ_OK) return st;
-        g->gv.seg_beg[k] = p;
-        d[k].col.clear();
-        d[k].col.shrink_to_fit();
-    }
     // single-query state, sized for 4-byte state words
     StateView &sv = g->sv;
     const size_t wbytes = 4 * static_cast<size_t>(V) + 256;
@@ -254,23 +292,23 @@ rpq_status rpq::graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32
         if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.q[k]), 4 * static_cast<size_t>(V), "queue")) != RPQ_OK)
             return st;
     }
-    const size_t items = g->nseg[OUT] + g->nseg[IN] + 1;
-    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.it_ebase), 4 * items, "items")) != RPQ_OK) return st;
-    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.it_beg), 4 * items, "items")) != RPQ_OK) return st;
-    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.it_mask), 4 * items, "items")) != RPQ_OK) return st;
-    const size_t tiles = (2 * static_cast<size_t>(E)) / TILE + 2;
-    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.tile_first), 4 * tiles, "tiles")) != RPQ_OK) return st;
+    // an item is one (vertex, label, direction) row: at most one per row and level
+    sv.item_cap = static_cast<uint64_t>(g->rows[OUT] + g->rows[IN]) + 1;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.it_ebase), 4 * sv.item_cap, "items")) != RPQ_OK) return st;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.it_beg), 4 * sv.item_cap, "items")) != RPQ_OK) return st;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.it_mask), 4 * sv.item_cap, "items")) != RPQ_OK) return st;
+    sv.tile_cap = (2 * static_cast<uint64_t>(E)) / TILE + 2;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.tile_first), 4 * sv.tile_cap, "tiles")) != RPQ_OK) return st;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.rec), sizeof(LevelRec) * REC_RING, "rec")) != RPQ_OK) return st;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.lvl_pairs), 8 * LVL_COUNT_CAP, "lvl")) != RPQ_OK) return st;
-    g->nwords = rpq_bitmap_words(V);
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&g->dev_out), 8 * g->nwords, "out")) != RPQ_OK) return st;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.status), 64, "status")) != RPQ_OK) return st;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.cnt), 64, "cnt")) != RPQ_OK) return st;
-    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.bar), 64, "barrier")) != RPQ_OK) return st;
-    g->qconst_cap = sizeof(QHeader) + 2 * MAX_SYMS * MAX_STATES * sizeof(uint32_t) + 4 * static_cast<size_t>(L) + 64;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.bar), sizeof(GridBarrier), "barrier")) != RPQ_OK) return st;
+    g->qconst_cap = sizeof(QHeader) + static_cast<size_t>(MAX_SYMS) * (2 * MAX_STATES * 4 + 2 * 8 + 2 * 4) + 64;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&g->qconst_dev), g->qconst_cap, "qconst")) != RPQ_OK) return st;
     g->pinned_cap = g->qconst_cap + 4096 + 8 * LVL_COUNT_CAP;
-    HIP_TRY(hipHostMalloc(&g->pinned, g->pinned_cap, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&g->pinned), g->pinned_cap, hipHostMallocDefault));
     HIP_TRY(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
     g->own_stream = true;
     for (int k = 0; k < 4; k++) HIP_TRY(hipEventCreate(&g->ev[k]));
@@ -278,7 +316,6 @@ rpq_status rpq::graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32
     HIP_TRY(launch_fill(sv.P, wbytes / 4, 0, g->stream));
     HIP_TRY(launch_fill(sv.M[0], wbytes / 4, 0, g->stream));
     HIP_TRY(launch_fill(sv.M[1], wbytes / 4, 0, g->stream));
-    HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(sv.bar), 16, 0, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
     for (int W : {1, 2, 4}) g->pgrid[W] = persistent_grid(W);
     return RPQ_OK;
@@ -297,8 +334,8 @@ rpq_status rpq_graph_info(const rpq_graph *g, const char *key, int64_t *value) {
     else if (!strcmp(key, "num_labels")) *value = g->L;
     else if (!strcmp(key, "num_edges")) *value = g->E;
     else if (!strcmp(key, "device_bytes")) *value = g->device_bytes;
-    else if (!strcmp(key, "num_segments_out")) *value = static_cast<int64_t>(g->nseg[OUT]);
-    else if (!strcmp(key, "num_segments_in")) *value = static_cast<int64_t>(g->nseg[IN]);
+    else if (!strcmp(key, "rows_out")) *value = g->rows[OUT];
+    else if (!strcmp(key, "rows_in")) *value = g->rows[IN];
     else if (!strcmp(key, "persistent_grid")) *value = g->pgrid[1];
     else if (!strcmp(key, "occupancy_blocks_per_cu")) *value = occupancy_blocks_per_cu(1);
     else return fail(RPQ_ENOTFOUND, "rpq_graph_info: unknown key '%s'", key);
@@ -360,7 +397,6 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
         HIP_TRY(launch_fill(g->sv.P, words, 0, s));
         HIP_TRY(launch_fill(g->sv.M[0], words, 0, s));
         HIP_TRY(launch_fill(g->sv.M[1], words, 0, s));
-        HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(g->sv.bar), 16, 0, s));
         g->dirty = false;
     }
     g->dirty = true;  // until this query completes
@@ -375,13 +411,7 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
         if (sz > g->qconst_cap) return fail(RPQ_EINVAL, "query constants too large");
         memcpy(g->pinned, g->qbuf.data(), sz);
         HIP_TRY(hipMemcpyAsync(g->qconst_dev, g->pinned, sz, hipMemcpyHostToDevice, s));
-        const size_t tab = static_cast<size_t>(nsym) * MAX_STATES * sizeof(uint32_t);
-        g->qv.h = reinterpret_cast<const QHeader *>(g->qconst_dev);
-        g->qv.succ = reinterpret_cast<const uint32_t *>(g->qconst_dev + sizeof(QHeader));
-        g->qv.pred = reinterpret_cast<const uint32_t *>(g->qconst_dev + sizeof(QHeader) + tab);
-        const int16_t *l2s = reinterpret_cast<const int16_t *>(g->qconst_dev + sizeof(QHeader) + 2 * tab);
-        g->qv.l2s[0] = l2s;
-        g->qv.l2s[1] = l2s + g->L;
+        g->qv = query_view(g->qconst_dev, nsym);
         g->q_serial = n->serial;
         g->q_force = force;
         g->q_counters = counters;
@@ -402,6 +432,7 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
     int32_t launches = 0;
     const int grid_p = g->grid_override ? std::min(g->grid_override, g->pgrid[W]) : g->pgrid[W];
     if (!(flags & RPQ_HOST_LOOP) && grid_p > 0) {
+        HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(p.st.bar), sizeof(GridBarrier) / 4, 0, s));
         if (timing) HIP_TRY(hipEventRecord(g->ev[2], s));
         HIP_TRY(launch_persistent(W, p, grid_p, s));
         if (timing) HIP_TRY(hipEventRecord(g->ev[3], s));
@@ -434,12 +465,14 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
     uint32_t *status = reinterpret_cast<uint32_t *>(stage);
     uint64_t *cnt = reinterpret_cast<uint64_t *>(stage + 64);
     HIP_TRY(hipMemcpyAsync(status, p.st.status, 16, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(status + 4, p.st.bar, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(status + 4, &p.st.bar->abort, 4, hipMemcpyDeviceToHost, s));
     if (counters) HIP_TRY(hipMemcpyAsync(cnt, p.st.cnt, 32, hipMemcpyDeviceToHost, s));
     if (!(flags & RPQ_OUT_DEVICE))
         HIP_TRY(hipMemcpyAsync(out, g->dev_out, 8 * g->nwords, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (status[4 + 2]) return fail(RPQ_EDEVICE, "persistent traversal aborted: grid barrier timed out");
+    if (status[4] && !(flags & RPQ_HOST_LOOP) && grid_p > 0)
+        return fail(RPQ_EDEVICE, "persistent traversal aborted: grid barrier timed out");
+    if (status[3]) return fail(RPQ_EDEVICE, "internal invariant violated %u times (index out of range)", status[3]);
     const uint32_t levels = (flags & RPQ_HOST_LOOP || grid_p <= 0) ? nlev : status[0];
     if (stats) {
         stats->levels = static_cast<int32_t>(levels);

@@ -39,7 +39,8 @@ struct rpq_graph {
     rpq::GraphView gv{};
     rpq::StateView sv{};
     std::vector<int64_t> label_edges;
-    size_t nseg[2] = {0, 0};
+    int64_t rows[2] = {0, 0};
+    std::vector<uint64_t> rbase;  // [direction * L + label] first rowptr entry
     std::vector<void *> allocs;
     int64_t device_bytes = 0;
     int64_t nwords = 0;
@@ -55,7 +56,7 @@ struct rpq_graph {
     int pgrid[5] = {0, 0, 0, 0, 0};
     bool dirty = false;
     // options
-    double pull_alpha = 15.0;
+    double pull_alpha = 0.0;  // push only until tuned (see rpq_set_option)
     double pull_beta = 24.0;
     int32_t max_batch = 256;
     int64_t mem_budget = 0;  // 0 = a quarter of the free device memory at first use
@@ -79,6 +80,7 @@ rpq_status fail(rpq_status st, const char *fmt, ...);
 rpq_status hip_fail(hipError_t e, const char *what);
 size_t build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, uint32_t counters,
                     std::vector<uint8_t> &buf, int32_t *nsym_out);
+QueryView query_view(uint8_t *base, int32_t nsym);
 rpq_status graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32_t *src, const int32_t *dst);
 rpq_status run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint64_t *out, uint32_t flags,
                       rpq_stats *stats);

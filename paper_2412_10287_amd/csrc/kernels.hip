@@ -92,17 +92,22 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t x) {
 }
 
 // Appends `value` for every lane with `flag` to queue[*counter ...] with one
-// atomic per wave. All 64 lanes must call it.
-__device__ __forceinline__ void wave_append(bool flag, int32_t value, int32_t *queue,
-                                            uint32_t *counter) {
+// atomic per wave. All 64 lanes must call it. Returns false if this lane's
+// slot would be at or beyond `cap` (then nothing is written).
+__device__ __forceinline__ bool wave_append(bool flag, int32_t value, int32_t *queue, uint32_t *counter,
+                                            uint32_t cap) {
     const uint64_t m = __ballot(flag);
-    if (m == 0) return;
+    if (m == 0) return true;
     const uint32_t lane = lane_id();
     const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
     uint32_t base = 0;
     if (static_cast<int>(lane) == leader) base = atomicAdd(counter, static_cast<uint32_t>(__popcll(m)));
     base = __shfl(base, leader, 64);
-    if (flag) queue[base + __popcll(m & ((1ull << lane) - 1ull))] = value;
+    if (!flag) return true;
+    const uint32_t pos = base + static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
+    if (pos >= cap) return false;
+    queue[pos] = value;
+    return true;
 }
 
 __device__ __forceinline__ uint32_t succ_of(const uint32_t *succ, uint32_t u, uint32_t S) {
@@ -128,39 +133,111 @@ __device__ __forceinline__ uint32_t count_succ(const uint32_t *succ, uint32_t u,
 __device__ __forceinline__ uint32_t gthread() { return blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ uint32_t gthreads() { return gridDim.x * blockDim.x; }
 
-// Grid-wide barrier for the persistent kernel (all workgroups co-resident, as
-// the cooperative launch guarantees). Each XCD has its own L2, so arrival is a
-// device-scope release (dirty lines written back) and departure a
-// device-scope acquire (stale lines dropped). The wait is bounded in time:
-// after BARRIER_TIMEOUT ticks of the 100 MHz wall clock the barrier records an
-// abort and every workgroup leaves the kernel at its next barrier.
+__device__ __forceinline__ uint32_t aload(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Records a violated invariant (an index read from device memory out of
+// range); the access is skipped and the host reports the query as failed.
+__device__ __forceinline__ void flag_violation(const Params &p) { atomicAdd(&p.st.status[3], 1u); }
+
+// Row of vertex v in one (direction, label) of the store: returns false when
+// v has no neighbours there, else the neighbour range [beg, end).
+__device__ __forceinline__ bool row_range(const GraphView &g, const RankWordD &rw, uint64_t rbase, uint32_t v,
+                                          uint32_t &beg, uint32_t &end) {
+    const uint64_t bit = 1ull << (v & 63);
+    if (!(rw.bits & bit)) return false;
+    const uint64_t row = rbase + rw.rank + static_cast<uint32_t>(__popcll(rw.bits & (bit - 1)));
+    beg = g.rowptr[row];
+    end = g.rowptr[row + 1];
+    return true;
+}
+
+// ------------------------------------------------------------ grid barrier
+// Two-level barrier for the persistent kernel (every workgroup is resident:
+// cooperative launch). Each XCD has its own L2. Workgroups first meet on a
+// per-XCD counter; their stores are already in that XCD's L2 (every wave
+// waits for its memory operations first). The last one on an XCD writes the
+// L2 back once (device-scope release) and meets the other XCDs' leaders on a
+// global counter; then every workgroup drops stale cached lines (device-scope
+// acquire). Counters only grow within a launch (barrier k completes at
+// k * members), and the host zeroes them before each launch. A wait longer
+// than BARRIER_TIMEOUT ticks of the 100 MHz wall clock sets `abort`, and
+// every workgroup leaves the kernel at its next barrier.
 constexpr uint64_t BARRIER_TIMEOUT = 5ull * 100000000ull;  // 5 s
 
-__device__ bool grid_barrier(GridBarrier *b) {
+struct BarCtx {
+    uint32_t xcd;    // this workgroup's XCD
+    uint32_t per;    // workgroups on that XCD
+    uint32_t nxcd;   // XCDs with workgroups
+    uint32_t k;      // barriers passed
+};
+
+__device__ __forceinline__ uint32_t xcc_id() {
+    // hardware register XCC_ID (id 20), bits [3:0]
+    return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u;
+}
+
+__device__ __forceinline__ bool spin_until_at_least(const GridBarrier *b, const uint32_t *ctr, uint32_t target) {
+    const uint64_t t0 = wall_clock64();
+    while (aload(ctr) < target) {
+        if (aload(&b->abort)) return false;
+        if (wall_clock64() - t0 > BARRIER_TIMEOUT) {
+            __hip_atomic_store(const_cast<uint32_t *>(&b->abort), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+
+// Registration at kernel start: every workgroup counts itself on its XCD.
+__device__ bool barrier_register(GridBarrier *b, BarCtx &c) {
+    __shared__ uint32_t s_v[3];
+    if (threadIdx.x == 0) {
+        const uint32_t x = xcc_id();
+        __hip_atomic_fetch_add(&b->reg[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&b->nreg, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t ok = spin_until_at_least(b, &b->nreg, gridDim.x);
+        uint32_t nx = 0;
+        for (int i = 0; i < MAX_XCD; i++) nx += aload(&b->reg[i]) ? 1u : 0u;
+        s_v[0] = x;
+        s_v[1] = aload(&b->reg[x]);
+        s_v[2] = ok ? nx : 0u;
+    }
     __syncthreads();
+    c.xcd = s_v[0];
+    c.per = s_v[1];
+    c.nxcd = s_v[2];
+    c.k = 0;
+    return c.nxcd != 0;
+}
+
+__device__ bool grid_barrier(GridBarrier *b, BarCtx &c) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads and stores are complete
+    __syncthreads();
+    c.k++;
     __shared__ uint32_t s_ok;
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const uint32_t gen = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t arrived =
-            __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t ok = 1;
-        if (arrived == gridDim.x - 1) {
-            __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&b->gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const uint64_t t0 = wall_clock64();
-            while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-                if (wall_clock64() - t0 > BARRIER_TIMEOUT) {
-                    __hip_atomic_store(&b->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
+        const uint32_t a =
+            __hip_atomic_fetch_add(&b->lcount[c.xcd][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == c.k * c.per - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const uint32_t ga = __hip_atomic_fetch_add(&b->gcount, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (ga == c.k * c.nxcd - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                __hip_atomic_store(&b->ggen, c.k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                ok = spin_until_at_least(b, &b->ggen, c.k);
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            __hip_atomic_store(&b->lgen[c.xcd][0], c.k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            ok = spin_until_at_least(b, &b->lgen[c.xcd][0], c.k);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+        if (aload(&b->abort)) ok = 0;
         s_ok = ok;
     }
     __syncthreads();
@@ -184,16 +261,24 @@ __device__ void init_phase(const Params &p) {
         r[0].pairs = __popc(sm);
     }
     for (int i = 0; i < 4; i++) p.st.cnt[i] = 0;
-    p.st.status[0] = p.st.status[1] = p.st.status[2] = 0;
+    for (int i = 0; i < 4; i++) p.st.status[i] = 0;
 }
 
+// Frontier -> push items. For each frontier vertex v with state set S and
+// each used symbol u, succ_u(S) is the column v of (N^u)^T M; when it is
+// non-empty and v has u-neighbours, (v, u) becomes an item carrying the
+// neighbour range and succ_u(S). Items are reserved per wave with one 64-bit
+// atomic that counts items (high half) and edges (low half) together, so item
+// order and edge numbering agree.
 template <int W>
 __device__ void select_phase(const Params &p, uint32_t n) {
     const GraphView &g = p.g;
-    const QHeader &h = *p.qv.h;
+    const QueryView &qv = p.qv;
+    const QHeader &h = *qv.h;
     LevelRec *rec = p.st.rec;
     LevelRec &R = rec[n % REC_RING];
     const uint32_t nq = ld_acq(&R.nq);
+    const uint32_t V = static_cast<uint32_t>(g.V);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         rec[(n + 1) % REC_RING] = LevelRec{};
         if (n < LVL_COUNT_CAP) p.st.lvl_pairs[n] = static_cast<int64_t>(ld_acq(&R.pairs));
@@ -204,67 +289,83 @@ __device__ void select_phase(const Params &p, uint32_t n) {
         const uint32_t nprev = ld_acq(&rec[(n - 1) % REC_RING].nq);
         uint32_t *Mold = p.st.M[(n + 1) & 1];
         const int32_t *qold = p.st.q[(n + 1) & 1];
-        for (uint32_t i = gthread(); i < nprev; i += gthreads()) st_state<W>(Mold, qold[i], 0);
+        for (uint32_t i = gthread(); i < nprev; i += gthreads()) {
+            const uint32_t v = static_cast<uint32_t>(qold[i]);
+            if (v < V) st_state<W>(Mold, v, 0);
+            else flag_violation(p);
+        }
     }
     const int32_t *qc = p.st.q[n & 1];
     const uint32_t *Mc = p.st.M[n & 1];
     const uint32_t lane = lane_id();
     const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
+    const uint32_t nsym = h.nsym;
     uint64_t c_pe = 0, c_sc = 0, c_sd = 0;
     for (uint32_t base = gw * 64; base < nq; base += nw * 64) {
         const uint32_t i = base + lane;
-        const bool act = i < nq;
-        const uint32_t v = act ? static_cast<uint32_t>(qc[i]) : 0u;
-        const uint32_t S = act ? ld_state<W>(Mc, v) : 0u;
-        uint32_t cnt = 0, len = 0;
-        if (S) {
-            for (int d = 0; d < 2; d++) {
-                const uint32_t s0 = g.vseg[d][v], s1 = g.vseg[d][v + 1];
-                for (uint32_t s = s0; s < s1; s++) {
-                    const int u = p.qv.l2s[d][g.seg_lab[d][s]];
-                    if (u < 0) continue;
-                    const uint32_t ln = g.seg_beg[d][s + 1] - g.seg_beg[d][s];
-                    if (ln == 0) continue;
-                    if (h.counters) c_pe += static_cast<uint64_t>(count_succ(p.qv.succ, u, S)) * ln;
-                    if (!succ_of(p.qv.succ, u, S)) continue;
+        uint32_t v = i < nq ? static_cast<uint32_t>(qc[i]) : 0u;
+        uint32_t S = 0;
+        if (i < nq) {
+            if (v < V) S = ld_state<W>(Mc, v);
+            else { flag_violation(p); v = 0; }
+        }
+        for (uint32_t u0 = 0; u0 < nsym; u0 += SYM_BATCH) {
+            uint32_t sp[SYM_BATCH], beg[SYM_BATCH], len[SYM_BATCH];
+            RankWordD rw[SYM_BATCH];
+#pragma unroll
+            for (int j = 0; j < SYM_BATCH; j++) {
+                const uint32_t u = u0 + j;
+                sp[j] = (S && u < nsym) ? succ_of(qv.succ, u, S) : 0u;
+                if (sp[j]) rw[j] = g.rankw[qv.push_w[u] + (v >> 6)];
+            }
+            uint32_t cnt = 0, tot = 0;
+#pragma unroll
+            for (int j = 0; j < SYM_BATCH; j++) {
+                len[j] = 0;
+                uint32_t e;
+                if (sp[j] && row_range(g, rw[j], qv.push_r[u0 + j], v, beg[j], e)) {
+                    if (e > beg[j] && e <= g.ncol) len[j] = e - beg[j];
+                    else if (e != beg[j]) flag_violation(p);
+                }
+                if (len[j]) {
                     cnt++;
-                    len += ln;
+                    tot += len[j];
+                    if (h.counters) c_pe += static_cast<uint64_t>(count_succ(qv.succ, u0 + j, S)) * len[j];
                 }
             }
-        }
-        if (h.counters) {
-            c_sc += cnt;
-            c_sd += len;
-        }
-        uint64_t tot;
-        const uint64_t ex = wave_excl_scan((static_cast<uint64_t>(cnt) << 32) | len, tot);
-        if (tot == 0) continue;
-        uint64_t old = 0;
-        if (lane == 63) old = atomicAdd(reinterpret_cast<unsigned long long *>(&R.sel),
-                                        static_cast<unsigned long long>(tot));
-        old = __shfl(old, 63, 64);
-        if (cnt) {
-            const uint64_t mine = old + ex;
-            uint32_t idx = static_cast<uint32_t>(mine >> 32);
-            uint32_t eb = static_cast<uint32_t>(mine);
-            for (int d = 0; d < 2; d++) {
-                const uint32_t s0 = g.vseg[d][v], s1 = g.vseg[d][v + 1];
-                for (uint32_t s = s0; s < s1; s++) {
-                    const int u = p.qv.l2s[d][g.seg_lab[d][s]];
-                    if (u < 0) continue;
-                    const uint32_t sp = succ_of(p.qv.succ, u, S);
-                    if (!sp) continue;
-                    const uint32_t b = g.seg_beg[d][s];
-                    const uint32_t ln = g.seg_beg[d][s + 1] - b;
-                    if (ln == 0) continue;  // never built; keeps the tile loop bounded
-                    p.st.it_ebase[idx] = eb;
-                    p.st.it_beg[idx] = b;
-                    p.st.it_mask[idx] = sp;
+            if (h.counters) {
+                c_sc += cnt;
+                c_sd += tot;
+            }
+            uint64_t wtot;
+            const uint64_t ex = wave_excl_scan((static_cast<uint64_t>(cnt) << 32) | tot, wtot);
+            if (wtot == 0) continue;
+            uint64_t old = 0;
+            if (lane == 63)
+                old = atomicAdd(reinterpret_cast<unsigned long long *>(&R.sel), static_cast<unsigned long long>(wtot));
+            old = __shfl(old, 63, 64);
+            if (cnt) {
+                const uint64_t mine = old + ex;
+                uint32_t idx = static_cast<uint32_t>(mine >> 32);
+                uint32_t eb = static_cast<uint32_t>(mine);
+#pragma unroll
+                for (int j = 0; j < SYM_BATCH; j++) {
+                    if (!len[j]) continue;
+                    if (idx < p.st.item_cap) {
+                        p.st.it_ebase[idx] = eb;
+                        p.st.it_beg[idx] = beg[j];
+                        p.st.it_mask[idx] = sp[j];
+                    } else {
+                        flag_violation(p);
+                    }
                     // this item owns the tiles whose first edge falls inside it
-                    for (uint32_t k = (eb + TILE - 1) / TILE; k <= (eb + ln - 1) / TILE; k++)
-                        p.st.tile_first[k] = idx;
+                    const uint32_t k1 = (eb + len[j] - 1) / TILE;
+                    for (uint32_t k = (eb + TILE - 1) / TILE; k <= k1; k++) {
+                        if (k < p.st.tile_cap) p.st.tile_first[k] = idx;
+                        else { flag_violation(p); break; }
+                    }
                     idx++;
-                    eb += ln;
+                    eb += len[j];
                 }
             }
         }
@@ -295,15 +396,20 @@ __device__ __forceinline__ uint32_t decide(const Params &p, uint32_t n) {
     return static_cast<double>(nq) * h.beta < static_cast<double>(p.g.V) ? 0u : 1u;
 }
 
+// Items -> edges, spread evenly: tile k holds edges [k*TILE, (k+1)*TILE) of
+// the level; its items are staged in LDS and each thread finds its edge's item
+// by binary search. Per edge (v, w) with successor set S': the bits of S' not
+// yet in P[w] are set with one atomic OR (the masked sum of Alg. 1), go to
+// M'[w], and the first writer of M'[w] appends w to the next queue.
 template <int W>
-__device__ void push_phase(const Params &p, uint32_t n, uint32_t *s_eb, uint32_t *s_beg,
-                           uint32_t *s_mask) {
+__device__ void push_phase(const Params &p, uint32_t n, uint32_t *s_eb, uint32_t *s_beg, uint32_t *s_mask) {
     LevelRec *rec = p.st.rec;
     const uint64_t sel = ld_acq(&rec[n % REC_RING].sel);
     const uint32_t nitems = static_cast<uint32_t>(sel >> 32);
     const uint32_t T = static_cast<uint32_t>(sel);
-    if (T == 0) return;
+    if (T == 0 || nitems == 0) return;
     const uint32_t ntiles = (T + TILE - 1) / TILE;
+    const uint32_t V = static_cast<uint32_t>(p.g.V);
     uint32_t *P = p.st.P;
     uint32_t *Mn = p.st.M[(n + 1) & 1];
     int32_t *qn = p.st.q[(n + 1) & 1];
@@ -313,8 +419,12 @@ __device__ void push_phase(const Params &p, uint32_t n, uint32_t *s_eb, uint32_t
     uint64_t pairs = 0;
     uint32_t su = 0;
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t i0 = p.st.tile_first[tile];
-        const uint32_t i1 = tile + 1 < ntiles ? p.st.tile_first[tile + 1] : nitems - 1;
+        uint32_t i0 = tile < p.st.tile_cap ? p.st.tile_first[tile] : 0u;
+        uint32_t i1 = (tile + 1 < ntiles && tile + 1 < p.st.tile_cap) ? p.st.tile_first[tile + 1] : nitems - 1;
+        if (i0 >= nitems || i1 >= nitems || i1 < i0 || i1 - i0 > static_cast<uint32_t>(TILE)) {
+            if (tid == 0) flag_violation(p);
+            i0 = i1 = 0;
+        }
         const uint32_t cnt = i1 - i0 + 1;  // <= TILE + 1
         for (uint32_t j = tid; j < cnt; j += BLOCK) {
             s_eb[j] = p.st.it_ebase[i0 + j];
@@ -323,11 +433,14 @@ __device__ void push_phase(const Params &p, uint32_t n, uint32_t *s_eb, uint32_t
         }
         __syncthreads();
         const uint32_t t0 = tile * TILE;
+        constexpr int EPT = TILE / BLOCK;  // edges per thread, processed together
+        uint32_t w[EPT], sp[EPT], nwd[EPT];
+        bool first[EPT];
 #pragma unroll
-        for (int k = 0; k < TILE / BLOCK; k++) {
+        for (int k = 0; k < EPT; k++) {
             const uint32_t t = t0 + k * BLOCK + tid;
-            bool first = false;
-            uint32_t w = 0, nwd = 0;
+            w[k] = V;
+            sp[k] = 0;
             if (t < T) {
                 uint32_t lo = 0, hi = cnt;  // s_eb[lo] <= t < s_eb[hi]
                 while (hi - lo > 1) {
@@ -335,17 +448,24 @@ __device__ void push_phase(const Params &p, uint32_t n, uint32_t *s_eb, uint32_t
                     if (s_eb[mid] <= t) lo = mid;
                     else hi = mid;
                 }
-                w = col[s_beg[lo] + (t - s_eb[lo])];
-                const uint32_t sp = s_mask[lo];
-                const uint32_t cand = sp & ~ld_state<W>(P, w);
-                if (cand) {
-                    nwd = cand & ~or_state<W>(P, w, cand);
-                    if (nwd) first = or_state<W>(Mn, w, nwd) == 0;
-                }
+                const uint32_t pos = s_beg[lo] + (t - s_eb[lo]);
+                sp[k] = s_mask[lo];
+                if (pos < p.g.ncol) w[k] = col[pos];
+                else flag_violation(p);
             }
-            wave_append(first, static_cast<int32_t>(w), qn, &RN.nq);
-            pairs += __popc(nwd);
-            su |= nwd;
+        }
+        uint32_t cand[EPT];
+#pragma unroll
+        for (int k = 0; k < EPT; k++) cand[k] = w[k] < V ? sp[k] & ~ld_state<W>(P, w[k]) : 0u;
+#pragma unroll
+        for (int k = 0; k < EPT; k++) nwd[k] = cand[k] ? cand[k] & ~or_state<W>(P, w[k], cand[k]) : 0u;
+#pragma unroll
+        for (int k = 0; k < EPT; k++) first[k] = nwd[k] ? or_state<W>(Mn, w[k], nwd[k]) == 0 : false;
+#pragma unroll
+        for (int k = 0; k < EPT; k++) {
+            if (!wave_append(first[k], static_cast<int32_t>(w[k]), qn, &RN.nq, V)) flag_violation(p);
+            pairs += __popc(nwd[k]);
+            su |= nwd[k];
         }
         __syncthreads();
     }
@@ -357,10 +477,54 @@ __device__ void push_phase(const Params &p, uint32_t n, uint32_t *s_eb, uint32_t
     }
 }
 
+// Dense levels: every vertex w with states U that it lacks and the level can
+// still produce looks, per used symbol u whose predecessor set pred_u(U) is
+// non-empty, through its reverse u-neighbours v, ORs succ_u(M[v]) & U and stops
+// once all of U is found. Each w is owned by one thread (light vertices) or
+// one wavefront (vertices with more than PULL_LIGHT such neighbours, queued
+// per workgroup in LDS and scanned 64 neighbours at a time): no atomics on P.
+constexpr uint32_t PULL_LIGHT = 64;
+constexpr uint32_t PULL_HEAVY_CAP = 512;
+
 template <int W>
-__device__ void pull_phase(const Params &p, uint32_t n) {
+__device__ __forceinline__ uint32_t pull_rows(const Params &p, uint32_t w, uint32_t U, uint32_t u0,
+                                              uint32_t *beg, uint32_t *end) {
+    // row ranges of w for symbols u0 .. u0+SYM_BATCH-1 in the pull direction;
+    // returns the summed length (0 for symbols that cannot reach U)
     const GraphView &g = p.g;
-    const QHeader &h = *p.qv.h;
+    const QueryView &qv = p.qv;
+    const uint32_t nsym = qv.h->nsym;
+    uint32_t pu[SYM_BATCH];
+    RankWordD rw[SYM_BATCH];
+#pragma unroll
+    for (int j = 0; j < SYM_BATCH; j++) {
+        const uint32_t u = u0 + j;
+        pu[j] = u < nsym ? succ_of(qv.pred, u, U) : 0u;
+        if (pu[j]) rw[j] = g.rankw[qv.pull_w[u] + (w >> 6)];
+    }
+    uint32_t tot = 0;
+#pragma unroll
+    for (int j = 0; j < SYM_BATCH; j++) {
+        beg[j] = end[j] = 0;
+        if (pu[j] && row_range(g, rw[j], qv.pull_r[u0 + j], w, beg[j], end[j])) {
+            if (end[j] > g.ncol || end[j] < beg[j]) {
+                flag_violation(p);
+                beg[j] = end[j] = 0;
+            }
+        } else {
+            beg[j] = end[j] = 0;
+        }
+        tot += end[j] - beg[j];
+    }
+    return tot;
+}
+
+template <int W>
+__device__ void pull_phase(const Params &p, uint32_t n, uint32_t *s_hw, uint32_t *s_hu, uint32_t *s_hp,
+                           uint32_t *s_hn) {
+    const GraphView &g = p.g;
+    const QueryView &qv = p.qv;
+    const QHeader &h = *qv.h;
     LevelRec *rec = p.st.rec;
     // states that can appear in the next frontier at all
     uint32_t su = ld_acq(&rec[n % REC_RING].su), ns = 0;
@@ -375,34 +539,56 @@ __device__ void pull_phase(const Params &p, uint32_t n) {
     uint32_t *P = p.st.P;
     LevelRec &RN = rec[(n + 1) % REC_RING];
     const uint32_t lane = lane_id();
-    const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
     const uint32_t V = static_cast<uint32_t>(g.V);
+    const uint32_t nsym = h.nsym;
     uint64_t pairs = 0;
     uint32_t sacc = 0;
+    if (threadIdx.x == 0) *s_hn = 0;
+    __syncthreads();
+    const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
     for (uint32_t base = gw * 64; base < V; base += nw * 64) {
         const uint32_t w = base + lane;
         uint32_t acc = 0;
         if (w < V) {
             const uint32_t pw = ld_state<W>(P, w);
             const uint32_t U = ns & ~pw;
+            bool deferred = false;
             if (U) {
-                // IN segments of w carry forward symbols, OUT segments inverse ones
-                for (int d = 1; d >= 0 && acc != U; d--) {
-                    const int16_t *l2s = p.qv.l2s[1 - d];
-                    const uint32_t s0 = g.vseg[d][w], s1 = g.vseg[d][w + 1];
-                    for (uint32_t s = s0; s < s1 && acc != U; s++) {
-                        const int u = l2s[g.seg_lab[d][s]];
-                        if (u < 0) continue;
-                        uint32_t pu = succ_of(p.qv.pred, u, U & ~acc);
-                        if (!pu) continue;
-                        const uint32_t e1 = g.seg_beg[d][s + 1];
-                        for (uint32_t e = g.seg_beg[d][s]; e < e1; e++) {
-                            const uint32_t m = ld_state<W>(Mc, g.col[e]) & pu;
+                // total work first: heavy vertices go to the workgroup's list
+                uint32_t beg0[SYM_BATCH], end0[SYM_BATCH];
+                uint32_t deg = pull_rows<W>(p, w, U, 0, beg0, end0);
+                for (uint32_t u0 = SYM_BATCH; u0 < nsym && deg <= PULL_LIGHT; u0 += SYM_BATCH) {
+                    uint32_t beg[SYM_BATCH], end[SYM_BATCH];
+                    deg += pull_rows<W>(p, w, U, u0, beg, end);
+                }
+                if (deg > PULL_LIGHT) {
+                    const uint32_t slot = atomicAdd(s_hn, 1u);
+                    if (slot < PULL_HEAVY_CAP) {
+                        s_hw[slot] = w;
+                        s_hu[slot] = U;
+                        s_hp[slot] = pw;
+                        deferred = true;
+                    }
+                }
+                for (uint32_t u0 = 0; !deferred && acc != U && u0 < nsym; u0 += SYM_BATCH) {
+                    uint32_t beg[SYM_BATCH], end[SYM_BATCH];
+                    if (u0 == 0) {
+#pragma unroll
+                        for (int j = 0; j < SYM_BATCH; j++) {
+                            beg[j] = beg0[j];
+                            end[j] = end0[j];
+                        }
+                    } else {
+                        pull_rows<W>(p, w, U & ~acc, u0, beg, end);
+                    }
+#pragma unroll
+                    for (int j = 0; j < SYM_BATCH; j++) {
+                        uint32_t pj = end[j] > beg[j] ? succ_of(qv.pred, u0 + j, U & ~acc) : 0u;
+                        for (uint32_t e = beg[j]; pj && e < end[j]; e++) {
+                            const uint32_t m = ld_state<W>(Mc, g.col[e]) & pj;
                             if (m) {
-                                acc |= succ_of(p.qv.succ, u, m) & U;
-                                if (acc == U) break;
-                                pu = succ_of(p.qv.pred, u, U & ~acc);
-                                if (!pu) break;
+                                acc |= succ_of(qv.succ, u0 + j, m) & U;
+                                pj = succ_of(qv.pred, u0 + j, U & ~acc);
                             }
                         }
                     }
@@ -413,9 +599,47 @@ __device__ void pull_phase(const Params &p, uint32_t n) {
                 }
             }
         }
-        wave_append(acc != 0, static_cast<int32_t>(w), qn, &RN.nq);
+        if (!wave_append(acc != 0, static_cast<int32_t>(w), qn, &RN.nq, V)) flag_violation(p);
         pairs += __popc(acc);
         sacc |= acc;
+    }
+    __syncthreads();
+    // heavy vertices of this workgroup: one wavefront each, 64 neighbours per step
+    const uint32_t nheavy = min(*s_hn, PULL_HEAVY_CAP);
+    const uint32_t wave = threadIdx.x >> 6, nwaves = BLOCK / 64;
+    for (uint32_t k = wave; k < nheavy; k += nwaves) {
+        const uint32_t w = s_hw[k], U = s_hu[k], pw = s_hp[k];
+        uint32_t acc = 0;
+        for (uint32_t u = 0; u < nsym && acc != U; u++) {
+            uint32_t pj = succ_of(qv.pred, u, U & ~acc);
+            if (!pj) continue;
+            const RankWordD rw = g.rankw[qv.pull_w[u] + (w >> 6)];
+            uint32_t beg, end;
+            if (!row_range(g, rw, qv.pull_r[u], w, beg, end)) continue;
+            if (end > g.ncol || end < beg) {
+                flag_violation(p);
+                continue;
+            }
+            for (uint32_t e0 = beg; pj && e0 < end; e0 += 64) {
+                const uint32_t e = e0 + lane;
+                uint32_t got = 0;
+                if (e < end) {
+                    const uint32_t m = ld_state<W>(Mc, g.col[e]) & pj;
+                    if (m) got = succ_of(qv.succ, u, m) & U;
+                }
+                acc |= wave_or(got);
+                pj = succ_of(qv.pred, u, U & ~acc);
+            }
+        }
+        if (lane == 0 && acc) {
+            st_state<W>(P, w, pw | acc);
+            st_state<W>(Mn, w, acc);
+            const uint32_t pos = atomicAdd(&RN.nq, 1u);
+            if (pos < V) qn[pos] = static_cast<int32_t>(w);
+            else flag_violation(p);
+            pairs += __popc(acc);
+            sacc |= acc;
+        }
     }
     pairs = wave_sum(pairs);
     sacc = wave_or(sacc);
@@ -429,15 +653,19 @@ __device__ void pull_phase(const Params &p, uint32_t n) {
 // final state: the product F P of Alg. 1) and resets P for the next query.
 template <int W>
 __device__ void final_phase(const Params &p, uint32_t nlev) {
+    const uint32_t V = static_cast<uint32_t>(p.g.V);
     if (nlev >= 1) {
         const uint32_t D = nlev - 1;
         const uint32_t nq = ld_acq(&p.st.rec[D % REC_RING].nq);
         uint32_t *M = p.st.M[D & 1];
         const int32_t *q = p.st.q[D & 1];
-        for (uint32_t i = gthread(); i < nq; i += gthreads()) st_state<W>(M, q[i], 0);
+        for (uint32_t i = gthread(); i < nq; i += gthreads()) {
+            const uint32_t v = static_cast<uint32_t>(q[i]);
+            if (v < V) st_state<W>(M, v, 0);
+            else flag_violation(p);
+        }
     }
     const uint32_t fm = p.qv.h->fmask;
-    const uint32_t V = static_cast<uint32_t>(p.g.V);
     const uint32_t nwords = (V + 63) / 64;
     const uint32_t lane = lane_id();
     const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
@@ -453,22 +681,25 @@ __device__ void final_phase(const Params &p, uint32_t nlev) {
 // ---------------------------------------------------------------- kernels
 template <int W>
 __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
-    __shared__ uint32_t s_eb[TILE + 1], s_beg[TILE + 1], s_mask[TILE + 1];
+    // push tiles and pull heavy lists share the workgroup's LDS
+    __shared__ uint32_t s_eb[TILE + 1], s_beg[TILE + 1], s_mask[TILE + 1], s_hn;
     GridBarrier *bar = p.st.bar;
+    BarCtx bc;
+    if (!barrier_register(bar, bc)) return;
     init_phase<W>(p);
-    if (!grid_barrier(bar)) return;
+    if (!grid_barrier(bar, bc)) return;
     uint32_t n = 0, npush = 0, npull = 0;
     while (true) {
         if (ld_acq(&p.st.rec[n % REC_RING].nq) == 0) break;
         select_phase<W>(p, n);
-        if (!grid_barrier(bar)) return;
+        if (!grid_barrier(bar, bc)) return;
         const uint32_t mode = decide(p, n);
         if (blockIdx.x == 0 && threadIdx.x == 0) p.st.rec[n % REC_RING].mode = mode;
         if (mode == 0) push_phase<W>(p, n, s_eb, s_beg, s_mask);
-        else pull_phase<W>(p, n);
+        else pull_phase<W>(p, n, s_eb, s_beg, s_mask, &s_hn);
         npush += mode == 0;
         npull += mode != 0;
-        if (!grid_barrier(bar)) return;
+        if (!grid_barrier(bar, bc)) return;
         n++;
     }
     final_phase<W>(p, n);
@@ -491,7 +722,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(Params p, uint32_t n) {
 
 template <int W>
 __global__ __launch_bounds__(BLOCK) void k_expand(Params p, uint32_t n) {
-    __shared__ uint32_t s_eb[TILE + 1], s_beg[TILE + 1], s_mask[TILE + 1];
+    __shared__ uint32_t s_eb[TILE + 1], s_beg[TILE + 1], s_mask[TILE + 1], s_hn;
     const uint32_t mode = decide(p, n);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         p.st.rec[n % REC_RING].mode = mode;
@@ -499,7 +730,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(Params p, uint32_t n) {
         p.st.status[1 + (mode != 0)] += 1;
     }
     if (mode == 0) push_phase<W>(p, n, s_eb, s_beg, s_mask);
-    else pull_phase<W>(p, n);
+    else pull_phase<W>(p, n, s_eb, s_beg, s_mask, &s_hn);
 }
 
 template <int W>

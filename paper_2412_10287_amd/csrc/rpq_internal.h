@@ -6,28 +6,38 @@
 
 namespace rpq {
 
-constexpr int OUT = 0;  // adjacency G^a: edges v -> w stored at v
-constexpr int IN = 1;   // transpose (G^a)^T: edges w -> v stored at v
+constexpr int OUT = 0;  // adjacency G^a: row v holds the w with v -> w
+constexpr int IN = 1;   // transpose (G^a)^T: row v holds the w with w -> v
 
 constexpr int MAX_STATES = 32;
-constexpr int MAX_SYMS = 256;          // distinct (label, direction) symbols one query may use
-constexpr uint32_t REC_RING = 1024;    // level records kept in a ring
+constexpr int MAX_SYMS = 256;              // distinct symbols one query may use
+constexpr uint32_t REC_RING = 1024;        // level records kept in a ring
 constexpr uint32_t LVL_COUNT_CAP = 65536;  // per-level pair counts kept for statistics
-constexpr int BLOCK = 512;             // threads per workgroup (8 waves)
-constexpr int TILE = 4 * BLOCK;        // push edges per tile (one workgroup iteration)
-// Persistent launches use at most this many workgroups per CU: 16 of the 28
-// wave slots a CU offers this kernel, so every workgroup is resident at once.
-constexpr int PERSISTENT_BLOCKS_PER_CU = 2;
+constexpr int BLOCK = 512;                 // threads per workgroup (8 waves)
+constexpr int TILE = 4 * BLOCK;            // push edges per tile (one workgroup iteration)
+constexpr int SYM_BATCH = 4;               // row lookups issued together per vertex
+// Persistent launches use at most this many workgroups per CU (the occupancy
+// API allows 3 for this kernel): every workgroup is resident at once, and
+// fewer workgroups make each grid barrier cheaper.
+constexpr int PERSISTENT_BLOCKS_PER_CU = 1;
+constexpr int MAX_XCD = 16;
 
-// Device-resident graph: per direction, a vertex-major "segment" layout.
-// Vertex v owns segments [vseg[v], vseg[v+1]); segment s holds the neighbours
-// of v under one label, seg_lab[s], at col[seg_beg[s] .. seg_beg[s+1]).
-// Both directions share one col array (IN segments start after the E OUT ones).
+struct RankWordD {
+    uint64_t bits;
+    uint32_t rank;
+    uint32_t pad;
+};
+
+// Device-resident graph store (label-major, both directions). For label l and
+// direction d, vertex v has a row iff bit (v & 63) of rankw[(d*L + l)*nwords +
+// (v >> 6)] is set; the row number is that word's rank plus the set bits below
+// v, and its neighbours are col[rowptr[rbase[d][l] + row] .. rowptr[... + 1]).
 struct GraphView {
-    const uint32_t *vseg[2];
-    const uint32_t *seg_lab[2];
-    const uint32_t *seg_beg[2];
+    const RankWordD *rankw;
+    const uint32_t *rowptr;
     const uint32_t *col;
+    uint64_t ncol;   // entries of col (both directions)
+    int64_t nwords;  // rank words per (direction, label)
     int32_t V;
     int32_t L;
 };
@@ -40,23 +50,29 @@ struct QHeader {
     uint32_t smask;      // start states
     uint32_t fmask;      // final states
     uint32_t inmask;     // states with an incoming transition on a used symbol
-    uint32_t pad0;
-    uint64_t e_rel;      // edges under the used symbols (both directions as used)
+    uint32_t force;      // 1 = push only, 2 = pull from level 0
+    uint64_t e_rel;      // edges under the used symbols
     float alpha;         // push->pull threshold (0 = never pull)
     float beta;          // pull->push threshold
-    uint32_t force;      // 1 = push only, 2 = pull from level 1
     uint32_t counters;   // 1 = accumulate the algorithmic counters
+    uint32_t pad;
     uint32_t succ_any[MAX_STATES];  // OR over used symbols of succ[u][q]
 };
 
-// Layout of the device query-constant block: QHeader, then succ[nsym][32],
-// pred[nsym][32] (uint32), then lab2sym[2][L] (int16; -1 = unused).
+// Layout of the device query-constant block: QHeader, then
+//   succ[nsym][32], pred[nsym][32]           (uint32 state sets)
+//   push_w[nsym], pull_w[nsym]               (uint64 rank-word base)
+//   push_r[nsym], pull_r[nsym]               (uint32 rowptr base)
+// A forward symbol pushes along OUT rows and pulls along IN rows; an inverse
+// symbol the other way round.
 struct QueryView {
     const QHeader *h;
     const uint32_t *succ;
     const uint32_t *pred;
-    const int16_t *l2s[2];  // push view: OUT segment label -> forward symbol,
-                            // IN segment label -> inverse symbol
+    const uint64_t *push_w;
+    const uint64_t *pull_w;
+    const uint32_t *push_r;
+    const uint32_t *pull_r;
 };
 
 // One BFS level's bookkeeping (a ring of REC_RING entries).
@@ -69,12 +85,15 @@ struct LevelRec {
     uint32_t pad;
 };
 
-// Software grid barrier state (see grid_barrier in kernels.hip).
+// Two-level grid barrier state (see grid_barrier in kernels.hip).
 struct GridBarrier {
-    uint32_t count;  // workgroups arrived at the current barrier
-    uint32_t gen;    // barrier generation
-    uint32_t abort;  // set when a wait timed out; the launch then ends early
-    uint32_t pad;
+    uint32_t reg[MAX_XCD];        // workgroups registered per XCD (this launch)
+    uint32_t nreg;                // workgroups registered in total
+    uint32_t abort;               // a wait timed out; the launch ends early
+    uint32_t gcount, ggen;        // XCD leaders arrived / generation
+    uint32_t pad0[12];
+    uint32_t lcount[MAX_XCD][16]; // per-XCD arrivals (one 64-byte line each)
+    uint32_t lgen[MAX_XCD][16];   // per-XCD generation
 };
 
 // Per-query mutable device state.
@@ -89,9 +108,11 @@ struct StateView {
     LevelRec *rec;        // REC_RING records
     int64_t *lvl_pairs;   // |M_n| for n < LVL_COUNT_CAP
     uint64_t *out;        // output bitmap (device)
-    uint32_t *status;     // [0] levels, [1] push levels, [2] pull levels
+    uint32_t *status;     // [0] levels, [1] push levels, [2] pull levels, [3] invariant violations
     uint64_t *cnt;        // [0] product edges, [1] scans, [2] scanned edges, [3] active
-    GridBarrier *bar;     // persistent-kernel barrier (zero between launches)
+    GridBarrier *bar;     // persistent-kernel barrier
+    uint64_t item_cap;    // entries of the item arrays
+    uint64_t tile_cap;    // entries of tile_first
 };
 
 struct Params {
@@ -103,7 +124,7 @@ struct Params {
 
 // Launchers (kernels.hip). W is the state-word width in bytes: 1, 2 or 4.
 hipError_t launch_persistent(int W, const Params &p, int grid, hipStream_t s);
-int persistent_grid(int W);  // co-resident workgroups for the persistent kernel
+int persistent_grid(int W);          // co-resident workgroups for the persistent kernel
 int occupancy_blocks_per_cu(int W);  // what the occupancy API reports
 hipError_t launch_init(int W, const Params &p, hipStream_t s);
 hipError_t launch_select(int W, const Params &p, uint32_t level, int grid, hipStream_t s);

@@ -83,6 +83,7 @@ def test_rmat_small_templates(rpq):
     w = C.rmat_workload(scale=14, edge_factor=16, num_labels=16, n_per_template=6)
     og = oracle.Graph(w.graph)
     gg = rpq.Graph(w.graph)
+    switched = 0
     for text, nfa, s in zip(w.queries, w.nfas, w.sources):
         want = og.ssr(nfa, int(s))
         nh = rpq.NFA(nfa)
@@ -90,6 +91,17 @@ def test_rmat_small_templates(rpq):
             bm, st = _run(rpq, gg, nh, int(s), fl, level_cap=4096)
             assert np.array_equal(bm, want.bitmap), (text, name)
             assert np.array_equal(st.level_counts, want.level_counts), (text, name)
+        # direction switching on: push->pull->push within one traversal
+        for alpha, beta in ((4, 24), (30, 4), (1000, 2)):
+            gg.set_option("pull_alpha", alpha)
+            gg.set_option("pull_beta", beta)
+            for fl in (0, rpq.HOST_LOOP):
+                bm, st = _run(rpq, gg, nh, int(s), fl, level_cap=4096)
+                assert np.array_equal(bm, want.bitmap), (text, alpha, beta, fl)
+                assert np.array_equal(st.level_counts, want.level_counts), (text, alpha, beta, fl)
+                switched += st.push_levels > 0 and st.pull_levels > 0
+        gg.set_option("pull_alpha", 0)
+    assert switched > 0
 
 
 def test_wide_state_words(rpq):
