@@ -1,0 +1,304 @@
+// Multi-query kernels: every admitted query (a slot, with its own NFA, source,
+// visited set P and frontier M) advances one level per launch pair. The level
+// is the same computation as the single-query path (Alg. 1's update: for each
+// frontier pair set, succ_a per used symbol, pushed along the symbol's rows,
+// masked by P), with a slot tag on every queue entry and push item, so one
+// edge-balanced launch carries the frontiers of all queries at once and the
+// per-level fixed cost is shared.
+#include "device_common.h"
+#include "multi.h"
+
+namespace rpq {
+
+__device__ __forceinline__ void mviolation(const MultiParams &p) { atomicAdd(p.status, 1u); }
+
+// Adds (cnt, pairs) of every lane to its slot's counters with one atomic pair
+// per distinct slot in the wave. All 64 lanes must call it.
+__device__ __forceinline__ void wave_slot_add(const MultiParams &p, uint32_t slot, uint32_t cnt, uint32_t pairs) {
+    const uint32_t lane = lane_id();
+    bool pending = (cnt | pairs) != 0;
+    uint64_t m;
+    while ((m = __ballot(pending)) != 0) {
+        const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+        const uint32_t ls = static_cast<uint32_t>(__shfl(static_cast<int>(slot), leader, 64));
+        const bool match = pending && slot == ls;
+        const uint64_t c = wave_sum(match ? cnt : 0u);
+        const uint64_t q = wave_sum(match ? pairs : 0u);
+        if (static_cast<int>(lane) == leader) {
+            if (c) atomicAdd(&p.next_count[ls], static_cast<uint32_t>(c));
+            if (q) atomicAdd(reinterpret_cast<unsigned long long *>(&p.pairs[ls]), static_cast<unsigned long long>(q));
+        }
+        if (match) pending = false;
+    }
+}
+
+// Tables of slot s (same layout as build_qconst).
+__device__ __forceinline__ QueryView slot_view(const MultiParams &p, uint32_t s) {
+    const uint8_t *base = p.qconst + static_cast<size_t>(s) * QC_STRIDE;
+    QueryView qv;
+    qv.h = reinterpret_cast<const QHeader *>(base);
+    const uint32_t nsym = qv.h->nsym;
+    const size_t tab = static_cast<size_t>(nsym) * MAX_STATES * sizeof(uint32_t);
+    qv.succ = reinterpret_cast<const uint32_t *>(base + sizeof(QHeader));
+    qv.pred = reinterpret_cast<const uint32_t *>(base + sizeof(QHeader) + tab);
+    qv.push_w = reinterpret_cast<const uint64_t *>(base + sizeof(QHeader) + 2 * tab);
+    qv.pull_w = qv.push_w + nsym;
+    qv.push_r = reinterpret_cast<const uint32_t *>(qv.pull_w + nsym);
+    qv.pull_r = qv.push_r + nsym;
+    return qv;
+}
+
+__global__ void k_multi_admit(MultiParams p, uint32_t parity, uint32_t n, const uint32_t *ss) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t s = ss[2 * i], v = ss[2 * i + 1];
+    if (s >= p.slots || v >= static_cast<uint32_t>(p.V)) {
+        mviolation(p);
+        return;
+    }
+    const uint32_t sm = reinterpret_cast<const QHeader *>(p.qconst + static_cast<size_t>(s) * QC_STRIDE)->smask;
+    p.pairs[s] = __popc(sm);
+    if (!sm) return;
+    p.P[s * p.swords + v] = sm;
+    p.M[parity][s * p.swords + v] = sm;
+    const uint32_t pos = atomicAdd(&p.qlen[parity], 1u);
+    if (pos < p.queue_cap) p.q[parity][pos] = (s << p.vbits) | v;
+    else mviolation(p);
+}
+
+// Queue entries [lo, hi) of the current level -> items. The first chunk of a
+// level also clears the previous level's frontier words (the buffer this level
+// writes) and resets the per-slot append counters and the next queue length.
+__global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t parity, uint32_t lo, uint32_t hi,
+                                                        uint32_t clear_n, int first_chunk, uint32_t chunk_id) {
+    const uint32_t V = static_cast<uint32_t>(p.V);
+    const uint32_t vmask = (1u << p.vbits) - 1u;
+    uint64_t *sel = p.sel + (chunk_id & 1);
+    // the other reservation counter was read by the previous push, which has
+    // finished: clear it for the next chunk
+    if (gthread() == 0) p.sel[(chunk_id + 1) & 1] = 0;
+    if (first_chunk) {
+        uint32_t *Mold = p.M[parity ^ 1];
+        const uint32_t *qold = p.q[parity ^ 1];
+        for (uint32_t i = gthread(); i < clear_n; i += gthreads()) {
+            const uint32_t e = qold[i], s = e >> p.vbits, v = e & vmask;
+            if (s < p.slots && v < V) Mold[s * p.swords + v] = 0;
+            else mviolation(p);
+        }
+        for (uint32_t i = gthread(); i < p.slots; i += gthreads()) p.next_count[i] = 0;
+        if (gthread() == 0) p.qlen[parity ^ 1] = 0;
+    }
+    const uint32_t *qc = p.q[parity];
+    const uint32_t *Mc = p.M[parity];
+    const uint32_t lane = lane_id();
+    const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
+    const GraphView &g = p.g;
+    for (uint32_t base = lo + gw * 64; base < hi; base += nw * 64) {
+        const uint32_t i = base + lane;
+        uint32_t s = 0, v = 0, S = 0, nsym = 0;
+        QueryView qv{};
+        if (i < hi) {
+            const uint32_t e = qc[i];
+            s = e >> p.vbits;
+            v = e & vmask;
+            if (s < p.slots && v < V) {
+                S = Mc[s * p.swords + v];
+                qv = slot_view(p, s);
+                nsym = qv.h->nsym;
+            } else {
+                mviolation(p);
+                s = v = 0;
+            }
+        }
+        // the symbol loop is wave-uniform: run to the wave's largest nsym
+        uint32_t wmax = nsym;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) wmax = max(wmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(wmax), d, 64)));
+        for (uint32_t u0 = 0; u0 < wmax; u0 += SYM_BATCH) {
+            uint32_t sp[SYM_BATCH], beg[SYM_BATCH], len[SYM_BATCH];
+            RankWordD rw[SYM_BATCH];
+#pragma unroll
+            for (int j = 0; j < SYM_BATCH; j++) {
+                const uint32_t u = u0 + j;
+                sp[j] = (S && u < nsym) ? succ_of(qv.succ, u, S) : 0u;
+                if (sp[j]) rw[j] = g.rankw[qv.push_w[u] + (v >> 6)];
+            }
+            uint32_t cnt = 0, tot = 0;
+#pragma unroll
+            for (int j = 0; j < SYM_BATCH; j++) {
+                len[j] = 0;
+                uint32_t e;
+                if (sp[j] && row_range(g, rw[j], qv.push_r[u0 + j], v, beg[j], e)) {
+                    if (e > beg[j] && e <= g.ncol) len[j] = e - beg[j];
+                    else if (e != beg[j]) mviolation(p);
+                }
+                if (len[j]) {
+                    cnt++;
+                    tot += len[j];
+                }
+            }
+            uint64_t wtot;
+            const uint64_t ex = wave_excl_scan((static_cast<uint64_t>(cnt) << 40) | tot, wtot);
+            if (wtot == 0) continue;
+            uint64_t old = 0;
+            if (lane == 63) old = atomicAdd(reinterpret_cast<unsigned long long *>(sel), (unsigned long long)wtot);
+            old = __shfl(old, 63, 64);
+            if (cnt) {
+                const uint64_t mine = old + ex;
+                uint64_t idx = mine >> 40;
+                uint64_t eb = mine & ((1ull << 40) - 1);
+#pragma unroll
+                for (int j = 0; j < SYM_BATCH; j++) {
+                    if (!len[j]) continue;
+                    if (idx < p.item_cap) {
+                        p.it_ebase[idx] = eb;
+                        p.it_beg[idx] = beg[j];
+                        p.it_mask[idx] = sp[j];
+                        p.it_slot[idx] = s;
+                    } else {
+                        mviolation(p);
+                    }
+                    const uint64_t k1 = (eb + len[j] - 1) / TILE;
+                    for (uint64_t k = (eb + TILE - 1) / TILE; k <= k1; k++) {
+                        if (k < p.tile_cap) p.tile_first[k] = static_cast<uint32_t>(idx);
+                        else { mviolation(p); break; }
+                    }
+                    idx++;
+                    eb += len[j];
+                }
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_multi_push(MultiParams p, uint32_t parity, uint32_t chunk_id) {
+    __shared__ uint64_t s_eb[TILE + 1];
+    __shared__ uint32_t s_beg[TILE + 1], s_mask[TILE + 1], s_slot[TILE + 1];
+    const uint64_t sel = __hip_atomic_load(p.sel + (chunk_id & 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t nitems = sel >> 40;
+    const uint64_t T = sel & ((1ull << 40) - 1);
+    if (T == 0 || nitems == 0) return;
+    const uint64_t ntiles = (T + TILE - 1) / TILE;
+    if (nitems > p.item_cap || ntiles > p.tile_cap) {
+        if (gthread() == 0) mviolation(p);
+        return;
+    }
+    const uint32_t V = static_cast<uint32_t>(p.V);
+    uint32_t *qn = p.q[parity ^ 1];
+    uint32_t *Mn = p.M[parity ^ 1];
+    const uint32_t *col = p.g.col;
+    const uint32_t tid = threadIdx.x;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        uint32_t i0 = p.tile_first[tile];
+        uint32_t i1 = tile + 1 < ntiles ? p.tile_first[tile + 1] : static_cast<uint32_t>(nitems - 1);
+        if (i0 >= nitems || i1 >= nitems || i1 < i0 || i1 - i0 > static_cast<uint32_t>(TILE)) {
+            if (tid == 0) mviolation(p);
+            i0 = i1 = 0;
+        }
+        const uint32_t cnt = i1 - i0 + 1;
+        for (uint32_t j = tid; j < cnt; j += BLOCK) {
+            s_eb[j] = p.it_ebase[i0 + j];
+            s_beg[j] = p.it_beg[i0 + j];
+            s_mask[j] = p.it_mask[i0 + j];
+            s_slot[j] = p.it_slot[i0 + j];
+        }
+        __syncthreads();
+        const uint64_t t0 = tile * TILE;
+        constexpr int EPT = TILE / BLOCK;
+        uint32_t w[EPT], sp[EPT], sl[EPT], nwd[EPT];
+        bool first[EPT];
+#pragma unroll
+        for (int k = 0; k < EPT; k++) {
+            const uint64_t t = t0 + k * BLOCK + tid;
+            w[k] = V;
+            sp[k] = 0;
+            sl[k] = 0;
+            if (t < T) {
+                uint32_t lo = 0, hi = cnt;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (s_eb[mid] <= t) lo = mid;
+                    else hi = mid;
+                }
+                const uint64_t pos = s_beg[lo] + (t - s_eb[lo]);
+                sp[k] = s_mask[lo];
+                sl[k] = s_slot[lo];
+                if (pos < p.g.ncol && sl[k] < p.slots) w[k] = col[pos];
+                else mviolation(p);
+            }
+        }
+        uint32_t cand[EPT];
+#pragma unroll
+        for (int k = 0; k < EPT; k++)
+            cand[k] = w[k] < V ? sp[k] & ~p.P[sl[k] * p.swords + w[k]] : 0u;
+#pragma unroll
+        for (int k = 0; k < EPT; k++) nwd[k] = cand[k] ? cand[k] & ~atomicOr(&p.P[sl[k] * p.swords + w[k]], cand[k]) : 0u;
+#pragma unroll
+        for (int k = 0; k < EPT; k++) first[k] = nwd[k] ? atomicOr(&Mn[sl[k] * p.swords + w[k]], nwd[k]) == 0 : false;
+#pragma unroll
+        for (int k = 0; k < EPT; k++) {
+            if (!wave_append(first[k], static_cast<int32_t>((sl[k] << p.vbits) | w[k]),
+                             reinterpret_cast<int32_t *>(qn), &p.qlen[parity ^ 1],
+                             static_cast<uint32_t>(p.queue_cap)))
+                mviolation(p);
+            wave_slot_add(p, sl[k], first[k] ? 1u : 0u, static_cast<uint32_t>(__popc(nwd[k])));
+        }
+        __syncthreads();
+    }
+}
+
+// One wavefront per 64-vertex word of each finished slot's answer: the ballot
+// of (P[v] & F != 0) is the word (the product F P of Alg. 1); P is reset.
+__global__ __launch_bounds__(BLOCK) void k_multi_extract(MultiParams p, uint32_t nfin, const uint32_t *fin,
+                                                         uint64_t nwords) {
+    const uint32_t V = static_cast<uint32_t>(p.V);
+    const uint32_t lane = lane_id();
+    const uint64_t total = static_cast<uint64_t>(nfin) * nwords;
+    for (uint64_t gw = gthread() >> 6; gw < total; gw += gthreads() >> 6) {
+        const uint32_t f = static_cast<uint32_t>(gw / nwords);
+        const uint64_t k = gw % nwords;
+        const uint32_t s = fin[f];
+        if (s >= p.slots) {
+            if (lane == 0) mviolation(p);
+            continue;
+        }
+        const uint32_t fm = reinterpret_cast<const QHeader *>(p.qconst + static_cast<size_t>(s) * QC_STRIDE)->fmask;
+        const uint64_t v = k * 64 + lane;
+        uint32_t *Ps = p.P + static_cast<uint64_t>(s) * p.swords;
+        const uint32_t pv = v < V ? Ps[v] : 0u;
+        const uint64_t b = __ballot((pv & fm) != 0);
+        if (lane == 0) p.out[static_cast<uint64_t>(f) * nwords + k] = b;
+        if (pv) Ps[v] = 0;
+    }
+}
+
+hipError_t multi_admit(const MultiParams &p, uint32_t parity, uint32_t n, const uint32_t *slot_src, hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_multi_admit, dim3((n + 255) / 256), dim3(256), 0, s, p, parity, n, slot_src);
+    return hipGetLastError();
+}
+
+hipError_t multi_select(const MultiParams &p, uint32_t parity, uint32_t lo, uint32_t hi, uint32_t clear_n,
+                        int first_chunk, uint32_t chunk_id, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_multi_select, dim3(grid), dim3(BLOCK), 0, s, p, parity, lo, hi, clear_n, first_chunk,
+                       chunk_id);
+    return hipGetLastError();
+}
+
+hipError_t multi_push(const MultiParams &p, uint32_t parity, uint32_t chunk_id, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_multi_push, dim3(grid), dim3(BLOCK), 0, s, p, parity, chunk_id);
+    return hipGetLastError();
+}
+
+hipError_t multi_extract(const MultiParams &p, uint32_t nfin, const uint32_t *fin_slots, uint64_t nwords,
+                         hipStream_t s) {
+    if (!nfin) return hipSuccess;
+    uint64_t waves = static_cast<uint64_t>(nfin) * nwords;
+    uint64_t blocks = (waves + (BLOCK / 64) - 1) / (BLOCK / 64);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_multi_extract, dim3(static_cast<uint32_t>(blocks)), dim3(BLOCK), 0, s, p, nfin, fin_slots,
+                       nwords);
+    return hipGetLastError();
+}
+
+}  // namespace rpq

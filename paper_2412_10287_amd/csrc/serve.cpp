@@ -1,24 +1,468 @@
-// Served path: rpq_submit / rpq_poll.
+// Served path: rpq_submit / rpq_poll, and rpq_multi_source on the same engine.
+//
+// A scheduler thread owns a multi-query engine (multi.hip). Each admitted
+// query occupies a slot with its own state words; every iteration of the loop
+//   1. admits queued requests into free slots (bounded by max_slots and the
+//      device-memory budget),
+//   2. runs ONE level of Alg. 1 for every admitted query in shared launches
+//      (select over the combined frontier queue, then edge-balanced push),
+//   3. retires the queries whose frontier became empty (one extract launch for
+//      all of them), copies their bitmaps out and wakes their pollers.
+// New requests therefore join while others are in flight (iteration-level
+// scheduling), and one launch carries the work of all of them.
+#include <string.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+
 #include "api_internal.h"
+#include "multi.h"
 
 using namespace rpq;
+using Clock = std::chrono::steady_clock;
 
-void rpq::serve_shutdown(rpq_graph *) {}
-bool rpq::serve_pending(rpq_graph *) { return false; }
-void rpq::batch_free(rpq_graph *) {}
+namespace rpq {
 
-rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
-                            uint64_t *out_bitmaps, uint32_t flags, rpq_stats *stats) {
-    (void)g; (void)n; (void)sources; (void)n_sources; (void)out_bitmaps; (void)flags; (void)stats;
-    return fail(RPQ_EINVAL, "rpq_multi_source: not built yet");
+struct Request {
+    rpq_ticket id = 0;
+    int32_t source = 0;
+    int32_t nsym = 0;
+    uint32_t smask = 0;
+    std::vector<uint8_t> qc;  // query constants (build_qconst layout)
+    Clock::time_point submitted;
+};
+
+struct Ticket {
+    int state = 0;  // 0 queued, 1 running, 2 done
+    rpq_status status = RPQ_OK;
+    std::string error;
+    std::vector<uint64_t> bitmap;
+    rpq_stats stats{};
+};
+
+struct SlotInfo {
+    rpq_ticket ticket = 0;
+    int32_t nsym = 0;
+    uint32_t admit_level = 0;
+    Clock::time_point submitted;
+};
+
+struct ServeState {
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request> pending;
+    std::unordered_map<rpq_ticket, Ticket> tickets;
+    std::thread worker;
+    bool stop = false;
+    bool failed = false;
+    std::string fail_msg;
+    rpq_ticket next_ticket = 1;
+    size_t running = 0;
+    // engine (owned by the worker thread after start)
+    MultiParams mp{};
+    hipStream_t stream = nullptr;
+    std::vector<void *> allocs;
+    uint8_t *pinned = nullptr;
+    size_t pinned_bytes = 0;
+    uint32_t slots = 0;
+    std::vector<SlotInfo> slot;
+    std::vector<uint32_t> free_slots;
+    uint32_t level = 0;
+    uint32_t chunk_id = 0;
+    uint32_t cur_len = 0, prev_len = 0;
+    uint32_t *d_admit = nullptr, *d_fin = nullptr;
+    // pinned host staging
+    uint32_t *h_admit = nullptr;  // 2 * slots
+    uint32_t *h_fin = nullptr;    // slots
+    uint8_t *h_ctl = nullptr;     // control block
+    uint8_t *h_qc = nullptr;      // slots * QC_STRIDE
+    uint64_t *h_out = nullptr;    // slots * nwords
+    int grid = 1024;
+};
+
+}  // namespace rpq
+
+static int vbits_for(int32_t V) {
+    int b = 1;
+    while ((1ll << b) < V) b++;
+    return b;
 }
 
+static hipError_t salloc(ServeState *ss, void **p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes ? bytes : 64);
+    if (e == hipSuccess) ss->allocs.push_back(*p);
+    return e;
+}
+
+// Allocates the engine for `slots` queries. Called by the worker thread.
+static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
+    const int32_t V = g->V;
+    const uint32_t vb = static_cast<uint32_t>(vbits_for(V));
+    uint64_t max_by_bits = vb >= 32 ? 1 : (1ull << (32 - vb));
+    uint32_t slots = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(g->max_slots), max_by_bits));
+    const uint64_t swords = static_cast<uint64_t>(V) + 64;
+    // per slot: P and two frontier arrays (4 B/vertex) + two queue shares (4 B/vertex)
+    const uint64_t per_slot = 3 * 4 * swords + 2 * 4 * static_cast<uint64_t>(V) + QC_STRIDE + 8 * g->nwords;
+    int64_t budget = g->mem_budget;
+    if (budget <= 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(RPQ_EDEVICE, "hipMemGetInfo failed");
+        budget = static_cast<int64_t>(fr / 4);
+    }
+    const uint64_t item_cap = std::min<uint64_t>(1ull << 23, static_cast<uint64_t>(g->rows[OUT] + g->rows[IN]) * 4 + 4096);
+    const uint64_t fixed = item_cap * 20 + (2 * static_cast<uint64_t>(g->E) * slots) / TILE * 4;
+    if (static_cast<int64_t>(fixed + per_slot) > budget)
+        return fail(RPQ_ENOMEM, "served path: memory budget %lld bytes is below one slot (%llu bytes)",
+                    (long long)budget, (unsigned long long)(fixed + per_slot));
+    slots = static_cast<uint32_t>(std::min<uint64_t>(slots, (budget - fixed) / per_slot));
+    if (slots < 1) slots = 1;
+    ss->slots = slots;
+    MultiParams &p = ss->mp;
+    p.g = g->gv;
+    p.slots = slots;
+    p.vbits = vb;
+    p.V = V;
+    p.swords = swords;
+    p.queue_cap = static_cast<uint64_t>(slots) * V;
+    p.item_cap = item_cap;
+    p.tile_cap = (2 * static_cast<uint64_t>(g->E) * slots) / TILE + 2;
+    hipError_t e = hipSuccess;
+#define SA(ptr, bytes)                                                                            \
+    if ((e = salloc(ss, reinterpret_cast<void **>(&(ptr)), (bytes))) != hipSuccess)               \
+        return fail(RPQ_ENOMEM, "served path: hipMalloc %s: %s", #ptr, hipGetErrorString(e));
+    uint8_t *qc = nullptr;
+    SA(qc, QC_STRIDE * slots);
+    p.qconst = qc;
+    SA(p.P, 4 * swords * slots);
+    SA(p.M[0], 4 * swords * slots);
+    SA(p.M[1], 4 * swords * slots);
+    SA(p.q[0], 4 * p.queue_cap);
+    SA(p.q[1], 4 * p.queue_cap);
+    SA(p.ctl, multi_ctl_bytes(slots));
+    p.qlen = p.ctl;
+    p.status = p.ctl + 2;
+    p.next_count = p.ctl + 4;
+    p.pairs = reinterpret_cast<uint64_t *>(reinterpret_cast<uint8_t *>(p.ctl) + multi_pairs_offset(slots));
+    SA(p.sel, 64);
+    SA(p.it_ebase, 8 * item_cap);
+    SA(p.it_beg, 4 * item_cap);
+    SA(p.it_mask, 4 * item_cap);
+    SA(p.it_slot, 4 * item_cap);
+    SA(p.tile_first, 4 * p.tile_cap);
+    SA(p.out, 8 * g->nwords * slots);
+    SA(ss->d_admit, 8 * slots);
+    SA(ss->d_fin, 4 * slots);
+#undef SA
+    const size_t ctl_b = (multi_ctl_bytes(slots) + 63) & ~static_cast<size_t>(63);
+    ss->pinned_bytes = 8 * slots + 4 * slots + ctl_b + QC_STRIDE * slots + 8 * g->nwords * slots + 256;
+    if ((e = hipHostMalloc(reinterpret_cast<void **>(&ss->pinned), ss->pinned_bytes, hipHostMallocDefault)) != hipSuccess)
+        return fail(RPQ_ENOMEM, "served path: hipHostMalloc: %s", hipGetErrorString(e));
+    uint8_t *hp = ss->pinned;
+    ss->h_out = reinterpret_cast<uint64_t *>(hp);
+    hp += 8 * g->nwords * slots;
+    ss->h_qc = hp;
+    hp += QC_STRIDE * slots;
+    ss->h_ctl = hp;
+    hp += ctl_b;
+    ss->h_admit = reinterpret_cast<uint32_t *>(hp);
+    hp += 8 * slots;
+    ss->h_fin = reinterpret_cast<uint32_t *>(hp);
+    if ((e = hipStreamCreateWithFlags(&ss->stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "hipStreamCreate");
+    for (uint32_t *a : {p.P, p.M[0], p.M[1]})
+        if ((e = launch_fill(a, swords * slots, 0, ss->stream)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_fill(p.ctl, multi_ctl_bytes(slots) / 4, 0, ss->stream)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_fill(reinterpret_cast<uint32_t *>(p.sel), 4, 0, ss->stream)) != hipSuccess)
+        return hip_fail(e, "fill");
+    if ((e = hipStreamSynchronize(ss->stream)) != hipSuccess) return hip_fail(e, "sync");
+    ss->slot.assign(slots, SlotInfo{});
+    for (uint32_t s = slots; s-- > 0;) ss->free_slots.push_back(s);
+    return RPQ_OK;
+}
+
+#define ST(call)                                                  \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);         \
+    } while (0)
+
+// One scheduler iteration with the lock released. Returns a failure status
+// for a device error (the engine then stops and fails every ticket).
+static rpq_status engine_step(rpq_graph *g, ServeState *ss, std::vector<Request> &admit) {
+    MultiParams &p = ss->mp;
+    hipStream_t s = ss->stream;
+    const uint32_t parity = ss->level & 1;
+    // 1. admission: query constants per slot, then the start pairs
+    if (!admit.empty()) {
+        uint32_t k = 0;
+        for (Request &r : admit) {
+            const uint32_t sl = ss->free_slots.back();
+            ss->free_slots.pop_back();
+            ss->slot[sl] = SlotInfo{r.id, r.nsym, ss->level, r.submitted};
+            uint8_t *stage = ss->h_qc + static_cast<size_t>(sl) * QC_STRIDE;
+            memcpy(stage, r.qc.data(), r.qc.size());
+            ST(hipMemcpyAsync(const_cast<uint8_t *>(p.qconst) + static_cast<size_t>(sl) * QC_STRIDE, stage,
+                              r.qc.size(), hipMemcpyHostToDevice, s));
+            ss->h_admit[2 * k] = sl;
+            ss->h_admit[2 * k + 1] = static_cast<uint32_t>(r.source);
+            k++;
+        }
+        ST(hipMemcpyAsync(ss->d_admit, ss->h_admit, 8 * k, hipMemcpyHostToDevice, s));
+        ST(multi_admit(p, parity, k, ss->d_admit, s));
+        ss->cur_len += k;  // every admitted request has a start state (checked at submit)
+    }
+    if (ss->cur_len == 0) return RPQ_OK;
+    // 2. one level for every admitted query, in chunks bounded by the item buffer
+    int32_t maxsym = 1;
+    for (uint32_t sl = 0; sl < ss->slots; sl++)
+        if (ss->slot[sl].ticket) maxsym = std::max(maxsym, ss->slot[sl].nsym);
+    const uint32_t chunk = static_cast<uint32_t>(std::max<uint64_t>(1, p.item_cap / static_cast<uint64_t>(maxsym)));
+    for (uint32_t lo = 0; lo < ss->cur_len; lo += chunk) {
+        const uint32_t hi = std::min(ss->cur_len, lo + chunk);
+        ST(multi_select(p, parity, lo, hi, ss->prev_len, lo == 0, ss->chunk_id, ss->grid, s));
+        ST(multi_push(p, parity, ss->chunk_id, ss->grid, s));
+        ss->chunk_id++;
+    }
+    ST(hipMemcpyAsync(ss->h_ctl, p.ctl, multi_ctl_bytes(ss->slots), hipMemcpyDeviceToHost, s));
+    ST(hipStreamSynchronize(s));
+    const uint32_t *h_qlen = reinterpret_cast<const uint32_t *>(ss->h_ctl);
+    const uint32_t h_status = h_qlen[2];
+    const uint32_t *h_cnt = h_qlen + 4;
+    const uint64_t *h_pairs = reinterpret_cast<const uint64_t *>(ss->h_ctl + multi_pairs_offset(ss->slots));
+    if (h_status) return fail(RPQ_EDEVICE, "served path: internal invariant violated %u times", h_status);
+    const uint32_t next_len = h_qlen[parity ^ 1];
+    // 3. retire the queries whose next frontier is empty
+    uint32_t nfin = 0;
+    for (uint32_t sl = 0; sl < ss->slots; sl++)
+        if (ss->slot[sl].ticket && h_cnt[sl] == 0) ss->h_fin[nfin++] = sl;
+    if (nfin) {
+        std::vector<uint64_t> fin_pairs(nfin);
+        for (uint32_t f = 0; f < nfin; f++) fin_pairs[f] = h_pairs[ss->h_fin[f]];
+        ST(hipMemcpyAsync(ss->d_fin, ss->h_fin, 4 * nfin, hipMemcpyHostToDevice, s));
+        ST(multi_extract(p, nfin, ss->d_fin, static_cast<uint64_t>(g->nwords), s));
+        ST(hipMemcpyAsync(ss->h_out, p.out, 8 * static_cast<size_t>(g->nwords) * nfin, hipMemcpyDeviceToHost, s));
+        ST(hipStreamSynchronize(s));
+        const Clock::time_point now = Clock::now();
+        std::lock_guard<std::mutex> lk(ss->mu);
+        for (uint32_t f = 0; f < nfin; f++) {
+            const uint32_t sl = ss->h_fin[f];
+            auto it = ss->tickets.find(ss->slot[sl].ticket);
+            if (it != ss->tickets.end()) {
+                Ticket &t = it->second;
+                const uint64_t *src = ss->h_out + static_cast<size_t>(f) * g->nwords;
+                t.bitmap.assign(src, src + g->nwords);
+                t.stats = rpq_stats{};
+                t.stats.levels = static_cast<int32_t>(ss->level - ss->slot[sl].admit_level + 1);
+                t.stats.push_levels = t.stats.levels;
+                t.stats.visited_pairs = static_cast<int64_t>(fin_pairs[f]);
+                t.stats.device_ms =
+                    std::chrono::duration<double, std::milli>(now - ss->slot[sl].submitted).count();
+                t.stats.batch = static_cast<int32_t>(ss->slots - ss->free_slots.size());
+                t.status = RPQ_OK;
+                t.state = 2;
+            }
+            ss->slot[sl] = SlotInfo{};
+            ss->free_slots.push_back(sl);
+            ss->running--;
+        }
+        ss->cv_done.notify_all();
+    }
+    ss->prev_len = ss->cur_len;
+    ss->cur_len = next_len;
+    ss->level++;
+    return RPQ_OK;
+}
+
+static void fail_all(ServeState *ss, rpq_status st, const std::string &msg) {
+    std::lock_guard<std::mutex> lk(ss->mu);
+    ss->failed = true;
+    ss->fail_msg = msg;
+    for (auto &kv : ss->tickets)
+        if (kv.second.state != 2) {
+            kv.second.state = 2;
+            kv.second.status = st;
+            kv.second.error = msg;
+        }
+    ss->pending.clear();
+    ss->running = 0;
+    ss->cv_done.notify_all();
+}
+
+static void worker_main(rpq_graph *g, ServeState *ss) {
+    if (hipSetDevice(g->device) != hipSuccess) {
+        fail_all(ss, RPQ_EDEVICE, "served path: hipSetDevice failed");
+        return;
+    }
+    rpq_status st = engine_init(g, ss);
+    if (st != RPQ_OK) {
+        fail_all(ss, st, rpq_last_error());
+        return;
+    }
+    std::vector<Request> admit;
+    while (true) {
+        admit.clear();
+        {
+            std::unique_lock<std::mutex> lk(ss->mu);
+            ss->cv_work.wait(lk, [&] { return ss->stop || !ss->pending.empty() || ss->cur_len > 0; });
+            if (ss->stop && ss->pending.empty() && ss->cur_len == 0) break;
+            while (!ss->pending.empty() && admit.size() < ss->free_slots.size()) {
+                admit.push_back(std::move(ss->pending.front()));
+                ss->pending.pop_front();
+                auto it = ss->tickets.find(admit.back().id);
+                if (it != ss->tickets.end()) it->second.state = 1;
+            }
+        }
+        st = engine_step(g, ss, admit);
+        if (st != RPQ_OK) {
+            fail_all(ss, st, rpq_last_error());
+            return;
+        }
+    }
+}
+
+static ServeState *serve_get(rpq_graph *g) {
+    // called with g->mu held
+    if (!g->serve) {
+        g->serve = new ServeState();
+        g->serve->worker = std::thread(worker_main, g, g->serve);
+    }
+    return g->serve;
+}
+
+void rpq::serve_shutdown(rpq_graph *g) {
+    ServeState *ss = g->serve;
+    if (!ss) return;
+    {
+        std::lock_guard<std::mutex> lk(ss->mu);
+        ss->stop = true;
+        ss->pending.clear();
+    }
+    ss->cv_work.notify_all();
+    if (ss->worker.joinable()) ss->worker.join();
+    if (ss->stream) (void)hipStreamDestroy(ss->stream);
+    if (ss->pinned) (void)hipHostFree(ss->pinned);
+    for (void *p : ss->allocs) (void)hipFree(p);
+    delete ss;
+    g->serve = nullptr;
+}
+
+bool rpq::serve_pending(rpq_graph *g) {
+    ServeState *ss = g->serve;
+    if (!ss) return false;
+    std::lock_guard<std::mutex> lk(ss->mu);
+    for (auto &kv : ss->tickets)
+        if (kv.second.state != 2) return true;
+    return false;
+}
+
+void rpq::batch_free(rpq_graph *) {}
+
 rpq_status rpq_submit(rpq_graph *g, const rpq_nfa *n, int32_t source, rpq_ticket *out) {
-    (void)g; (void)n; (void)source; (void)out;
-    return fail(RPQ_EINVAL, "rpq_submit: not built yet");
+    if (!g || !n || !out) return fail(RPQ_EINVAL, "rpq_submit: NULL argument");
+    if (source < 0 || source >= g->V) return fail(RPQ_EINVAL, "rpq_submit: source %d outside [0, %d)", source, g->V);
+    Request r;
+    r.source = source;
+    r.smask = n->smask;
+    const size_t sz = build_qconst(g, n, 1u, 0u, r.qc, &r.nsym);
+    if (r.nsym > MAX_SYMS || sz > QC_STRIDE)
+        return fail(RPQ_EINVAL, "rpq_submit: query uses %d symbols; the limit is %d", r.nsym, MAX_SYMS);
+    r.submitted = Clock::now();
+    std::lock_guard<std::recursive_mutex> glk(g->mu);
+    ServeState *ss = serve_get(g);
+    std::lock_guard<std::mutex> lk(ss->mu);
+    if (ss->failed) return fail(RPQ_EDEVICE, "served path failed earlier: %s", ss->fail_msg.c_str());
+    const rpq_ticket id = ss->next_ticket++;
+    r.id = id;
+    Ticket &t = ss->tickets[id];
+    if (r.smask == 0) {  // no start state: the answer is empty, nothing to run
+        t.state = 2;
+        t.bitmap.assign(static_cast<size_t>(g->nwords), 0);
+        t.stats.batch = 1;
+    } else {
+        ss->pending.push_back(std::move(r));
+        ss->running++;
+    }
+    *out = id;
+    ss->cv_work.notify_one();
+    return RPQ_OK;
 }
 
 rpq_status rpq_poll(rpq_graph *g, rpq_ticket t, uint64_t *out_bitmap, rpq_stats *stats, int64_t timeout_us) {
-    (void)g; (void)t; (void)out_bitmap; (void)stats; (void)timeout_us;
-    return fail(RPQ_EINVAL, "rpq_poll: not built yet");
+    if (!g || !out_bitmap) return fail(RPQ_EINVAL, "rpq_poll: NULL argument");
+    ServeState *ss = g->serve;
+    if (!ss) return fail(RPQ_ENOTFOUND, "rpq_poll: unknown ticket %llu", (unsigned long long)t);
+    std::unique_lock<std::mutex> lk(ss->mu);
+    auto it = ss->tickets.find(t);
+    if (it == ss->tickets.end()) return fail(RPQ_ENOTFOUND, "rpq_poll: unknown ticket %llu", (unsigned long long)t);
+    auto done = [&] { return it->second.state == 2; };
+    if (!done()) {
+        if (timeout_us == 0) return RPQ_PENDING;
+        if (timeout_us < 0) ss->cv_done.wait(lk, done);
+        else if (!ss->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done))
+            return fail(RPQ_ETIMEDOUT, "rpq_poll: ticket %llu not finished within %lld us", (unsigned long long)t,
+                        (long long)timeout_us);
+    }
+    Ticket &tk = it->second;
+    const rpq_status st = tk.status;
+    if (st == RPQ_OK) {
+        memcpy(out_bitmap, tk.bitmap.data(), 8 * tk.bitmap.size());
+        if (stats) {
+            int64_t *lc = stats->level_counts;
+            const int32_t cap = stats->level_cap;
+            *stats = tk.stats;
+            stats->level_counts = lc;
+            stats->level_cap = cap;
+        }
+    } else {
+        fail(st, "%s", tk.error.c_str());
+    }
+    ss->tickets.erase(it);
+    return st;
+}
+
+rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
+                            uint64_t *out_bitmaps, uint32_t flags, rpq_stats *stats) {
+    if (!g || !n || !sources || !out_bitmaps) return fail(RPQ_EINVAL, "rpq_multi_source: NULL argument");
+    if (n_sources < 1) return fail(RPQ_EINVAL, "rpq_multi_source: n_sources < 1");
+    for (int32_t i = 0; i < n_sources; i++)
+        if (sources[i] < 0 || sources[i] >= g->V)
+            return fail(RPQ_EINVAL, "rpq_multi_source: source %d outside [0, %d)", sources[i], g->V);
+    std::vector<rpq_ticket> tk(static_cast<size_t>(n_sources));
+    for (int32_t i = 0; i < n_sources; i++) {
+        rpq_status st = rpq_submit(g, n, sources[i], &tk[i]);
+        if (st != RPQ_OK) return st;
+    }
+    const auto t0 = Clock::now();
+    std::vector<uint64_t> host(static_cast<size_t>(g->nwords));
+    int32_t maxlev = 0;
+    int64_t pairs = 0;
+    for (int32_t i = 0; i < n_sources; i++) {
+        rpq_stats st1{};
+        uint64_t *dst = (flags & RPQ_OUT_DEVICE) ? host.data() : out_bitmaps + static_cast<size_t>(i) * g->nwords;
+        rpq_status st = rpq_poll(g, tk[i], dst, &st1, -1);
+        if (st != RPQ_OK) return st;
+        if (flags & RPQ_OUT_DEVICE) {
+            hipError_t e = hipMemcpy(out_bitmaps + static_cast<size_t>(i) * g->nwords, host.data(), 8 * g->nwords,
+                                     hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+        }
+        maxlev = std::max(maxlev, st1.levels);
+        pairs += st1.visited_pairs;
+    }
+    if (stats) {
+        int64_t *lc = stats->level_counts;
+        const int32_t cap = stats->level_cap;
+        *stats = rpq_stats{};
+        stats->level_counts = lc;
+        stats->level_cap = cap;
+        stats->levels = maxlev;
+        stats->push_levels = maxlev;
+        stats->visited_pairs = pairs;
+        stats->batch = n_sources;
+        stats->device_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+    }
+    return RPQ_OK;
 }

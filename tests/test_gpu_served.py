@@ -1,0 +1,135 @@
+"""GPU parity of the served path (rpq_submit / rpq_poll) and rpq_multi_source:
+every result equals the oracle's bit for bit, and the same query gives the same
+bitmap alone and inside a mix of concurrently admitted queries."""
+import threading
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle
+from workloads import configs as C
+from workloads import graphs as G
+from workloads import regex as R
+
+
+@pytest.fixture(scope="module")
+def rpq():
+    from paper_2412_10287_amd import rpq as mod
+    return mod
+
+
+def _submit_all(gg, nfas, sources):
+    return [gg.submit(n, int(s)) for n, s in zip(nfas, sources)]
+
+
+def _poll_all(gg, tickets):
+    out = []
+    for t in tickets:
+        r = gg.poll(t, timeout_us=-1)
+        assert r is not None
+        out.append(r)
+    return out
+
+
+def test_served_er_vs_oracle_and_alone(rpq):
+    w = C.er_workload()
+    og = oracle.Graph(w.graph)
+    gg = rpq.Graph(w.graph)
+    nh = [rpq.NFA(n) for n in w.nfas]
+    want = [og.ssr(n, int(s)) for n, s in zip(w.nfas, w.sources)]
+    mixed = _poll_all(gg, _submit_all(gg, nh, w.sources))
+    for (bm, st), wr, text in zip(mixed, want, w.queries):
+        assert np.array_equal(bm, wr.bitmap), text
+        assert st.levels == wr.levels, text
+        assert st.visited_pairs == int(wr.level_counts.sum()), text
+    # alone = in the mix
+    for h, s, (bm_mix, _) in zip(nh, w.sources, mixed):
+        bm, _ = _poll_all(gg, [gg.submit(h, int(s))])[0]
+        assert np.array_equal(bm, bm_mix)
+
+
+def test_served_rmat_templates_small_slots(rpq):
+    w = C.rmat_workload(scale=14, edge_factor=16, num_labels=16, n_per_template=8)
+    og = oracle.Graph(w.graph)
+    gg = rpq.Graph(w.graph)
+    gg.set_option("max_slots", 3)  # most requests wait for a free slot
+    nh = [rpq.NFA(n) for n in w.nfas]
+    res = _poll_all(gg, _submit_all(gg, nh, w.sources))
+    for (bm, st), n, s, text in zip(res, w.nfas, w.sources, w.queries):
+        r = og.ssr(n, int(s))
+        assert np.array_equal(bm, r.bitmap), text
+        assert st.levels == r.levels, text
+
+
+def test_served_mixed_state_counts(rpq):
+    # NFAs from 1 to 32 states in one mix (state words of 1, 2 and 4 bytes on
+    # the plain path; 4-byte words in the served engine)
+    rng = np.random.default_rng(12)
+    g = G.rmat(12, 8, 6, 1.1, 5)
+    og = oracle.Graph(g)
+    gg = rpq.Graph(g)
+    nfas, srcs = [], []
+    for leaves in (1, 2, 3, 5, 8, 12, 15, 20, 26, 31):
+        ast = R.random_ast(rng, leaves, lambda r: r.integers(0, 6), 0.3)
+        nfas.append(R.glushkov(ast, 6))
+        srcs.append(int(rng.integers(0, g.num_vertices)))
+    nh = [rpq.NFA(n) for n in nfas]
+    res = _poll_all(gg, _submit_all(gg, nh, srcs))
+    for (bm, st), n, s in zip(res, nfas, srcs):
+        assert np.array_equal(bm, og.ssr(n, s).bitmap)
+        plain, _ = gg.single_source(rpq.NFA(n), s)
+        assert np.array_equal(bm, plain)
+
+
+def test_multi_source_equals_single(rpq):
+    g = G.rmat(13, 8, 4, 1.1, 8)
+    gg = rpq.Graph(g)
+    og = oracle.Graph(g)
+    nfa = R.compile_regex("(0|^1)* 2", 4)
+    nh = rpq.NFA(nfa)
+    srcs = np.random.default_rng(3).integers(0, g.num_vertices, size=40)
+    srcs[5] = srcs[6]  # repeated source
+    bms, st = gg.multi_source(nh, srcs)
+    assert st.batch == 40
+    for i, s in enumerate(srcs):
+        assert np.array_equal(bms[i], og.ssr(nfa, int(s)).bitmap)
+
+
+def test_concurrent_submitters(rpq):
+    w = C.er_workload(n=3000, m=12000, num_labels=4, n_queries=24)
+    og = oracle.Graph(w.graph)
+    gg = rpq.Graph(w.graph)
+    nh = [rpq.NFA(n) for n in w.nfas]
+    results = {}
+
+    def worker(k):
+        for i in range(k, len(nh), 3):
+            t = gg.submit(nh[i], int(w.sources[i]))
+            results[i] = gg.poll(t, timeout_us=-1)
+
+    ths = [threading.Thread(target=worker, args=(k,)) for k in range(3)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    for i, (n, s) in enumerate(zip(w.nfas, w.sources)):
+        assert np.array_equal(results[i][0], og.ssr(n, int(s)).bitmap)
+
+
+def test_poll_semantics(rpq):
+    g = G.erdos_renyi(500, 2000, 2, 1)
+    gg = rpq.Graph(g)
+    nh = rpq.NFA(R.compile_regex("(0|1)*", 2))
+    t = gg.submit(nh, 0)
+    r = gg.poll(t, timeout_us=-1)
+    assert r is not None
+    with pytest.raises(rpq.RPQError) as e:
+        gg.poll(t, timeout_us=0)  # retired
+    assert e.value.status == rpq.RPQ_ENOTFOUND
+    empty = rpq.NFA(R.nfa_from_triples(2, 2, [(0, 0, 1)], [], [1]))
+    bm, _ = gg.poll(gg.submit(empty, 3), timeout_us=-1)
+    assert not bm.any()
+    with pytest.raises(rpq.RPQError):
+        gg.submit(nh, 500)
