@@ -37,97 +37,6 @@ namespace rpq {
 // range); the access is skipped and the host reports the query as failed.
 __device__ __forceinline__ void flag_violation(const Params &p) { atomicAdd(&p.st.status[3], 1u); }
 
-// ------------------------------------------------------------ grid barrier
-// Two-level barrier for the persistent kernel (every workgroup is resident:
-// cooperative launch). Each XCD has its own L2. Workgroups first meet on a
-// per-XCD counter; their stores are already in that XCD's L2 (every wave
-// waits for its memory operations first). The last one on an XCD writes the
-// L2 back once (device-scope release) and meets the other XCDs' leaders on a
-// global counter; then every workgroup drops stale cached lines (device-scope
-// acquire). Counters only grow within a launch (barrier k completes at
-// k * members), and the host zeroes them before each launch. A wait longer
-// than BARRIER_TIMEOUT ticks of the 100 MHz wall clock sets `abort`, and
-// every workgroup leaves the kernel at its next barrier.
-constexpr uint64_t BARRIER_TIMEOUT = 5ull * 100000000ull;  // 5 s
-
-struct BarCtx {
-    uint32_t xcd;    // this workgroup's XCD
-    uint32_t per;    // workgroups on that XCD
-    uint32_t nxcd;   // XCDs with workgroups
-    uint32_t k;      // barriers passed
-};
-
-__device__ __forceinline__ uint32_t xcc_id() {
-    // hardware register XCC_ID (id 20), bits [3:0]
-    return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u;
-}
-
-__device__ __forceinline__ bool spin_until_at_least(const GridBarrier *b, const uint32_t *ctr, uint32_t target) {
-    const uint64_t t0 = wall_clock64();
-    while (aload(ctr) < target) {
-        if (aload(&b->abort)) return false;
-        if (wall_clock64() - t0 > BARRIER_TIMEOUT) {
-            __hip_atomic_store(const_cast<uint32_t *>(&b->abort), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-    return true;
-}
-
-// Registration at kernel start: every workgroup counts itself on its XCD.
-__device__ bool barrier_register(GridBarrier *b, BarCtx &c) {
-    __shared__ uint32_t s_v[3];
-    if (threadIdx.x == 0) {
-        const uint32_t x = xcc_id();
-        __hip_atomic_fetch_add(&b->reg[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&b->nreg, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t ok = spin_until_at_least(b, &b->nreg, gridDim.x);
-        uint32_t nx = 0;
-        for (int i = 0; i < MAX_XCD; i++) nx += aload(&b->reg[i]) ? 1u : 0u;
-        s_v[0] = x;
-        s_v[1] = aload(&b->reg[x]);
-        s_v[2] = ok ? nx : 0u;
-    }
-    __syncthreads();
-    c.xcd = s_v[0];
-    c.per = s_v[1];
-    c.nxcd = s_v[2];
-    c.k = 0;
-    return c.nxcd != 0;
-}
-
-__device__ bool grid_barrier(GridBarrier *b, BarCtx &c) {
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads and stores are complete
-    __syncthreads();
-    c.k++;
-    __shared__ uint32_t s_ok;
-    if (threadIdx.x == 0) {
-        uint32_t ok = 1;
-        const uint32_t a =
-            __hip_atomic_fetch_add(&b->lcount[c.xcd][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (a == c.k * c.per - 1) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            const uint32_t ga = __hip_atomic_fetch_add(&b->gcount, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (ga == c.k * c.nxcd - 1) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-                __hip_atomic_store(&b->ggen, c.k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                ok = spin_until_at_least(b, &b->ggen, c.k);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-            __hip_atomic_store(&b->lgen[c.xcd][0], c.k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            ok = spin_until_at_least(b, &b->lgen[c.xcd][0], c.k);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-        if (aload(&b->abort)) ok = 0;
-        s_ok = ok;
-    }
-    __syncthreads();
-    return s_ok != 0;
-}
-
 // ---------------------------------------------------------------- phases
 template <int W>
 __device__ void init_phase(const Params &p) {

@@ -358,7 +358,6 @@ bool rpq::serve_pending(rpq_graph *g) {
     return false;
 }
 
-void rpq::batch_free(rpq_graph *) {}
 
 rpq_status rpq_submit(rpq_graph *g, const rpq_nfa *n, int32_t source, rpq_ticket *out) {
     if (!g || !n || !out) return fail(RPQ_EINVAL, "rpq_submit: NULL argument");
@@ -421,48 +420,4 @@ rpq_status rpq_poll(rpq_graph *g, rpq_ticket t, uint64_t *out_bitmap, rpq_stats 
     }
     ss->tickets.erase(it);
     return st;
-}
-
-rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
-                            uint64_t *out_bitmaps, uint32_t flags, rpq_stats *stats) {
-    if (!g || !n || !sources || !out_bitmaps) return fail(RPQ_EINVAL, "rpq_multi_source: NULL argument");
-    if (n_sources < 1) return fail(RPQ_EINVAL, "rpq_multi_source: n_sources < 1");
-    for (int32_t i = 0; i < n_sources; i++)
-        if (sources[i] < 0 || sources[i] >= g->V)
-            return fail(RPQ_EINVAL, "rpq_multi_source: source %d outside [0, %d)", sources[i], g->V);
-    std::vector<rpq_ticket> tk(static_cast<size_t>(n_sources));
-    for (int32_t i = 0; i < n_sources; i++) {
-        rpq_status st = rpq_submit(g, n, sources[i], &tk[i]);
-        if (st != RPQ_OK) return st;
-    }
-    const auto t0 = Clock::now();
-    std::vector<uint64_t> host(static_cast<size_t>(g->nwords));
-    int32_t maxlev = 0;
-    int64_t pairs = 0;
-    for (int32_t i = 0; i < n_sources; i++) {
-        rpq_stats st1{};
-        uint64_t *dst = (flags & RPQ_OUT_DEVICE) ? host.data() : out_bitmaps + static_cast<size_t>(i) * g->nwords;
-        rpq_status st = rpq_poll(g, tk[i], dst, &st1, -1);
-        if (st != RPQ_OK) return st;
-        if (flags & RPQ_OUT_DEVICE) {
-            hipError_t e = hipMemcpy(out_bitmaps + static_cast<size_t>(i) * g->nwords, host.data(), 8 * g->nwords,
-                                     hipMemcpyHostToDevice);
-            if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
-        }
-        maxlev = std::max(maxlev, st1.levels);
-        pairs += st1.visited_pairs;
-    }
-    if (stats) {
-        int64_t *lc = stats->level_counts;
-        const int32_t cap = stats->level_cap;
-        *stats = rpq_stats{};
-        stats->level_counts = lc;
-        stats->level_cap = cap;
-        stats->levels = maxlev;
-        stats->push_levels = maxlev;
-        stats->visited_pairs = pairs;
-        stats->batch = n_sources;
-        stats->device_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
-    }
-    return RPQ_OK;
 }

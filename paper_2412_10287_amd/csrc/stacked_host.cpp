@@ -1,0 +1,189 @@
+// rpq_multi_source: sources under one NFA evaluated together by the stacked
+// kernel (stacked.hip), in batches of at most max_batch sources.
+#include <string.h>
+
+#include <algorithm>
+
+#include "api_internal.h"
+#include "stacked.h"
+
+using namespace rpq;
+
+namespace rpq {
+
+struct BatchState {
+    std::vector<void *> allocs;
+    uint64_t state_words = 0;  // capacity of P / M arrays (uint64 words)
+    StackParams p{};
+    uint8_t *qconst = nullptr;
+    size_t qconst_cap = 0;
+    uint64_t *out = nullptr;  // internal output (host-memory results)
+    int64_t out_words = 0;
+    int32_t *sources = nullptr;  // device copy of one batch's sources (MAX_BATCH entries)
+    uint8_t *pinned = nullptr;
+    int grid[17] = {0};
+};
+
+}  // namespace rpq
+
+#define BT(call)                                                  \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);         \
+    } while (0)
+
+static void free_batch(BatchState *b) {
+    if (!b) return;
+    for (void *x : b->allocs) (void)hipFree(x);
+    if (b->pinned) (void)hipHostFree(b->pinned);
+    delete b;
+}
+
+void rpq::batch_free(rpq_graph *g) {
+    free_batch(g->batch);
+    g->batch = nullptr;
+}
+
+static rpq_status balloc(BatchState *b, void **p, size_t bytes, const char *what) {
+    hipError_t e = hipMalloc(p, bytes ? bytes : 64);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(RPQ_ENOMEM, "rpq_multi_source: hipMalloc(%s, %zu bytes): %s", what, bytes, hipGetErrorString(e));
+    }
+    b->allocs.push_back(*p);
+    return RPQ_OK;
+}
+
+// (Re)allocates the stacked state for rows of Q*G words, zeroed.
+static rpq_status batch_prepare(rpq_graph *g, int32_t Q, int G, int32_t B, hipStream_t s) {
+    const uint64_t need = static_cast<uint64_t>(g->V) * Q * G + 64;
+    BatchState *b = g->batch;
+    if (b && b->state_words >= need && b->out_words >= static_cast<int64_t>(B) * g->nwords) return RPQ_OK;
+    batch_free(g);
+    b = g->batch = new (std::nothrow) BatchState;
+    if (!b) return fail(RPQ_ENOMEM, "rpq_multi_source: out of host memory");
+    rpq_status st;
+    StackParams &p = b->p;
+    const uint64_t words = need;
+    b->state_words = words;
+    if ((st = balloc(b, reinterpret_cast<void **>(&p.P), 8 * words, "P")) != RPQ_OK) return st;
+    if ((st = balloc(b, reinterpret_cast<void **>(&p.M[0]), 8 * words, "M")) != RPQ_OK) return st;
+    if ((st = balloc(b, reinterpret_cast<void **>(&p.M[1]), 8 * words, "M")) != RPQ_OK) return st;
+    for (int k = 0; k < 2; k++) {
+        if ((st = balloc(b, reinterpret_cast<void **>(&p.sup[k]), 4 * static_cast<size_t>(g->V) + 64, "sup")) != RPQ_OK)
+            return st;
+        if ((st = balloc(b, reinterpret_cast<void **>(&p.q[k]), 4 * static_cast<size_t>(g->V) + 64, "queue")) != RPQ_OK)
+            return st;
+    }
+    p.item_cap = static_cast<uint64_t>(g->rows[OUT] + g->rows[IN]) + 1;
+    for (uint32_t **a : {&p.it_ebase, &p.it_beg, &p.it_v, &p.it_u})
+        if ((st = balloc(b, reinterpret_cast<void **>(a), 4 * p.item_cap, "items")) != RPQ_OK) return st;
+    p.tile_cap = (2 * static_cast<uint64_t>(g->E)) / (TILE / 16) + 2;
+    if ((st = balloc(b, reinterpret_cast<void **>(&p.tile_first), 4 * p.tile_cap, "tiles")) != RPQ_OK) return st;
+    if ((st = balloc(b, reinterpret_cast<void **>(&p.rec), sizeof(LevelRec) * REC_RING, "rec")) != RPQ_OK) return st;
+    if ((st = balloc(b, reinterpret_cast<void **>(&p.bar), sizeof(GridBarrier), "barrier")) != RPQ_OK) return st;
+    if ((st = balloc(b, reinterpret_cast<void **>(&p.status), 64, "status")) != RPQ_OK) return st;
+    if ((st = balloc(b, reinterpret_cast<void **>(&p.lvl_pairs), 8 * LVL_COUNT_CAP, "lvl")) != RPQ_OK) return st;
+    if ((st = balloc(b, reinterpret_cast<void **>(&b->sources), 4 * static_cast<size_t>(MAX_BATCH), "sources")) !=
+        RPQ_OK)
+        return st;
+    b->qconst_cap = g->qconst_cap;
+    if ((st = balloc(b, reinterpret_cast<void **>(&b->qconst), b->qconst_cap, "qconst")) != RPQ_OK) return st;
+    b->out_words = static_cast<int64_t>(std::max<int32_t>(B, g->max_batch)) * g->nwords;
+    if ((st = balloc(b, reinterpret_cast<void **>(&b->out), 8 * static_cast<size_t>(b->out_words), "out")) != RPQ_OK)
+        return st;
+    BT(hipHostMalloc(reinterpret_cast<void **>(&b->pinned), b->qconst_cap + 4096 + 8 * LVL_COUNT_CAP,
+                     hipHostMallocDefault));
+    for (uint64_t *a : {p.P, p.M[0], p.M[1]}) BT(launch_fill(reinterpret_cast<uint32_t *>(a), 2 * words, 0, s));
+    for (int k = 0; k < 2; k++) BT(launch_fill(p.sup[k], static_cast<uint64_t>(g->V) + 16, 0, s));
+    for (int G2 : {1, 2, 4, 8, 16}) b->grid[G2] = stacked_grid(G2);
+    BT(hipStreamSynchronize(s));
+    return RPQ_OK;
+}
+
+rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
+                            uint64_t *out_bitmaps, uint32_t flags, rpq_stats *stats) {
+    if (!g || !n || !sources || !out_bitmaps) return fail(RPQ_EINVAL, "rpq_multi_source: NULL argument");
+    if (n_sources < 1) return fail(RPQ_EINVAL, "rpq_multi_source: n_sources < 1");
+    for (int32_t i = 0; i < n_sources; i++)
+        if (sources[i] < 0 || sources[i] >= g->V)
+            return fail(RPQ_EINVAL, "rpq_multi_source: source %d outside [0, %d)", sources[i], g->V);
+    std::lock_guard<std::recursive_mutex> lk(g->mu);
+    BT(hipSetDevice(g->device));
+    hipStream_t s = g->user_stream ? g->user_stream : g->stream;
+    const int32_t maxb = std::min<int32_t>(g->max_batch, 1024);
+    std::vector<uint8_t> qbuf;
+    int32_t nsym = 0;
+    const size_t qsz = build_qconst(g, n, 1u, 0u, qbuf, &nsym);
+    if (nsym > MAX_SYMS || qsz > g->qconst_cap)
+        return fail(RPQ_EINVAL, "rpq_multi_source: query uses %d symbols; the limit is %d", nsym, MAX_SYMS);
+    int32_t levels = 0;
+    int64_t pairs = 0;
+    float total_ms = 0.f;
+    for (int32_t b0 = 0; b0 < n_sources; b0 += maxb) {
+        const int32_t B = std::min(maxb, n_sources - b0);
+        int G = 1;
+        while (G * 64 < B) G *= 2;
+        rpq_status st = batch_prepare(g, n->Q, G, B, s);
+        if (st != RPQ_OK) return st;
+        BatchState *bs = g->batch;
+        StackParams p = bs->p;
+        memcpy(bs->pinned, qbuf.data(), qsz);
+        int32_t *hsrc = reinterpret_cast<int32_t *>(bs->pinned + bs->qconst_cap);
+        memcpy(hsrc, sources + b0, 4 * static_cast<size_t>(B));
+        BT(hipMemcpyAsync(bs->qconst, bs->pinned, qsz, hipMemcpyHostToDevice, s));
+        BT(hipMemcpyAsync(bs->sources, hsrc, 4 * static_cast<size_t>(B), hipMemcpyHostToDevice, s));
+        p.g = g->gv;
+        p.qv = query_view(bs->qconst, nsym);
+        p.sources = bs->sources;
+        p.B = B;
+        p.Q = n->Q;
+        p.V = g->V;
+        p.nwords = g->nwords;
+        p.out = (flags & RPQ_OUT_DEVICE) ? out_bitmaps + static_cast<size_t>(b0) * g->nwords : bs->out;
+        const int grid = g->grid_override ? std::min(g->grid_override, bs->grid[G]) : bs->grid[G];
+        if (grid <= 0) return fail(RPQ_EDEVICE, "rpq_multi_source: no co-resident grid for the stacked kernel");
+        BT(launch_fill(reinterpret_cast<uint32_t *>(p.bar), sizeof(GridBarrier) / 4, 0, s));
+        BT(hipEventRecord(g->ev[2], s));
+        BT(launch_stacked(G, p, grid, s));
+        BT(hipEventRecord(g->ev[3], s));
+        uint32_t *hst = reinterpret_cast<uint32_t *>(bs->pinned + bs->qconst_cap + 4 * 1024);
+        BT(hipMemcpyAsync(hst, p.status, 16, hipMemcpyDeviceToHost, s));
+        BT(hipMemcpyAsync(hst + 4, &p.bar->abort, 4, hipMemcpyDeviceToHost, s));
+        if (!(flags & RPQ_OUT_DEVICE))
+            BT(hipMemcpyAsync(out_bitmaps + static_cast<size_t>(b0) * g->nwords, bs->out,
+                              8 * static_cast<size_t>(B) * g->nwords, hipMemcpyDeviceToHost, s));
+        BT(hipStreamSynchronize(s));
+        if (hst[4]) {
+            batch_free(g);
+            return fail(RPQ_EDEVICE, "rpq_multi_source: traversal aborted (grid barrier timed out)");
+        }
+        if (hst[3]) {
+            batch_free(g);
+            return fail(RPQ_EDEVICE, "rpq_multi_source: internal invariant violated %u times", hst[3]);
+        }
+        float ms = 0.f;
+        BT(hipEventElapsedTime(&ms, g->ev[2], g->ev[3]));
+        total_ms += ms;
+        levels = std::max<int32_t>(levels, static_cast<int32_t>(hst[0]));
+        const uint32_t nl = std::min<uint32_t>(hst[0], LVL_COUNT_CAP);
+        std::vector<int64_t> lp(nl);
+        if (nl) BT(hipMemcpy(lp.data(), p.lvl_pairs, 8 * nl, hipMemcpyDeviceToHost));
+        for (int64_t x : lp) pairs += x;
+    }
+    if (stats) {
+        int64_t *lc = stats->level_counts;
+        const int32_t cap = stats->level_cap;
+        *stats = rpq_stats{};
+        stats->level_counts = lc;
+        stats->level_cap = cap;
+        stats->levels = levels;
+        stats->push_levels = levels;
+        stats->visited_pairs = pairs;
+        stats->batch = std::min(n_sources, maxb);
+        stats->device_ms = total_ms;
+        stats->expand_ms = total_ms;
+        stats->expand_launches = (n_sources + maxb - 1) / maxb;
+    }
+    return RPQ_OK;
+}

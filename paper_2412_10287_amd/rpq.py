@@ -89,6 +89,51 @@ def load_library(path: str = LIB_PATH):
 
 lib = load_library()
 
+# The HIP runtime librpq itself links (the system ROCm one). Device buffers for
+# RPQ_OUT_DEVICE results come from it, so no second runtime enters the process.
+_hip = ctypes.CDLL("libamdhip64.so.7", mode=ctypes.RTLD_GLOBAL)
+_hip.hipMalloc.restype = ctypes.c_int
+_hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+_hip.hipFree.restype = ctypes.c_int
+_hip.hipFree.argtypes = [ctypes.c_void_p]
+_hip.hipMemcpy.restype = ctypes.c_int
+_hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+_hip.hipMemset.restype = ctypes.c_int
+_hip.hipMemset.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t]
+_hip.hipDeviceSynchronize.restype = ctypes.c_int
+_HIP_D2H = 2
+
+
+class DeviceBuffer:
+    """A zeroed device allocation of ``nbytes`` (plumbing for RPQ_OUT_DEVICE)."""
+
+    def __init__(self, nbytes: int):
+        self.nbytes = int(nbytes)
+        p = ctypes.c_void_p()
+        if _hip.hipMalloc(ctypes.byref(p), max(self.nbytes, 1)) != 0:
+            raise MemoryError("hipMalloc of %d bytes failed" % self.nbytes)
+        self.ptr = p.value
+        if _hip.hipMemset(ctypes.c_void_p(self.ptr), 0, self.nbytes) != 0:
+            raise RuntimeError("hipMemset failed")
+
+    def to_host(self, dtype=np.uint64) -> np.ndarray:
+        out = np.empty(self.nbytes // np.dtype(dtype).itemsize, dtype=dtype)
+        if _hip.hipMemcpy(ctypes.c_void_p(out.ctypes.data), ctypes.c_void_p(self.ptr), self.nbytes, _HIP_D2H) != 0:
+            raise RuntimeError("hipMemcpy failed")
+        return out
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            _hip.hipFree(ctypes.c_void_p(self.ptr))
+            self.ptr = None
+
+    __del__ = close
+
+
+def device_synchronize():
+    if _hip.hipDeviceSynchronize() != 0:
+        raise RuntimeError("hipDeviceSynchronize failed")
+
 
 def last_error() -> str:
     return lib.rpq_last_error().decode(errors="replace")
