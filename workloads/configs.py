@@ -90,7 +90,7 @@ def rmat_workload(scale: int = 20, edge_factor: int = 16, num_labels: int = 64,
 
 def kg_graph(n: int = 20_000_000, m: int = 200_000_000, num_labels: int = 1000,
              cfg: int = 3) -> G.LabeledGraph:
-    return G.chung_lu(n, m, 2.1, num_labels, 1.2, seed(cfg, 1))
+    return G.chung_lu_fast(n, m, 2.1, num_labels, 1.2, seed(cfg, 1))
 
 
 def kg_query(rng, g: G.LabeledGraph, min_leaves: int = 3, max_leaves: int = 11,

@@ -152,6 +152,40 @@ def chung_lu(n: int, m: int, gamma: float, num_labels: int, zipf_s: float, seed:
                         name="chunglu-%d-%d-L%d" % (n, m, num_labels))
 
 
+def chung_lu_fast(n: int, m: int, gamma: float, num_labels: int, zipf_s: float, seed: int,
+                  i0: float = 10.0) -> LabeledGraph:
+    """Directed Chung-Lu graph for large sizes, without sorting.
+
+    Per-label edge counts are drawn from the Zipf(s) multinomial, so edges are
+    produced already grouped by label. Endpoints are drawn by inverting the
+    CDF of the continuous weight density (x + i0)^(-1/(gamma-1)) on [0, n)
+    (the continuous counterpart of ``chung_lu``'s discrete weights), then
+    relabelled by independent seeded permutations for sources and targets.
+    Duplicate (src, dst, label) entries are kept: consumers merge them.
+    """
+    rng = np.random.default_rng(seed)
+    w = 1.0 / np.arange(1, num_labels + 1, dtype=np.float64) ** zipf_s
+    counts = rng.multinomial(m, w / w.sum()).astype(np.int64)
+    ptr = np.zeros(num_labels + 1, dtype=np.int64)
+    np.cumsum(counts, out=ptr[1:])
+    beta = 1.0 / (gamma - 1.0)
+    a = 1.0 - beta
+    x0, x1 = i0 ** a, (n + i0) ** a
+    perm_s = rng.permutation(n).astype(np.int32)
+    perm_d = rng.permutation(n).astype(np.int32)
+    src = np.empty(m, dtype=np.int32)
+    dst = np.empty(m, dtype=np.int32)
+    chunk = 1 << 24
+    for lo in range(0, m, chunk):
+        hi = min(m, lo + chunk)
+        for out, perm in ((src, perm_s), (dst, perm_d)):
+            u = rng.random(hi - lo)
+            x = (x0 + u * (x1 - x0)) ** (1.0 / a) - i0
+            idx = np.minimum(x.astype(np.int64), n - 1)
+            out[lo:hi] = perm[idx]
+    return LabeledGraph(n, num_labels, ptr, src, dst, name="chunglu-%d-%d-L%d" % (n, m, num_labels))
+
+
 GRID_E, GRID_N, GRID_W, GRID_S = 0, 1, 2, 3
 
 
