@@ -49,6 +49,24 @@ def build_workload(name: str, scale: int):
     raise SystemExit("unknown workload %r" % name)
 
 
+def committed_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was measured."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_persistent_rmat20_traffic.md")
+    src = os.path.join(ROOT, "paper_2412_10287_amd", "csrc", "kernels.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    m = re.search(r"kernel=(\S+) traffic_bytes_per_launch=(\d+) kernels_hip_sha256_16=(\w+)", text)
+    if not m or m.group(1) != kernel or m.group(3) != sha:
+        return None
+    return int(m.group(2))
+
+
 def percentile(xs, p):
     return float(np.percentile(np.asarray(xs), p)) if len(xs) else 0.0
 
@@ -179,7 +197,18 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--host-loop", action="store_true", help="drive levels from the host")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (for traffic-counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        from paper_2412_10287_amd import rpq
+        n = args.calibrate_copy << 20
+        a, b = rpq.DeviceBuffer(n), rpq.DeviceBuffer(n)
+        for _ in range(3):
+            b.copy_from(a)
+        rpq.device_synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n, "copies": 3}))
+        return
     if args.gpus != 1:
         print("bench.py: this engine runs on one GPU; --gpus %d is not supported (use --gpus 1)"
               % args.gpus, file=sys.stderr)
@@ -287,7 +316,8 @@ def main():
         "latency_ms_p50": round(percentile(lat, 50) * 1e3, 4),
         "latency_ms_p99": round(percentile(lat, 99) * 1e3, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": committed_traffic("rpq::k_persistent<1>") if not args.host_loop else None,
                      "kernel": "rpq::k_persistent<1>", "launches": n_launch,
                      "mean_launch_us": round(kern_ms.sum() * 1e3 / max(n_launch, 1), 3),
                      "alg_bytes_per_launch": round(bytes_total / max(n_launch, 1), 1)},

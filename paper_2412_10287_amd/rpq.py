@@ -102,6 +102,7 @@ _hip.hipMemset.restype = ctypes.c_int
 _hip.hipMemset.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t]
 _hip.hipDeviceSynchronize.restype = ctypes.c_int
 _HIP_D2H = 2
+_HIP_D2D = 3
 
 
 class DeviceBuffer:
@@ -121,6 +122,12 @@ class DeviceBuffer:
         if _hip.hipMemcpy(ctypes.c_void_p(out.ctypes.data), ctypes.c_void_p(self.ptr), self.nbytes, _HIP_D2H) != 0:
             raise RuntimeError("hipMemcpy failed")
         return out
+
+    def copy_from(self, other: "DeviceBuffer"):
+        """Device-to-device copy of min(sizes) bytes (used to calibrate traffic counters)."""
+        n = min(self.nbytes, other.nbytes)
+        if _hip.hipMemcpy(ctypes.c_void_p(self.ptr), ctypes.c_void_p(other.ptr), n, _HIP_D2D) != 0:
+            raise RuntimeError("hipMemcpy failed")
 
     def close(self):
         if getattr(self, "ptr", None):
