@@ -131,7 +131,7 @@ def bench_batched(args, w):
 
     def stacked_step():
         _, st = g.multi_source(nh, srcs, out_device_ptr=out.ptr)
-        kern.append(st.expand_ms)
+        kern.append((st.expand_ms, st.expand_launches, st.alg_bytes))
 
     res = {}
     for name, fn in (("plain", plain_step), ("stacked", stacked_step)):
@@ -151,7 +151,11 @@ def bench_batched(args, w):
         if lat:
             res[name]["latency_ms_p50"] = percentile(lat, 50) * 1e3
             res[name]["latency_ms_p99"] = percentile(lat, 99) * 1e3
-    stacked_ms = float(np.mean(kern)) if kern else 0.0
+    k_ms = sum(k[0] for k in kern)
+    k_launch = sum(k[1] for k in kern)
+    k_bytes = sum(k[2] for k in kern)
+    stacked_ms = k_ms / max(k_launch, 1)
+    achieved = k_bytes / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
     same = bool(np.array_equal(out.to_host().reshape(B, words), plain_ref))
     slat = []
     t0 = time.perf_counter()
@@ -181,6 +185,11 @@ def bench_batched(args, w):
         "stacked_same_as_plain": same,
         "stacked_kernel_ms": round(stacked_ms, 3),
         "levels_max": int(lv.max()),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": "rpq::k_stacked<%d>" % max(1, 1 << (max(0, (B - 1)) // 64).bit_length()),
+                     "launches": k_launch, "mean_launch_us": round(stacked_ms * 1e3, 1),
+                     "alg_bytes_per_launch": round(k_bytes / max(k_launch, 1), 1)},
     }
     if not args.no_cpu:
         out_json["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)

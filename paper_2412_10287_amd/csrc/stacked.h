@@ -20,6 +20,7 @@ struct StackParams {
     LevelRec *rec;
     GridBarrier *bar;
     uint32_t *status;        // [0] levels, [3] invariant violations
+    uint64_t *cnt;           // [0] items, [1] scanned edges, [2] word updates, [3] active vertices
     int64_t *lvl_pairs;      // |M_n| summed over sources, n < LVL_COUNT_CAP
     uint64_t *out;           // B bitmaps of nwords words
     const int32_t *sources;  // B vertex ids

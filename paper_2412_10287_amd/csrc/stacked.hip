@@ -137,6 +137,11 @@ __device__ void st_push(const StackParams &p, uint32_t n, uint32_t *s_eb, uint32
     const uint64_t sel = ld_acq(&rec[n % REC_RING].sel);
     const uint32_t nitems = static_cast<uint32_t>(sel >> 32);
     const uint32_t T = static_cast<uint32_t>(sel);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        p.cnt[0] += nitems;
+        p.cnt[1] += T;
+        p.cnt[3] += ld_acq(&rec[n % REC_RING].nq);
+    }
     if (T == 0 || nitems == 0) return;
     constexpr uint32_t TE = TILE / G;
     const uint32_t ntiles = (T + TE - 1) / TE;
@@ -149,7 +154,7 @@ __device__ void st_push(const StackParams &p, uint32_t n, uint32_t *s_eb, uint32
     int32_t *qn = p.q[(n + 1) & 1];
     LevelRec &RN = rec[(n + 1) % REC_RING];
     const uint32_t tid = threadIdx.x;
-    uint64_t pairs = 0;
+    uint64_t pairs = 0, updates = 0;
     uint32_t su = 0;
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         uint32_t i0 = tile < p.tile_cap ? p.tile_first[tile] : 0u;
@@ -201,6 +206,7 @@ __device__ void st_push(const StackParams &p, uint32_t n, uint32_t *s_eb, uint32
                         while (tq) {
                             const uint32_t q2 = __ffs(tq) - 1;
                             tq &= tq - 1;
+                            updates++;
                             const uint64_t idx = row_index<G>(p, w, q2) + j;
                             const uint64_t cand = x & ~p.P[idx];
                             if (!cand) continue;
@@ -223,11 +229,14 @@ __device__ void st_push(const StackParams &p, uint32_t n, uint32_t *s_eb, uint32
         __syncthreads();
     }
     pairs = wave_sum(pairs);
+    updates = wave_sum(updates);
     su = wave_or(su);
     if (lane_id() == 0 && pairs) {
         atomicAdd(reinterpret_cast<unsigned long long *>(&RN.pairs), (unsigned long long)pairs);
         atomicOr(&RN.su, su);
     }
+    if (lane_id() == 0 && updates)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[2]), (unsigned long long)updates);
 }
 
 // Result: source b reaches v iff some final state's row at v has bit b. One
@@ -293,6 +302,7 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         p.rec[0] = LevelRec{};
         for (int i = 0; i < 4; i++) p.status[i] = 0;
+        for (int i = 0; i < 4; i++) p.cnt[i] = 0;
     }
     if (!grid_barrier(bar, bc)) return;
     // start pairs: every source's bit in every start state's row

@@ -83,6 +83,7 @@ static rpq_status batch_prepare(rpq_graph *g, int32_t Q, int G, int32_t B, hipSt
     if ((st = balloc(b, reinterpret_cast<void **>(&p.rec), sizeof(LevelRec) * REC_RING, "rec")) != RPQ_OK) return st;
     if ((st = balloc(b, reinterpret_cast<void **>(&p.bar), sizeof(GridBarrier), "barrier")) != RPQ_OK) return st;
     if ((st = balloc(b, reinterpret_cast<void **>(&p.status), 64, "status")) != RPQ_OK) return st;
+    if ((st = balloc(b, reinterpret_cast<void **>(&p.cnt), 64, "counters")) != RPQ_OK) return st;
     if ((st = balloc(b, reinterpret_cast<void **>(&p.lvl_pairs), 8 * LVL_COUNT_CAP, "lvl")) != RPQ_OK) return st;
     if ((st = balloc(b, reinterpret_cast<void **>(&b->sources), 4 * static_cast<size_t>(MAX_BATCH), "sources")) !=
         RPQ_OK)
@@ -118,7 +119,7 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
     if (nsym > MAX_SYMS || qsz > g->qconst_cap)
         return fail(RPQ_EINVAL, "rpq_multi_source: query uses %d symbols; the limit is %d", nsym, MAX_SYMS);
     int32_t levels = 0;
-    int64_t pairs = 0;
+    int64_t pairs = 0, items = 0, edges = 0, updates = 0, active = 0, bytes = 0;
     float total_ms = 0.f;
     for (int32_t b0 = 0; b0 < n_sources; b0 += maxb) {
         const int32_t B = std::min(maxb, n_sources - b0);
@@ -148,7 +149,9 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         BT(launch_stacked(G, p, grid, s));
         BT(hipEventRecord(g->ev[3], s));
         uint32_t *hst = reinterpret_cast<uint32_t *>(bs->pinned + bs->qconst_cap + 4 * 1024);
+        uint64_t *hcnt = reinterpret_cast<uint64_t *>(bs->pinned + bs->qconst_cap + 4 * 1024 + 64);
         BT(hipMemcpyAsync(hst, p.status, 16, hipMemcpyDeviceToHost, s));
+        BT(hipMemcpyAsync(hcnt, p.cnt, 32, hipMemcpyDeviceToHost, s));
         BT(hipMemcpyAsync(hst + 4, &p.bar->abort, 4, hipMemcpyDeviceToHost, s));
         if (!(flags & RPQ_OUT_DEVICE))
             BT(hipMemcpyAsync(out_bitmaps + static_cast<size_t>(b0) * g->nwords, bs->out,
@@ -170,6 +173,18 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         std::vector<int64_t> lp(nl);
         if (nl) BT(hipMemcpy(lp.data(), p.lvl_pairs, 8 * nl, hipMemcpyDeviceToHost));
         for (int64_t x : lp) pairs += x;
+        // algorithmic bytes of the stacked traversal: 8 B of row pointers per
+        // item, 4 B per scanned edge, a read and a write of one 8-byte source
+        // word per (edge, transition, word) with a non-empty source word, the
+        // Q*G frontier words of every active vertex read and cleared, and the
+        // B result bitmaps
+        items += static_cast<int64_t>(hcnt[0]);
+        edges += static_cast<int64_t>(hcnt[1]);
+        updates += static_cast<int64_t>(hcnt[2]);
+        active += static_cast<int64_t>(hcnt[3]);
+        bytes += 8 * static_cast<int64_t>(hcnt[0]) + 4 * static_cast<int64_t>(hcnt[1]) +
+                 16 * static_cast<int64_t>(hcnt[2]) + 16 * static_cast<int64_t>(n->Q) * G * static_cast<int64_t>(hcnt[3]) +
+                 static_cast<int64_t>(B) * ((static_cast<int64_t>(g->V) + 7) / 8);
     }
     if (stats) {
         int64_t *lc = stats->level_counts;
@@ -184,6 +199,11 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         stats->device_ms = total_ms;
         stats->expand_ms = total_ms;
         stats->expand_launches = (n_sources + maxb - 1) / maxb;
+        stats->scans = items;
+        stats->scanned_edges = edges;
+        stats->active = active;
+        stats->alg_bytes = bytes;
+        stats->product_edges = updates;  // (edge, transition, 64-source word) updates
     }
     return RPQ_OK;
 }
