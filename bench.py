@@ -67,6 +67,18 @@ def committed_traffic(kernel: str):
     return int(m.group(2))
 
 
+def log_levels(tag, st, limit=64):
+    """Per-level profile of one call on stderr: frontier vertices, new pairs,
+    push edges and device microseconds per level."""
+    n = len(st.level_us)
+    log("%s: %d levels, %.3f ms on the device clock" % (tag, st.levels, st.level_us.sum() / 1e3))
+    log("  level  frontier        pairs        edges         us  select_us")
+    idx = list(range(n)) if n <= limit else list(range(limit // 2)) + list(range(n - limit // 2, n))
+    for i in idx:
+        log("  %5d %9d %12d %12d %10.1f %10.1f" % (i, st.level_frontier[i], st.level_counts[i], st.level_edges[i],
+                                                  st.level_us[i], st.level_select_us[i]))
+
+
 def percentile(xs, p):
     return float(np.percentile(np.asarray(xs), p)) if len(xs) else 0.0
 
@@ -107,6 +119,8 @@ def bench_batched(args, w):
     srcs = [int(s) for s in w.sources]
     B = len(srcs)
     g.set_option("max_batch", B)
+    if args.stacked_alpha is not None:
+        g.set_option("stacked_alpha", args.stacked_alpha)
     words = g.words
     out = rpq.DeviceBuffer(8 * B * words)
     pe = np.zeros(B, np.int64)
@@ -117,6 +131,11 @@ def bench_batched(args, w):
         pe[i], ab[i], lv[i] = st.product_edges, st.alg_bytes, st.levels
     log("query %r (%d states): product edges %d, levels max %d" % (w.queries[0], nfa.num_states, pe.sum(), lv.max()))
     plain_ref = out.to_host().reshape(B, words)
+    for tag, fl in (("stacked", 0), ("stacked, push only", rpq.FORCE_PUSH), ("stacked, pull only", rpq.FORCE_PULL)):
+        _, st = g.multi_source(nh, srcs, flags=fl, out_device_ptr=out.ptr, level_cap=1 << 14)
+        log_levels(tag, st)
+    if args.levels_only:
+        return
 
     def plain_step(lat=None):
         for i, s in enumerate(srcs):
@@ -206,6 +225,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--host-loop", action="store_true", help="drive levels from the host")
+    ap.add_argument("--stacked-alpha", type=int, default=None, help="push->pull threshold of the stacked path")
+    ap.add_argument("--levels-only", action="store_true", help="batched workloads: per-level profiles only")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (for traffic-counter calibration)")
     args = ap.parse_args()
@@ -249,6 +270,10 @@ def main():
         _, st = g.single_source(nh, int(s), flags=mode | rpq.COUNTERS, out_device_ptr=base_ptr + i * row_bytes)
         pe[i], ab[i], levels[i] = st.product_edges, st.alg_bytes, st.levels
     log("counters: product edges %d, algorithmic bytes %d, levels max %d" % (pe.sum(), ab.sum(), levels.max()))
+    for i in (int(np.argmax(pe)), int(np.argsort(pe)[len(pe) // 2])):
+        _, st = g.single_source(nfas[i], int(w.sources[i]), flags=mode, level_cap=1 << 14,
+                                out_device_ptr=base_ptr + i * row_bytes)
+        log_levels("query %d %r" % (i, w.queries[i]), st)
 
     def step(timing: bool, lat=None, kern=None):
         fl = mode | (rpq.KERNEL_TIMING if timing else 0)

@@ -82,6 +82,20 @@ typedef struct {
     double expand_ms;        /* out, with RPQ_KERNEL_TIMING: summed expansion-kernel time */
     int32_t expand_launches; /* out, with RPQ_KERNEL_TIMING */
     int32_t batch;           /* out: sources evaluated together */
+    /* in: optional per-level outputs, each a caller buffer of level_cap
+       entries (any may be NULL), filled for n < min(levels, level_cap) by
+       rpq_single_source and rpq_multi_source (summed over a batch's sources,
+       levels in lockstep; a call with several batches reports the last one):
+       level_us: device time of level n in microseconds (GPU wall clock);
+       level_frontier: vertices with a non-empty frontier state set at level n;
+       level_edges: edges leaving the level-n frontier under symbols its state
+       sets can take (the push work of level n, whichever direction ran);
+       level_select_us: the part of level_us spent building the frontier and
+       its work items, before the expansion (0 where not measured). */
+    double *level_us;
+    int64_t *level_frontier;
+    int64_t *level_edges;
+    double *level_select_us;
 } rpq_stats;
 
 /* Number of uint64 words of a reachable-vertex bitmap over V vertices. */
@@ -114,6 +128,9 @@ rpq_status rpq_graph_info(const rpq_graph *g, const char *key, int64_t *value);
  *                (edges of the query's symbols) / alpha; 0 disables pull.
  *  "pull_beta"   pull->push switch: back to push when the frontier has fewer
  *                than num_vertices / beta vertices.
+ *  "stacked_alpha", "stacked_beta"  the same two thresholds for
+ *                rpq_multi_source (defaults 0, i.e. push only, and 24; pull
+ *                needs <= 8 states).
  *  "max_batch"   largest number of sources stacked in one launch (<= 1024).
  *  "mem_budget"  device bytes the served path may use for query state.
  *  "max_slots"   concurrent queries in the served path.

@@ -35,6 +35,39 @@ rpq_status rpq::hip_fail(hipError_t e, const char *what) {
         if (e_ != hipSuccess) return hip_fail(e_, #call); \
     } while (0)
 
+void rpq::stats_reset(rpq_stats *st) {
+    rpq_stats in = *st;
+    *st = rpq_stats{};
+    st->level_counts = in.level_counts;
+    st->level_cap = in.level_cap;
+    st->level_us = in.level_us;
+    st->level_frontier = in.level_frontier;
+    st->level_edges = in.level_edges;
+    st->level_select_us = in.level_select_us;
+}
+
+int64_t rpq::stats_levels(rpq_stats *st, const uint64_t *lvl, uint32_t nrec, uint32_t levels) {
+    int64_t visited = 0;
+    const uint32_t nl = std::min(nrec, levels);
+    for (uint32_t i = 0; i < nl; i++) visited += static_cast<int64_t>(lvl[static_cast<size_t>(i) * LVL_STRIDE]);
+    if (!st || st->level_cap <= 0) return visited;
+    for (int32_t i = 0; i < st->level_cap; i++) {
+        const bool have = static_cast<uint32_t>(i) < nl;
+        const uint64_t *r = lvl + static_cast<size_t>(i) * LVL_STRIDE;
+        if (st->level_counts) st->level_counts[i] = have ? static_cast<int64_t>(r[0]) : 0;
+        if (st->level_frontier) st->level_frontier[i] = have ? static_cast<int64_t>(r[1]) : 0;
+        if (st->level_edges) st->level_edges[i] = have ? static_cast<int64_t>(r[2] & 0xffffffffull) : 0;
+        if (st->level_select_us)
+            st->level_select_us[i] = have && r[4] > r[3] ? static_cast<double>(r[4] - r[3]) * 0.01 : 0.0;
+        if (st->level_us) {
+            // the device wall clock runs at 100 MHz
+            const bool end = have && static_cast<uint32_t>(i) + 1 < nrec;
+            st->level_us[i] = end ? static_cast<double>(r[LVL_STRIDE + 3] - r[3]) * 0.01 : 0.0;
+        }
+    }
+    return visited;
+}
+
 int64_t rpq_bitmap_words(int32_t num_vertices) {
     return num_vertices > 0 ? (static_cast<int64_t>(num_vertices) + 63) / 64 : 0;
 }
@@ -111,7 +144,7 @@ size_t rpq::build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, u
     *nsym_out = ns;
     if (ns > MAX_SYMS) return 0;
     const size_t tab = static_cast<size_t>(ns) * MAX_STATES * sizeof(uint32_t);
-    const size_t sz = sizeof(QHeader) + 2 * tab + 2 * static_cast<size_t>(ns) * 8 + 2 * static_cast<size_t>(ns) * 4;
+    const size_t sz = qconst_bytes(static_cast<size_t>(ns));
     buf.assign(sz, 0);
     QHeader *h = reinterpret_cast<QHeader *>(buf.data());
     uint32_t *succ = reinterpret_cast<uint32_t *>(buf.data() + sizeof(QHeader));
@@ -120,6 +153,7 @@ size_t rpq::build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, u
     uint64_t *pull_w = push_w + ns;
     uint32_t *push_r = reinterpret_cast<uint32_t *>(pull_w + ns);
     uint32_t *pull_r = push_r + ns;
+    uint32_t *pull_n = pull_r + ns;
     h->Q = n->Q;
     h->nsym = ns;
     h->smask = n->smask;
@@ -140,6 +174,7 @@ size_t rpq::build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, u
         pull_w[u] = (static_cast<uint64_t>(dpull) * L + lab) * static_cast<uint64_t>(g->nwords);
         push_r[u] = static_cast<uint32_t>(g->rbase[static_cast<size_t>(dpush) * L + lab]);
         pull_r[u] = static_cast<uint32_t>(g->rbase[static_cast<size_t>(dpull) * L + lab]);
+        pull_n[u] = static_cast<uint32_t>(g->label_rows[static_cast<size_t>(dpull)][lab]);
         erel += static_cast<uint64_t>(g->label_edges[lab]);
     }
     for (const auto &t : n->trans) {
@@ -165,6 +200,7 @@ QueryView rpq::query_view(uint8_t *base, int32_t nsym) {
     qv.pull_w = qv.push_w + nsym;
     qv.push_r = reinterpret_cast<const uint32_t *>(qv.pull_w + nsym);
     qv.pull_r = qv.push_r + nsym;
+    qv.pull_n = qv.pull_r + nsym;
     return qv;
 }
 
@@ -244,6 +280,8 @@ rpq_status rpq::graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32
     build_direction(V, dst, src, label_ptr, L, static_cast<uint32_t>(E), d[IN]);
     g->E = E;
     g->label_edges = d[OUT].label_edges;
+    g->label_rows[OUT] = d[OUT].label_rows;
+    g->label_rows[IN] = d[IN].label_rows;
     g->nwords = rpq_bitmap_words(V);
     g->rows[OUT] = g->rows[IN] = 0;
     for (int32_t l = 0; l < L; l++) {
@@ -257,12 +295,15 @@ rpq_status rpq::graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32
         g->rbase[l] = d[OUT].rbase[l];
         g->rbase[L + l] = nrp_out + d[IN].rbase[l];
     }
-    uint32_t *col = nullptr, *rowptr = nullptr;
+    uint32_t *col = nullptr, *rowptr = nullptr, *rowvert = nullptr;
     RankWordD *rankw = nullptr;
     const size_t nrank = static_cast<size_t>(L) * g->nwords;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&col), 2 * E * sizeof(uint32_t), "col")) != RPQ_OK) return st;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&rowptr),
                         (nrp_out + d[IN].rowptr.size()) * sizeof(uint32_t), "rowptr")) != RPQ_OK)
+        return st;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&rowvert),
+                        (nrp_out + d[IN].rowptr.size()) * sizeof(uint32_t), "rowvert")) != RPQ_OK)
         return st;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&rankw), 2 * nrank * sizeof(RankWordD), "rank")) != RPQ_OK)
         return st;
@@ -270,6 +311,8 @@ rpq_status rpq::graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32
     for (int k = 0; k < 2; k++) {
         if (d[k].E)
             HIP_TRY(hipMemcpy(col + (k ? E : 0), d[k].col.data(), d[k].E * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(rowvert + (k ? nrp_out : 0), d[k].rowvert.data(), d[k].rowvert.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(rowptr + (k ? nrp_out : 0), d[k].rowptr.data(), d[k].rowptr.size() * sizeof(uint32_t),
                           hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(rankw + (k ? nrank : 0), d[k].rankw.data(), nrank * sizeof(RankWordD),
@@ -278,6 +321,7 @@ rpq_status rpq::graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32
     }
     g->gv.col = col;
     g->gv.rowptr = rowptr;
+    g->gv.rowvert = rowvert;
     g->gv.rankw = rankw;
     g->gv.ncol = 2 * static_cast<uint64_t>(E);
     g->gv.nwords = g->nwords;
@@ -300,14 +344,16 @@ rpq_status rpq::graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32
     sv.tile_cap = (2 * static_cast<uint64_t>(E)) / TILE + 2;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.tile_first), 4 * sv.tile_cap, "tiles")) != RPQ_OK) return st;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.rec), sizeof(LevelRec) * REC_RING, "rec")) != RPQ_OK) return st;
-    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.lvl_pairs), 8 * LVL_COUNT_CAP, "lvl")) != RPQ_OK) return st;
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.lvl), 8 * LVL_STRIDE * (LVL_COUNT_CAP + 1), "lvl")) !=
+        RPQ_OK)
+        return st;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&g->dev_out), 8 * g->nwords, "out")) != RPQ_OK) return st;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.status), 64, "status")) != RPQ_OK) return st;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.cnt), 64, "cnt")) != RPQ_OK) return st;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.bar), sizeof(GridBarrier), "barrier")) != RPQ_OK) return st;
-    g->qconst_cap = sizeof(QHeader) + static_cast<size_t>(MAX_SYMS) * (2 * MAX_STATES * 4 + 2 * 8 + 2 * 4) + 64;
+    g->qconst_cap = qconst_bytes(MAX_SYMS) + 64;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&g->qconst_dev), g->qconst_cap, "qconst")) != RPQ_OK) return st;
-    g->pinned_cap = g->qconst_cap + 4096 + 8 * LVL_COUNT_CAP;
+    g->pinned_cap = g->qconst_cap + 4096 + 8 * LVL_STRIDE * (LVL_COUNT_CAP + 1);
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&g->pinned), g->pinned_cap, hipHostMallocDefault));
     HIP_TRY(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
     g->own_stream = true;
@@ -354,6 +400,12 @@ rpq_status rpq_set_option(rpq_graph *g, const char *key, int64_t value) {
     } else if (!strcmp(key, "pull_beta")) {
         if (value < 1) return fail(RPQ_EINVAL, "rpq_set_option: pull_beta < 1");
         g->pull_beta = static_cast<double>(value);
+    } else if (!strcmp(key, "stacked_alpha")) {
+        if (value < 0) return fail(RPQ_EINVAL, "rpq_set_option: stacked_alpha < 0");
+        g->stack_alpha = static_cast<double>(value);
+    } else if (!strcmp(key, "stacked_beta")) {
+        if (value < 1) return fail(RPQ_EINVAL, "rpq_set_option: stacked_beta < 1");
+        g->stack_beta = static_cast<double>(value);
     } else if (!strcmp(key, "max_batch")) {
         if (value < 1 || value > MAX_BATCH) return fail(RPQ_EINVAL, "rpq_set_option: max_batch outside [1, %d]", MAX_BATCH);
         g->max_batch = static_cast<int32_t>(value);
@@ -377,6 +429,8 @@ rpq_status rpq_get_option(const rpq_graph *g, const char *key, int64_t *value) {
     if (!strcmp(key, "stream")) *value = static_cast<int64_t>(reinterpret_cast<intptr_t>(g->user_stream));
     else if (!strcmp(key, "pull_alpha")) *value = static_cast<int64_t>(g->pull_alpha);
     else if (!strcmp(key, "pull_beta")) *value = static_cast<int64_t>(g->pull_beta);
+    else if (!strcmp(key, "stacked_alpha")) *value = static_cast<int64_t>(g->stack_alpha);
+    else if (!strcmp(key, "stacked_beta")) *value = static_cast<int64_t>(g->stack_beta);
     else if (!strcmp(key, "max_batch")) *value = g->max_batch;
     else if (!strcmp(key, "mem_budget")) *value = g->mem_budget;
     else if (!strcmp(key, "max_slots")) *value = g->max_slots;
@@ -487,17 +541,10 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
         }
         stats->expand_ms = timing ? expand_ms : 0.0;
         stats->expand_launches = timing ? launches : 0;
-        int64_t *lp = reinterpret_cast<int64_t *>(stage + 128);
-        const uint32_t ncopy = std::min<uint32_t>(levels, LVL_COUNT_CAP);
-        int64_t visited = 0;
-        if (ncopy) {
-            HIP_TRY(hipMemcpy(lp, p.st.lvl_pairs, 8 * ncopy, hipMemcpyDeviceToHost));
-            for (uint32_t i = 0; i < ncopy; i++) visited += lp[i];
-        }
-        stats->visited_pairs = visited;
-        if (stats->level_counts && stats->level_cap > 0)
-            for (int32_t i = 0; i < stats->level_cap; i++)
-                stats->level_counts[i] = static_cast<uint32_t>(i) < ncopy ? lp[i] : 0;
+        uint64_t *lp = reinterpret_cast<uint64_t *>(stage + 128);
+        const uint32_t ncopy = std::min<uint32_t>(levels + 1, LVL_COUNT_CAP);
+        HIP_TRY(hipMemcpy(lp, p.st.lvl, 8 * LVL_STRIDE * static_cast<size_t>(ncopy), hipMemcpyDeviceToHost));
+        stats->visited_pairs = stats_levels(stats, lp, ncopy, levels);
         if (counters) {
             const int64_t w = W;
             stats->product_edges = static_cast<int64_t>(cnt[0]);

@@ -39,6 +39,7 @@ struct rpq_graph {
     rpq::GraphView gv{};
     rpq::StateView sv{};
     std::vector<int64_t> label_edges;
+    std::vector<int64_t> label_rows[2];  // rows per (direction, label)
     int64_t rows[2] = {0, 0};
     std::vector<uint64_t> rbase;  // [direction * L + label] first rowptr entry
     std::vector<void *> allocs;
@@ -58,6 +59,8 @@ struct rpq_graph {
     // options
     double pull_alpha = 0.0;  // push only until tuned (see rpq_set_option)
     double pull_beta = 24.0;
+    double stack_alpha = 0.0;  // the same thresholds for the stacked multi-source path (push only until tuned)
+    double stack_beta = 24.0;
     int32_t max_batch = 256;
     int64_t mem_budget = 0;  // 0 = a quarter of the free device memory at first use
     int32_t max_slots = 64;
@@ -87,5 +90,12 @@ rpq_status run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint64_t *
 void serve_shutdown(rpq_graph *g);
 bool serve_pending(rpq_graph *g);
 void batch_free(rpq_graph *g);
+// Clears the outputs of *st and keeps its caller-supplied input fields.
+void stats_reset(rpq_stats *st);
+// Fills the per-level outputs of *st (level_counts, level_us, level_frontier,
+// level_edges) from `nrec` host copies of the device's per-level records
+// (LVL_STRIDE words each; record `levels` carries only the end clock).
+// Returns the sum of |M_n| over the copied levels.
+int64_t stats_levels(rpq_stats *st, const uint64_t *lvl, uint32_t nrec, uint32_t levels);
 
 }  // namespace rpq

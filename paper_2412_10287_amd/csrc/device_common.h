@@ -84,6 +84,44 @@ __device__ __forceinline__ bool wave_append(bool flag, int32_t value, int32_t *q
     return true;
 }
 
+// wave_append for four (flag, value) pairs per lane with one atomic per wave.
+__device__ __forceinline__ bool wave_append4(bool f0, int32_t v0, bool f1, int32_t v1, bool f2, int32_t v2, bool f3,
+                                             int32_t v3, int32_t *queue, uint32_t *counter, uint32_t cap) {
+    const uint64_t m0 = __ballot(f0), m1 = __ballot(f1), m2 = __ballot(f2), m3 = __ballot(f3);
+    const uint32_t c0 = static_cast<uint32_t>(__popcll(m0)), c1 = static_cast<uint32_t>(__popcll(m1));
+    const uint32_t c2 = static_cast<uint32_t>(__popcll(m2)), c3 = static_cast<uint32_t>(__popcll(m3));
+    const uint32_t tot = c0 + c1 + c2 + c3;
+    if (tot == 0) return true;
+    const uint32_t lane = lane_id();
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(counter, tot);
+    base = __shfl(base, 0, 64);
+    const uint64_t below = (1ull << lane) - 1ull;
+    bool ok = true;
+    uint32_t pos;
+    if (f0) {
+        pos = base + static_cast<uint32_t>(__popcll(m0 & below));
+        if (pos < cap) queue[pos] = v0;
+        else ok = false;
+    }
+    if (f1) {
+        pos = base + c0 + static_cast<uint32_t>(__popcll(m1 & below));
+        if (pos < cap) queue[pos] = v1;
+        else ok = false;
+    }
+    if (f2) {
+        pos = base + c0 + c1 + static_cast<uint32_t>(__popcll(m2 & below));
+        if (pos < cap) queue[pos] = v2;
+        else ok = false;
+    }
+    if (f3) {
+        pos = base + c0 + c1 + c2 + static_cast<uint32_t>(__popcll(m3 & below));
+        if (pos < cap) queue[pos] = v3;
+        else ok = false;
+    }
+    return ok;
+}
+
 __device__ __forceinline__ uint32_t succ_of(const uint32_t *succ, uint32_t u, uint32_t S) {
     const uint32_t *t = succ + u * MAX_STATES;
     uint32_t r = 0;

@@ -64,6 +64,7 @@ void build_direction(int32_t V, const int32_t *a, const int32_t *b, const int64_
     }
     out.E = cbase[L];
     out.rowptr.assign(rtotal, 0);
+    out.rowvert.assign(rtotal, static_cast<uint32_t>(V));
     out.col.assign(static_cast<size_t>(out.E), 0);
     out.rankw.assign(static_cast<size_t>(L) * nw, RankWord{0, 0, 0});
     parallel_dynamic(L, [&](int64_t i) {
@@ -71,12 +72,14 @@ void build_direction(int32_t V, const int32_t *a, const int32_t *b, const int64_
         const std::vector<uint64_t> &k = keys[l];
         RankWord *rw = out.rankw.data() + static_cast<size_t>(l) * nw;
         uint32_t *rp = out.rowptr.data() + out.rbase[l];
+        uint32_t *rv = out.rowvert.data() + out.rbase[l];
         uint32_t *c = out.col.data() + cbase[l];
         int64_t row = 0;
         for (size_t j = 0; j < k.size(); j++) {
             const uint32_t v = static_cast<uint32_t>(k[j] >> 32);
             if (j == 0 || (k[j] >> 32) != (k[j - 1] >> 32)) {
                 rw[v >> 6].bits |= 1ull << (v & 63);
+                rv[row] = v;
                 rp[row++] = col_offset + static_cast<uint32_t>(cbase[l] + j);
             }
             c[j] = static_cast<uint32_t>(k[j]);

@@ -20,6 +20,7 @@ struct RankWord {
 struct HostDir {
     std::vector<RankWord> rankw;      // L * nwords
     std::vector<uint32_t> rowptr;     // per label: rows+1 entries, positions in col
+    std::vector<uint32_t> rowvert;    // same indexing as rowptr: the vertex of each row (V after the last)
     std::vector<uint64_t> rbase;      // per label: first rowptr entry
     std::vector<uint32_t> col;        // neighbours, label-major
     std::vector<int64_t> label_edges; // distinct edges per label

@@ -74,7 +74,12 @@ __device__ void select_phase(const Params &p, uint32_t n) {
     const uint32_t V = static_cast<uint32_t>(g.V);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         rec[(n + 1) % REC_RING] = LevelRec{};
-        if (n < LVL_COUNT_CAP) p.st.lvl_pairs[n] = static_cast<int64_t>(ld_acq(&R.pairs));
+        if (n < LVL_COUNT_CAP) {
+            uint64_t *L = p.st.lvl + static_cast<uint64_t>(n) * LVL_STRIDE;
+            L[0] = ld_acq(&R.pairs);
+            L[1] = nq;
+            L[3] = wall_clock64();
+        }
         if (h.counters) p.st.cnt[3] += nq;
     }
     // frontier words of level n-1 live in the buffer level n writes: clear them
@@ -447,6 +452,8 @@ __device__ void pull_phase(const Params &p, uint32_t n, uint32_t *s_hw, uint32_t
 template <int W>
 __device__ void final_phase(const Params &p, uint32_t nlev) {
     const uint32_t V = static_cast<uint32_t>(p.g.V);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && nlev < LVL_COUNT_CAP)
+        p.st.lvl[static_cast<uint64_t>(nlev) * LVL_STRIDE + 3] = wall_clock64();
     if (nlev >= 1) {
         const uint32_t D = nlev - 1;
         const uint32_t nq = ld_acq(&p.st.rec[D % REC_RING].nq);
@@ -487,7 +494,13 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
         select_phase<W>(p, n);
         if (!grid_barrier(bar, bc)) return;
         const uint32_t mode = decide(p, n);
-        if (blockIdx.x == 0 && threadIdx.x == 0) p.st.rec[n % REC_RING].mode = mode;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            p.st.rec[n % REC_RING].mode = mode;
+            if (n < LVL_COUNT_CAP) {
+                p.st.lvl[static_cast<uint64_t>(n) * LVL_STRIDE + 2] = ld_acq(&p.st.rec[n % REC_RING].sel);
+                p.st.lvl[static_cast<uint64_t>(n) * LVL_STRIDE + 4] = wall_clock64();
+            }
+        }
         if (mode == 0) push_phase<W>(p, n, s_eb, s_beg, s_mask);
         else pull_phase<W>(p, n, s_eb, s_beg, s_mask, &s_hn);
         npush += mode == 0;
@@ -519,6 +532,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(Params p, uint32_t n) {
     const uint32_t mode = decide(p, n);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         p.st.rec[n % REC_RING].mode = mode;
+        if (n < LVL_COUNT_CAP) p.st.lvl[static_cast<uint64_t>(n) * LVL_STRIDE + 2] = ld_acq(&p.st.rec[n % REC_RING].sel);
         p.st.status[0] = n + 1;
         p.st.status[1 + (mode != 0)] += 1;
     }

@@ -45,6 +45,7 @@ __device__ __forceinline__ QueryView slot_view(const MultiParams &p, uint32_t s)
     qv.pull_w = qv.push_w + nsym;
     qv.push_r = reinterpret_cast<const uint32_t *>(qv.pull_w + nsym);
     qv.pull_r = qv.push_r + nsym;
+    qv.pull_n = qv.pull_r + nsym;
     return qv;
 }
 

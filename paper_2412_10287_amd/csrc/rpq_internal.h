@@ -12,7 +12,14 @@ constexpr int IN = 1;   // transpose (G^a)^T: row v holds the w with w -> v
 constexpr int MAX_STATES = 32;
 constexpr int MAX_SYMS = 256;              // distinct symbols one query may use
 constexpr uint32_t REC_RING = 1024;        // level records kept in a ring
-constexpr uint32_t LVL_COUNT_CAP = 65536;  // per-level pair counts kept for statistics
+constexpr uint32_t LVL_COUNT_CAP = 65536;  // levels whose statistics are kept
+// Per-level statistics, LVL_STRIDE uint64 per level n < LVL_COUNT_CAP:
+//   [0] |M_n| (pairs first reached at level n), [1] frontier vertices,
+//   [2] push reservation (items << 32 | edges), [3] device clock (100 MHz
+//   wall clock) when level n started; entry [3] of the level after the last
+//   one holds the clock when the traversal ended; [4] device clock when the
+//   level's select phase ended (0 where no separate select phase exists).
+constexpr uint32_t LVL_STRIDE = 5;
 constexpr int BLOCK = 512;                 // threads per workgroup (8 waves)
 constexpr int TILE = 4 * BLOCK;            // push edges per tile (one workgroup iteration)
 constexpr int SYM_BATCH = 4;               // row lookups issued together per vertex
@@ -35,6 +42,7 @@ struct RankWordD {
 struct GraphView {
     const RankWordD *rankw;
     const uint32_t *rowptr;
+    const uint32_t *rowvert;  // vertex of each row (indexed like rowptr)
     const uint32_t *col;
     uint64_t ncol;   // entries of col (both directions)
     int64_t nwords;  // rank words per (direction, label)
@@ -63,6 +71,7 @@ struct QHeader {
 //   succ[nsym][32], pred[nsym][32]           (uint32 state sets)
 //   push_w[nsym], pull_w[nsym]               (uint64 rank-word base)
 //   push_r[nsym], pull_r[nsym]               (uint32 rowptr base)
+//   pull_n[nsym]                             (uint32 rows in the pull direction)
 // A forward symbol pushes along OUT rows and pulls along IN rows; an inverse
 // symbol the other way round.
 struct QueryView {
@@ -73,7 +82,13 @@ struct QueryView {
     const uint64_t *pull_w;
     const uint32_t *push_r;
     const uint32_t *pull_r;
+    const uint32_t *pull_n;
 };
+
+// Bytes of the query-constant block for nsym used symbols.
+inline size_t qconst_bytes(size_t nsym) {
+    return sizeof(QHeader) + nsym * (2 * MAX_STATES * sizeof(uint32_t) + 2 * sizeof(uint64_t) + 3 * sizeof(uint32_t));
+}
 
 // One BFS level's bookkeeping (a ring of REC_RING entries).
 struct LevelRec {
@@ -82,7 +97,8 @@ struct LevelRec {
     uint64_t pairs;       // |M_n|
     uint64_t sel;         // select phase: (items << 32) | push edges
     uint32_t mode;        // 0 push, 1 pull (decided when the level is expanded)
-    uint32_t pad;
+    uint32_t nfront;      // stacked path: vertices with a non-empty frontier set
+    uint64_t hsel;        // stacked pull: long rows deferred to the edge-balanced pass, (items << 32) | edges
 };
 
 // Two-level grid barrier state (see grid_barrier in kernels.hip).
@@ -106,7 +122,7 @@ struct StateView {
     uint32_t *it_mask;    // push items: successor state set
     uint32_t *tile_first; // first item of each push tile
     LevelRec *rec;        // REC_RING records
-    int64_t *lvl_pairs;   // |M_n| for n < LVL_COUNT_CAP
+    uint64_t *lvl;        // per-level statistics (LVL_STRIDE words per level)
     uint64_t *out;        // output bitmap (device)
     uint32_t *status;     // [0] levels, [1] push levels, [2] pull levels, [3] invariant violations
     uint64_t *cnt;        // [0] product edges, [1] scans, [2] scanned edges, [3] active

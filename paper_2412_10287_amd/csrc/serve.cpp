@@ -409,11 +409,14 @@ rpq_status rpq_poll(rpq_graph *g, rpq_ticket t, uint64_t *out_bitmap, rpq_stats 
     if (st == RPQ_OK) {
         memcpy(out_bitmap, tk.bitmap.data(), 8 * tk.bitmap.size());
         if (stats) {
-            int64_t *lc = stats->level_counts;
-            const int32_t cap = stats->level_cap;
+            rpq_stats in = *stats;
             *stats = tk.stats;
-            stats->level_counts = lc;
-            stats->level_cap = cap;
+            stats->level_counts = in.level_counts;
+            stats->level_cap = in.level_cap;
+            stats->level_us = in.level_us;
+            stats->level_frontier = in.level_frontier;
+            stats->level_edges = in.level_edges;
+            stats->level_select_us = in.level_select_us;
         }
     } else {
         fail(st, "%s", tk.error.c_str());

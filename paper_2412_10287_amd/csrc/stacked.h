@@ -7,7 +7,13 @@ namespace rpq {
 
 // Every vertex v carries, per state q, a row of B source bits stored as G
 // 64-bit words (G = ceil(B/64)): P, M[0], M[1] are [V][Q][G] uint64 arrays.
-// sup[parity][v] is the set of states whose row in M[parity] is non-zero.
+//
+// Level n works on the buffers of parity n & 1. While level n-1 expands, the
+// rows M[n&1][w] collect candidate bits (not yet masked by P) and sup[n&1][w]
+// the states that received any; the first writer of sup[n&1][w] appends w to
+// q[n&1]. Level n's select then masks every candidate row by P, adds the new
+// bits to P, and leaves in M[n&1][w] the frontier rows M_n and in sup[n&1][w]
+// the frontier's state set (0 when every candidate bit was already visited).
 struct StackParams {
     GraphView g;
     QueryView qv;
@@ -15,13 +21,15 @@ struct StackParams {
     uint64_t *M[2];
     uint32_t *sup[2];
     int32_t *q[2];
-    uint32_t *it_ebase, *it_beg, *it_v, *it_u;  // push items: (vertex, symbol) rows
+    // work items: one (vertex, symbol) row each; it_s is the frontier state
+    // set of the item's source vertex (push) or unused (pull)
+    uint32_t *it_ebase, *it_beg, *it_v, *it_u, *it_s;
     uint32_t *tile_first;
     LevelRec *rec;
     GridBarrier *bar;
-    uint32_t *status;        // [0] levels, [3] invariant violations
+    uint32_t *status;        // [0] levels, [1] push levels, [2] pull levels, [3] invariant violations
     uint64_t *cnt;           // [0] items, [1] scanned edges, [2] word updates, [3] active vertices
-    int64_t *lvl_pairs;      // |M_n| summed over sources, n < LVL_COUNT_CAP
+    uint64_t *lvl;           // per-level statistics (LVL_STRIDE words), pairs summed over sources
     uint64_t *out;           // B bitmaps of nwords words
     const int32_t *sources;  // B vertex ids
     uint64_t item_cap, tile_cap;
@@ -29,7 +37,9 @@ struct StackParams {
     int32_t B, Q, V;
 };
 
-hipError_t launch_stacked(int G, const StackParams &p, int grid, hipStream_t s);
-int stacked_grid(int G);
+// QM is the state bound the kernel is compiled for: 8 (every state set fits a
+// byte; enables the pull direction) or 32.
+hipError_t launch_stacked(int G, int QM, const StackParams &p, int grid, hipStream_t s);
+int stacked_grid(int G, int QM);
 
 }  // namespace rpq

@@ -1,98 +1,229 @@
 // Stacked multi-source traversal (the multiple-source direction of Sec. 6):
 // B sources under one NFA share one level-synchronous traversal. For every
-// vertex v and state q, the frontier and visited sets hold a row of B source
-// bits, so the level update of Alg. 1 becomes, per edge (v, w) of symbol a and
-// transition q -a-> q',
-//     new = M[v][q] AND NOT P[w][q'],   P[w][q'] |= new,   M'[w][q'] |= new
-// on 64-bit words: one random access to w's row serves 64 sources per word
-// (the bit-parallel multi-source BFS idea of Then et al., VLDB 2014).
+// vertex v and state q, the frontier M and visited set P hold a row of B
+// source bits (G = ceil(B/64) words), so the update of Alg. 1,
+//     M' = ( OR over symbols a of (N^a)^T M G^a ) masked by not-P,   P = P + M',
+// becomes, per edge (v, w) of symbol a and transition q -a-> q', an OR of the
+// 64-bit words M[v][q][j] into w's row of q': one access to w's row serves 64
+// sources per word (bit-parallel multi-source BFS, Then et al., VLDB 2014).
+//
+// The mask by not-P is deferred: an expansion ORs candidate bits into the next
+// level's rows with fire-and-forget atomics (no read of P on the critical
+// path of the scatter), and the next level's select applies the mask once
+// per touched row while it builds the work items. On MI355X random 64-bit
+// atomics cost more than twice a random load and never hit in L2, so this
+// halves the atomics per edge against an atomic update of P.
 //
 // Phases per level (one cooperative launch, grid barriers between phases):
-//   select  frontier vertex v with state support S(v) -> one item per used
-//           symbol u with succ_u(S(v)) non-empty and a u-row at v;
-//   push    edges of all items spread evenly, G lanes per edge (one 64-bit
-//           word each), atomics fused with the not-P mask;
-// and after the last level an extract phase that turns the per-vertex rows of
-// final states into one result bitmap per source and resets P.
+//   select  candidate vertex w -> masked frontier rows (P updated), frontier
+//           state set S(w), and one item per used symbol u with
+//           succ_u(S(w)) non-empty and a u-row at w;
+//   push    (sparse levels) edges of all items spread evenly, G lanes per
+//           edge (one source word each);
+//   pull    (dense levels, at most 8 states) every row of the reverse
+//           adjacency under a used symbol whose target states still miss
+//           source bits gathers the frontier rows of its neighbours, stopping
+//           once every bit is found; rows longer than PULL_LIGHT_ROW go to an
+//           edge-balanced pass after a barrier.
+// After the last level an extract phase turns the rows of final states into
+// one result bitmap per source and resets P.
 #include "device_common.h"
 #include "stacked.h"
 
 namespace rpq {
 
+constexpr uint32_t PULL_LIGHT_ROW = 128;  // longer pull rows are processed edge-balanced
+
 __device__ __forceinline__ void sviol(const StackParams &p) { atomicAdd(&p.status[3], 1u); }
 
 template <int G>
-__device__ __forceinline__ uint64_t row_index(const StackParams &p, uint32_t v, uint32_t q) {
+__device__ __forceinline__ uint64_t rowi(const StackParams &p, uint32_t v, uint32_t q) {
     return (static_cast<uint64_t>(v) * static_cast<uint32_t>(p.Q) + q) * G;
 }
 
+// The states of the automaton as a bit set (state sets read back from device
+// memory are masked with it, so a row index never leaves its vertex).
+__device__ __forceinline__ uint32_t state_mask(const StackParams &p) {
+    return p.Q >= 32 ? ~0u : (1u << p.Q) - 1u;
+}
+
+// Queue length of record R, at most V (each vertex enters a queue once per
+// level; a larger count is reported as a violated invariant).
+__device__ __forceinline__ uint32_t queue_len(const StackParams &p, const LevelRec &R) {
+    const uint32_t nq = ld_acq(&R.nq);
+    const uint32_t V = static_cast<uint32_t>(p.V);
+    if (nq > V) {
+        if (gthread() == 0) sviol(p);
+        return V;
+    }
+    return nq;
+}
+
+// Bits of source word j that belong to real sources.
+__device__ __forceinline__ uint64_t word_full(int32_t B, uint32_t j) {
+    const int32_t r = B - 64 * static_cast<int32_t>(j);
+    return r >= 64 ? ~0ull : r <= 0 ? 0ull : ((1ull << r) - 1ull);
+}
+
+// OR over the G consecutive lanes that work on one vertex (or edge). The
+// lanes of a group always take the same branches, so they are active together.
 template <int G>
-__device__ void st_select(const StackParams &p, uint32_t n) {
+__device__ __forceinline__ uint32_t group_or(uint32_t x) {
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) x |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(x), d, 64));
+    return x;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t group_or64(uint64_t x) {
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) x |= __shfl_xor(x, d, 64);
+    return x;
+}
+
+// LDS copy of the work items one workgroup is processing.
+struct StLds {
+    uint32_t eb[TILE + 1], beg[TILE + 1], v[TILE + 1], u[TILE + 1], s[TILE + 1];
+};
+
+// Records item idx: `len` edges numbered from eb (both reserved by the caller
+// with one atomic on a word that counts items in its high half and edges in
+// its low half, so item order follows edge numbers), read from col[beg...].
+// Every tile of TILE/G edges whose first edge the item holds points to it.
+template <int G>
+__device__ __forceinline__ void put_item(const StackParams &p, uint32_t idx, uint32_t eb, uint32_t beg, uint32_t len,
+                                         uint32_t v, uint32_t u, uint32_t s) {
+    constexpr uint32_t TE = TILE / G;
+    if (idx < p.item_cap) {
+        p.it_ebase[idx] = eb;
+        p.it_beg[idx] = beg;
+        p.it_v[idx] = v;
+        p.it_u[idx] = u;
+        p.it_s[idx] = s;
+    } else {
+        sviol(p);
+    }
+    const uint32_t k1 = (eb + len - 1) / TE;
+    for (uint32_t k = (eb + TE - 1) / TE; k <= k1; k++) {
+        if (k < p.tile_cap) p.tile_first[k] = idx;
+        else { sviol(p); break; }
+    }
+}
+
+// ------------------------------------------------------------------ select
+template <int G, int QM>
+__device__ __forceinline__ void st_select(const StackParams &p, uint32_t n) {
     const GraphView &g = p.g;
     const QueryView &qv = p.qv;
     LevelRec *rec = p.rec;
     LevelRec &R = rec[n % REC_RING];
-    const uint32_t nq = ld_acq(&R.nq);
+    const uint32_t nq = queue_len(p, R);
     const uint32_t V = static_cast<uint32_t>(p.V);
-    const uint32_t Q = static_cast<uint32_t>(p.Q);
+    const uint32_t qmask = state_mask(p);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         rec[(n + 1) % REC_RING] = LevelRec{};
-        if (n < LVL_COUNT_CAP) p.lvl_pairs[n] = static_cast<int64_t>(ld_acq(&R.pairs));
+        if (n < LVL_COUNT_CAP) p.lvl[static_cast<uint64_t>(n) * LVL_STRIDE + 3] = wall_clock64();
     }
-    // rows of the previous frontier live in the buffer this level writes
+    const uint32_t lane = lane_id();
+    const uint32_t j = lane % G;
+    const uint32_t grp = lane / G;
+    constexpr uint32_t GPW = 64 / G;  // vertices per wave and step
+    const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
+    // level n-1's frontier state sets live in the array level n's expansion
+    // fills: clear them. Its frontier rows may stay: every bit in them is in P
+    // already, so a later select masks them out (it rewrites every row it
+    // reads), and the extract phase clears both row buffers.
     if (n >= 1) {
-        const uint32_t nprev = ld_acq(&rec[(n - 1) % REC_RING].nq);
-        uint64_t *Mold = p.M[(n + 1) & 1];
+        const uint32_t nprev = queue_len(p, rec[(n - 1) % REC_RING]);
         uint32_t *sold = p.sup[(n + 1) & 1];
         const int32_t *qold = p.q[(n + 1) & 1];
-        const uint64_t words = static_cast<uint64_t>(Q) * G;
-        const uint64_t total = static_cast<uint64_t>(nprev) * words;
-        for (uint64_t x = gthread(); x < total; x += gthreads()) {
-            const uint32_t v = static_cast<uint32_t>(qold[x / words]);
-            const uint32_t k = static_cast<uint32_t>(x % words);
-            if (v >= V) {
-                sviol(p);
-                continue;
-            }
-            Mold[static_cast<uint64_t>(v) * words + k] = 0;
-            if (k == 0) sold[v] = 0;
+        for (uint32_t i = gthread(); i < nprev; i += gthreads()) {
+            const uint32_t v = static_cast<uint32_t>(qold[i]);
+            if (v < V) sold[v] = 0;
+            else sviol(p);
         }
     }
     const int32_t *qc = p.q[n & 1];
-    const uint32_t *sc = p.sup[n & 1];
-    const uint32_t lane = lane_id();
-    const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
+    uint64_t *Mc = p.M[n & 1];
+    uint32_t *sc = p.sup[n & 1];
     const uint32_t nsym = qv.h->nsym;
-    constexpr uint32_t TE = TILE / G;  // edges per push tile
-    for (uint32_t base = gw * 64; base < nq; base += nw * 64) {
-        const uint32_t i = base + lane;
-        uint32_t v = i < nq ? static_cast<uint32_t>(qc[i]) : 0u;
-        uint32_t S = 0;
+    uint64_t pairs = 0, upd = 0, c_items = 0, c_edges = 0;
+    uint32_t nfront = 0, su = 0;
+    for (uint32_t base = gw * GPW; base < nq; base += nw * GPW) {
+        const uint32_t i = base + grp;
+        uint32_t w = 0, cs = 0;
+        bool ok = false;
         if (i < nq) {
-            if (v < V) S = sc[v];
-            else { sviol(p); v = 0; }
+            w = static_cast<uint32_t>(qc[i]);
+            if (w < V) {
+                cs = sc[w] & qmask;
+                ok = true;
+            } else {
+                if (j == 0) sviol(p);
+                w = 0;
+            }
         }
-        for (uint32_t u0 = 0; u0 < nsym; u0 += SYM_BATCH) {
-            uint32_t sp[SYM_BATCH], beg[SYM_BATCH], len[SYM_BATCH];
+        // mask the candidate rows by P (Alg. 1's complement mask), add the new
+        // bits to P; rows that gained nothing are cleared
+        uint32_t S = 0, nzm = 0;
+#pragma unroll
+        for (int k = 0; k < QM; k++) {
+            if ((cs >> k) & 1u) {
+                const uint64_t idx = rowi<G>(p, w, k) + j;
+                const uint64_t c = Mc[idx];
+                const uint64_t pv = p.P[idx];
+                const uint64_t nb = c & ~pv;
+                if (nb) {
+                    p.P[idx] = pv | nb;
+                    nzm |= 1u << k;
+                    pairs += __popcll(nb);
+                }
+                if (nb != c) Mc[idx] = nb;
+            }
+        }
+        S = group_or<G>(nzm);
+        if (ok && j == 0) {
+            sc[w] = S;
+            if (S) nfront++;
+            su |= S;
+        }
+        // nonzero source words per state over the group (for the work counter)
+        uint32_t nzc[QM];
+        const uint64_t gmask = ((1ull << G) - 1ull) << (grp * G);
+#pragma unroll
+        for (int k = 0; k < QM; k++) nzc[k] = static_cast<uint32_t>(__popcll(__ballot((nzm >> k) & 1u) & gmask));
+        // items: the small NFA factor first (succ_u of the state set), then
+        // the neighbour range of the u-row at w; the G lanes of the group look
+        // up different symbols
+        for (uint32_t u0 = 0; u0 < nsym; u0 += G * SYM_BATCH) {
+            uint32_t tu[SYM_BATCH], beg[SYM_BATCH], len[SYM_BATCH];
             RankWordD rw[SYM_BATCH];
 #pragma unroll
-            for (int j = 0; j < SYM_BATCH; j++) {
-                const uint32_t u = u0 + j;
-                sp[j] = (S && u < nsym) ? succ_of(qv.succ, u, S) : 0u;
-                if (sp[j]) rw[j] = g.rankw[qv.push_w[u] + (v >> 6)];
+            for (int jj = 0; jj < SYM_BATCH; jj++) {
+                const uint32_t u = u0 + jj * G + j;
+                tu[jj] = (S && u < nsym) ? succ_of(qv.succ, u, S) : 0u;
+                if (tu[jj]) rw[jj] = g.rankw[qv.push_w[u] + (w >> 6)];
             }
             uint32_t cnt = 0, tot = 0;
 #pragma unroll
-            for (int j = 0; j < SYM_BATCH; j++) {
-                len[j] = 0;
+            for (int jj = 0; jj < SYM_BATCH; jj++) {
+                const uint32_t u = u0 + jj * G + j;
+                len[jj] = 0;
                 uint32_t e;
-                if (sp[j] && row_range(g, rw[j], qv.push_r[u0 + j], v, beg[j], e)) {
-                    if (e > beg[j] && e <= g.ncol) len[j] = e - beg[j];
-                    else if (e != beg[j]) sviol(p);
+                if (tu[jj] && row_range(g, rw[jj], qv.push_r[u], w, beg[jj], e)) {
+                    if (e > beg[jj] && e <= g.ncol) len[jj] = e - beg[jj];
+                    else if (e != beg[jj]) sviol(p);
                 }
-                if (len[j]) {
+                if (len[jj]) {
+                    // (edge, transition, word) updates this item carries
+                    const uint32_t *su_tab = qv.succ + u * MAX_STATES;
+                    uint32_t c = 0;
+#pragma unroll
+                    for (int k = 0; k < QM; k++)
+                        if ((S >> k) & 1u) c += static_cast<uint32_t>(__popc(su_tab[k])) * nzc[k];
+                    upd += static_cast<uint64_t>(c) * len[jj];
                     cnt++;
-                    tot += len[j];
+                    tot += len[jj];
                 }
             }
             uint64_t wtot;
@@ -106,56 +237,281 @@ __device__ void st_select(const StackParams &p, uint32_t n) {
                 const uint64_t mine = old + ex;
                 uint32_t idx = static_cast<uint32_t>(mine >> 32);
                 uint32_t eb = static_cast<uint32_t>(mine);
+                c_items += cnt;
+                c_edges += tot;
 #pragma unroll
-                for (int j = 0; j < SYM_BATCH; j++) {
-                    if (!len[j]) continue;
-                    if (idx < p.item_cap) {
-                        p.it_ebase[idx] = eb;
-                        p.it_beg[idx] = beg[j];
-                        p.it_v[idx] = v;
-                        p.it_u[idx] = u0 + j;
-                    } else {
-                        sviol(p);
-                    }
-                    const uint32_t k1 = (eb + len[j] - 1) / TE;
-                    for (uint32_t k = (eb + TE - 1) / TE; k <= k1; k++) {
-                        if (k < p.tile_cap) p.tile_first[k] = idx;
-                        else { sviol(p); break; }
-                    }
+                for (int jj = 0; jj < SYM_BATCH; jj++) {
+                    if (!len[jj]) continue;
+                    put_item<G>(p, idx, eb, beg[jj], len[jj], w, u0 + jj * G + j, S);
                     idx++;
-                    eb += len[j];
+                    eb += len[jj];
+                }
+            }
+        }
+    }
+    pairs = wave_sum(pairs);
+    upd = wave_sum(upd);
+    c_items = wave_sum(c_items);
+    c_edges = wave_sum(c_edges);
+    const uint64_t nf = wave_sum(nfront);
+    su = wave_or(su);
+    if (lane == 0) {
+        if (pairs) atomicAdd(reinterpret_cast<unsigned long long *>(&R.pairs), static_cast<unsigned long long>(pairs));
+        if (nf) {
+            atomicAdd(&R.nfront, static_cast<uint32_t>(nf));
+            atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[3]), static_cast<unsigned long long>(nf));
+        }
+        if (su) atomicOr(&R.su, su);
+        if (c_items) {
+            atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[0]), static_cast<unsigned long long>(c_items));
+            atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[1]), static_cast<unsigned long long>(c_edges));
+        }
+        if (upd) atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[2]), static_cast<unsigned long long>(upd));
+    }
+}
+
+// --------------------------------------------------------------- expansion
+// One unit's state between its gather and its scatter.
+template <int QM>
+struct UnitC {
+    uint64_t c[QM <= 8 ? QM : 1];  // new candidate bits per target state (QM <= 8)
+    uint32_t dst;                  // target vertex (V when the unit is idle)
+    uint32_t tb;                   // target states that received bits
+};
+
+// Gather of one unit: locate its item and edge, OR the source's frontier rows
+// over the transitions into each target state, and drop the bits already in
+// P. Wide automata (QM = 32) scatter here, one transition at a time.
+template <int G, int QM, bool PULL>
+__device__ __forceinline__ void unit_gather(const StackParams &p, uint32_t n, const StLds &L, uint32_t cnt,
+                                            uint64_t unit, uint64_t uend, uint32_t ns, UnitC<QM> &U) {
+    const uint32_t V = static_cast<uint32_t>(p.V);
+    const uint32_t j = static_cast<uint32_t>(unit % G);
+    const uint64_t *Mc = p.M[n & 1];
+    uint64_t *Mn = p.M[(n + 1) & 1];
+    U.dst = V;
+    U.tb = 0;
+#pragma unroll
+    for (int q2 = 0; q2 < (QM <= 8 ? QM : 1); q2++) U.c[q2] = 0;
+    const uint32_t t = static_cast<uint32_t>(unit / G);
+    // item holding edge t: the last staged item with L.eb <= t
+    // (fixed-step search: cnt <= TILE + 1 < 2^12)
+    uint32_t lo = 0, len = cnt;
+#pragma unroll
+    for (int step = 0; step < 12; step++) {
+        const uint32_t half = len >> 1;
+        if (half && unit < uend) {
+            if (L.eb[lo + half] <= t) lo += half;
+            len -= half;
+        }
+    }
+    if (unit >= uend) return;
+    const uint32_t pos = L.beg[lo] + (t - L.eb[lo]);
+    const uint32_t iv = L.v[lo], u = L.u[lo];
+    if (pos >= p.g.ncol || iv >= V || u >= p.qv.h->nsym) {
+        sviol(p);
+        return;
+    }
+    const uint32_t other = p.g.col[pos];
+    if (other >= V) {
+        sviol(p);
+        return;
+    }
+    const uint32_t src = PULL ? other : iv;
+    const uint32_t w = PULL ? iv : other;
+    const uint32_t *succ = p.qv.succ + u * MAX_STATES;
+    const uint32_t tmask = PULL ? ns : ~0u;
+    const uint32_t S = (PULL ? (p.sup[n & 1][src] & L.s[lo]) : L.s[lo]) & state_mask(p);
+    U.dst = w;
+    if constexpr (QM <= 8) {
+        // y[q'] = OR of the source's rows over the transitions into q'
+        uint64_t y[QM];
+#pragma unroll
+        for (int q2 = 0; q2 < QM; q2++) y[q2] = 0;
+#pragma unroll
+        for (int kq = 0; kq < QM; kq++) {
+            if ((S >> kq) & 1u) {
+                const uint64_t x = Mc[rowi<G>(p, src, kq) + j];
+                const uint32_t tq = succ[kq] & tmask;
+#pragma unroll
+                for (int q2 = 0; q2 < QM; q2++)
+                    if ((tq >> q2) & 1u) y[q2] |= x;
+            }
+        }
+#pragma unroll
+        for (int q2 = 0; q2 < QM; q2++)
+            if (y[q2]) U.c[q2] = y[q2] & ~p.P[rowi<G>(p, w, q2) + j];
+    } else {
+        uint32_t SS = S;
+        while (SS) {
+            const uint32_t kq = __ffs(SS) - 1;
+            SS &= SS - 1;
+            uint32_t tq = succ[kq] & tmask;
+            if (!tq) continue;
+            const uint64_t x = Mc[rowi<G>(p, src, kq) + j];
+            if (!x) continue;
+            while (tq) {
+                const uint32_t q2 = __ffs(tq) - 1;
+                tq &= tq - 1;
+                const uint64_t idx = rowi<G>(p, w, q2) + j;
+                const uint64_t c = x & ~p.P[idx];
+                if (c) {
+                    atomicOr(reinterpret_cast<unsigned long long *>(Mn + idx), static_cast<unsigned long long>(c));
+                    U.tb |= 1u << q2;
                 }
             }
         }
     }
 }
 
-template <int G>
-__device__ void st_push(const StackParams &p, uint32_t n, uint32_t *s_eb, uint32_t *s_beg, uint32_t *s_v,
-                        uint32_t *s_u) {
-    LevelRec *rec = p.rec;
-    const uint64_t sel = ld_acq(&rec[n % REC_RING].sel);
+// Scatter of one unit (QM <= 8): fire-and-forget ORs into the target's rows.
+template <int G, int QM>
+__device__ __forceinline__ void unit_scatter(const StackParams &p, uint32_t n, uint32_t j, UnitC<QM> &U) {
+    if constexpr (QM <= 8) {
+        uint64_t *Mn = p.M[(n + 1) & 1];
+#pragma unroll
+        for (int q2 = 0; q2 < QM; q2++) {
+            if (U.c[q2]) {
+                atomicOr(reinterpret_cast<unsigned long long *>(Mn + rowi<G>(p, U.dst, q2) + j),
+                         static_cast<unsigned long long>(U.c[q2]));
+                U.tb |= 1u << q2;
+            }
+        }
+    }
+}
+
+// The first writer of the target's candidate state set appends it to the
+// next queue. All 64 lanes of the wave call this.
+template <int G, int QM>
+__device__ __forceinline__ void unit_append(const StackParams &p, uint32_t n, uint32_t j, const UnitC<QM> &U) {
+    const uint32_t tg = group_or<G>(U.tb);
+    bool first = false;
+    if (tg && j == 0) first = atomicOr(&p.sup[(n + 1) & 1][U.dst], tg) == 0u;
+    if (!wave_append(first, static_cast<int32_t>(U.dst), p.q[(n + 1) & 1], &p.rec[(n + 1) % REC_RING].nq,
+                     static_cast<uint32_t>(p.V)))
+        sviol(p);
+}
+
+// Four units' appends with their sup atomics issued together and one queue
+// reservation per wave. All 64 lanes of the wave call this.
+template <int G, int QM>
+__device__ __forceinline__ void unit_append4(const StackParams &p, uint32_t n, uint32_t j, const UnitC<QM> &U0,
+                                             const UnitC<QM> &U1, const UnitC<QM> &U2, const UnitC<QM> &U3) {
+    uint32_t *sn = p.sup[(n + 1) & 1];
+    const uint32_t t0 = group_or<G>(U0.tb), t1 = group_or<G>(U1.tb);
+    const uint32_t t2 = group_or<G>(U2.tb), t3 = group_or<G>(U3.tb);
+    const bool lead = j == 0;
+    // a plain load first: on dense levels most targets already hold the
+    // states (values read during the phase only ever lack bits, never have
+    // extra ones), and a load costs far less than an atomic
+    uint32_t o0 = 1, o1 = 1, o2 = 1, o3 = 1;
+    if (t0 && lead) o0 = sn[U0.dst];
+    if (t1 && lead) o1 = sn[U1.dst];
+    if (t2 && lead) o2 = sn[U2.dst];
+    if (t3 && lead) o3 = sn[U3.dst];
+    if (t0 && lead && (o0 & t0) != t0) o0 = atomicOr(&sn[U0.dst], t0);
+    if (t1 && lead && (o1 & t1) != t1) o1 = atomicOr(&sn[U1.dst], t1);
+    if (t2 && lead && (o2 & t2) != t2) o2 = atomicOr(&sn[U2.dst], t2);
+    if (t3 && lead && (o3 & t3) != t3) o3 = atomicOr(&sn[U3.dst], t3);
+    if (!wave_append4(o0 == 0, static_cast<int32_t>(U0.dst), o1 == 0, static_cast<int32_t>(U1.dst), o2 == 0,
+                      static_cast<int32_t>(U2.dst), o3 == 0, static_cast<int32_t>(U3.dst), p.q[(n + 1) & 1],
+                      &p.rec[(n + 1) % REC_RING].nq, static_cast<uint32_t>(p.V)))
+        sviol(p);
+}
+
+// Edge-balanced pull of long rows: when every lane of the wave works on the
+// same target row, OR the candidate words of each source word j over the
+// wave and leave them in lanes 0..G-1, so a hub's row costs one atomic per
+// (state, word) and wave instead of one per edge.
+template <int G, int QM>
+__device__ __forceinline__ void wave_merge(UnitC<QM> &U) {
+    const uint32_t d0 = static_cast<uint32_t>(__shfl(static_cast<int>(U.dst), 0, 64));
+    if (__ballot(U.dst != d0) != 0) return;
+#pragma unroll
+    for (int q2 = 0; q2 < QM; q2++) {
+        uint64_t c = U.c[q2];
+#pragma unroll
+        for (int d = G; d < 64; d <<= 1) c |= __shfl_xor(c, d, 64);
+        U.c[q2] = lane_id() < static_cast<uint32_t>(G) ? c : 0ull;
+    }
+}
+
+// Units [ubase, uend) of the items staged in L (cnt of them): unit t*G + j is
+// source word j of the level's edge number t. Push: the item is (v, u) and the
+// edge leads to w; the frontier rows of v are ORed into w's candidate rows.
+// Pull (long rows): the item is (w, u) with the reverse neighbour v on the
+// edge; only states in sup[v] & L.s (predecessors of the wanted states) count.
+// Either way the candidate bits already in P are dropped before the atomic
+// OR, and the first writer of sup_next[w] appends w to the next queue. Four
+// units per thread are gathered before any is scattered (QM <= 8), so their
+// loads overlap.
+template <int G, int QM, bool PULL>
+__device__ __forceinline__ void expand_range(const StackParams &p, uint32_t n, const StLds &L, uint32_t cnt, uint64_t ubase,
+                             uint64_t uend, uint32_t ns) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t j = tid % G;
+    if constexpr (QM <= 8) {
+        static_assert(TILE == 4 * BLOCK, "four units per thread and step");
+        for (uint64_t ub = ubase; ub < uend; ub += TILE) {
+            UnitC<QM> U0, U1, U2, U3;
+            unit_gather<G, QM, PULL>(p, n, L, cnt, ub + tid, uend, ns, U0);
+            unit_gather<G, QM, PULL>(p, n, L, cnt, ub + BLOCK + tid, uend, ns, U1);
+            unit_gather<G, QM, PULL>(p, n, L, cnt, ub + 2 * BLOCK + tid, uend, ns, U2);
+            unit_gather<G, QM, PULL>(p, n, L, cnt, ub + 3 * BLOCK + tid, uend, ns, U3);
+            if constexpr (PULL) {
+                wave_merge<G, QM>(U0);
+                wave_merge<G, QM>(U1);
+                wave_merge<G, QM>(U2);
+                wave_merge<G, QM>(U3);
+            }
+            unit_scatter<G, QM>(p, n, j, U0);
+            unit_scatter<G, QM>(p, n, j, U1);
+            unit_scatter<G, QM>(p, n, j, U2);
+            unit_scatter<G, QM>(p, n, j, U3);
+            unit_append4<G, QM>(p, n, j, U0, U1, U2, U3);
+        }
+    } else {
+        for (uint64_t ub = ubase; ub < uend; ub += BLOCK) {
+            UnitC<QM> U0;
+            unit_gather<G, QM, PULL>(p, n, L, cnt, ub + tid, uend, ns, U0);
+            unit_append<G, QM>(p, n, j, U0);
+        }
+    }
+}
+
+// Items [0, nitems) with `T` edges (packed in sel) -> units spread over the grid.
+template <int G, int QM, bool PULL>
+__device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, StLds &L, uint64_t sel, uint32_t ns) {
     const uint32_t nitems = static_cast<uint32_t>(sel >> 32);
     const uint32_t T = static_cast<uint32_t>(sel);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        p.cnt[0] += nitems;
-        p.cnt[1] += T;
-        p.cnt[3] += ld_acq(&rec[n % REC_RING].nq);
-    }
     if (T == 0 || nitems == 0) return;
+    if (nitems > p.item_cap) {
+        if (gthread() == 0) sviol(p);
+        return;
+    }
+    const uint64_t units = static_cast<uint64_t>(T) * G;
+    const uint32_t tid = threadIdx.x;
+    if (nitems <= TILE) {
+        // few items: every workgroup stages all of them and takes an even,
+        // wave-aligned share of the units, so small levels use the whole chip
+        for (uint32_t x = tid; x < nitems; x += BLOCK) {
+            L.eb[x] = p.it_ebase[x];
+            L.beg[x] = p.it_beg[x];
+            L.v[x] = p.it_v[x];
+            L.u[x] = p.it_u[x];
+            L.s[x] = p.it_s[x];
+        }
+        __syncthreads();
+        uint64_t per = (units + gridDim.x - 1) / gridDim.x;
+        per = (per + 63) & ~63ull;
+        const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * per;
+        const uint64_t b1 = b0 + per < units ? b0 + per : units;
+        if (b0 < b1) expand_range<G, QM, PULL>(p, n, L, nitems, b0, b1, ns);
+        __syncthreads();
+        return;
+    }
     constexpr uint32_t TE = TILE / G;
     const uint32_t ntiles = (T + TE - 1) / TE;
-    const uint32_t V = static_cast<uint32_t>(p.V);
-    const QueryView &qv = p.qv;
-    const uint64_t *Mc = p.M[n & 1];
-    uint64_t *Mn = p.M[(n + 1) & 1];
-    const uint32_t *sc = p.sup[n & 1];
-    uint32_t *sn = p.sup[(n + 1) & 1];
-    int32_t *qn = p.q[(n + 1) & 1];
-    LevelRec &RN = rec[(n + 1) % REC_RING];
-    const uint32_t tid = threadIdx.x;
-    uint64_t pairs = 0, updates = 0;
-    uint32_t su = 0;
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         uint32_t i0 = tile < p.tile_cap ? p.tile_first[tile] : 0u;
         uint32_t i1 = (tile + 1 < ntiles && tile + 1 < p.tile_cap) ? p.tile_first[tile + 1] : nitems - 1;
@@ -164,109 +520,193 @@ __device__ void st_push(const StackParams &p, uint32_t n, uint32_t *s_eb, uint32
             i0 = i1 = 0;
         }
         const uint32_t cnt = i1 - i0 + 1;
-        for (uint32_t j = tid; j < cnt; j += BLOCK) {
-            s_eb[j] = p.it_ebase[i0 + j];
-            s_beg[j] = p.it_beg[i0 + j];
-            s_v[j] = p.it_v[i0 + j];
-            s_u[j] = p.it_u[i0 + j];
+        for (uint32_t x = tid; x < cnt; x += BLOCK) {
+            L.eb[x] = p.it_ebase[i0 + x];
+            L.beg[x] = p.it_beg[i0 + x];
+            L.v[x] = p.it_v[i0 + x];
+            L.u[x] = p.it_u[i0 + x];
+            L.s[x] = p.it_s[i0 + x];
         }
         __syncthreads();
-        const uint32_t t0 = tile * TE;
+        const uint64_t u0 = static_cast<uint64_t>(tile) * TILE;
+        const uint64_t u1 = u0 + TILE < units ? u0 + TILE : units;
+        expand_range<G, QM, PULL>(p, n, L, cnt, u0, u1, ns);
+        __syncthreads();
+    }
+}
+
+// Dense levels (at most 8 states), row by row: for every used symbol u that
+// leads into the states `ns` the level can produce, every row of u's pull
+// direction (a vertex w with reverse u-neighbours; rows are stored in vertex
+// order with their vertex ids, so no lookup is needed) whose target states
+// still miss source bits gathers the frontier rows of its neighbours (4 in
+// flight) and stops as soon as every missing bit is found. One atomic OR per
+// (row, target state, word) carries the result. Rows longer than
+// PULL_LIGHT_ROW become items of the edge-balanced pass.
+template <int G>
+__device__ __forceinline__ void st_pull_rows(const StackParams &p, uint32_t n, uint32_t ns) {
+    const GraphView &g = p.g;
+    const QueryView &qv = p.qv;
+    const uint32_t V = static_cast<uint32_t>(p.V);
+    const uint32_t nsym = qv.h->nsym;
+    const uint32_t lane = lane_id();
+    const uint32_t j = lane % G;
+    const uint32_t grp = lane / G;
+    constexpr uint32_t GPW = 64 / G;
+    const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
+    const uint64_t full = word_full(p.B, j);
+    const uint64_t *Mc = p.M[n & 1];
+    uint64_t *Mn = p.M[(n + 1) & 1];
+    const uint32_t *sc = p.sup[n & 1];
+    uint32_t *sn = p.sup[(n + 1) & 1];
+    int32_t *qn = p.q[(n + 1) & 1];
+    LevelRec &R = p.rec[n % REC_RING];
+    LevelRec &RN = p.rec[(n + 1) % REC_RING];
+    for (uint32_t u = 0; u < nsym; u++) {
+        const uint32_t *pred = qv.pred + u * MAX_STATES;
+        const uint32_t *succ = qv.succ + u * MAX_STATES;
+        // states that reach `ns` over u, and the states they reach
+        uint32_t pu = 0, x = ns;
+        while (x) {
+            pu |= pred[__ffs(x) - 1];
+            x &= x - 1;
+        }
+        uint32_t tu = 0;
+        x = pu;
+        while (x) {
+            tu |= succ[__ffs(x) - 1];
+            x &= x - 1;
+        }
+        tu &= ns;
+        if (!pu || !tu) continue;
+        const uint64_t rb = qv.pull_r[u];
+        const uint32_t rows = qv.pull_n[u];
+        for (uint32_t base = gw * GPW; base < rows; base += nw * GPW) {
+            const uint32_t r = base + grp;
+            uint32_t w = V, beg = 0, end = 0;
+            if (r < rows) {
+                w = g.rowvert[rb + r];
+                beg = g.rowptr[rb + r];
+                end = g.rowptr[rb + r + 1];
+                if (w >= V || end > g.ncol || end < beg) {
+                    if (j == 0) sviol(p);
+                    w = V;
+                }
+            }
+            uint64_t prow[8], acc[8];
+            uint64_t need = 0;
 #pragma unroll
-        for (int k = 0; k < TILE / BLOCK; k++) {
-            const uint32_t unit = k * BLOCK + tid;
-            const uint32_t t = t0 + unit / G;
-            const uint32_t j = unit % G;
-            uint32_t w = V, sbits = 0;
-            if (t < T) {
-                uint32_t lo = 0, hi = cnt;
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (s_eb[mid] <= t) lo = mid;
-                    else hi = mid;
+            for (int k = 0; k < 8; k++) {
+                prow[k] = 0;
+                acc[k] = 0;
+                if (w < V && ((tu >> k) & 1u)) {
+                    prow[k] = p.P[rowi<G>(p, w, k) + j];
+                    need |= full & ~prow[k];
                 }
-                const uint32_t pos = s_beg[lo] + (t - s_eb[lo]);
-                const uint32_t v = s_v[lo], u = s_u[lo];
-                if (pos < p.g.ncol && v < V && u < qv.h->nsym) {
-                    w = p.g.col[pos];
-                    if (w >= V) sviol(p);
+            }
+            need = group_or64<G>(need);
+            uint32_t tb = 0;
+            if (need) {
+                if (end - beg > PULL_LIGHT_ROW) {
+                    if (j == 0) {
+                        const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long *>(&R.hsel),
+                                                       (1ull << 32) | static_cast<unsigned long long>(end - beg));
+                        put_item<G>(p, static_cast<uint32_t>(old >> 32), static_cast<uint32_t>(old), beg, end - beg, w,
+                                    u, pu);
+                    }
                 } else {
-                    sviol(p);
-                }
-                if (w < V) {
-                    const uint32_t *succ = qv.succ + u * MAX_STATES;
-                    uint32_t S = sc[v];
-                    while (S) {
-                        const uint32_t q = __ffs(S) - 1;
-                        S &= S - 1;
-                        uint32_t tq = succ[q];
-                        if (!tq) continue;
-                        const uint64_t x = Mc[row_index<G>(p, v, q) + j];
-                        if (!x) continue;
-                        while (tq) {
-                            const uint32_t q2 = __ffs(tq) - 1;
-                            tq &= tq - 1;
-                            updates++;
-                            const uint64_t idx = row_index<G>(p, w, q2) + j;
-                            const uint64_t cand = x & ~p.P[idx];
-                            if (!cand) continue;
-                            const uint64_t nb =
-                                cand & ~atomicOr(reinterpret_cast<unsigned long long *>(p.P + idx),
-                                                 static_cast<unsigned long long>(cand));
-                            if (!nb) continue;
-                            atomicOr(reinterpret_cast<unsigned long long *>(Mn + idx), static_cast<unsigned long long>(nb));
-                            sbits |= 1u << q2;
-                            pairs += __popcll(nb);
+                    for (uint32_t e0 = beg; e0 < end && need; e0 += 4) {
+                        uint32_t vv[4], sv[4];
+#pragma unroll
+                        for (int a = 0; a < 4; a++) vv[a] = e0 + a < end ? g.col[e0 + a] : V;
+#pragma unroll
+                        for (int a = 0; a < 4; a++) sv[a] = vv[a] < V ? (sc[vv[a]] & pu) : 0u;  // pu: states only
+#pragma unroll
+                        for (int a = 0; a < 4; a++) {
+#pragma unroll
+                            for (int kq = 0; kq < 8; kq++) {
+                                if ((sv[a] >> kq) & 1u) {
+                                    const uint64_t xw = Mc[rowi<G>(p, vv[a], kq) + j];
+                                    const uint32_t tq = succ[kq] & tu;
+#pragma unroll
+                                    for (int k2 = 0; k2 < 8; k2++)
+                                        if ((tq >> k2) & 1u) acc[k2] |= xw;
+                                }
+                            }
+                        }
+                        uint64_t rem = 0;
+#pragma unroll
+                        for (int k = 0; k < 8; k++)
+                            if ((tu >> k) & 1u) rem |= full & ~(prow[k] | acc[k]);
+                        need = group_or64<G>(rem);
+                    }
+#pragma unroll
+                    for (int k = 0; k < 8; k++) {
+                        const uint64_t m = acc[k] & ~prow[k];
+                        if (m) {
+                            atomicOr(reinterpret_cast<unsigned long long *>(Mn + rowi<G>(p, w, k) + j),
+                                     static_cast<unsigned long long>(m));
+                            tb |= 1u << k;
                         }
                     }
                 }
             }
+            tb = group_or<G>(tb);
             bool first = false;
-            if (sbits) first = atomicOr(&sn[w], sbits) == 0;
+            if (tb && j == 0) first = atomicOr(&sn[w], tb) == 0u;
             if (!wave_append(first, static_cast<int32_t>(w), qn, &RN.nq, V)) sviol(p);
-            su |= sbits;
         }
-        __syncthreads();
     }
-    pairs = wave_sum(pairs);
-    updates = wave_sum(updates);
-    su = wave_or(su);
-    if (lane_id() == 0 && pairs) {
-        atomicAdd(reinterpret_cast<unsigned long long *>(&RN.pairs), (unsigned long long)pairs);
-        atomicOr(&RN.su, su);
-    }
-    if (lane_id() == 0 && updates)
-        atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[2]), (unsigned long long)updates);
 }
 
+// ------------------------------------------------------------- direction
+// push (0) or pull (1) for level n; every workgroup computes the same answer
+template <int QM>
+__device__ __forceinline__ uint32_t st_decide(const StackParams &p, uint32_t n, uint32_t prev) {
+    const QHeader &h = *p.qv.h;
+    if (QM > 8 || h.force == 1) return 0;
+    if (h.force == 2) return 1;
+    if (!(h.alpha > 0.f)) return 0;
+    const LevelRec &R = p.rec[n % REC_RING];
+    const uint64_t T = ld_acq(&R.sel) & 0xffffffffull;
+    if (prev == 0) return static_cast<double>(T) * h.alpha > static_cast<double>(h.e_rel) ? 1u : 0u;
+    const uint32_t nf = ld_acq(&R.nfront);
+    return static_cast<double>(nf) * h.beta < static_cast<double>(p.V) ? 0u : 1u;
+}
+
+// --------------------------------------------------------------- extract
 // Result: source b reaches v iff some final state's row at v has bit b. One
 // wavefront per (64-vertex block, word): 64 ballots transpose the block into
 // one output word per source. P and the last frontier are reset.
 template <int G>
-__device__ void st_final(const StackParams &p, uint32_t nlev) {
+__device__ __forceinline__ void st_final(const StackParams &p, uint32_t nexit, uint32_t levels) {
     const uint32_t V = static_cast<uint32_t>(p.V);
     const uint32_t Q = static_cast<uint32_t>(p.Q);
-    if (nlev >= 1) {
-        const uint32_t D = nlev - 1;
-        const uint32_t nq = ld_acq(&p.rec[D % REC_RING].nq);
-        uint64_t *M = p.M[D & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && levels < LVL_COUNT_CAP)
+        p.lvl[static_cast<uint64_t>(levels) * LVL_STRIDE + 3] = wall_clock64();
+    const uint32_t lane = lane_id();
+    // the last frontier's state sets, then both row buffers (rows keep
+    // visited bits between levels; see the select phase)
+    if (nexit >= 1) {
+        const uint32_t D = nexit - 1;
+        const uint32_t nq = queue_len(p, p.rec[D % REC_RING]);
         uint32_t *sp = p.sup[D & 1];
         const int32_t *q = p.q[D & 1];
-        const uint64_t words = static_cast<uint64_t>(Q) * G;
-        const uint64_t total = static_cast<uint64_t>(nq) * words;
-        for (uint64_t x = gthread(); x < total; x += gthreads()) {
-            const uint32_t v = static_cast<uint32_t>(q[x / words]);
-            const uint32_t k = static_cast<uint32_t>(x % words);
-            if (v >= V) {
-                sviol(p);
-                continue;
-            }
-            M[static_cast<uint64_t>(v) * words + k] = 0;
-            if (k == 0) sp[v] = 0;
+        for (uint32_t i = gthread(); i < nq; i += gthreads()) {
+            const uint32_t v = static_cast<uint32_t>(q[i]);
+            if (v < V) sp[v] = 0;
+            else sviol(p);
+        }
+    }
+    {
+        const uint64_t words = static_cast<uint64_t>(V) * Q * G;  // both buffers hold words + 64 entries
+        for (int b = 0; b < 2; b++) {
+            uint4 *m4 = reinterpret_cast<uint4 *>(p.M[b]);
+            for (uint64_t i = gthread(); i < words / 2; i += gthreads()) m4[i] = make_uint4(0, 0, 0, 0);
+            if (gthread() == 0 && (words & 1)) p.M[b][words - 1] = 0;
         }
     }
     const uint32_t fm = p.qv.h->fmask;
-    const uint32_t lane = lane_id();
     const uint64_t nwords = static_cast<uint64_t>(p.nwords);
     const uint64_t total = nwords * G;
     const uint32_t B = static_cast<uint32_t>(p.B);
@@ -277,7 +717,7 @@ __device__ void st_final(const StackParams &p, uint32_t nlev) {
         uint64_t f = 0;
         if (v < V) {
             for (uint32_t q = 0; q < Q; q++) {
-                const uint64_t idx = row_index<G>(p, static_cast<uint32_t>(v), q) + j;
+                const uint64_t idx = rowi<G>(p, static_cast<uint32_t>(v), q) + j;
                 const uint64_t x = p.P[idx];
                 if (x) {
                     if (fm >> q & 1u) f |= x;
@@ -293,9 +733,10 @@ __device__ void st_final(const StackParams &p, uint32_t nlev) {
     }
 }
 
-template <int G>
+// ----------------------------------------------------------------- kernel
+template <int G, int QM>
 __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
-    __shared__ uint32_t s_eb[TILE + 1], s_beg[TILE + 1], s_v[TILE + 1], s_u[TILE + 1];
+    __shared__ StLds L;
     GridBarrier *bar = p.bar;
     BarCtx bc;
     if (!barrier_register(bar, bc)) return;
@@ -305,77 +746,127 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
         for (int i = 0; i < 4; i++) p.cnt[i] = 0;
     }
     if (!grid_barrier(bar, bc)) return;
-    // start pairs: every source's bit in every start state's row
+    // start pairs M_0 = Q_S x {source}: every source's bit in its start rows,
+    // as candidates that level 0's select adds to P
     const QHeader &h = *p.qv.h;
     const uint32_t V = static_cast<uint32_t>(p.V);
     for (uint32_t i = gthread(); i < static_cast<uint32_t>(p.B); i += gthreads()) {
         const uint32_t s = static_cast<uint32_t>(p.sources[i]);
-        if (s >= V || !h.smask) {
-            if (s >= V) sviol(p);
+        if (s >= V) {
+            sviol(p);
             continue;
         }
+        if (!h.smask) continue;
         const uint64_t bit = 1ull << (i & 63);
         uint32_t sm = h.smask;
         while (sm) {
             const uint32_t q = __ffs(sm) - 1;
             sm &= sm - 1;
-            const uint64_t idx = row_index<G>(p, s, q) + (i >> 6);
-            atomicOr(reinterpret_cast<unsigned long long *>(p.P + idx), static_cast<unsigned long long>(bit));
-            atomicOr(reinterpret_cast<unsigned long long *>(p.M[0] + idx), static_cast<unsigned long long>(bit));
+            atomicOr(reinterpret_cast<unsigned long long *>(p.M[0] + rowi<G>(p, s, q) + (i >> 6)),
+                     static_cast<unsigned long long>(bit));
         }
         if (atomicOr(&p.sup[0][s], h.smask) == 0) {
             const uint32_t pos = atomicAdd(&p.rec[0].nq, 1u);
             if (pos < V) p.q[0][pos] = static_cast<int32_t>(s);
             else sviol(p);
         }
-        atomicAdd(reinterpret_cast<unsigned long long *>(&p.rec[0].pairs),
-                  static_cast<unsigned long long>(__popc(h.smask)));
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) p.rec[0].su = h.smask;
     if (!grid_barrier(bar, bc)) return;
-    uint32_t n = 0;
+    uint32_t n = 0, npush = 0, npull = 0, prev = 0;
+    uint64_t last_pairs = 0;
     while (true) {
         if (ld_acq(&p.rec[n % REC_RING].nq) == 0) break;
-        st_select<G>(p, n);
+        st_select<G, QM>(p, n);
         if (!grid_barrier(bar, bc)) return;
-        st_push<G>(p, n, s_eb, s_beg, s_v, s_u);
-        if (!grid_barrier(bar, bc)) return;
+        LevelRec &R = p.rec[n % REC_RING];
+        last_pairs = ld_acq(&R.pairs);
+        const uint32_t mode = st_decide<QM>(p, n, prev);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            R.mode = mode;
+            if (n < LVL_COUNT_CAP) {
+                uint64_t *Lv = p.lvl + static_cast<uint64_t>(n) * LVL_STRIDE;
+                Lv[0] = last_pairs;
+                Lv[1] = ld_acq(&R.nfront);
+                Lv[2] = ld_acq(&R.sel);
+                Lv[4] = wall_clock64();
+            }
+        }
+        if (mode == 0) {
+            expand_items<G, QM, false>(p, n, L, ld_acq(&R.sel), ~0u);
+            if (!grid_barrier(bar, bc)) return;
+            npush++;
+        } else {
+            if constexpr (QM <= 8) {
+                // states the level can produce: successors of the frontier's states
+                uint32_t su = ld_acq(&R.su), ns = 0;
+                while (su) {
+                    ns |= h.succ_any[__ffs(su) - 1];
+                    su &= su - 1;
+                }
+                ns &= h.inmask;
+                st_pull_rows<G>(p, n, ns);
+                if (!grid_barrier(bar, bc)) return;
+                const uint64_t hsel = ld_acq(&R.hsel);
+                if (hsel) {
+                    expand_items<G, 8, true>(p, n, L, hsel, ns);
+                    if (!grid_barrier(bar, bc)) return;
+                }
+            }
+            npull++;
+        }
+        prev = mode;
         n++;
     }
-    st_final<G>(p, n);
-    if (blockIdx.x == 0 && threadIdx.x == 0) p.status[0] = n;
+    // the last level may have found only visited pairs
+    const uint32_t levels = (n > 0 && last_pairs == 0) ? n - 1 : n;
+    st_final<G>(p, n, levels);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        p.status[0] = levels;
+        p.status[1] = npush;
+        p.status[2] = npull;
+    }
 }
 
-template <int G>
+template <int G, int QM>
 static hipError_t launch_g(const StackParams &p, int grid, hipStream_t s) {
     StackParams a = p;
     void *args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_stacked<G>), dim3(grid), dim3(BLOCK), args,
-                                      0, s);
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_stacked<G, QM>), dim3(grid), dim3(BLOCK),
+                                      args, 0, s);
 }
 
-hipError_t launch_stacked(int G, const StackParams &p, int grid, hipStream_t s) {
-    switch (G) {
-        case 1: return launch_g<1>(p, grid, s);
-        case 2: return launch_g<2>(p, grid, s);
-        case 4: return launch_g<4>(p, grid, s);
-        case 8: return launch_g<8>(p, grid, s);
-        default: return launch_g<16>(p, grid, s);
+#define RPQ_STACKED_DISPATCH(G, QM, CALL8, CALL32)             \
+    if ((QM) <= 8) {                                           \
+        switch (G) {                                           \
+            case 1: { constexpr int GG = 1; CALL8; } break;    \
+            case 2: { constexpr int GG = 2; CALL8; } break;    \
+            case 4: { constexpr int GG = 4; CALL8; } break;    \
+            case 8: { constexpr int GG = 8; CALL8; } break;    \
+            default: { constexpr int GG = 16; CALL8; } break;  \
+        }                                                      \
+    } else {                                                   \
+        switch (G) {                                           \
+            case 1: { constexpr int GG = 1; CALL32; } break;   \
+            case 2: { constexpr int GG = 2; CALL32; } break;   \
+            case 4: { constexpr int GG = 4; CALL32; } break;   \
+            case 8: { constexpr int GG = 8; CALL32; } break;   \
+            default: { constexpr int GG = 16; CALL32; } break; \
+        }                                                      \
     }
+
+hipError_t launch_stacked(int G, int QM, const StackParams &p, int grid, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    RPQ_STACKED_DISPATCH(G, QM, (e = launch_g<GG, 8>(p, grid, s)), (e = launch_g<GG, 32>(p, grid, s)));
+    return e;
 }
 
-int stacked_grid(int G) {
+int stacked_grid(int G, int QM) {
     int dev = 0, ncu = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    hipError_t e;
-    switch (G) {
-        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stacked<1>, BLOCK, 0); break;
-        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stacked<2>, BLOCK, 0); break;
-        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stacked<4>, BLOCK, 0); break;
-        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stacked<8>, BLOCK, 0); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stacked<16>, BLOCK, 0); break;
-    }
+    hipError_t e = hipSuccess;
+    RPQ_STACKED_DISPATCH(G, QM, (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stacked<GG, 8>, BLOCK, 0)),
+                         (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stacked<GG, 32>, BLOCK, 0)));
     if (e != hipSuccess || per < 1) return 0;
     return ncu * (per < PERSISTENT_BLOCKS_PER_CU ? per : PERSISTENT_BLOCKS_PER_CU);
 }

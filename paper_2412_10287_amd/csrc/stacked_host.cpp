@@ -21,7 +21,7 @@ struct BatchState {
     int64_t out_words = 0;
     int32_t *sources = nullptr;  // device copy of one batch's sources (MAX_BATCH entries)
     uint8_t *pinned = nullptr;
-    int grid[17] = {0};
+    int grid[2][17] = {{0}};  // [QM == 32][G]
 };
 
 }  // namespace rpq
@@ -76,7 +76,7 @@ static rpq_status batch_prepare(rpq_graph *g, int32_t Q, int G, int32_t B, hipSt
             return st;
     }
     p.item_cap = static_cast<uint64_t>(g->rows[OUT] + g->rows[IN]) + 1;
-    for (uint32_t **a : {&p.it_ebase, &p.it_beg, &p.it_v, &p.it_u})
+    for (uint32_t **a : {&p.it_ebase, &p.it_beg, &p.it_v, &p.it_u, &p.it_s})
         if ((st = balloc(b, reinterpret_cast<void **>(a), 4 * p.item_cap, "items")) != RPQ_OK) return st;
     p.tile_cap = (2 * static_cast<uint64_t>(g->E)) / (TILE / 16) + 2;
     if ((st = balloc(b, reinterpret_cast<void **>(&p.tile_first), 4 * p.tile_cap, "tiles")) != RPQ_OK) return st;
@@ -84,7 +84,8 @@ static rpq_status batch_prepare(rpq_graph *g, int32_t Q, int G, int32_t B, hipSt
     if ((st = balloc(b, reinterpret_cast<void **>(&p.bar), sizeof(GridBarrier), "barrier")) != RPQ_OK) return st;
     if ((st = balloc(b, reinterpret_cast<void **>(&p.status), 64, "status")) != RPQ_OK) return st;
     if ((st = balloc(b, reinterpret_cast<void **>(&p.cnt), 64, "counters")) != RPQ_OK) return st;
-    if ((st = balloc(b, reinterpret_cast<void **>(&p.lvl_pairs), 8 * LVL_COUNT_CAP, "lvl")) != RPQ_OK) return st;
+    if ((st = balloc(b, reinterpret_cast<void **>(&p.lvl), 8 * LVL_STRIDE * (LVL_COUNT_CAP + 1), "lvl")) != RPQ_OK)
+        return st;
     if ((st = balloc(b, reinterpret_cast<void **>(&b->sources), 4 * static_cast<size_t>(MAX_BATCH), "sources")) !=
         RPQ_OK)
         return st;
@@ -97,7 +98,10 @@ static rpq_status batch_prepare(rpq_graph *g, int32_t Q, int G, int32_t B, hipSt
                      hipHostMallocDefault));
     for (uint64_t *a : {p.P, p.M[0], p.M[1]}) BT(launch_fill(reinterpret_cast<uint32_t *>(a), 2 * words, 0, s));
     for (int k = 0; k < 2; k++) BT(launch_fill(p.sup[k], static_cast<uint64_t>(g->V) + 16, 0, s));
-    for (int G2 : {1, 2, 4, 8, 16}) b->grid[G2] = stacked_grid(G2);
+    for (int G2 : {1, 2, 4, 8, 16}) {
+        b->grid[0][G2] = stacked_grid(G2, 8);
+        b->grid[1][G2] = stacked_grid(G2, 32);
+    }
     BT(hipStreamSynchronize(s));
     return RPQ_OK;
 }
@@ -115,12 +119,27 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
     const int32_t maxb = std::min<int32_t>(g->max_batch, 1024);
     std::vector<uint8_t> qbuf;
     int32_t nsym = 0;
-    const size_t qsz = build_qconst(g, n, 1u, 0u, qbuf, &nsym);
+    if ((flags & RPQ_FORCE_PUSH) && (flags & RPQ_FORCE_PULL))
+        return fail(RPQ_EINVAL, "rpq_multi_source: RPQ_FORCE_PUSH and RPQ_FORCE_PULL together");
+    const uint32_t force = (flags & RPQ_FORCE_PUSH) ? 1u : (flags & RPQ_FORCE_PULL) ? 2u : 0u;
+    const size_t qsz = build_qconst(g, n, force, 0u, qbuf, &nsym);
     if (nsym > MAX_SYMS || qsz > g->qconst_cap)
         return fail(RPQ_EINVAL, "rpq_multi_source: query uses %d symbols; the limit is %d", nsym, MAX_SYMS);
+    {
+        // the stacked path has its own direction thresholds
+        QHeader *h = reinterpret_cast<QHeader *>(qbuf.data());
+        h->alpha = static_cast<float>(g->stack_alpha);
+        h->beta = static_cast<float>(g->stack_beta);
+    }
+    // automata with at most 8 states use the kernel with byte-sized state sets
+    // (which also has the pull direction)
+    const int QM = n->Q <= 8 ? 8 : 32;
+    int32_t push_levels = 0, pull_levels = 0;
     int32_t levels = 0;
     int64_t pairs = 0, items = 0, edges = 0, updates = 0, active = 0, bytes = 0;
     float total_ms = 0.f;
+    std::vector<uint64_t> lvl_host;
+    uint32_t lvl_nrec = 0, lvl_levels = 0;
     for (int32_t b0 = 0; b0 < n_sources; b0 += maxb) {
         const int32_t B = std::min(maxb, n_sources - b0);
         int G = 1;
@@ -142,11 +161,12 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         p.V = g->V;
         p.nwords = g->nwords;
         p.out = (flags & RPQ_OUT_DEVICE) ? out_bitmaps + static_cast<size_t>(b0) * g->nwords : bs->out;
-        const int grid = g->grid_override ? std::min(g->grid_override, bs->grid[G]) : bs->grid[G];
+        const int full = bs->grid[QM == 8 ? 0 : 1][G];
+        const int grid = g->grid_override ? std::min(g->grid_override, full) : full;
         if (grid <= 0) return fail(RPQ_EDEVICE, "rpq_multi_source: no co-resident grid for the stacked kernel");
         BT(launch_fill(reinterpret_cast<uint32_t *>(p.bar), sizeof(GridBarrier) / 4, 0, s));
         BT(hipEventRecord(g->ev[2], s));
-        BT(launch_stacked(G, p, grid, s));
+        BT(launch_stacked(G, QM, p, grid, s));
         BT(hipEventRecord(g->ev[3], s));
         uint32_t *hst = reinterpret_cast<uint32_t *>(bs->pinned + bs->qconst_cap + 4 * 1024);
         uint64_t *hcnt = reinterpret_cast<uint64_t *>(bs->pinned + bs->qconst_cap + 4 * 1024 + 64);
@@ -169,10 +189,14 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         BT(hipEventElapsedTime(&ms, g->ev[2], g->ev[3]));
         total_ms += ms;
         levels = std::max<int32_t>(levels, static_cast<int32_t>(hst[0]));
-        const uint32_t nl = std::min<uint32_t>(hst[0], LVL_COUNT_CAP);
-        std::vector<int64_t> lp(nl);
-        if (nl) BT(hipMemcpy(lp.data(), p.lvl_pairs, 8 * nl, hipMemcpyDeviceToHost));
-        for (int64_t x : lp) pairs += x;
+        push_levels += static_cast<int32_t>(hst[1]);
+        pull_levels += static_cast<int32_t>(hst[2]);
+        const uint32_t nrec = std::min<uint32_t>(hst[0] + 1, LVL_COUNT_CAP);
+        lvl_host.assign(static_cast<size_t>(nrec) * LVL_STRIDE, 0);
+        BT(hipMemcpy(lvl_host.data(), p.lvl, 8 * lvl_host.size(), hipMemcpyDeviceToHost));
+        lvl_nrec = nrec;
+        lvl_levels = hst[0];
+        pairs += stats_levels(nullptr, lvl_host.data(), nrec, hst[0]);
         // algorithmic bytes of the stacked traversal: 8 B of row pointers per
         // item, 4 B per scanned edge, a read and a write of one 8-byte source
         // word per (edge, transition, word) with a non-empty source word, the
@@ -187,13 +211,11 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
                  static_cast<int64_t>(B) * ((static_cast<int64_t>(g->V) + 7) / 8);
     }
     if (stats) {
-        int64_t *lc = stats->level_counts;
-        const int32_t cap = stats->level_cap;
-        *stats = rpq_stats{};
-        stats->level_counts = lc;
-        stats->level_cap = cap;
+        stats_reset(stats);
+        stats_levels(stats, lvl_host.data(), lvl_nrec, lvl_levels);
         stats->levels = levels;
-        stats->push_levels = levels;
+        stats->push_levels = push_levels;
+        stats->pull_levels = pull_levels;
         stats->visited_pairs = pairs;
         stats->batch = std::min(n_sources, maxb);
         stats->device_ms = total_ms;

@@ -51,7 +51,13 @@ class rpq_stats(ctypes.Structure):
         ("expand_ms", ctypes.c_double),
         ("expand_launches", ctypes.c_int32),
         ("batch", ctypes.c_int32),
+        ("level_us", ctypes.POINTER(ctypes.c_double)),
+        ("level_frontier", ctypes.POINTER(ctypes.c_int64)),
+        ("level_edges", ctypes.POINTER(ctypes.c_int64)),
+        ("level_select_us", ctypes.POINTER(ctypes.c_double)),
     ]
+
+_LEVEL_FIELDS = ("level_counts", "level_cap", "level_us", "level_frontier", "level_edges", "level_select_us")
 
 
 class RPQError(RuntimeError):
@@ -176,24 +182,38 @@ class Stats:
     expand_launches: int = 0
     batch: int = 0
     level_counts: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
+    level_us: np.ndarray = field(default_factory=lambda: np.zeros(0, np.float64))
+    level_frontier: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
+    level_edges: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
+    level_select_us: np.ndarray = field(default_factory=lambda: np.zeros(0, np.float64))
 
     @classmethod
-    def from_c(cls, s: rpq_stats, lc: Optional[np.ndarray]):
-        out = cls(**{k: getattr(s, k) for k, _ in rpq_stats._fields_
-                     if k not in ("level_counts", "level_cap")})
-        if lc is not None:
-            out.level_counts = lc[:min(lc.size, max(s.levels, 0))].copy()
+    def from_c(cls, s: rpq_stats, lv: Optional[dict]):
+        out = cls(**{k: getattr(s, k) for k, _ in rpq_stats._fields_ if k not in _LEVEL_FIELDS})
+        if lv is not None:
+            n = max(s.levels, 0)
+            for k, a in lv.items():
+                setattr(out, k, a[:min(a.size, n)].copy())
         return out
 
 
 def _stats_struct(level_cap: int):
+    """An rpq_stats with per-level output buffers of level_cap entries."""
     st = rpq_stats()
-    lc = None
+    lv = None
     if level_cap > 0:
-        lc = np.zeros(level_cap, dtype=np.int64)
-        st.level_counts = lc.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        lv = {"level_counts": np.zeros(level_cap, dtype=np.int64),
+              "level_us": np.zeros(level_cap, dtype=np.float64),
+              "level_frontier": np.zeros(level_cap, dtype=np.int64),
+              "level_edges": np.zeros(level_cap, dtype=np.int64),
+              "level_select_us": np.zeros(level_cap, dtype=np.float64)}
+        st.level_counts = lv["level_counts"].ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        st.level_us = lv["level_us"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        st.level_frontier = lv["level_frontier"].ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        st.level_edges = lv["level_edges"].ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        st.level_select_us = lv["level_select_us"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         st.level_cap = level_cap
-    return st, lc
+    return st, lv
 
 
 class NFA:

@@ -1,7 +1,8 @@
 """GPU parity of the stacked multi-source path (rpq_multi_source): each
 source's bitmap equals the oracle's, for batch sizes that use 1, 2, 4, 8 and 16
-64-bit words per state row, with repeated sources and NFAs of 1..32 states;
-the summed frontier sizes equal the oracle's summed |M_n|."""
+64-bit words per state row, with repeated sources and NFAs of 1..32 states, in
+the push direction, the pull direction and with the automatic switch; the
+per-level frontier sizes summed over sources equal the oracle's |M_n| sums."""
 import numpy as np
 import pytest
 
@@ -20,16 +21,28 @@ def rpq():
     return mod
 
 
-def _check(rpq, gg, og, nfa, srcs):
-    bms, st = gg.multi_source(rpq.NFA(nfa), srcs)
+# direction modes of the stacked kernel: automatic switch, push only, pull
+# from level 0 (pull needs at most 8 states; wider automata always push)
+STACK_MODES = {"auto": 0, "push": 8, "pull": 16}
+
+
+def _check(rpq, gg, og, nfa, srcs, flags=0):
+    """Every source's bitmap equals the oracle's; the level count, |P| and the
+    per-level |M_n| (summed over sources) too, when one launch holds the batch."""
+    bms, st = gg.multi_source(rpq.NFA(nfa), srcs, flags=flags, level_cap=4096)
     lv, pairs = 0, 0
+    lc = np.zeros(4096, np.int64)
     for i, s in enumerate(srcs):
         r = og.ssr(nfa, int(s))
-        assert np.array_equal(bms[i], r.bitmap), (nfa.text, i, int(s))
+        assert np.array_equal(bms[i], r.bitmap), (nfa.text, i, int(s), flags)
         lv = max(lv, r.levels)
         pairs += int(r.level_counts.sum())
-    assert st.levels == lv
-    assert st.visited_pairs == pairs
+        lc[:len(r.level_counts)] += r.level_counts
+    assert st.levels == lv, (nfa.text, flags)
+    assert st.visited_pairs == pairs, (nfa.text, flags)
+    if len(srcs) <= gg.get_option("max_batch"):
+        assert np.array_equal(st.level_counts, lc[:lv]), (nfa.text, flags)
+    return st
 
 
 @pytest.mark.parametrize("B", [1, 5, 64, 65, 130, 256, 513, 1000])
@@ -42,7 +55,48 @@ def test_batch_sizes(rpq, B):
     if B > 3:
         srcs[1] = srcs[2]
     gg.set_option("max_batch", 1024)
-    _check(rpq, gg, og, R.compile_regex("(0|^1)* 2 3*", 6), srcs)
+    for name, fl in STACK_MODES.items():
+        print("B", B, "mode", name, flush=True)
+        _check(rpq, gg, og, R.compile_regex("(0|^1)* 2 3*", 6), srcs, fl)
+
+
+def test_direction_thresholds(rpq):
+    # the automatic switch at several thresholds, including pull at almost
+    # every level (alpha large, beta 1) and a switch back to push
+    g = G.rmat(13, 8, 4, 1.1, 5)
+    gg = rpq.Graph(g)
+    og = oracle.Graph(g)
+    srcs = np.random.default_rng(4).integers(0, g.num_vertices, size=150)
+    nfa = R.compile_regex("(0|1)* ^2 (3|0)*", 4)
+    seen = set()
+    for alpha, beta in ((1, 24), (4, 24), (64, 1), (1000, 1), (2, 1000)):
+        gg.set_option("stacked_alpha", alpha)
+        gg.set_option("stacked_beta", beta)
+        st = _check(rpq, gg, og, nfa, srcs)
+        seen.add((st.push_levels > 0, st.pull_levels > 0))
+    assert (True, True) in seen  # some setting mixed both directions
+
+
+def test_hubs_pull_heavy(rpq):
+    # stars far above the pull pass's light-row bound: a hub with 1499 in-edges
+    # of label 0 and 1500 out-edges of label 1, plus random edges
+    rng = np.random.default_rng(11)
+    n, hub = 3000, 7
+    src = list(rng.integers(0, n, 6000))
+    dst = list(rng.integers(0, n, 6000))
+    lab = list(rng.integers(0, 3, 6000))
+    src += list(range(1, 1500)) + [hub] * 1500
+    dst += [hub] * 1499 + list(range(1500, 3000))
+    lab += [0] * 1499 + [1] * 1500
+    g = G.from_triples(n, 3, np.array(src), np.array(dst), np.array(lab))
+    gg = rpq.Graph(g)
+    og = oracle.Graph(g)
+    srcs = rng.integers(0, n, size=100)
+    for text in ("(0|1)*", "0 ^0 1*", "(^1|2)* 0", "(0|^0|1|^1|2)*"):
+        nfa = R.compile_regex(text, 3)
+        for name, fl in STACK_MODES.items():
+            print(text, name, flush=True)
+            _check(rpq, gg, og, nfa, srcs, fl)
 
 
 def test_state_counts_and_templates(rpq):
@@ -52,10 +106,12 @@ def test_state_counts_and_templates(rpq):
     og = oracle.Graph(w.graph)
     srcs = rng.integers(0, w.graph.num_vertices, size=70)
     for nfa in w.nfas:
-        _check(rpq, gg, og, nfa, srcs)
-    for leaves in (1, 7, 12, 20, 31):
+        for fl in STACK_MODES.values():
+            _check(rpq, gg, og, nfa, srcs, fl)
+    for leaves in (1, 4, 7, 12, 20, 31):
         nfa = R.glushkov(R.random_ast(rng, leaves, lambda r: r.integers(0, 8), 0.3), 8)
-        _check(rpq, gg, og, nfa, srcs[:40])
+        for fl in STACK_MODES.values():
+            _check(rpq, gg, og, nfa, srcs[:40], fl)
 
 
 def test_er_and_tiny(rpq):
@@ -68,7 +124,9 @@ def test_er_and_tiny(rpq):
     for _ in range(20):
         g = OC.tiny_graph(rng)
         nfa = R.compile_regex(OC.tiny_expr(rng, g.num_labels), g.num_labels)
-        _check(rpq, rpq.Graph(g), oracle.Graph(g), nfa, list(range(g.num_vertices)) * 2)
+        gg, og = rpq.Graph(g), oracle.Graph(g)
+        for fl in STACK_MODES.values():
+            _check(rpq, gg, og, nfa, list(range(g.num_vertices)) * 2, fl)
 
 
 def test_grid_batch(rpq):
@@ -76,12 +134,14 @@ def test_grid_batch(rpq):
     g = G.grid(side, 0.0, 0)
     gg = rpq.Graph(g)
     srcs = [0, side * side - 1, 5 * side + 7, 17 * side + 3]
-    bms, st = gg.multi_source(rpq.NFA(R.compile_regex("(0|1)*", 4)), srcs)
-    assert st.levels == 2 * side - 1  # from the corner (0, 0)
-    for i, s in enumerate(srcs):
-        x0, y0 = s % side, s // side
-        want = OC.bitmap_of([y * side + x for y in range(y0, side) for x in range(x0, side)], side * side)
-        assert np.array_equal(bms[i], want)
+    for fl in STACK_MODES.values():
+        bms, st = gg.multi_source(rpq.NFA(R.compile_regex("(0|1)*", 4)), srcs, flags=fl, level_cap=256)
+        assert st.levels == 2 * side - 1  # from the corner (0, 0)
+        assert len(st.level_us) == st.levels and (st.level_us > 0).all()
+        for i, s in enumerate(srcs):
+            x0, y0 = s % side, s // side
+            want = OC.bitmap_of([y * side + x for y in range(y0, side) for x in range(x0, side)], side * side)
+            assert np.array_equal(bms[i], want)
 
 
 def test_repeat_and_device_output(rpq):
