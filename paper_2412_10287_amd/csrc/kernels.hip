@@ -4,20 +4,28 @@
 //     M' = ( sum_a (N^a)^T M G^a ) masked by not-P,      P = P + M'
 // over the Boolean semiring. The kernels never form a matrix. Per vertex the
 // |Q| states of M and P are one bit-packed word (1, 2 or 4 bytes), and a level
-// runs as three phases:
+// runs as two phases separated by a grid barrier:
 //
-//  select  for every frontier vertex v and every segment (v, label) of the
-//          symbols the query uses, the product (N^a)^T M restricted to column v
-//          is the successor set succ_a(M[v]) (a few table ORs); each non-empty
-//          one becomes a push item (neighbour range, state set). This applies
-//          the small NFA factor first, the evaluation order Sec. 4 recommends.
+//  select  every candidate vertex w (one that received state bits in the
+//          previous expansion) is masked by P: its new states M[w] & ~P[w]
+//          are added to P and become w's frontier word. Then, for each used
+//          symbol u, the product (N^u)^T M restricted to column w is the
+//          successor set succ_u(M[w]) (a few table ORs); each non-empty one
+//          with a u-row at w becomes a push item (neighbour range, state set).
+//          This applies the small NFA factor first, the evaluation order
+//          Sec. 4 recommends.
 //  push    the items' edges are spread evenly over the grid; each edge (v, w)
-//          ORs the item's set into P[w] with one atomic; the bits that were
-//          not yet set (the not-P mask) go to M'[w], and the first writer of
-//          M'[w] appends w to the next frontier queue (wave ballot + popc).
+//          drops the item's states already in P[w] (a load) and ORs the rest
+//          into the next level's word of w with one atomic; the first writer
+//          of that word appends w to the next candidate queue (wave ballot +
+//          popc, one reservation per wave for four edges per lane).
 //  pull    used instead of push on dense levels: every vertex w with states
 //          still unvisited scans its reverse neighbours under the symbols that
 //          can reach those states and stops as soon as all are found.
+//
+// Masking by P in the next select instead of with an atomic on P during the
+// scatter takes one atomic round trip off every edge; random 32-bit atomics
+// are the most expensive operation of the traversal on MI355X.
 //
 // Inverse symbols a^- read the transposed adjacency (Sec. 3: G^{a^-} = (G^a)^T):
 // the graph store holds both directions, and the label -> symbol tables map an
@@ -39,52 +47,49 @@ __device__ __forceinline__ void flag_violation(const Params &p) { atomicAdd(&p.s
 
 // ---------------------------------------------------------------- phases
 template <int W>
-__device__ void init_phase(const Params &p) {
+__device__ __forceinline__ void init_phase(const Params &p) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     const QHeader &h = *p.qv.h;
     LevelRec *r = p.st.rec;
     r[0] = LevelRec{};
     const uint32_t sm = h.smask;
     if (sm) {
-        st_state<W>(p.st.P, p.source, sm);
+        // M_0 = Q_S x {source}, as a candidate that level 0's select adds to P
         st_state<W>(p.st.M[0], p.source, sm);
         p.st.q[0][0] = p.source;
         r[0].nq = 1;
-        r[0].su = sm;
-        r[0].pairs = __popc(sm);
     }
     for (int i = 0; i < 4; i++) p.st.cnt[i] = 0;
     for (int i = 0; i < 4; i++) p.st.status[i] = 0;
 }
 
-// Frontier -> push items. For each frontier vertex v with state set S and
-// each used symbol u, succ_u(S) is the column v of (N^u)^T M; when it is
-// non-empty and v has u-neighbours, (v, u) becomes an item carrying the
-// neighbour range and succ_u(S). Items are reserved per wave with one 64-bit
-// atomic that counts items (high half) and edges (low half) together, so item
-// order and edge numbering agree.
+// Candidates -> frontier -> push items. Each candidate w gets its new states
+// S = M[w] & ~P[w] (added to P); for each used symbol u, succ_u(S) is the
+// column w of (N^u)^T M, and when it is non-empty and w has u-neighbours,
+// (w, u) becomes an item carrying the neighbour range and succ_u(S). Items are
+// reserved per wave with one 64-bit atomic that counts items (high half) and
+// edges (low half) together, so item order and edge numbering agree.
 template <int W>
-__device__ void select_phase(const Params &p, uint32_t n) {
+__device__ __forceinline__ void select_phase(const Params &p, uint32_t n) {
     const GraphView &g = p.g;
     const QueryView &qv = p.qv;
     const QHeader &h = *qv.h;
     LevelRec *rec = p.st.rec;
     LevelRec &R = rec[n % REC_RING];
-    const uint32_t nq = ld_acq(&R.nq);
     const uint32_t V = static_cast<uint32_t>(g.V);
+    uint32_t nq = ld_acq(&R.nq);
+    if (nq > V) {
+        if (gthread() == 0) flag_violation(p);
+        nq = V;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         rec[(n + 1) % REC_RING] = LevelRec{};
-        if (n < LVL_COUNT_CAP) {
-            uint64_t *L = p.st.lvl + static_cast<uint64_t>(n) * LVL_STRIDE;
-            L[0] = ld_acq(&R.pairs);
-            L[1] = nq;
-            L[3] = wall_clock64();
-        }
-        if (h.counters) p.st.cnt[3] += nq;
+        if (n < LVL_COUNT_CAP) p.st.lvl[static_cast<uint64_t>(n) * LVL_STRIDE + 3] = wall_clock64();
     }
     // frontier words of level n-1 live in the buffer level n writes: clear them
     if (n >= 1) {
-        const uint32_t nprev = ld_acq(&rec[(n - 1) % REC_RING].nq);
+        uint32_t nprev = ld_acq(&rec[(n - 1) % REC_RING].nq);
+        if (nprev > V) nprev = V;
         uint32_t *Mold = p.st.M[(n + 1) & 1];
         const int32_t *qold = p.st.q[(n + 1) & 1];
         for (uint32_t i = gthread(); i < nprev; i += gthreads()) {
@@ -94,18 +99,32 @@ __device__ void select_phase(const Params &p, uint32_t n) {
         }
     }
     const int32_t *qc = p.st.q[n & 1];
-    const uint32_t *Mc = p.st.M[n & 1];
+    uint32_t *Mc = p.st.M[n & 1];
+    uint32_t *P = p.st.P;
     const uint32_t lane = lane_id();
     const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
     const uint32_t nsym = h.nsym;
-    uint64_t c_pe = 0, c_sc = 0, c_sd = 0;
+    uint64_t c_pe = 0, c_sc = 0, c_sd = 0, pairs = 0;
+    uint32_t nfront = 0, su = 0;
     for (uint32_t base = gw * 64; base < nq; base += nw * 64) {
         const uint32_t i = base + lane;
-        uint32_t v = i < nq ? static_cast<uint32_t>(qc[i]) : 0u;
-        uint32_t S = 0;
+        uint32_t v = 0, S = 0;
         if (i < nq) {
-            if (v < V) S = ld_state<W>(Mc, v);
-            else { flag_violation(p); v = 0; }
+            v = static_cast<uint32_t>(qc[i]);
+            if (v < V) {
+                // the complement mask of Alg. 1, then P = P + M
+                const uint32_t c = ld_state<W>(Mc, v);
+                const uint32_t pv = ld_state<W>(P, v);
+                S = c & ~pv;
+                if (S) st_state<W>(P, v, pv | S);
+                if (S != c) st_state<W>(Mc, v, S);
+                pairs += __popc(S);
+                nfront += S != 0;
+                su |= S;
+            } else {
+                flag_violation(p);
+                v = 0;
+            }
         }
         for (uint32_t u0 = 0; u0 < nsym; u0 += SYM_BATCH) {
             uint32_t sp[SYM_BATCH], beg[SYM_BATCH], len[SYM_BATCH];
@@ -168,15 +187,39 @@ __device__ void select_phase(const Params &p, uint32_t n) {
             }
         }
     }
+    pairs = wave_sum(pairs);
+    const uint64_t nf = wave_sum(static_cast<uint64_t>(nfront));
+    su = wave_or(su);
+    if (lane == 0) {
+        if (pairs) atomicAdd(reinterpret_cast<unsigned long long *>(&R.pairs), static_cast<unsigned long long>(pairs));
+        if (nf) atomicAdd(&R.nfront, static_cast<uint32_t>(nf));
+        if (su) atomicOr(&R.su, su);
+    }
     if (h.counters) {
         c_pe = wave_sum(c_pe);
         c_sc = wave_sum(c_sc);
         c_sd = wave_sum(c_sd);
-        if (lane == 0 && (c_pe | c_sc)) {
-            atomicAdd(reinterpret_cast<unsigned long long *>(&p.st.cnt[0]), (unsigned long long)c_pe);
-            atomicAdd(reinterpret_cast<unsigned long long *>(&p.st.cnt[1]), (unsigned long long)c_sc);
-            atomicAdd(reinterpret_cast<unsigned long long *>(&p.st.cnt[2]), (unsigned long long)c_sd);
+        if (lane == 0) {
+            if (c_pe | c_sc) {
+                atomicAdd(reinterpret_cast<unsigned long long *>(&p.st.cnt[0]), (unsigned long long)c_pe);
+                atomicAdd(reinterpret_cast<unsigned long long *>(&p.st.cnt[1]), (unsigned long long)c_sc);
+                atomicAdd(reinterpret_cast<unsigned long long *>(&p.st.cnt[2]), (unsigned long long)c_sd);
+            }
+            if (nf) atomicAdd(reinterpret_cast<unsigned long long *>(&p.st.cnt[3]), (unsigned long long)nf);
         }
+    }
+}
+
+// Level n's statistics once its select phase is complete (one thread).
+__device__ __forceinline__ void record_level(const Params &p, uint32_t n, uint32_t mode) {
+    LevelRec &R = p.st.rec[n % REC_RING];
+    R.mode = mode;
+    if (n < LVL_COUNT_CAP) {
+        uint64_t *L = p.st.lvl + static_cast<uint64_t>(n) * LVL_STRIDE;
+        L[0] = ld_acq(&R.pairs);
+        L[1] = ld_acq(&R.nfront);
+        L[2] = ld_acq(&R.sel);
+        L[4] = wall_clock64();
     }
 }
 
@@ -189,34 +232,106 @@ __device__ __forceinline__ uint32_t decide(const Params &p, uint32_t n) {
     const LevelRec *rec = p.st.rec;
     const uint32_t prev = n ? ld_acq(&rec[(n - 1) % REC_RING].mode) : 0u;
     const uint64_t T = ld_acq(&rec[n % REC_RING].sel) & 0xffffffffull;
-    const uint32_t nq = ld_acq(&rec[n % REC_RING].nq);
+    const uint32_t nq = ld_acq(&rec[n % REC_RING].nfront);
     if (prev == 0) return static_cast<double>(T) * h.alpha > static_cast<double>(h.e_rel) ? 1u : 0u;
     return static_cast<double>(nq) * h.beta < static_cast<double>(p.g.V) ? 0u : 1u;
 }
 
-// Items -> edges, spread evenly: tile k holds edges [k*TILE, (k+1)*TILE) of
-// the level; its items are staged in LDS and each thread finds its edge's item
-// by binary search. Per edge (v, w) with successor set S': the bits of S' not
-// yet in P[w] are set with one atomic OR (the masked sum of Alg. 1), go to
-// M'[w], and the first writer of M'[w] appends w to the next queue.
+// Edges [ubase, uend) of the items staged in LDS (cnt of them), four per
+// thread and step: all four loads of col, then of P, then the atomics, then
+// one queue reservation per wave. Per edge (v, w) with successor set S' the
+// states of S' not yet in P[w] (the complement mask) are ORed into the next
+// level's word of w; the first writer appends w to the candidate queue.
 template <int W>
-__device__ void push_phase(const Params &p, uint32_t n, uint32_t *s_eb, uint32_t *s_beg, uint32_t *s_mask) {
-    LevelRec *rec = p.st.rec;
-    const uint64_t sel = ld_acq(&rec[n % REC_RING].sel);
+__device__ __forceinline__ void push_range(const Params &p, uint32_t n, const uint32_t *s_eb, const uint32_t *s_beg,
+                                           const uint32_t *s_mask, uint32_t cnt, uint32_t ubase, uint32_t uend) {
+    const uint32_t V = static_cast<uint32_t>(p.g.V);
+    const uint32_t *P = p.st.P;
+    uint32_t *Mn = p.st.M[(n + 1) & 1];
+    int32_t *qn = p.st.q[(n + 1) & 1];
+    uint32_t *qlen = &p.st.rec[(n + 1) % REC_RING].nq;
+    const uint32_t *col = p.g.col;
+    const uint32_t tid = threadIdx.x;
+    static_assert(TILE == 4 * BLOCK, "four edges per thread and step");
+    for (uint32_t ub = ubase; ub < uend; ub += TILE) {
+        uint32_t w[4], sp[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint32_t t = ub + k * BLOCK + tid;
+            w[k] = V;
+            sp[k] = 0;
+            // item holding edge t: the last staged item with s_eb <= t
+            // (fixed-step search: cnt <= TILE + 1 < 2^12)
+            uint32_t lo = 0, len = cnt;
+#pragma unroll
+            for (int step = 0; step < 12; step++) {
+                const uint32_t half = len >> 1;
+                if (half && t < uend) {
+                    if (s_eb[lo + half] <= t) lo += half;
+                    len -= half;
+                }
+            }
+            if (t < uend) {
+                const uint32_t pos = s_beg[lo] + (t - s_eb[lo]);
+                sp[k] = s_mask[lo];
+                if (pos < p.g.ncol) w[k] = col[pos];
+                else flag_violation(p);
+                if (w[k] >= V && pos < p.g.ncol) {
+                    flag_violation(p);
+                    w[k] = V;
+                }
+            }
+        }
+        uint32_t cand[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) cand[k] = w[k] < V ? sp[k] & ~ld_state<W>(P, w[k]) : 0u;
+        bool first[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) first[k] = cand[k] ? or_state<W>(Mn, w[k], cand[k]) == 0 : false;
+        if (!wave_append4(first[0], static_cast<int32_t>(w[0]), first[1], static_cast<int32_t>(w[1]), first[2],
+                          static_cast<int32_t>(w[2]), first[3], static_cast<int32_t>(w[3]), qn, qlen, V))
+            flag_violation(p);
+    }
+}
+
+// Items -> edges, spread evenly over the grid. Few items: every workgroup
+// stages all of them and takes an even, wave-aligned share of the edges, so
+// small levels use the whole chip. Otherwise tile k holds edges
+// [k*TILE, (k+1)*TILE) and its items are staged in LDS; with fewer tiles than
+// workgroups each tile is split into parts of at least a wave's worth.
+template <int W>
+__device__ __forceinline__ void push_phase(const Params &p, uint32_t n, uint32_t *s_eb, uint32_t *s_beg,
+                                           uint32_t *s_mask) {
+    const uint64_t sel = ld_acq(&p.st.rec[n % REC_RING].sel);
     const uint32_t nitems = static_cast<uint32_t>(sel >> 32);
     const uint32_t T = static_cast<uint32_t>(sel);
     if (T == 0 || nitems == 0) return;
-    const uint32_t ntiles = (T + TILE - 1) / TILE;
-    const uint32_t V = static_cast<uint32_t>(p.g.V);
-    uint32_t *P = p.st.P;
-    uint32_t *Mn = p.st.M[(n + 1) & 1];
-    int32_t *qn = p.st.q[(n + 1) & 1];
-    LevelRec &RN = rec[(n + 1) % REC_RING];
-    const uint32_t *col = p.g.col;
+    if (nitems > p.st.item_cap) {
+        if (gthread() == 0) flag_violation(p);
+        return;
+    }
     const uint32_t tid = threadIdx.x;
-    uint64_t pairs = 0;
-    uint32_t su = 0;
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    if (nitems <= static_cast<uint32_t>(TILE)) {
+        for (uint32_t j = tid; j < nitems; j += BLOCK) {
+            s_eb[j] = p.st.it_ebase[j];
+            s_beg[j] = p.st.it_beg[j];
+            s_mask[j] = p.st.it_mask[j];
+        }
+        __syncthreads();
+        uint32_t per = (T + gridDim.x - 1) / gridDim.x;
+        per = (per + 63) & ~63u;
+        const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * per;
+        const uint32_t b1 = b0 + per < T ? static_cast<uint32_t>(b0 + per) : T;
+        if (b0 < b1) push_range<W>(p, n, s_eb, s_beg, s_mask, nitems, static_cast<uint32_t>(b0), b1);
+        __syncthreads();
+        return;
+    }
+    const uint32_t ntiles = (T + TILE - 1) / TILE;
+    uint32_t sub = 1;
+    while (sub < TILE / 64 && ntiles * sub * 2 <= gridDim.x) sub *= 2;
+    const uint32_t part = TILE / sub;
+    for (uint32_t vt = blockIdx.x; vt < ntiles * sub; vt += gridDim.x) {
+        const uint32_t tile = vt / sub, k = vt % sub;
         uint32_t i0 = tile < p.st.tile_cap ? p.st.tile_first[tile] : 0u;
         uint32_t i1 = (tile + 1 < ntiles && tile + 1 < p.st.tile_cap) ? p.st.tile_first[tile + 1] : nitems - 1;
         if (i0 >= nitems || i1 >= nitems || i1 < i0 || i1 - i0 > static_cast<uint32_t>(TILE)) {
@@ -230,48 +345,10 @@ __device__ void push_phase(const Params &p, uint32_t n, uint32_t *s_eb, uint32_t
             s_mask[j] = p.st.it_mask[i0 + j];
         }
         __syncthreads();
-        const uint32_t t0 = tile * TILE;
-        constexpr int EPT = TILE / BLOCK;  // edges per thread, processed together
-        uint32_t w[EPT], sp[EPT], nwd[EPT];
-        bool first[EPT];
-#pragma unroll
-        for (int k = 0; k < EPT; k++) {
-            const uint32_t t = t0 + k * BLOCK + tid;
-            w[k] = V;
-            sp[k] = 0;
-            if (t < T) {
-                uint32_t lo = 0, hi = cnt;  // s_eb[lo] <= t < s_eb[hi]
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (s_eb[mid] <= t) lo = mid;
-                    else hi = mid;
-                }
-                const uint32_t pos = s_beg[lo] + (t - s_eb[lo]);
-                sp[k] = s_mask[lo];
-                if (pos < p.g.ncol) w[k] = col[pos];
-                else flag_violation(p);
-            }
-        }
-        uint32_t cand[EPT];
-#pragma unroll
-        for (int k = 0; k < EPT; k++) cand[k] = w[k] < V ? sp[k] & ~ld_state<W>(P, w[k]) : 0u;
-#pragma unroll
-        for (int k = 0; k < EPT; k++) nwd[k] = cand[k] ? cand[k] & ~or_state<W>(P, w[k], cand[k]) : 0u;
-#pragma unroll
-        for (int k = 0; k < EPT; k++) first[k] = nwd[k] ? or_state<W>(Mn, w[k], nwd[k]) == 0 : false;
-#pragma unroll
-        for (int k = 0; k < EPT; k++) {
-            if (!wave_append(first[k], static_cast<int32_t>(w[k]), qn, &RN.nq, V)) flag_violation(p);
-            pairs += __popc(nwd[k]);
-            su |= nwd[k];
-        }
+        const uint32_t u0 = tile * TILE + k * part;
+        const uint32_t u1 = u0 + part < T ? u0 + part : T;
+        if (u0 < u1) push_range<W>(p, n, s_eb, s_beg, s_mask, cnt, u0, u1);
         __syncthreads();
-    }
-    pairs = wave_sum(pairs);
-    su = wave_or(su);
-    if (lane_id() == 0 && pairs) {
-        atomicAdd(reinterpret_cast<unsigned long long *>(&RN.pairs), (unsigned long long)pairs);
-        atomicOr(&RN.su, su);
     }
 }
 
@@ -318,7 +395,7 @@ __device__ __forceinline__ uint32_t pull_rows(const Params &p, uint32_t w, uint3
 }
 
 template <int W>
-__device__ void pull_phase(const Params &p, uint32_t n, uint32_t *s_hw, uint32_t *s_hu, uint32_t *s_hp,
+__device__ __forceinline__ void pull_phase(const Params &p, uint32_t n, uint32_t *s_hw, uint32_t *s_hu, uint32_t *s_hp,
                            uint32_t *s_hn) {
     const GraphView &g = p.g;
     const QueryView &qv = p.qv;
@@ -334,13 +411,11 @@ __device__ void pull_phase(const Params &p, uint32_t n, uint32_t *s_hw, uint32_t
     const uint32_t *Mc = p.st.M[n & 1];
     uint32_t *Mn = p.st.M[(n + 1) & 1];
     int32_t *qn = p.st.q[(n + 1) & 1];
-    uint32_t *P = p.st.P;
+    const uint32_t *P = p.st.P;
     LevelRec &RN = rec[(n + 1) % REC_RING];
     const uint32_t lane = lane_id();
     const uint32_t V = static_cast<uint32_t>(g.V);
     const uint32_t nsym = h.nsym;
-    uint64_t pairs = 0;
-    uint32_t sacc = 0;
     if (threadIdx.x == 0) *s_hn = 0;
     __syncthreads();
     const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
@@ -391,15 +466,10 @@ __device__ void pull_phase(const Params &p, uint32_t n, uint32_t *s_hw, uint32_t
                         }
                     }
                 }
-                if (acc) {
-                    st_state<W>(P, w, pw | acc);
-                    st_state<W>(Mn, w, acc);
-                }
+                if (acc) st_state<W>(Mn, w, acc);  // only unvisited states: the next select adds them to P
             }
         }
         if (!wave_append(acc != 0, static_cast<int32_t>(w), qn, &RN.nq, V)) flag_violation(p);
-        pairs += __popc(acc);
-        sacc |= acc;
     }
     __syncthreads();
     // heavy vertices of this workgroup: one wavefront each, 64 neighbours per step
@@ -430,27 +500,19 @@ __device__ void pull_phase(const Params &p, uint32_t n, uint32_t *s_hw, uint32_t
             }
         }
         if (lane == 0 && acc) {
-            st_state<W>(P, w, pw | acc);
             st_state<W>(Mn, w, acc);
             const uint32_t pos = atomicAdd(&RN.nq, 1u);
             if (pos < V) qn[pos] = static_cast<int32_t>(w);
             else flag_violation(p);
-            pairs += __popc(acc);
-            sacc |= acc;
         }
-    }
-    pairs = wave_sum(pairs);
-    sacc = wave_or(sacc);
-    if (lane == 0 && pairs) {
-        atomicAdd(reinterpret_cast<unsigned long long *>(&RN.pairs), (unsigned long long)pairs);
-        atomicOr(&RN.su, sacc);
+        (void)pw;
     }
 }
 
 // Clears the last frontier's words, writes the result bitmap (vertex v has a
 // final state: the product F P of Alg. 1) and resets P for the next query.
 template <int W>
-__device__ void final_phase(const Params &p, uint32_t nlev) {
+__device__ __forceinline__ void final_phase(const Params &p, uint32_t nlev) {
     const uint32_t V = static_cast<uint32_t>(p.g.V);
     if (blockIdx.x == 0 && threadIdx.x == 0 && nlev < LVL_COUNT_CAP)
         p.st.lvl[static_cast<uint64_t>(nlev) * LVL_STRIDE + 3] = wall_clock64();
@@ -494,13 +556,7 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
         select_phase<W>(p, n);
         if (!grid_barrier(bar, bc)) return;
         const uint32_t mode = decide(p, n);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            p.st.rec[n % REC_RING].mode = mode;
-            if (n < LVL_COUNT_CAP) {
-                p.st.lvl[static_cast<uint64_t>(n) * LVL_STRIDE + 2] = ld_acq(&p.st.rec[n % REC_RING].sel);
-                p.st.lvl[static_cast<uint64_t>(n) * LVL_STRIDE + 4] = wall_clock64();
-            }
-        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) record_level(p, n, mode);
         if (mode == 0) push_phase<W>(p, n, s_eb, s_beg, s_mask);
         else pull_phase<W>(p, n, s_eb, s_beg, s_mask, &s_hn);
         npush += mode == 0;
@@ -531,8 +587,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(Params p, uint32_t n) {
     __shared__ uint32_t s_eb[TILE + 1], s_beg[TILE + 1], s_mask[TILE + 1], s_hn;
     const uint32_t mode = decide(p, n);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        p.st.rec[n % REC_RING].mode = mode;
-        if (n < LVL_COUNT_CAP) p.st.lvl[static_cast<uint64_t>(n) * LVL_STRIDE + 2] = ld_acq(&p.st.rec[n % REC_RING].sel);
+        record_level(p, n, mode);
         p.st.status[0] = n + 1;
         p.st.status[1 + (mode != 0)] += 1;
     }

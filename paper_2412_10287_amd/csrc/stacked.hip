@@ -512,7 +512,13 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, S
     }
     constexpr uint32_t TE = TILE / G;
     const uint32_t ntiles = (T + TE - 1) / TE;
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // fewer tiles than workgroups: split each tile into parts of at least a
+    // wave's worth of units, so the level still spreads over the grid
+    uint32_t sub = 1;
+    while (sub < TILE / 64 && ntiles * sub * 2 <= gridDim.x) sub *= 2;
+    const uint32_t part_units = TILE / sub;
+    for (uint32_t vt = blockIdx.x; vt < ntiles * sub; vt += gridDim.x) {
+        const uint32_t tile = vt / sub, part = vt % sub;
         uint32_t i0 = tile < p.tile_cap ? p.tile_first[tile] : 0u;
         uint32_t i1 = (tile + 1 < ntiles && tile + 1 < p.tile_cap) ? p.tile_first[tile + 1] : nitems - 1;
         if (i0 >= nitems || i1 >= nitems || i1 < i0 || i1 - i0 > TE) {
@@ -528,9 +534,9 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, S
             L.s[x] = p.it_s[i0 + x];
         }
         __syncthreads();
-        const uint64_t u0 = static_cast<uint64_t>(tile) * TILE;
-        const uint64_t u1 = u0 + TILE < units ? u0 + TILE : units;
-        expand_range<G, QM, PULL>(p, n, L, cnt, u0, u1, ns);
+        const uint64_t u0 = static_cast<uint64_t>(tile) * TILE + static_cast<uint64_t>(part) * part_units;
+        const uint64_t u1 = u0 + part_units < units ? u0 + part_units : units;
+        if (u0 < u1) expand_range<G, QM, PULL>(p, n, L, cnt, u0, u1, ns);
         __syncthreads();
     }
 }
