@@ -2,9 +2,10 @@
 // visited set P and frontier M) advances one level per launch pair. The level
 // is the same computation as the single-query path (Alg. 1's update: for each
 // frontier pair set, succ_a per used symbol, pushed along the symbol's rows,
-// masked by P), with a slot tag on every queue entry and push item, so one
-// edge-balanced launch carries the frontiers of all queries at once and the
-// per-level fixed cost is shared.
+// masked by P, the mask applied to the candidates in the next select), with a
+// slot tag on every queue entry and push item, so one edge-balanced launch
+// carries the frontiers of all queries at once and the per-level fixed cost
+// is shared.
 #include "device_common.h"
 #include "multi.h"
 
@@ -58,9 +59,9 @@ __global__ void k_multi_admit(MultiParams p, uint32_t parity, uint32_t n, const 
         return;
     }
     const uint32_t sm = reinterpret_cast<const QHeader *>(p.qconst + static_cast<size_t>(s) * QC_STRIDE)->smask;
-    p.pairs[s] = __popc(sm);
+    p.pairs[s] = 0;
     if (!sm) return;
-    p.P[s * p.swords + v] = sm;
+    // M_0 = Q_S x {source} as a candidate: the next select adds it to P
     p.M[parity][s * p.swords + v] = sm;
     const uint32_t pos = atomicAdd(&p.qlen[parity], 1u);
     if (pos < p.queue_cap) p.q[parity][pos] = (s << p.vbits) | v;
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
         if (gthread() == 0) p.qlen[parity ^ 1] = 0;
     }
     const uint32_t *qc = p.q[parity];
-    const uint32_t *Mc = p.M[parity];
+    uint32_t *Mc = p.M[parity];
     const uint32_t lane = lane_id();
     const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
     const GraphView &g = p.g;
@@ -103,7 +104,13 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
             s = e >> p.vbits;
             v = e & vmask;
             if (s < p.slots && v < V) {
-                S = Mc[s * p.swords + v];
+                // the complement mask of Alg. 1, then P = P + M
+                const uint64_t at = s * p.swords + v;
+                const uint32_t c = Mc[at];
+                const uint32_t pv = p.P[at];
+                S = c & ~pv;
+                if (S) p.P[at] = pv | S;
+                if (S != c) Mc[at] = S;
                 qv = slot_view(p, s);
                 nsym = qv.h->nsym;
             } else {
@@ -111,6 +118,7 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
                 s = v = 0;
             }
         }
+        wave_slot_add(p, s, 0u, static_cast<uint32_t>(__popc(S)));
         // the symbol loop is wave-uniform: run to the wave's largest nsym
         uint32_t wmax = nsym;
 #pragma unroll
@@ -172,6 +180,72 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
     }
 }
 
+// Edges [ubase, uend) of the items staged in LDS (cnt of them), four per
+// thread and step: the loads of col and P for all four, then the atomics,
+// then one queue reservation per wave. The states of an item not yet in P[w]
+// are ORed into w's next word; the first writer appends (slot, w).
+__device__ __forceinline__ void multi_push_range(const MultiParams &p, uint32_t parity, const uint64_t *s_eb,
+                                                 const uint32_t *s_beg, const uint32_t *s_mask, const uint32_t *s_slot,
+                                                 uint32_t cnt, uint64_t ubase, uint64_t uend) {
+    const uint32_t V = static_cast<uint32_t>(p.V);
+    uint32_t *qn = p.q[parity ^ 1];
+    uint32_t *Mn = p.M[parity ^ 1];
+    const uint32_t *col = p.g.col;
+    const uint32_t tid = threadIdx.x;
+    static_assert(TILE == 4 * BLOCK, "four edges per thread and step");
+    for (uint64_t ub = ubase; ub < uend; ub += TILE) {
+        uint32_t w[4], sp[4], sl[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint64_t t = ub + static_cast<uint64_t>(k) * BLOCK + tid;
+            w[k] = V;
+            sp[k] = 0;
+            sl[k] = 0;
+            uint32_t lo = 0, len = cnt;  // last staged item with s_eb <= t (cnt <= TILE + 1 < 2^12)
+#pragma unroll
+            for (int step = 0; step < 12; step++) {
+                const uint32_t half = len >> 1;
+                if (half && t < uend) {
+                    if (s_eb[lo + half] <= t) lo += half;
+                    len -= half;
+                }
+            }
+            if (t < uend) {
+                const uint64_t pos = s_beg[lo] + (t - s_eb[lo]);
+                sp[k] = s_mask[lo];
+                sl[k] = s_slot[lo];
+                if (pos < p.g.ncol && sl[k] < p.slots) {
+                    w[k] = col[pos];
+                    if (w[k] >= V) {
+                        mviolation(p);
+                        w[k] = V;
+                    }
+                } else {
+                    mviolation(p);
+                }
+            }
+        }
+        uint32_t cand[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) cand[k] = w[k] < V ? sp[k] & ~p.P[sl[k] * p.swords + w[k]] : 0u;
+        bool first[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) first[k] = cand[k] ? atomicOr(&Mn[sl[k] * p.swords + w[k]], cand[k]) == 0u : false;
+        if (!wave_append4(first[0], static_cast<int32_t>((sl[0] << p.vbits) | w[0]), first[1],
+                          static_cast<int32_t>((sl[1] << p.vbits) | w[1]), first[2],
+                          static_cast<int32_t>((sl[2] << p.vbits) | w[2]), first[3],
+                          static_cast<int32_t>((sl[3] << p.vbits) | w[3]), reinterpret_cast<int32_t *>(qn),
+                          &p.qlen[parity ^ 1], static_cast<uint32_t>(p.queue_cap)))
+            mviolation(p);
+#pragma unroll
+        for (int k = 0; k < 4; k++) wave_slot_add(p, sl[k], first[k] ? 1u : 0u, 0u);
+    }
+}
+
+// Items -> edges, spread evenly over the grid: with few items every workgroup
+// stages all of them and takes an even, wave-aligned share of the edges;
+// otherwise tiles of TILE edges (split into parts when there are fewer tiles
+// than workgroups) stage their own items.
 __global__ __launch_bounds__(BLOCK) void k_multi_push(MultiParams p, uint32_t parity, uint32_t chunk_id) {
     __shared__ uint64_t s_eb[TILE + 1];
     __shared__ uint32_t s_beg[TILE + 1], s_mask[TILE + 1], s_slot[TILE + 1];
@@ -184,12 +258,28 @@ __global__ __launch_bounds__(BLOCK) void k_multi_push(MultiParams p, uint32_t pa
         if (gthread() == 0) mviolation(p);
         return;
     }
-    const uint32_t V = static_cast<uint32_t>(p.V);
-    uint32_t *qn = p.q[parity ^ 1];
-    uint32_t *Mn = p.M[parity ^ 1];
-    const uint32_t *col = p.g.col;
     const uint32_t tid = threadIdx.x;
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    if (nitems <= static_cast<uint64_t>(TILE)) {
+        for (uint32_t j = tid; j < nitems; j += BLOCK) {
+            s_eb[j] = p.it_ebase[j];
+            s_beg[j] = p.it_beg[j];
+            s_mask[j] = p.it_mask[j];
+            s_slot[j] = p.it_slot[j];
+        }
+        __syncthreads();
+        uint64_t per = (T + gridDim.x - 1) / gridDim.x;
+        per = (per + 63) & ~63ull;
+        const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * per;
+        const uint64_t b1 = b0 + per < T ? b0 + per : T;
+        if (b0 < b1) multi_push_range(p, parity, s_eb, s_beg, s_mask, s_slot, static_cast<uint32_t>(nitems), b0, b1);
+        return;
+    }
+    uint32_t sub = 1;
+    while (sub < TILE / 64 && ntiles * sub * 2 <= gridDim.x) sub *= 2;
+    const uint32_t part = TILE / sub;
+    for (uint64_t vt = blockIdx.x; vt < ntiles * sub; vt += gridDim.x) {
+        const uint64_t tile = vt / sub;
+        const uint32_t k = static_cast<uint32_t>(vt % sub);
         uint32_t i0 = p.tile_first[tile];
         uint32_t i1 = tile + 1 < ntiles ? p.tile_first[tile + 1] : static_cast<uint32_t>(nitems - 1);
         if (i0 >= nitems || i1 >= nitems || i1 < i0 || i1 - i0 > static_cast<uint32_t>(TILE)) {
@@ -204,46 +294,9 @@ __global__ __launch_bounds__(BLOCK) void k_multi_push(MultiParams p, uint32_t pa
             s_slot[j] = p.it_slot[i0 + j];
         }
         __syncthreads();
-        const uint64_t t0 = tile * TILE;
-        constexpr int EPT = TILE / BLOCK;
-        uint32_t w[EPT], sp[EPT], sl[EPT], nwd[EPT];
-        bool first[EPT];
-#pragma unroll
-        for (int k = 0; k < EPT; k++) {
-            const uint64_t t = t0 + k * BLOCK + tid;
-            w[k] = V;
-            sp[k] = 0;
-            sl[k] = 0;
-            if (t < T) {
-                uint32_t lo = 0, hi = cnt;
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (s_eb[mid] <= t) lo = mid;
-                    else hi = mid;
-                }
-                const uint64_t pos = s_beg[lo] + (t - s_eb[lo]);
-                sp[k] = s_mask[lo];
-                sl[k] = s_slot[lo];
-                if (pos < p.g.ncol && sl[k] < p.slots) w[k] = col[pos];
-                else mviolation(p);
-            }
-        }
-        uint32_t cand[EPT];
-#pragma unroll
-        for (int k = 0; k < EPT; k++)
-            cand[k] = w[k] < V ? sp[k] & ~p.P[sl[k] * p.swords + w[k]] : 0u;
-#pragma unroll
-        for (int k = 0; k < EPT; k++) nwd[k] = cand[k] ? cand[k] & ~atomicOr(&p.P[sl[k] * p.swords + w[k]], cand[k]) : 0u;
-#pragma unroll
-        for (int k = 0; k < EPT; k++) first[k] = nwd[k] ? atomicOr(&Mn[sl[k] * p.swords + w[k]], nwd[k]) == 0 : false;
-#pragma unroll
-        for (int k = 0; k < EPT; k++) {
-            if (!wave_append(first[k], static_cast<int32_t>((sl[k] << p.vbits) | w[k]),
-                             reinterpret_cast<int32_t *>(qn), &p.qlen[parity ^ 1],
-                             static_cast<uint32_t>(p.queue_cap)))
-                mviolation(p);
-            wave_slot_add(p, sl[k], first[k] ? 1u : 0u, static_cast<uint32_t>(__popc(nwd[k])));
-        }
+        const uint64_t u0 = tile * TILE + static_cast<uint64_t>(k) * part;
+        const uint64_t u1 = u0 + part < T ? u0 + part : T;
+        if (u0 < u1) multi_push_range(p, parity, s_eb, s_beg, s_mask, s_slot, cnt, u0, u1);
         __syncthreads();
     }
 }
