@@ -215,6 +215,116 @@ def bench_batched(args, w):
     print(json.dumps(out_json), flush=True)
 
 
+def bench_serve(args):
+    """Serving loop on the knowledge graph: a seeded stream of mixed queries
+    (template queries and random expressions of 1..31 label occurrences) with
+    Poisson arrivals. The served path (rpq_submit / rpq_poll) is driven open
+    loop: a submitter thread submits each query at its arrival time and the
+    latency of a query is completion minus arrival. The arrival rate is 0.8 of
+    the served path's saturated rate (all queries submitted at once). The plain
+    path serves the same stream one query at a time in arrival order (a FIFO
+    single server), so its latency includes the wait behind earlier queries."""
+    import queue
+    import threading
+    from workloads import configs as C
+    from workloads import regex as R
+    from paper_2412_10287_amd import rpq
+    n = 20_000_000 if args.scale >= 20 else 1 << args.scale
+    t0 = time.time()
+    graph = C.kg_graph(n=n, m=10 * n)
+    texts, srcs, _ = C.serve_queries(graph, args.serve_queries, 1.0)
+    nfas = [R.compile_regex(q, graph.num_labels) for q in texts]
+    states = np.array([a.num_states for a in nfas])
+    log("serve workload: V=%d E=%d, %d queries, states %d..%d (mean %.1f) (%.1fs)" % (
+        graph.num_vertices, graph.num_edges, len(nfas), states.min(), states.max(), states.mean(), time.time() - t0))
+    g = rpq.Graph(graph)
+    if args.max_slots:
+        g.set_option("max_slots", args.max_slots)
+    handles = [rpq.NFA(a) for a in nfas]
+    N = len(handles)
+    out = rpq.DeviceBuffer(8 * g.words)
+    # work per query and plain service times (one untimed pass with counters)
+    pe = np.zeros(N, np.int64)
+    for i, (h, s) in enumerate(zip(handles, srcs)):
+        _, st = g.single_source(h, int(s), flags=rpq.COUNTERS, out_device_ptr=out.ptr)
+        pe[i] = st.product_edges
+    log("product edges: total %d, per query median %d max %d" % (pe.sum(), np.median(pe), pe.max()))
+
+    def served_saturated():
+        t = time.perf_counter()
+        tickets = [g.submit(h, int(s)) for h, s in zip(handles, srcs)]
+        for tk in tickets:
+            g.poll(tk, timeout_us=-1)
+        return N / (time.perf_counter() - t)
+
+    served_saturated()  # warm-up (engine allocation)
+    qps_sat = served_saturated()
+    rate = 0.8 * qps_sat
+    arr = np.cumsum(np.random.default_rng(C.seed(4, 4)).exponential(1.0 / rate, size=N))
+    log("served saturated %.1f q/s -> Poisson arrivals at %.1f q/s" % (qps_sat, rate))
+
+    # served, open loop
+    tq = queue.Queue()
+    start = time.perf_counter() + 0.05
+
+    def submitter():
+        for i in range(N):
+            d = start + arr[i] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            lag = time.perf_counter() - (start + arr[i])
+            tq.put((i, g.submit(handles[i], int(srcs[i])), lag))
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat = np.zeros(N)
+    for _ in range(N):
+        i, tk, lag = tq.get()
+        _, st = g.poll(tk, timeout_us=-1)
+        lat[i] = lag + st.device_ms * 1e-3
+    th.join()
+    served_span = max(arr[i] + lat[i] for i in range(N)) - arr[0]
+    log("served open loop done")
+
+    # plain, same arrivals, one query at a time
+    plat = np.zeros(N)
+    start = time.perf_counter()
+    for i in range(N):
+        d = start + arr[i] - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        g.single_source(handles[i], int(srcs[i]), out_device_ptr=out.ptr)
+        plat[i] = time.perf_counter() - start - arr[i]
+    plain_span = max(arr[i] + plat[i] for i in range(N)) - arr[0]
+    # plain service rate when never idle
+    t = time.perf_counter()
+    for h, s in zip(handles, srcs):
+        g.single_source(h, int(s), out_device_ptr=out.ptr)
+    plain_sat = N / (time.perf_counter() - t)
+    res = {
+        "metric": "queries/s and p50/p99 latency, served path under Poisson arrivals",
+        "value": round(N / served_span, 2),
+        "unit": "queries/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(served_span * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "serve on kg-%d-%d-L1000: %d mixed queries, Poisson arrivals at %.1f q/s"
+                   % (graph.num_vertices, graph.num_edges, N, rate),
+                   "states_min": int(states.min()), "states_max": int(states.max()),
+                   "slots": g.get_option("max_slots")},
+        "served": {"qps": round(N / served_span, 2), "gteps": round(pe.sum() / served_span / 1e9, 4),
+                   "latency_ms_p50": round(percentile(lat, 50) * 1e3, 3),
+                   "latency_ms_p99": round(percentile(lat, 99) * 1e3, 3),
+                   "saturated_qps": round(qps_sat, 2)},
+        "plain": {"qps": round(N / plain_span, 2), "gteps": round(pe.sum() / plain_span / 1e9, 4),
+                  "latency_ms_p50": round(percentile(plat, 50) * 1e3, 3),
+                  "latency_ms_p99": round(percentile(plat, 99) * 1e3, 3),
+                  "saturated_qps": round(plain_sat, 2)},
+        "arrival_qps": round(rate, 2),
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +337,8 @@ def main():
     ap.add_argument("--host-loop", action="store_true", help="drive levels from the host")
     ap.add_argument("--stacked-alpha", type=int, default=None, help="push->pull threshold of the stacked path")
     ap.add_argument("--levels-only", action="store_true", help="batched workloads: per-level profiles only")
+    ap.add_argument("--serve-queries", type=int, default=256, help="serve workload: queries in the stream")
+    ap.add_argument("--max-slots", type=int, default=0, help="served path: concurrent queries (0 = library default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (for traffic-counter calibration)")
     args = ap.parse_args()
@@ -244,6 +356,8 @@ def main():
               % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "serve":
+        return bench_serve(args)
     t0 = time.time()
     w = build_workload(args.workload, args.scale)
     log("workload %s: V=%d E=%d queries=%d (%.1fs)" % (w.name, w.graph.num_vertices, w.graph.num_edges,

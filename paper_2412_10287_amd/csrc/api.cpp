@@ -143,17 +143,18 @@ size_t rpq::build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, u
     const int32_t ns = static_cast<int32_t>(used.size());
     *nsym_out = ns;
     if (ns > MAX_SYMS) return 0;
-    const size_t tab = static_cast<size_t>(ns) * MAX_STATES * sizeof(uint32_t);
     const size_t sz = qconst_bytes(static_cast<size_t>(ns));
     buf.assign(sz, 0);
+    const QOffsets o = qconst_offsets(static_cast<size_t>(ns));
     QHeader *h = reinterpret_cast<QHeader *>(buf.data());
-    uint32_t *succ = reinterpret_cast<uint32_t *>(buf.data() + sizeof(QHeader));
-    uint32_t *pred = succ + static_cast<size_t>(ns) * MAX_STATES;
-    uint64_t *push_w = reinterpret_cast<uint64_t *>(buf.data() + sizeof(QHeader) + 2 * tab);
-    uint64_t *pull_w = push_w + ns;
-    uint32_t *push_r = reinterpret_cast<uint32_t *>(pull_w + ns);
-    uint32_t *pull_r = push_r + ns;
-    uint32_t *pull_n = pull_r + ns;
+    uint64_t *symmask = reinterpret_cast<uint64_t *>(buf.data() + o.symmask);
+    uint32_t *succ = reinterpret_cast<uint32_t *>(buf.data() + o.succ);
+    uint32_t *pred = reinterpret_cast<uint32_t *>(buf.data() + o.pred);
+    uint64_t *push_w = reinterpret_cast<uint64_t *>(buf.data() + o.push_w);
+    uint64_t *pull_w = reinterpret_cast<uint64_t *>(buf.data() + o.pull_w);
+    uint32_t *push_r = reinterpret_cast<uint32_t *>(buf.data() + o.push_r);
+    uint32_t *pull_r = reinterpret_cast<uint32_t *>(buf.data() + o.pull_r);
+    uint32_t *pull_n = reinterpret_cast<uint32_t *>(buf.data() + o.pull_n);
     h->Q = n->Q;
     h->nsym = ns;
     h->smask = n->smask;
@@ -182,6 +183,7 @@ size_t rpq::build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, u
         if (u < 0) continue;
         succ[u * MAX_STATES + t.from] |= 1u << t.to;
         pred[u * MAX_STATES + t.to] |= 1u << t.from;
+        symmask[t.from * SYM_WORDS + u / 64] |= 1ull << (u % 64);
         h->inmask |= 1u << t.to;
         h->succ_any[t.from] |= 1u << t.to;
     }
@@ -190,19 +192,7 @@ size_t rpq::build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, u
 }
 
 // Device addresses of the tables inside a query-constant block at `base`.
-QueryView rpq::query_view(uint8_t *base, int32_t nsym) {
-    QueryView qv;
-    const size_t tab = static_cast<size_t>(nsym) * MAX_STATES * sizeof(uint32_t);
-    qv.h = reinterpret_cast<const QHeader *>(base);
-    qv.succ = reinterpret_cast<const uint32_t *>(base + sizeof(QHeader));
-    qv.pred = reinterpret_cast<const uint32_t *>(base + sizeof(QHeader) + tab);
-    qv.push_w = reinterpret_cast<const uint64_t *>(base + sizeof(QHeader) + 2 * tab);
-    qv.pull_w = qv.push_w + nsym;
-    qv.push_r = reinterpret_cast<const uint32_t *>(qv.pull_w + nsym);
-    qv.pull_r = qv.push_r + nsym;
-    qv.pull_n = qv.pull_r + nsym;
-    return qv;
-}
+QueryView rpq::query_view(uint8_t *base, int32_t nsym) { return qconst_view(base, static_cast<size_t>(nsym)); }
 
 // ------------------------------------------------------------------ graph
 static rpq_status dev_alloc(rpq_graph *g, void **p, size_t bytes, const char *what) {

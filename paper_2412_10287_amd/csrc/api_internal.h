@@ -63,7 +63,7 @@ struct rpq_graph {
     double stack_beta = 24.0;
     int32_t max_batch = 256;
     int64_t mem_budget = 0;  // 0 = a quarter of the free device memory at first use
-    int32_t max_slots = 64;
+    int32_t max_slots = 128;
     int32_t grid_override = 0;
     std::recursive_mutex mu;
     // cached query constants of the single-query path

@@ -122,6 +122,44 @@ __device__ __forceinline__ bool wave_append4(bool f0, int32_t v0, bool f1, int32
     return ok;
 }
 
+// A set of used symbols (up to MAX_SYMS) as SYM_WORDS 64-bit words.
+struct SymSet {
+    uint64_t w[SYM_WORDS];
+};
+
+// The used symbols with a transition out of some state of S (nsym used
+// symbols in all): the only symbols whose successor set of S can be non-empty.
+__device__ __forceinline__ SymSet symbols_of(const QueryView &qv, uint32_t S, uint32_t nsym) {
+    SymSet r;
+#pragma unroll
+    for (int k = 0; k < SYM_WORDS; k++) r.w[k] = 0;
+    while (S) {
+        const uint64_t *m = qv.symmask + (__ffs(S) - 1) * SYM_WORDS;
+        S &= S - 1;
+#pragma unroll
+        for (int k = 0; k < SYM_WORDS; k++)
+            if (static_cast<uint32_t>(k) * 64 < nsym) r.w[k] |= m[k];
+    }
+    return r;
+}
+
+// Removes the lowest symbol of r and returns it, or ~0u when r is empty.
+__device__ __forceinline__ uint32_t symbol_pop(SymSet &r) {
+    uint32_t out = ~0u;
+    bool found = false;
+#pragma unroll
+    for (int k = 0; k < SYM_WORDS; k++) {
+        const bool here = !found && r.w[k] != 0;
+        if (here) {
+            out = static_cast<uint32_t>(k) * 64 +
+                  static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(r.w[k]))) - 1;
+            r.w[k] &= r.w[k] - 1;
+        }
+        found = found || here;
+    }
+    return out;
+}
+
 __device__ __forceinline__ uint32_t succ_of(const uint32_t *succ, uint32_t u, uint32_t S) {
     const uint32_t *t = succ + u * MAX_STATES;
     uint32_t r = 0;

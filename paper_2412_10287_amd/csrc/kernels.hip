@@ -126,28 +126,32 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n) {
                 v = 0;
             }
         }
-        for (uint32_t u0 = 0; u0 < nsym; u0 += SYM_BATCH) {
-            uint32_t sp[SYM_BATCH], beg[SYM_BATCH], len[SYM_BATCH];
+        // only the symbols with a transition out of S can give an item
+        SymSet Rs = symbols_of(qv, S, nsym);
+        while (true) {
+            uint32_t us[SYM_BATCH], sp[SYM_BATCH], beg[SYM_BATCH], len[SYM_BATCH];
             RankWordD rw[SYM_BATCH];
 #pragma unroll
+            for (int j = 0; j < SYM_BATCH; j++) us[j] = symbol_pop(Rs);
+            if (__ballot(us[0] < nsym) == 0) break;
+#pragma unroll
             for (int j = 0; j < SYM_BATCH; j++) {
-                const uint32_t u = u0 + j;
-                sp[j] = (S && u < nsym) ? succ_of(qv.succ, u, S) : 0u;
-                if (sp[j]) rw[j] = g.rankw[qv.push_w[u] + (v >> 6)];
+                sp[j] = us[j] < nsym ? succ_of(qv.succ, us[j], S) : 0u;
+                if (sp[j]) rw[j] = g.rankw[qv.push_w[us[j]] + (v >> 6)];
             }
             uint32_t cnt = 0, tot = 0;
 #pragma unroll
             for (int j = 0; j < SYM_BATCH; j++) {
                 len[j] = 0;
                 uint32_t e;
-                if (sp[j] && row_range(g, rw[j], qv.push_r[u0 + j], v, beg[j], e)) {
+                if (sp[j] && row_range(g, rw[j], qv.push_r[us[j]], v, beg[j], e)) {
                     if (e > beg[j] && e <= g.ncol) len[j] = e - beg[j];
                     else if (e != beg[j]) flag_violation(p);
                 }
                 if (len[j]) {
                     cnt++;
                     tot += len[j];
-                    if (h.counters) c_pe += static_cast<uint64_t>(count_succ(qv.succ, u0 + j, S)) * len[j];
+                    if (h.counters) c_pe += static_cast<uint64_t>(count_succ(qv.succ, us[j], S)) * len[j];
                 }
             }
             if (h.counters) {

@@ -6,8 +6,12 @@
 
 namespace rpq {
 
-constexpr size_t QC_STRIDE = 64 * 1024;  // bytes of query constants per slot (<= MAX_SYMS symbols)
+constexpr size_t QC_STRIDE = 80 * 1024;  // bytes of query constants per slot (MAX_SYMS symbols fit)
 constexpr int MW = 4;                     // state-word bytes of the multi-query engine
+// select reservations pack items (high 26 bits) and edges (low 38 bits)
+constexpr int SEL_SHIFT = 38;
+constexpr uint64_t MAX_MULTI_ITEMS = 1ull << (64 - SEL_SHIFT);
+constexpr uint32_t MAX_SLOTS_DEV = 256;   // slots the kernels' per-slot LDS tables hold
 
 struct MultiParams {
     GraphView g;
@@ -17,14 +21,14 @@ struct MultiParams {
     uint32_t *q[2];          // combined frontier queues: (slot << vbits) | vertex
     // control block, copied to the host in one transfer per level:
     //   qlen[2] (queue lengths by parity), status (invariant violations),
-    //   next_count[slots] (entries appended per slot this level),
+    //   next_count[slots] (non-zero when the slot's next frontier is not empty),
     //   pairs[slots] (reached (state, vertex) pairs per slot, 8-byte aligned)
     uint32_t *ctl;
-    uint32_t *qlen;
+    uint32_t *qlen[2];        // next-queue lengths by parity (separate lines)
     uint32_t *status;
     uint32_t *next_count;
     uint64_t *pairs;
-    uint64_t *sel;           // [2] select reservations by chunk parity: (items << 40) | edges
+    uint64_t *sel;           // [2] select reservations by chunk parity: (items << SEL_SHIFT) | edges
     uint64_t *it_ebase;      // items: first edge number
     uint32_t *it_beg;        // items: first col position
     uint32_t *it_mask;       // items: successor state set
@@ -44,8 +48,18 @@ hipError_t multi_select(const MultiParams &p, uint32_t parity, uint32_t lo, uint
                         int first_chunk, uint32_t chunk_id, int grid, hipStream_t s);
 hipError_t multi_push(const MultiParams &p, uint32_t parity, uint32_t chunk_id, int grid, hipStream_t s);
 // bytes of the control block for `slots` slots, and the offset of pairs[] in it
-inline size_t multi_ctl_bytes(uint32_t slots) { return 16 + 4 * static_cast<size_t>(slots) + 8 + 8 * static_cast<size_t>(slots); }
-inline size_t multi_pairs_offset(uint32_t slots) { return (16 + 4 * static_cast<size_t>(slots) + 7) & ~static_cast<size_t>(7); }
+// Control block layout (bytes). Each field that kernels update heavily sits
+// on a cache line of its own: the next queue's length (one atomic per wave
+// and step of every push), the per-slot frontier flags (stored by appending
+// lanes) and the per-slot pair counters (atomics at select time).
+constexpr size_t CTL_LINE = 128;
+constexpr size_t CTL_QLEN = 0;              // uint32 qlen[2], one line each
+constexpr size_t CTL_STATUS = 2 * CTL_LINE; // uint32 invariant violations
+constexpr size_t CTL_NEXT = 3 * CTL_LINE;   // uint32 next_count[slots]
+inline size_t multi_pairs_offset(uint32_t slots) {
+    return CTL_NEXT + ((4 * static_cast<size_t>(slots) + CTL_LINE - 1) / CTL_LINE) * CTL_LINE;
+}
+inline size_t multi_ctl_bytes(uint32_t slots) { return multi_pairs_offset(slots) + 8 * static_cast<size_t>(slots); }
 hipError_t multi_extract(const MultiParams &p, uint32_t nfin, const uint32_t *fin_slots, uint64_t nwords,
                          hipStream_t s);
 

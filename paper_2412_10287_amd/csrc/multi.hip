@@ -13,41 +13,10 @@ namespace rpq {
 
 __device__ __forceinline__ void mviolation(const MultiParams &p) { atomicAdd(p.status, 1u); }
 
-// Adds (cnt, pairs) of every lane to its slot's counters with one atomic pair
-// per distinct slot in the wave. All 64 lanes must call it.
-__device__ __forceinline__ void wave_slot_add(const MultiParams &p, uint32_t slot, uint32_t cnt, uint32_t pairs) {
-    const uint32_t lane = lane_id();
-    bool pending = (cnt | pairs) != 0;
-    uint64_t m;
-    while ((m = __ballot(pending)) != 0) {
-        const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-        const uint32_t ls = static_cast<uint32_t>(__shfl(static_cast<int>(slot), leader, 64));
-        const bool match = pending && slot == ls;
-        const uint64_t c = wave_sum(match ? cnt : 0u);
-        const uint64_t q = wave_sum(match ? pairs : 0u);
-        if (static_cast<int>(lane) == leader) {
-            if (c) atomicAdd(&p.next_count[ls], static_cast<uint32_t>(c));
-            if (q) atomicAdd(reinterpret_cast<unsigned long long *>(&p.pairs[ls]), static_cast<unsigned long long>(q));
-        }
-        if (match) pending = false;
-    }
-}
-
 // Tables of slot s (same layout as build_qconst).
 __device__ __forceinline__ QueryView slot_view(const MultiParams &p, uint32_t s) {
     const uint8_t *base = p.qconst + static_cast<size_t>(s) * QC_STRIDE;
-    QueryView qv;
-    qv.h = reinterpret_cast<const QHeader *>(base);
-    const uint32_t nsym = qv.h->nsym;
-    const size_t tab = static_cast<size_t>(nsym) * MAX_STATES * sizeof(uint32_t);
-    qv.succ = reinterpret_cast<const uint32_t *>(base + sizeof(QHeader));
-    qv.pred = reinterpret_cast<const uint32_t *>(base + sizeof(QHeader) + tab);
-    qv.push_w = reinterpret_cast<const uint64_t *>(base + sizeof(QHeader) + 2 * tab);
-    qv.pull_w = qv.push_w + nsym;
-    qv.push_r = reinterpret_cast<const uint32_t *>(qv.pull_w + nsym);
-    qv.pull_r = qv.push_r + nsym;
-    qv.pull_n = qv.pull_r + nsym;
-    return qv;
+    return qconst_view(base, reinterpret_cast<const QHeader *>(base)->nsym);
 }
 
 __global__ void k_multi_admit(MultiParams p, uint32_t parity, uint32_t n, const uint32_t *ss) {
@@ -63,7 +32,7 @@ __global__ void k_multi_admit(MultiParams p, uint32_t parity, uint32_t n, const 
     if (!sm) return;
     // M_0 = Q_S x {source} as a candidate: the next select adds it to P
     p.M[parity][s * p.swords + v] = sm;
-    const uint32_t pos = atomicAdd(&p.qlen[parity], 1u);
+    const uint32_t pos = atomicAdd(p.qlen[parity], 1u);
     if (pos < p.queue_cap) p.q[parity][pos] = (s << p.vbits) | v;
     else mviolation(p);
 }
@@ -76,6 +45,11 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
     const uint32_t V = static_cast<uint32_t>(p.V);
     const uint32_t vmask = (1u << p.vbits) - 1u;
     uint64_t *sel = p.sel + (chunk_id & 1);
+    // reached pairs per slot, summed in LDS and added to the slot counters
+    // once per workgroup
+    __shared__ unsigned long long s_pairs[MAX_SLOTS_DEV];
+    for (uint32_t i = threadIdx.x; i < MAX_SLOTS_DEV; i += BLOCK) s_pairs[i] = 0;
+    __syncthreads();
     // the other reservation counter was read by the previous push, which has
     // finished: clear it for the next chunk
     if (gthread() == 0) p.sel[(chunk_id + 1) & 1] = 0;
@@ -88,7 +62,7 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
             else mviolation(p);
         }
         for (uint32_t i = gthread(); i < p.slots; i += gthreads()) p.next_count[i] = 0;
-        if (gthread() == 0) p.qlen[parity ^ 1] = 0;
+        if (gthread() == 0) *p.qlen[parity ^ 1] = 0;
     }
     const uint32_t *qc = p.q[parity];
     uint32_t *Mc = p.M[parity];
@@ -118,26 +92,27 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
                 s = v = 0;
             }
         }
-        wave_slot_add(p, s, 0u, static_cast<uint32_t>(__popc(S)));
-        // the symbol loop is wave-uniform: run to the wave's largest nsym
-        uint32_t wmax = nsym;
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) wmax = max(wmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(wmax), d, 64)));
-        for (uint32_t u0 = 0; u0 < wmax; u0 += SYM_BATCH) {
-            uint32_t sp[SYM_BATCH], beg[SYM_BATCH], len[SYM_BATCH];
+        if (S) atomicAdd(&s_pairs[s < MAX_SLOTS_DEV ? s : 0], static_cast<unsigned long long>(__popc(S)));
+        // only the symbols with a transition out of S can give an item; the
+        // loop runs until every lane of the wave is done
+        SymSet Rs = symbols_of(qv, S, nsym);
+        while (true) {
+            uint32_t us[SYM_BATCH], sp[SYM_BATCH], beg[SYM_BATCH], len[SYM_BATCH];
             RankWordD rw[SYM_BATCH];
 #pragma unroll
+            for (int j = 0; j < SYM_BATCH; j++) us[j] = symbol_pop(Rs);
+            if (__ballot(us[0] < nsym) == 0) break;
+#pragma unroll
             for (int j = 0; j < SYM_BATCH; j++) {
-                const uint32_t u = u0 + j;
-                sp[j] = (S && u < nsym) ? succ_of(qv.succ, u, S) : 0u;
-                if (sp[j]) rw[j] = g.rankw[qv.push_w[u] + (v >> 6)];
+                sp[j] = us[j] < nsym ? succ_of(qv.succ, us[j], S) : 0u;
+                if (sp[j]) rw[j] = g.rankw[qv.push_w[us[j]] + (v >> 6)];
             }
             uint32_t cnt = 0, tot = 0;
 #pragma unroll
             for (int j = 0; j < SYM_BATCH; j++) {
                 len[j] = 0;
                 uint32_t e;
-                if (sp[j] && row_range(g, rw[j], qv.push_r[u0 + j], v, beg[j], e)) {
+                if (sp[j] && row_range(g, rw[j], qv.push_r[us[j]], v, beg[j], e)) {
                     if (e > beg[j] && e <= g.ncol) len[j] = e - beg[j];
                     else if (e != beg[j]) mviolation(p);
                 }
@@ -147,15 +122,15 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
                 }
             }
             uint64_t wtot;
-            const uint64_t ex = wave_excl_scan((static_cast<uint64_t>(cnt) << 40) | tot, wtot);
+            const uint64_t ex = wave_excl_scan((static_cast<uint64_t>(cnt) << SEL_SHIFT) | tot, wtot);
             if (wtot == 0) continue;
             uint64_t old = 0;
             if (lane == 63) old = atomicAdd(reinterpret_cast<unsigned long long *>(sel), (unsigned long long)wtot);
             old = __shfl(old, 63, 64);
             if (cnt) {
                 const uint64_t mine = old + ex;
-                uint64_t idx = mine >> 40;
-                uint64_t eb = mine & ((1ull << 40) - 1);
+                uint64_t idx = mine >> SEL_SHIFT;
+                uint64_t eb = mine & ((1ull << SEL_SHIFT) - 1);
 #pragma unroll
                 for (int j = 0; j < SYM_BATCH; j++) {
                     if (!len[j]) continue;
@@ -178,6 +153,9 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
             }
         }
     }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < p.slots && i < MAX_SLOTS_DEV; i += BLOCK)
+        if (s_pairs[i]) atomicAdd(reinterpret_cast<unsigned long long *>(&p.pairs[i]), s_pairs[i]);
 }
 
 // Edges [ubase, uend) of the items staged in LDS (cnt of them), four per
@@ -235,10 +213,14 @@ __device__ __forceinline__ void multi_push_range(const MultiParams &p, uint32_t 
                           static_cast<int32_t>((sl[1] << p.vbits) | w[1]), first[2],
                           static_cast<int32_t>((sl[2] << p.vbits) | w[2]), first[3],
                           static_cast<int32_t>((sl[3] << p.vbits) | w[3]), reinterpret_cast<int32_t *>(qn),
-                          &p.qlen[parity ^ 1], static_cast<uint32_t>(p.queue_cap)))
+                          p.qlen[parity ^ 1], static_cast<uint32_t>(p.queue_cap)))
             mviolation(p);
+        // the host only asks whether a slot still has a frontier: a plain
+        // store of 1 (every writer stores the same value), skipped once this
+        // XCD's copy of the flag reads 1
 #pragma unroll
-        for (int k = 0; k < 4; k++) wave_slot_add(p, sl[k], first[k] ? 1u : 0u, 0u);
+        for (int k = 0; k < 4; k++)
+            if (first[k] && p.next_count[sl[k]] == 0u) p.next_count[sl[k]] = 1u;
     }
 }
 
@@ -250,8 +232,8 @@ __global__ __launch_bounds__(BLOCK) void k_multi_push(MultiParams p, uint32_t pa
     __shared__ uint64_t s_eb[TILE + 1];
     __shared__ uint32_t s_beg[TILE + 1], s_mask[TILE + 1], s_slot[TILE + 1];
     const uint64_t sel = __hip_atomic_load(p.sel + (chunk_id & 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t nitems = sel >> 40;
-    const uint64_t T = sel & ((1ull << 40) - 1);
+    const uint64_t nitems = sel >> SEL_SHIFT;
+    const uint64_t T = sel & ((1ull << SEL_SHIFT) - 1);
     if (T == 0 || nitems == 0) return;
     const uint64_t ntiles = (T + TILE - 1) / TILE;
     if (nitems > p.item_cap || ntiles > p.tile_cap) {

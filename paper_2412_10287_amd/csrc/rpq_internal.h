@@ -68,14 +68,19 @@ struct QHeader {
 };
 
 // Layout of the device query-constant block: QHeader, then
+//   symmask[32][4]                           (uint64: per state, the used
+//                                             symbols with a transition out of it)
 //   succ[nsym][32], pred[nsym][32]           (uint32 state sets)
 //   push_w[nsym], pull_w[nsym]               (uint64 rank-word base)
 //   push_r[nsym], pull_r[nsym]               (uint32 rowptr base)
 //   pull_n[nsym]                             (uint32 rows in the pull direction)
 // A forward symbol pushes along OUT rows and pulls along IN rows; an inverse
 // symbol the other way round.
+constexpr int SYM_WORDS = MAX_SYMS / 64;  // uint64 words of a symbol set
+
 struct QueryView {
     const QHeader *h;
+    const uint64_t *symmask;
     const uint32_t *succ;
     const uint32_t *pred;
     const uint64_t *push_w;
@@ -85,9 +90,42 @@ struct QueryView {
     const uint32_t *pull_n;
 };
 
+struct QOffsets {
+    size_t symmask, succ, pred, push_w, pull_w, push_r, pull_r, pull_n, end;
+};
+
+// Byte offsets of the tables in a query-constant block for nsym used symbols.
+__host__ __device__ inline QOffsets qconst_offsets(size_t nsym) {
+    QOffsets o;
+    o.symmask = sizeof(QHeader);
+    o.succ = o.symmask + MAX_STATES * SYM_WORDS * sizeof(uint64_t);
+    o.pred = o.succ + nsym * MAX_STATES * sizeof(uint32_t);
+    o.push_w = o.pred + nsym * MAX_STATES * sizeof(uint32_t);
+    o.pull_w = o.push_w + nsym * sizeof(uint64_t);
+    o.push_r = o.pull_w + nsym * sizeof(uint64_t);
+    o.pull_r = o.push_r + nsym * sizeof(uint32_t);
+    o.pull_n = o.pull_r + nsym * sizeof(uint32_t);
+    o.end = o.pull_n + nsym * sizeof(uint32_t);
+    return o;
+}
+
 // Bytes of the query-constant block for nsym used symbols.
-inline size_t qconst_bytes(size_t nsym) {
-    return sizeof(QHeader) + nsym * (2 * MAX_STATES * sizeof(uint32_t) + 2 * sizeof(uint64_t) + 3 * sizeof(uint32_t));
+inline size_t qconst_bytes(size_t nsym) { return qconst_offsets(nsym).end; }
+
+// Table addresses of the block at `base` (host or device address).
+__host__ __device__ inline QueryView qconst_view(const uint8_t *base, size_t nsym) {
+    const QOffsets o = qconst_offsets(nsym);
+    QueryView qv;
+    qv.h = reinterpret_cast<const QHeader *>(base);
+    qv.symmask = reinterpret_cast<const uint64_t *>(base + o.symmask);
+    qv.succ = reinterpret_cast<const uint32_t *>(base + o.succ);
+    qv.pred = reinterpret_cast<const uint32_t *>(base + o.pred);
+    qv.push_w = reinterpret_cast<const uint64_t *>(base + o.push_w);
+    qv.pull_w = reinterpret_cast<const uint64_t *>(base + o.pull_w);
+    qv.push_r = reinterpret_cast<const uint32_t *>(base + o.push_r);
+    qv.pull_r = reinterpret_cast<const uint32_t *>(base + o.pull_r);
+    qv.pull_n = reinterpret_cast<const uint32_t *>(base + o.pull_n);
+    return qv;
 }
 
 // One BFS level's bookkeeping (a ring of REC_RING entries).

@@ -112,7 +112,11 @@ static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(RPQ_EDEVICE, "hipMemGetInfo failed");
         budget = static_cast<int64_t>(fr / 4);
     }
-    const uint64_t item_cap = std::min<uint64_t>(1ull << 23, static_cast<uint64_t>(g->rows[OUT] + g->rows[IN]) * 4 + 4096);
+    // the item buffer bounds how many queue entries one select handles (each
+    // may yield an item per used symbol); up to 2^26 items, at most an eighth
+    // of the budget
+    uint64_t item_cap = std::min<uint64_t>(MAX_MULTI_ITEMS - 1, static_cast<uint64_t>(g->rows[OUT] + g->rows[IN]) * 4 + 4096);
+    item_cap = std::max<uint64_t>(4096, std::min<uint64_t>(item_cap, static_cast<uint64_t>(budget) / (8 * 20)));
     const uint64_t fixed = item_cap * 20 + (2 * static_cast<uint64_t>(g->E) * slots) / TILE * 4;
     if (static_cast<int64_t>(fixed + per_slot) > budget)
         return fail(RPQ_ENOMEM, "served path: memory budget %lld bytes is below one slot (%llu bytes)",
@@ -142,10 +146,12 @@ static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
     SA(p.q[0], 4 * p.queue_cap);
     SA(p.q[1], 4 * p.queue_cap);
     SA(p.ctl, multi_ctl_bytes(slots));
-    p.qlen = p.ctl;
-    p.status = p.ctl + 2;
-    p.next_count = p.ctl + 4;
-    p.pairs = reinterpret_cast<uint64_t *>(reinterpret_cast<uint8_t *>(p.ctl) + multi_pairs_offset(slots));
+    uint8_t *ctl8 = reinterpret_cast<uint8_t *>(p.ctl);
+    p.qlen[0] = reinterpret_cast<uint32_t *>(ctl8 + CTL_QLEN);
+    p.qlen[1] = reinterpret_cast<uint32_t *>(ctl8 + CTL_QLEN + CTL_LINE);
+    p.status = reinterpret_cast<uint32_t *>(ctl8 + CTL_STATUS);
+    p.next_count = reinterpret_cast<uint32_t *>(ctl8 + CTL_NEXT);
+    p.pairs = reinterpret_cast<uint64_t *>(ctl8 + multi_pairs_offset(slots));
     SA(p.sel, 64);
     SA(p.it_ebase, 8 * item_cap);
     SA(p.it_beg, 4 * item_cap);
@@ -228,12 +234,11 @@ static rpq_status engine_step(rpq_graph *g, ServeState *ss, std::vector<Request>
     }
     ST(hipMemcpyAsync(ss->h_ctl, p.ctl, multi_ctl_bytes(ss->slots), hipMemcpyDeviceToHost, s));
     ST(hipStreamSynchronize(s));
-    const uint32_t *h_qlen = reinterpret_cast<const uint32_t *>(ss->h_ctl);
-    const uint32_t h_status = h_qlen[2];
-    const uint32_t *h_cnt = h_qlen + 4;
+    const uint32_t h_status = *reinterpret_cast<const uint32_t *>(ss->h_ctl + CTL_STATUS);
+    const uint32_t *h_cnt = reinterpret_cast<const uint32_t *>(ss->h_ctl + CTL_NEXT);
     const uint64_t *h_pairs = reinterpret_cast<const uint64_t *>(ss->h_ctl + multi_pairs_offset(ss->slots));
     if (h_status) return fail(RPQ_EDEVICE, "served path: internal invariant violated %u times", h_status);
-    const uint32_t next_len = h_qlen[parity ^ 1];
+    const uint32_t next_len = *reinterpret_cast<const uint32_t *>(ss->h_ctl + CTL_QLEN + (parity ^ 1) * CTL_LINE);
     // 3. retire the queries whose next frontier is empty
     uint32_t nfin = 0;
     for (uint32_t sl = 0; sl < ss->slots; sl++)

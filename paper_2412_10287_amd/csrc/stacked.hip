@@ -193,21 +193,35 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n) {
 #pragma unroll
         for (int k = 0; k < QM; k++) nzc[k] = static_cast<uint32_t>(__popcll(__ballot((nzm >> k) & 1u) & gmask));
         // items: the small NFA factor first (succ_u of the state set), then
-        // the neighbour range of the u-row at w; the G lanes of the group look
-        // up different symbols
-        for (uint32_t u0 = 0; u0 < nsym; u0 += G * SYM_BATCH) {
-            uint32_t tu[SYM_BATCH], beg[SYM_BATCH], len[SYM_BATCH];
+        // the neighbour range of the u-row at w. Only the symbols with a
+        // transition out of S can give an item; lane j of the group looks up
+        // and writes the items of the symbols u with u % G == j
+        SymSet Rs = symbols_of(qv, S, nsym);
+        {
+            constexpr uint64_t PAT = G == 1 ? ~0ull
+                                     : G == 2 ? 0x5555555555555555ull
+                                     : G == 4 ? 0x1111111111111111ull
+                                     : G == 8 ? 0x0101010101010101ull
+                                              : 0x0001000100010001ull;
+#pragma unroll
+            for (int k = 0; k < SYM_WORDS; k++) Rs.w[k] &= PAT << j;
+        }
+        while (true) {
+            uint32_t us[SYM_BATCH], tu[SYM_BATCH], beg[SYM_BATCH], len[SYM_BATCH];
             RankWordD rw[SYM_BATCH];
 #pragma unroll
+            for (int jj = 0; jj < SYM_BATCH; jj++) us[jj] = symbol_pop(Rs);
+            if (__ballot(us[0] < nsym) == 0) break;
+#pragma unroll
             for (int jj = 0; jj < SYM_BATCH; jj++) {
-                const uint32_t u = u0 + jj * G + j;
+                const uint32_t u = us[jj];
                 tu[jj] = (S && u < nsym) ? succ_of(qv.succ, u, S) : 0u;
                 if (tu[jj]) rw[jj] = g.rankw[qv.push_w[u] + (w >> 6)];
             }
             uint32_t cnt = 0, tot = 0;
 #pragma unroll
             for (int jj = 0; jj < SYM_BATCH; jj++) {
-                const uint32_t u = u0 + jj * G + j;
+                const uint32_t u = us[jj];
                 len[jj] = 0;
                 uint32_t e;
                 if (tu[jj] && row_range(g, rw[jj], qv.push_r[u], w, beg[jj], e)) {
@@ -242,7 +256,7 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n) {
 #pragma unroll
                 for (int jj = 0; jj < SYM_BATCH; jj++) {
                     if (!len[jj]) continue;
-                    put_item<G>(p, idx, eb, beg[jj], len[jj], w, u0 + jj * G + j, S);
+                    put_item<G>(p, idx, eb, beg[jj], len[jj], w, us[jj], S);
                     idx++;
                     eb += len[jj];
                 }
