@@ -180,8 +180,8 @@ def bench_batched(args, w):
     t0 = time.perf_counter()
     for k in range(args.steps):
         tickets = [g.submit(nh, s) for s in srcs]
-        for t in tickets:
-            _, st = g.poll(t, timeout_us=-1)
+        for i, t in enumerate(tickets):
+            _, st = g.poll(t, timeout_us=-1, out_device_ptr=out.ptr + 8 * i * words)
             slat.append(st.device_ms * 1e-3)
     sdt = time.perf_counter() - t0
     res["served"] = {"qps": B * args.steps / sdt, "gteps": pe.sum() * args.steps / sdt / 1e9,
@@ -254,7 +254,7 @@ def bench_serve(args):
         t = time.perf_counter()
         tickets = [g.submit(h, int(s)) for h, s in zip(handles, srcs)]
         for tk in tickets:
-            g.poll(tk, timeout_us=-1)
+            g.poll(tk, timeout_us=-1, out_device_ptr=out.ptr)
         return N / (time.perf_counter() - t)
 
     served_saturated()  # warm-up (engine allocation)
@@ -280,7 +280,7 @@ def bench_serve(args):
     lat = np.zeros(N)
     for _ in range(N):
         i, tk, lag = tq.get()
-        _, st = g.poll(tk, timeout_us=-1)
+        _, st = g.poll(tk, timeout_us=-1, out_device_ptr=out.ptr)
         lat[i] = lag + st.device_ms * 1e-3
     th.join()
     served_span = max(arr[i] + lat[i] for i in range(N)) - arr[0]
@@ -423,8 +423,8 @@ def main():
     # up, advanced one level per shared launch (continuous batching)
     def served_step(lat=None):
         tickets = [g.submit(nh, int(s)) for nh, s in zip(nfas, w.sources)]
-        for t in tickets:
-            bm, st = g.poll(t, timeout_us=-1)
+        for i, t in enumerate(tickets):
+            _, st = g.poll(t, timeout_us=-1, out_device_ptr=base_ptr + i * row_bytes)
             if lat is not None:
                 lat.append(st.device_ms * 1e-3)
     for _ in range(args.warmup):

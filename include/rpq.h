@@ -183,14 +183,18 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
  * Served path. rpq_submit copies what it needs (the NFA may be freed after it
  * returns) and queues the query; a scheduler thread admits queued queries into
  * free slots while memory allows, advances all admitted queries level by level
- * in shared launches, and retires finished ones. Thread-safe.
+ * in shared launches, and moves finished answers into a device-side result
+ * pool (2 * slots entries). Thread-safe.
  * rpq_poll waits up to timeout_us microseconds (0 = just check, < 0 = forever):
- * RPQ_OK when finished (bitmap copied to out_bitmap, host memory, and the
- * ticket retired), RPQ_PENDING if not finished and timeout_us == 0,
+ * RPQ_OK when finished (the bitmap copied to out_bitmap: host memory, or
+ * device memory on the graph's GPU with RPQ_OUT_DEVICE; the ticket retired and
+ * its pool entry freed), RPQ_PENDING if not finished and timeout_us == 0,
  * RPQ_ETIMEDOUT if the wait elapsed, RPQ_ENOTFOUND for an unknown ticket.
+ * Finished answers hold their pool entry until polled; while every entry is
+ * held, further finished queries keep their slots and new ones wait.
  */
 rpq_status rpq_submit(rpq_graph *g, const rpq_nfa *n, int32_t source, rpq_ticket *out);
-rpq_status rpq_poll(rpq_graph *g, rpq_ticket t, uint64_t *out_bitmap, rpq_stats *stats,
+rpq_status rpq_poll(rpq_graph *g, rpq_ticket t, uint64_t *out_bitmap, uint32_t flags, rpq_stats *stats,
                     int64_t timeout_us);
 
 /* Thread-local description of the last failure on this thread. */

@@ -34,7 +34,7 @@ struct MultiParams {
     uint32_t *it_mask;       // items: successor state set
     uint32_t *it_slot;       // items: slot
     uint32_t *tile_first;    // first item of each push tile
-    uint64_t *out;           // extract: one bitmap per finished slot (nwords each)
+    uint64_t *out;           // result pool: 3 * slots bitmaps of nwords words (the last slots stage spills)
     uint64_t swords;         // 32-bit words per slot array
     uint64_t item_cap, tile_cap, queue_cap;
     uint32_t slots;

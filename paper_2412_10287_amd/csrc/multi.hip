@@ -285,6 +285,9 @@ __global__ __launch_bounds__(BLOCK) void k_multi_push(MultiParams p, uint32_t pa
 
 // One wavefront per 64-vertex word of each finished slot's answer: the ballot
 // of (P[v] & F != 0) is the word (the product F P of Alg. 1); P is reset.
+// One wavefront per 64-vertex word of each finished slot's answer: the ballot
+// of (P[v] & F != 0) is the word (the product F P of Alg. 1); P is reset.
+// fin holds (slot, result-pool entry) pairs.
 __global__ __launch_bounds__(BLOCK) void k_multi_extract(MultiParams p, uint32_t nfin, const uint32_t *fin,
                                                          uint64_t nwords) {
     const uint32_t V = static_cast<uint32_t>(p.V);
@@ -293,8 +296,8 @@ __global__ __launch_bounds__(BLOCK) void k_multi_extract(MultiParams p, uint32_t
     for (uint64_t gw = gthread() >> 6; gw < total; gw += gthreads() >> 6) {
         const uint32_t f = static_cast<uint32_t>(gw / nwords);
         const uint64_t k = gw % nwords;
-        const uint32_t s = fin[f];
-        if (s >= p.slots) {
+        const uint32_t s = fin[2 * f], entry = fin[2 * f + 1];
+        if (s >= p.slots || entry >= 3 * p.slots) {
             if (lane == 0) mviolation(p);
             continue;
         }
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(BLOCK) void k_multi_extract(MultiParams p, uint32_t
         uint32_t *Ps = p.P + static_cast<uint64_t>(s) * p.swords;
         const uint32_t pv = v < V ? Ps[v] : 0u;
         const uint64_t b = __ballot((pv & fm) != 0);
-        if (lane == 0) p.out[static_cast<uint64_t>(f) * nwords + k] = b;
+        if (lane == 0) p.out[static_cast<uint64_t>(entry) * nwords + k] = b;
         if (pv) Ps[v] = 0;
     }
 }

@@ -36,10 +36,12 @@ struct Request {
 };
 
 struct Ticket {
-    int state = 0;  // 0 queued, 1 running, 2 done
+    int state = 0;  // 0 queued, 1 running, 2 done, 3 being collected by rpq_poll
     rpq_status status = RPQ_OK;
     std::string error;
-    std::vector<uint64_t> bitmap;
+    int64_t entry = -1;          // result-pool entry holding the bitmap (done, RPQ_OK)
+    std::vector<uint64_t> spill; // or the bitmap in host memory (the pool was full)
+    bool empty_result = false;   // no start state: the answer is empty
     rpq_stats stats{};
 };
 
@@ -48,6 +50,9 @@ struct SlotInfo {
     int32_t nsym = 0;
     uint32_t admit_level = 0;
     Clock::time_point submitted;
+    bool finished = false;  // frontier empty; waiting for a result-pool entry
+    uint32_t levels = 0;
+    uint64_t pairs = 0;
 };
 
 struct ServeState {
@@ -74,12 +79,19 @@ struct ServeState {
     uint32_t chunk_id = 0;
     uint32_t cur_len = 0, prev_len = 0;
     uint32_t *d_admit = nullptr, *d_fin = nullptr;
+    // result pool: finished queries' bitmaps stay on the device until polled
+    // (entries [0, pool_n)); entries [pool_n, pool_n + slots) stage answers
+    // that spill to host memory while every pool entry is held
+    uint32_t pool_n = 0;
+    std::vector<uint32_t> free_entries;  // guarded by mu
+    std::vector<uint32_t> ready;         // finished slots to retire (worker only)
+    hipStream_t copy_stream = nullptr;   // rpq_poll's copies out of the pool
+    std::mutex copy_mu;
     // pinned host staging
     uint32_t *h_admit = nullptr;  // 2 * slots
-    uint32_t *h_fin = nullptr;    // slots
+    uint32_t *h_fin = nullptr;    // 2 * slots: (slot, pool entry)
     uint8_t *h_ctl = nullptr;     // control block
     uint8_t *h_qc = nullptr;      // slots * QC_STRIDE
-    uint64_t *h_out = nullptr;    // slots * nwords
     int grid = 1024;
 };
 
@@ -104,8 +116,9 @@ static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
     uint64_t max_by_bits = vb >= 32 ? 1 : (1ull << (32 - vb));
     uint32_t slots = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(g->max_slots), max_by_bits));
     const uint64_t swords = static_cast<uint64_t>(V) + 64;
-    // per slot: P and two frontier arrays (4 B/vertex) + two queue shares (4 B/vertex)
-    const uint64_t per_slot = 3 * 4 * swords + 2 * 4 * static_cast<uint64_t>(V) + QC_STRIDE + 8 * g->nwords;
+    // per slot: P and two frontier arrays (4 B/vertex), two queue shares
+    // (4 B/vertex), query constants and three result-pool bitmaps
+    const uint64_t per_slot = 3 * 4 * swords + 2 * 4 * static_cast<uint64_t>(V) + QC_STRIDE + 24 * g->nwords;
     int64_t budget = g->mem_budget;
     if (budget <= 0) {
         size_t fr = 0, tot = 0;
@@ -158,17 +171,16 @@ static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
     SA(p.it_mask, 4 * item_cap);
     SA(p.it_slot, 4 * item_cap);
     SA(p.tile_first, 4 * p.tile_cap);
-    SA(p.out, 8 * g->nwords * slots);
+    ss->pool_n = 2 * slots;
+    SA(p.out, 8 * g->nwords * (ss->pool_n + slots));
     SA(ss->d_admit, 8 * slots);
-    SA(ss->d_fin, 4 * slots);
+    SA(ss->d_fin, 8 * slots);
 #undef SA
     const size_t ctl_b = (multi_ctl_bytes(slots) + 63) & ~static_cast<size_t>(63);
-    ss->pinned_bytes = 8 * slots + 4 * slots + ctl_b + QC_STRIDE * slots + 8 * g->nwords * slots + 256;
+    ss->pinned_bytes = 8 * slots + 8 * slots + ctl_b + QC_STRIDE * slots + 256;
     if ((e = hipHostMalloc(reinterpret_cast<void **>(&ss->pinned), ss->pinned_bytes, hipHostMallocDefault)) != hipSuccess)
         return fail(RPQ_ENOMEM, "served path: hipHostMalloc: %s", hipGetErrorString(e));
     uint8_t *hp = ss->pinned;
-    ss->h_out = reinterpret_cast<uint64_t *>(hp);
-    hp += 8 * g->nwords * slots;
     ss->h_qc = hp;
     hp += QC_STRIDE * slots;
     ss->h_ctl = hp;
@@ -178,6 +190,8 @@ static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
     ss->h_fin = reinterpret_cast<uint32_t *>(hp);
     if ((e = hipStreamCreateWithFlags(&ss->stream, hipStreamNonBlocking)) != hipSuccess)
         return hip_fail(e, "hipStreamCreate");
+    if ((e = hipStreamCreateWithFlags(&ss->copy_stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "hipStreamCreate");
     for (uint32_t *a : {p.P, p.M[0], p.M[1]})
         if ((e = launch_fill(a, swords * slots, 0, ss->stream)) != hipSuccess) return hip_fail(e, "fill");
     if ((e = launch_fill(p.ctl, multi_ctl_bytes(slots) / 4, 0, ss->stream)) != hipSuccess) return hip_fail(e, "fill");
@@ -186,6 +200,10 @@ static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
     if ((e = hipStreamSynchronize(ss->stream)) != hipSuccess) return hip_fail(e, "sync");
     ss->slot.assign(slots, SlotInfo{});
     for (uint32_t s = slots; s-- > 0;) ss->free_slots.push_back(s);
+    {
+        std::lock_guard<std::mutex> lk(ss->mu);
+        for (uint32_t k = ss->pool_n; k-- > 0;) ss->free_entries.push_back(k);
+    }
     return RPQ_OK;
 }
 
@@ -194,6 +212,8 @@ static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
         hipError_t e_ = (call);                                   \
         if (e_ != hipSuccess) return hip_fail(e_, #call);         \
     } while (0)
+
+static rpq_status retire(rpq_graph *g, ServeState *ss);
 
 // One scheduler iteration with the lock released. Returns a failure status
 // for a device error (the engine then stops and fails every ticket).
@@ -220,7 +240,7 @@ static rpq_status engine_step(rpq_graph *g, ServeState *ss, std::vector<Request>
         ST(multi_admit(p, parity, k, ss->d_admit, s));
         ss->cur_len += k;  // every admitted request has a start state (checked at submit)
     }
-    if (ss->cur_len == 0) return RPQ_OK;
+    if (ss->cur_len == 0) return retire(g, ss);
     // 2. one level for every admitted query, in chunks bounded by the item buffer
     int32_t maxsym = 1;
     for (uint32_t sl = 0; sl < ss->slots; sl++)
@@ -239,45 +259,86 @@ static rpq_status engine_step(rpq_graph *g, ServeState *ss, std::vector<Request>
     const uint64_t *h_pairs = reinterpret_cast<const uint64_t *>(ss->h_ctl + multi_pairs_offset(ss->slots));
     if (h_status) return fail(RPQ_EDEVICE, "served path: internal invariant violated %u times", h_status);
     const uint32_t next_len = *reinterpret_cast<const uint32_t *>(ss->h_ctl + CTL_QLEN + (parity ^ 1) * CTL_LINE);
-    // 3. retire the queries whose next frontier is empty
-    uint32_t nfin = 0;
-    for (uint32_t sl = 0; sl < ss->slots; sl++)
-        if (ss->slot[sl].ticket && h_cnt[sl] == 0) ss->h_fin[nfin++] = sl;
-    if (nfin) {
-        std::vector<uint64_t> fin_pairs(nfin);
-        for (uint32_t f = 0; f < nfin; f++) fin_pairs[f] = h_pairs[ss->h_fin[f]];
-        ST(hipMemcpyAsync(ss->d_fin, ss->h_fin, 4 * nfin, hipMemcpyHostToDevice, s));
-        ST(multi_extract(p, nfin, ss->d_fin, static_cast<uint64_t>(g->nwords), s));
-        ST(hipMemcpyAsync(ss->h_out, p.out, 8 * static_cast<size_t>(g->nwords) * nfin, hipMemcpyDeviceToHost, s));
-        ST(hipStreamSynchronize(s));
-        const Clock::time_point now = Clock::now();
-        std::lock_guard<std::mutex> lk(ss->mu);
-        for (uint32_t f = 0; f < nfin; f++) {
-            const uint32_t sl = ss->h_fin[f];
-            auto it = ss->tickets.find(ss->slot[sl].ticket);
-            if (it != ss->tickets.end()) {
-                Ticket &t = it->second;
-                const uint64_t *src = ss->h_out + static_cast<size_t>(f) * g->nwords;
-                t.bitmap.assign(src, src + g->nwords);
-                t.stats = rpq_stats{};
-                t.stats.levels = static_cast<int32_t>(ss->level - ss->slot[sl].admit_level + 1);
-                t.stats.push_levels = t.stats.levels;
-                t.stats.visited_pairs = static_cast<int64_t>(fin_pairs[f]);
-                t.stats.device_ms =
-                    std::chrono::duration<double, std::milli>(now - ss->slot[sl].submitted).count();
-                t.stats.batch = static_cast<int32_t>(ss->slots - ss->free_slots.size());
-                t.status = RPQ_OK;
-                t.state = 2;
-            }
-            ss->slot[sl] = SlotInfo{};
-            ss->free_slots.push_back(sl);
-            ss->running--;
+    // 3. queries whose next frontier is empty are finished
+    for (uint32_t sl = 0; sl < ss->slots; sl++) {
+        SlotInfo &si = ss->slot[sl];
+        if (si.ticket && !si.finished && h_cnt[sl] == 0) {
+            si.finished = true;
+            si.levels = ss->level - si.admit_level + 1;
+            si.pairs = h_pairs[sl];
+            ss->ready.push_back(sl);
         }
-        ss->cv_done.notify_all();
     }
     ss->prev_len = ss->cur_len;
     ss->cur_len = next_len;
     ss->level++;
+    return retire(g, ss);
+}
+
+// Moves finished queries' answers into result-pool entries (one extract
+// launch for all of them) and frees their slots. When every pool entry is
+// held by an answer nobody has polled yet, the answer is copied to host
+// memory instead, so no poll order can stall the scheduler.
+static rpq_status retire(rpq_graph *g, ServeState *ss) {
+    if (ss->ready.empty()) return RPQ_OK;
+    MultiParams &p = ss->mp;
+    hipStream_t s = ss->stream;
+    const uint32_t nfin = static_cast<uint32_t>(ss->ready.size());  // <= slots
+    uint32_t nspill = 0;
+    {
+        std::lock_guard<std::mutex> lk(ss->mu);
+        for (uint32_t f = 0; f < nfin; f++) {
+            ss->h_fin[2 * f] = ss->ready[f];
+            if (!ss->free_entries.empty()) {
+                ss->h_fin[2 * f + 1] = ss->free_entries.back();
+                ss->free_entries.pop_back();
+            } else {
+                ss->h_fin[2 * f + 1] = ss->pool_n + nspill++;
+            }
+        }
+    }
+    ST(hipMemcpyAsync(ss->d_fin, ss->h_fin, 8 * nfin, hipMemcpyHostToDevice, s));
+    ST(multi_extract(p, nfin, ss->d_fin, static_cast<uint64_t>(g->nwords), s));
+    ST(hipStreamSynchronize(s));
+    std::vector<std::vector<uint64_t>> spilled(nspill);
+    for (uint32_t f = 0, k = 0; f < nfin; f++) {
+        const uint32_t entry = ss->h_fin[2 * f + 1];
+        if (entry < ss->pool_n) continue;
+        spilled[k].resize(static_cast<size_t>(g->nwords));
+        ST(hipMemcpy(spilled[k].data(), p.out + static_cast<size_t>(entry) * g->nwords, 8 * static_cast<size_t>(g->nwords),
+                     hipMemcpyDeviceToHost));
+        k++;
+    }
+    const Clock::time_point now = Clock::now();
+    std::lock_guard<std::mutex> lk(ss->mu);
+    for (uint32_t f = 0, k = 0; f < nfin; f++) {
+        const uint32_t sl = ss->h_fin[2 * f];
+        const uint32_t entry = ss->h_fin[2 * f + 1];
+        const bool spill = entry >= ss->pool_n;
+        SlotInfo &si = ss->slot[sl];
+        auto it = ss->tickets.find(si.ticket);
+        if (it != ss->tickets.end()) {
+            Ticket &t = it->second;
+            if (spill) t.spill.swap(spilled[k]);
+            else t.entry = entry;
+            t.stats = rpq_stats{};
+            t.stats.levels = static_cast<int32_t>(si.levels);
+            t.stats.push_levels = t.stats.levels;
+            t.stats.visited_pairs = static_cast<int64_t>(si.pairs);
+            t.stats.device_ms = std::chrono::duration<double, std::milli>(now - si.submitted).count();
+            t.stats.batch = static_cast<int32_t>(ss->slots - ss->free_slots.size());
+            t.status = RPQ_OK;
+            t.state = 2;
+        } else if (!spill) {
+            ss->free_entries.push_back(entry);
+        }
+        if (spill) k++;
+        si = SlotInfo{};
+        ss->free_slots.push_back(sl);
+        ss->running--;
+    }
+    ss->ready.clear();
+    ss->cv_done.notify_all();
     return RPQ_OK;
 }
 
@@ -311,7 +372,10 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
         admit.clear();
         {
             std::unique_lock<std::mutex> lk(ss->mu);
-            ss->cv_work.wait(lk, [&] { return ss->stop || !ss->pending.empty() || ss->cur_len > 0; });
+            // work: a level to run or a request and a free slot
+            ss->cv_work.wait(lk, [&] {
+                return ss->stop || ss->cur_len > 0 || (!ss->pending.empty() && !ss->free_slots.empty());
+            });
             if (ss->stop && ss->pending.empty() && ss->cur_len == 0) break;
             while (!ss->pending.empty() && admit.size() < ss->free_slots.size()) {
                 admit.push_back(std::move(ss->pending.front()));
@@ -348,6 +412,7 @@ void rpq::serve_shutdown(rpq_graph *g) {
     ss->cv_work.notify_all();
     if (ss->worker.joinable()) ss->worker.join();
     if (ss->stream) (void)hipStreamDestroy(ss->stream);
+    if (ss->copy_stream) (void)hipStreamDestroy(ss->copy_stream);
     if (ss->pinned) (void)hipHostFree(ss->pinned);
     for (void *p : ss->allocs) (void)hipFree(p);
     delete ss;
@@ -383,7 +448,7 @@ rpq_status rpq_submit(rpq_graph *g, const rpq_nfa *n, int32_t source, rpq_ticket
     Ticket &t = ss->tickets[id];
     if (r.smask == 0) {  // no start state: the answer is empty, nothing to run
         t.state = 2;
-        t.bitmap.assign(static_cast<size_t>(g->nwords), 0);
+        t.empty_result = true;
         t.stats.batch = 1;
     } else {
         ss->pending.push_back(std::move(r));
@@ -394,38 +459,73 @@ rpq_status rpq_submit(rpq_graph *g, const rpq_nfa *n, int32_t source, rpq_ticket
     return RPQ_OK;
 }
 
-rpq_status rpq_poll(rpq_graph *g, rpq_ticket t, uint64_t *out_bitmap, rpq_stats *stats, int64_t timeout_us) {
+rpq_status rpq_poll(rpq_graph *g, rpq_ticket t, uint64_t *out_bitmap, uint32_t flags, rpq_stats *stats,
+                    int64_t timeout_us) {
     if (!g || !out_bitmap) return fail(RPQ_EINVAL, "rpq_poll: NULL argument");
     ServeState *ss = g->serve;
     if (!ss) return fail(RPQ_ENOTFOUND, "rpq_poll: unknown ticket %llu", (unsigned long long)t);
-    std::unique_lock<std::mutex> lk(ss->mu);
-    auto it = ss->tickets.find(t);
-    if (it == ss->tickets.end()) return fail(RPQ_ENOTFOUND, "rpq_poll: unknown ticket %llu", (unsigned long long)t);
-    auto done = [&] { return it->second.state == 2; };
-    if (!done()) {
-        if (timeout_us == 0) return RPQ_PENDING;
-        if (timeout_us < 0) ss->cv_done.wait(lk, done);
-        else if (!ss->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done))
-            return fail(RPQ_ETIMEDOUT, "rpq_poll: ticket %llu not finished within %lld us", (unsigned long long)t,
-                        (long long)timeout_us);
-    }
-    Ticket &tk = it->second;
-    const rpq_status st = tk.status;
-    if (st == RPQ_OK) {
-        memcpy(out_bitmap, tk.bitmap.data(), 8 * tk.bitmap.size());
-        if (stats) {
-            rpq_stats in = *stats;
-            *stats = tk.stats;
-            stats->level_counts = in.level_counts;
-            stats->level_cap = in.level_cap;
-            stats->level_us = in.level_us;
-            stats->level_frontier = in.level_frontier;
-            stats->level_edges = in.level_edges;
-            stats->level_select_us = in.level_select_us;
+    const bool dev = (flags & RPQ_OUT_DEVICE) != 0;
+    const size_t bytes = 8 * static_cast<size_t>(g->nwords);
+    int64_t entry = -1;
+    bool empty = false;
+    std::vector<uint64_t> spill;
+    rpq_stats tstats{};
+    {
+        std::unique_lock<std::mutex> lk(ss->mu);
+        auto it = ss->tickets.find(t);
+        if (it == ss->tickets.end() || it->second.state == 3)
+            return fail(RPQ_ENOTFOUND, "rpq_poll: unknown ticket %llu", (unsigned long long)t);
+        auto done = [&] { return it->second.state == 2; };
+        if (!done()) {
+            if (timeout_us == 0) return RPQ_PENDING;
+            if (timeout_us < 0) ss->cv_done.wait(lk, done);
+            else if (!ss->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done))
+                return fail(RPQ_ETIMEDOUT, "rpq_poll: ticket %llu not finished within %lld us", (unsigned long long)t,
+                            (long long)timeout_us);
         }
-    } else {
-        fail(st, "%s", tk.error.c_str());
+        Ticket &tk = it->second;
+        if (tk.status != RPQ_OK) {
+            const rpq_status st = tk.status;
+            fail(st, "%s", tk.error.c_str());
+            ss->tickets.erase(it);
+            return st;
+        }
+        tk.state = 3;  // this call collects it
+        entry = tk.entry;
+        empty = tk.empty_result;
+        spill.swap(tk.spill);
+        tstats = tk.stats;
     }
-    ss->tickets.erase(it);
-    return st;
+    // copy the answer out of the result pool (outside the scheduler's lock)
+    hipError_t e = hipSuccess;
+    if (empty) {
+        if (dev) e = hipMemset(out_bitmap, 0, bytes);
+        else memset(out_bitmap, 0, bytes);
+    } else if (entry < 0) {
+        if (dev) e = hipMemcpy(out_bitmap, spill.data(), bytes, hipMemcpyHostToDevice);
+        else memcpy(out_bitmap, spill.data(), bytes);
+    } else {
+        std::lock_guard<std::mutex> ck(ss->copy_mu);
+        e = hipMemcpyAsync(out_bitmap, ss->mp.out + static_cast<size_t>(entry) * g->nwords, bytes,
+                           dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ss->copy_stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ss->copy_stream);
+    }
+    {
+        std::lock_guard<std::mutex> lk(ss->mu);
+        if (entry >= 0) ss->free_entries.push_back(static_cast<uint32_t>(entry));
+        ss->tickets.erase(t);
+    }
+    ss->cv_work.notify_one();
+    if (e != hipSuccess) return hip_fail(e, "rpq_poll: copying the answer");
+    if (stats) {
+        rpq_stats in = *stats;
+        *stats = tstats;
+        stats->level_counts = in.level_counts;
+        stats->level_cap = in.level_cap;
+        stats->level_us = in.level_us;
+        stats->level_frontier = in.level_frontier;
+        stats->level_edges = in.level_edges;
+        stats->level_select_us = in.level_select_us;
+    }
+    return RPQ_OK;
 }

@@ -83,7 +83,7 @@ def load_library(path: str = LIB_PATH):
         "rpq_single_source": (ctypes.c_int, [P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
         "rpq_multi_source": (ctypes.c_int, [P, P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
         "rpq_submit": (ctypes.c_int, [P, P, i32, ctypes.POINTER(u64)]),
-        "rpq_poll": (ctypes.c_int, [P, u64, P, ctypes.POINTER(rpq_stats), i64]),
+        "rpq_poll": (ctypes.c_int, [P, u64, P, u32, ctypes.POINTER(rpq_stats), i64]),
         "rpq_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -304,11 +304,17 @@ class Graph:
         check(lib.rpq_submit(self.h, nfa.h, int(source), ctypes.byref(t)))
         return t.value
 
-    def poll(self, ticket: int, timeout_us: int = 0):
-        """Returns (bitmap, Stats) when finished, None while pending."""
-        bm = np.zeros(self.words, dtype=np.uint64)
+    def poll(self, ticket: int, timeout_us: int = 0, out_device_ptr: Optional[int] = None):
+        """Returns (bitmap, Stats) when finished, None while pending. With
+        out_device_ptr the bitmap goes to that device address (RPQ_OUT_DEVICE)
+        and (None, Stats) is returned."""
         st, lc = _stats_struct(0)
-        r = lib.rpq_poll(self.h, ctypes.c_uint64(ticket), _p(bm), ctypes.byref(st), int(timeout_us))
+        if out_device_ptr is not None:
+            bm, ptr, fl = None, ctypes.c_void_p(out_device_ptr), OUT_DEVICE
+        else:
+            bm = np.empty(self.words, dtype=np.uint64)
+            ptr, fl = _p(bm), 0
+        r = lib.rpq_poll(self.h, ctypes.c_uint64(ticket), ptr, fl, ctypes.byref(st), int(timeout_us))
         if r in (RPQ_PENDING, RPQ_ETIMEDOUT):
             return None
         check(r)

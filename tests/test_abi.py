@@ -77,4 +77,4 @@ def test_query_argument_checks(rpq):
     assert lib.rpq_multi_source(None, None, None, 0, None, 0, None) == rpq.RPQ_EINVAL
     t = ctypes.c_uint64()
     assert lib.rpq_submit(None, None, 0, ctypes.byref(t)) == rpq.RPQ_EINVAL
-    assert lib.rpq_poll(None, 1, None, None, 0) == rpq.RPQ_EINVAL
+    assert lib.rpq_poll(None, 1, None, 0, None, 0) == rpq.RPQ_EINVAL

@@ -133,3 +133,27 @@ def test_poll_semantics(rpq):
     assert not bm.any()
     with pytest.raises(rpq.RPQError):
         gg.submit(nh, 500)
+
+
+def test_result_pool_backpressure_and_device_output(rpq):
+    # two slots give four result-pool entries: twelve queries submitted before
+    # any poll must wait for entries and slots, then every answer arrives, in
+    # any poll order, to host or device memory
+    w = C.er_workload(n=2000, m=9000, num_labels=4, n_queries=12)
+    og = oracle.Graph(w.graph)
+    gg = rpq.Graph(w.graph)
+    gg.set_option("max_slots", 2)
+    nh = [rpq.NFA(n) for n in w.nfas]
+    tickets = [gg.submit(h, int(s)) for h, s in zip(nh, w.sources)]
+    out = rpq.DeviceBuffer(8 * gg.words)
+    for i in reversed(range(len(tickets))):
+        want = og.ssr(w.nfas[i], int(w.sources[i])).bitmap
+        if i % 2:
+            r = gg.poll(tickets[i], timeout_us=30_000_000)
+            assert r is not None, i  # a stalled scheduler times out instead of hanging
+            bm = r[0]
+        else:
+            r = gg.poll(tickets[i], timeout_us=30_000_000, out_device_ptr=out.ptr)
+            assert r is not None, i
+            bm = out.to_host()
+        assert np.array_equal(bm, want), i
