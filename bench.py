@@ -119,8 +119,13 @@ def bench_batched(args, w):
     srcs = [int(s) for s in w.sources]
     B = len(srcs)
     g.set_option("max_batch", B)
+    tuning = None
     if args.stacked_alpha is not None:
         g.set_option("stacked_alpha", args.stacked_alpha)
+    elif not args.no_tune and args.workload == "kg":
+        from paper_2412_10287_amd import autotune
+        tuning = autotune.tune(g, rpq.TUNE_STACKED, [nh], srcs, cache=None)
+        log("autotune (stacked, one batch): %s" % tuning)
     words = g.words
     out = rpq.DeviceBuffer(8 * B * words)
     pe = np.zeros(B, np.int64)
@@ -203,6 +208,7 @@ def bench_batched(args, w):
         "stacked_vs_plain_qps": round(res["stacked"]["qps"] / res["plain"]["qps"], 2),
         "stacked_same_as_plain": same,
         "stacked_kernel_ms": round(stacked_ms, 3),
+        "tuning": tuning,
         "levels_max": int(lv.max()),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
@@ -337,6 +343,7 @@ def main():
     ap.add_argument("--host-loop", action="store_true", help="drive levels from the host")
     ap.add_argument("--stacked-alpha", type=int, default=None, help="push->pull threshold of the stacked path")
     ap.add_argument("--levels-only", action="store_true", help="batched workloads: per-level profiles only")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
     ap.add_argument("--serve-queries", type=int, default=256, help="serve workload: queries in the stream")
     ap.add_argument("--max-slots", type=int, default=0, help="served path: concurrent queries (0 = library default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -375,6 +382,13 @@ def main():
     base_ptr = out.ptr
     row_bytes = words * 8
     mode = rpq.HOST_LOOP if args.host_loop else 0
+    tuning = None
+    if not args.no_tune:
+        # settings measured on a sample of the queries, before the timed region
+        from paper_2412_10287_amd import autotune
+        k = min(16, len(nfas))
+        tuning = autotune.tune(g, rpq.TUNE_PLAIN, nfas[:k], [int(s) for s in w.sources[:k]], cache=None)
+        log("autotune (plain, %d sample queries): %s" % (k, tuning))
 
     # algorithmic work per query (deterministic; the GPU counters match the oracle's)
     pe = np.zeros(len(nfas), np.int64)
@@ -472,6 +486,7 @@ def main():
         "nonzero_result_words": reached,
         "served": served,
         "served_vs_plain_qps": round(served["qps"] / (len(nfas) * args.steps / dt), 3),
+        "tuning": tuning,
     }
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)

@@ -128,6 +128,8 @@ rpq_status rpq_graph_info(const rpq_graph *g, const char *key, int64_t *value);
  *                (edges of the query's symbols) / alpha; 0 disables pull.
  *  "pull_beta"   pull->push switch: back to push when the frontier has fewer
  *                than num_vertices / beta vertices.
+ *  "persistent_grid"  workgroups of the persistent single-query launch
+ *                (0 = one per CU; larger values are capped at that).
  *  "stacked_alpha", "stacked_beta"  the same two thresholds for
  *                rpq_multi_source (defaults 0, i.e. push only, and 24; pull
  *                needs <= 8 states).
@@ -169,6 +171,16 @@ rpq_status rpq_single_source(rpq_graph *g, const rpq_nfa *n, int32_t source,
                              uint64_t *out_bitmap, uint32_t flags, rpq_stats *stats);
 
 /*
+ * Single-destination reachability (Sec. 2, the SDR map): every vertex s such
+ * that some two-way walk from s to `target` spells a word the NFA accepts.
+ * Evaluated as the single-source query of the reversed automaton (Sec. 4):
+ * each transition turned around with its symbol inverted, start and final
+ * sets swapped. Arguments, flags, output and errors as rpq_single_source.
+ */
+rpq_status rpq_single_destination(rpq_graph *g, const rpq_nfa *n, int32_t target, uint64_t *out_bitmap,
+                                  uint32_t flags, rpq_stats *stats);
+
+/*
  * Many sources under one NFA, stacked into one traversal (the multiple-source
  * direction of Sec. 6): every vertex carries one bit per (state, source). The
  * result of source i is identical to rpq_single_source's and is written to
@@ -196,6 +208,34 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
 rpq_status rpq_submit(rpq_graph *g, const rpq_nfa *n, int32_t source, rpq_ticket *out);
 rpq_status rpq_poll(rpq_graph *g, rpq_ticket t, uint64_t *out_bitmap, uint32_t flags, rpq_stats *stats,
                     int64_t timeout_us);
+
+/*
+ * Autotuner (setting selection by measurement). Times every candidate setting
+ * of one path on a sample of queries and keeps the fastest on the handle:
+ *  RPQ_TUNE_PLAIN: queries nfas[i] from sources[i], i < n_queries, through
+ *    rpq_single_source; tunes "persistent_grid" (workgroups of the persistent
+ *    launch: one per CU, or a half, quarter or eighth of that) and the
+ *    direction thresholds "pull_alpha" / "pull_beta".
+ *  RPQ_TUNE_STACKED: nfas[0] from all n_queries sources through
+ *    rpq_multi_source; tunes "stacked_alpha" / "stacked_beta".
+ * Candidates: alpha in {0 (push only), 1, 2, 4, 8, 16, 64} x beta in
+ * {4, 24, 128}. The time of a setting is the summed device time (HIP events)
+ * of the sample after one warm-up pass with the handle's previous settings.
+ * out receives the chosen values, their time and the previous settings'
+ * time. Errors: RPQ_EINVAL for bad arguments, others as the query paths (the
+ * previous settings are then kept).
+ */
+#define RPQ_TUNE_PLAIN 0
+#define RPQ_TUNE_STACKED 1
+typedef struct {
+    int64_t grid;        /* persistent-launch workgroups chosen (0 = one per CU) */
+    int64_t alpha, beta; /* direction thresholds chosen (alpha 0 = push only) */
+    double best_ms;      /* device time of the sample with the chosen setting */
+    double default_ms;   /* device time with the settings the handle had before */
+    int32_t candidates;  /* settings timed */
+} rpq_tuning;
+rpq_status rpq_autotune(rpq_graph *g, int32_t path, const rpq_nfa *const *nfas, const int32_t *sources,
+                        int32_t n_queries, rpq_tuning *out);
 
 /* Thread-local description of the last failure on this thread. */
 const char *rpq_last_error(void);

@@ -17,7 +17,8 @@ LIB = os.path.join(HERE, "librpq.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "multi.hip", "stacked.hip", "graph_build.cpp", "api.cpp", "serve.cpp", "stacked_host.cpp"]
+SOURCES = ["kernels.hip", "multi.hip", "stacked.hip", "graph_build.cpp", "api.cpp", "serve.cpp", "stacked_host.cpp",
+           "tune.cpp"]
 
 COMMON = [
     "--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-Wall",

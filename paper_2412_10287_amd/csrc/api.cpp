@@ -390,6 +390,9 @@ rpq_status rpq_set_option(rpq_graph *g, const char *key, int64_t value) {
     } else if (!strcmp(key, "pull_beta")) {
         if (value < 1) return fail(RPQ_EINVAL, "rpq_set_option: pull_beta < 1");
         g->pull_beta = static_cast<double>(value);
+    } else if (!strcmp(key, "persistent_grid")) {
+        if (value < 0) return fail(RPQ_EINVAL, "rpq_set_option: persistent_grid < 0");
+        g->plain_grid = static_cast<int32_t>(std::min<int64_t>(value, 1 << 20));
     } else if (!strcmp(key, "stacked_alpha")) {
         if (value < 0) return fail(RPQ_EINVAL, "rpq_set_option: stacked_alpha < 0");
         g->stack_alpha = static_cast<double>(value);
@@ -419,6 +422,7 @@ rpq_status rpq_get_option(const rpq_graph *g, const char *key, int64_t *value) {
     if (!strcmp(key, "stream")) *value = static_cast<int64_t>(reinterpret_cast<intptr_t>(g->user_stream));
     else if (!strcmp(key, "pull_alpha")) *value = static_cast<int64_t>(g->pull_alpha);
     else if (!strcmp(key, "pull_beta")) *value = static_cast<int64_t>(g->pull_beta);
+    else if (!strcmp(key, "persistent_grid")) *value = g->plain_grid;
     else if (!strcmp(key, "stacked_alpha")) *value = static_cast<int64_t>(g->stack_alpha);
     else if (!strcmp(key, "stacked_beta")) *value = static_cast<int64_t>(g->stack_beta);
     else if (!strcmp(key, "max_batch")) *value = g->max_batch;
@@ -474,7 +478,9 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
     uint32_t nlev = 0;
     float expand_ms = 0.f;
     int32_t launches = 0;
-    const int grid_p = g->grid_override ? std::min(g->grid_override, g->pgrid[W]) : g->pgrid[W];
+    int grid_p = g->pgrid[W];
+    if (g->plain_grid) grid_p = std::min(g->plain_grid, grid_p);
+    if (g->grid_override) grid_p = std::min(g->grid_override, grid_p);
     if (!(flags & RPQ_HOST_LOOP) && grid_p > 0) {
         HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(p.st.bar), sizeof(GridBarrier) / 4, 0, s));
         if (timing) HIP_TRY(hipEventRecord(g->ev[2], s));
@@ -559,4 +565,31 @@ rpq_status rpq_single_source(rpq_graph *g, const rpq_nfa *n, int32_t source, uin
     std::lock_guard<std::recursive_mutex> lk(g->mu);
     HIP_TRY(hipSetDevice(g->device));
     return run_single(g, n, source, out_bitmap, flags, stats);
+}
+
+// Single-destination reachability (Sec. 2, the SDR map; Sec. 4 evaluates it
+// as the single-source query of the reversed automaton): every transition
+// turned around with its symbol inverted (a walk read backwards crosses each
+// edge the other way), start and final sets swapped.
+rpq_status rpq_single_destination(rpq_graph *g, const rpq_nfa *n, int32_t target, uint64_t *out_bitmap,
+                                  uint32_t flags, rpq_stats *stats) {
+    if (!g || !n || !out_bitmap) return fail(RPQ_EINVAL, "rpq_single_destination: NULL argument");
+    if (target < 0 || target >= g->V)
+        return fail(RPQ_EINVAL, "rpq_single_destination: target %d outside [0, %d)", target, g->V);
+    if ((flags & RPQ_FORCE_PUSH) && (flags & RPQ_FORCE_PULL))
+        return fail(RPQ_EINVAL, "rpq_single_destination: RPQ_FORCE_PUSH and RPQ_FORCE_PULL together");
+    rpq_nfa rev;
+    rev.Q = n->Q;
+    rev.NL = n->NL;
+    rev.smask = n->fmask;
+    rev.fmask = n->smask;
+    rev.serial = n->serial | (1ull << 63);  // the reversal of n, cached under its own key
+    rev.trans.reserve(n->trans.size());
+    for (const Trans &t : n->trans) {
+        const int32_t inv = t.sym < n->NL ? t.sym + n->NL : t.sym - n->NL;
+        rev.trans.push_back({inv, t.to, t.from});
+    }
+    std::lock_guard<std::recursive_mutex> lk(g->mu);
+    HIP_TRY(hipSetDevice(g->device));
+    return run_single(g, &rev, target, out_bitmap, flags, stats);
 }

@@ -65,6 +65,7 @@ struct rpq_graph {
     int64_t mem_budget = 0;  // 0 = a quarter of the free device memory at first use
     int32_t max_slots = 128;
     int32_t grid_override = 0;
+    int32_t plain_grid = 0;  // persistent single-query launch workgroups (0 = one per CU)
     std::recursive_mutex mu;
     // cached query constants of the single-query path
     rpq::QueryView qv{};

@@ -30,8 +30,15 @@ STATUS_NAMES = {0: "RPQ_OK", 1: "RPQ_PENDING", -1: "RPQ_EINVAL", -2: "RPQ_ENOMEM
 OUT_DEVICE, COUNTERS, KERNEL_TIMING, FORCE_PUSH, FORCE_PULL, HOST_LOOP = 1, 2, 4, 8, 16, 32
 
 EXPORTS = ("rpq_bitmap_words", "rpq_graph_load", "rpq_graph_free", "rpq_graph_info", "rpq_set_option",
-           "rpq_get_option", "rpq_nfa_load", "rpq_nfa_free", "rpq_single_source", "rpq_multi_source",
-           "rpq_submit", "rpq_poll", "rpq_last_error")
+           "rpq_get_option", "rpq_nfa_load", "rpq_nfa_free", "rpq_single_source", "rpq_single_destination",
+           "rpq_multi_source", "rpq_submit", "rpq_poll", "rpq_autotune", "rpq_last_error")
+
+TUNE_PLAIN, TUNE_STACKED = 0, 1
+
+
+class rpq_tuning(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int64), ("alpha", ctypes.c_int64), ("beta", ctypes.c_int64),
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double), ("candidates", ctypes.c_int32)]
 
 
 class rpq_stats(ctypes.Structure):
@@ -81,9 +88,11 @@ def load_library(path: str = LIB_PATH):
         "rpq_nfa_load": (ctypes.c_int, [i32, i32, P, P, P, P, i32, P, i32, ctypes.POINTER(P)]),
         "rpq_nfa_free": (ctypes.c_int, [P]),
         "rpq_single_source": (ctypes.c_int, [P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
+        "rpq_single_destination": (ctypes.c_int, [P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
         "rpq_multi_source": (ctypes.c_int, [P, P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
         "rpq_submit": (ctypes.c_int, [P, P, i32, ctypes.POINTER(u64)]),
         "rpq_poll": (ctypes.c_int, [P, u64, P, u32, ctypes.POINTER(rpq_stats), i64]),
+        "rpq_autotune": (ctypes.c_int, [P, i32, P, P, i32, ctypes.POINTER(rpq_tuning)]),
         "rpq_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -287,6 +296,13 @@ class Graph:
         check(lib.rpq_single_source(self.h, nfa.h, int(source), _p(bm), flags, ctypes.byref(st)))
         return bm, Stats.from_c(st, lc)
 
+    def single_destination(self, nfa: NFA, target: int, flags: int = 0, level_cap: int = 0):
+        """Vertices with a matching walk to `target`: (bitmap, Stats)."""
+        st, lc = _stats_struct(level_cap)
+        bm = np.zeros(self.words, dtype=np.uint64)
+        check(lib.rpq_single_destination(self.h, nfa.h, int(target), _p(bm), flags, ctypes.byref(st)))
+        return bm, Stats.from_c(st, lc)
+
     def multi_source(self, nfa: NFA, sources: Sequence[int], flags: int = 0,
                      out_device_ptr: Optional[int] = None, level_cap: int = 0):
         src = np.ascontiguousarray(sources, dtype=np.int32)
@@ -298,6 +314,21 @@ class Graph:
         bm = np.zeros((src.size, self.words), dtype=np.uint64)
         check(lib.rpq_multi_source(self.h, nfa.h, _p(src), int(src.size), _p(bm), flags, ctypes.byref(st)))
         return bm, Stats.from_c(st, lc)
+
+    def autotune(self, path: int, nfas: Sequence[NFA], sources: Sequence[int]) -> dict:
+        """rpq_autotune: time the candidate settings of `path` (TUNE_PLAIN:
+        nfas[i] from sources[i]; TUNE_STACKED: nfas[0] from every source) and
+        keep the fastest. Returns the chosen values and times."""
+        src = np.ascontiguousarray(sources, dtype=np.int32)
+        hs = (ctypes.c_void_p * len(nfas))(*[n.h.value for n in nfas])
+        out = rpq_tuning()
+        check(lib.rpq_autotune(self.h, int(path), hs, _p(src), int(src.size), ctypes.byref(out)))
+        return {k: getattr(out, k) for k, _ in rpq_tuning._fields_}
+
+    def signature(self) -> str:
+        """A key for per-graph settings: sizes and row counts of the store."""
+        return "V%d-L%d-E%d-R%d-%d" % (self.num_vertices, self.num_labels, self.info("num_edges"),
+                                       self.info("rows_out"), self.info("rows_in"))
 
     def submit(self, nfa: NFA, source: int) -> int:
         t = ctypes.c_uint64()

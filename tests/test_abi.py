@@ -75,6 +75,41 @@ def test_query_argument_checks(rpq):
     out = np.zeros(4, dtype=np.uint64)
     assert lib.rpq_single_source(None, None, 0, ctypes.c_void_p(out.ctypes.data), 0, None) == rpq.RPQ_EINVAL
     assert lib.rpq_multi_source(None, None, None, 0, None, 0, None) == rpq.RPQ_EINVAL
+    assert lib.rpq_single_destination(None, None, 0, ctypes.c_void_p(out.ctypes.data), 0, None) == rpq.RPQ_EINVAL
+    tun = rpq.rpq_tuning()
+    assert lib.rpq_autotune(None, 0, None, None, 1, ctypes.byref(tun)) == rpq.RPQ_EINVAL
     t = ctypes.c_uint64()
     assert lib.rpq_submit(None, None, 0, ctypes.byref(t)) == rpq.RPQ_EINVAL
     assert lib.rpq_poll(None, 1, None, 0, None, 0) == rpq.RPQ_EINVAL
+
+
+def test_tuning_cache_roundtrip(rpq, tmp_path):
+    # the persisted-settings layer (no GPU): a stand-in graph records what the
+    # tuner is asked and which options are applied
+    from paper_2412_10287_amd import autotune
+
+    class FakeGraph:
+        def __init__(self):
+            self.options, self.tuned = {}, 0
+
+        def signature(self):
+            return "V10-L2-E20-R5-5"
+
+        def autotune(self, path, nfas, sources):
+            self.tuned += 1
+            return {"grid": 64, "alpha": 4, "beta": 24, "best_ms": 1.0, "default_ms": 2.0, "candidates": 22}
+
+        def set_option(self, key, value):
+            self.options[key] = value
+
+    cache = str(tmp_path / "tuning.json")
+    g1 = FakeGraph()
+    r1 = autotune.tune(g1, rpq.TUNE_PLAIN, [], [], cache=cache)
+    assert not r1["cached"] and g1.tuned == 1
+    g2 = FakeGraph()
+    r2 = autotune.tune(g2, rpq.TUNE_PLAIN, [], [], cache=cache)
+    assert r2["cached"] and g2.tuned == 0
+    assert g2.options == {"persistent_grid": 64, "pull_alpha": 4, "pull_beta": 24}
+    g3 = FakeGraph()
+    autotune.tune(g3, rpq.TUNE_STACKED, [], [], cache=cache)  # another path: measured again
+    assert g3.tuned == 1 and g3.options == {}

@@ -196,3 +196,46 @@ def test_repeat_is_stable(rpq):
             bm, st = gg.single_source(nh, int(s), level_cap=1024)
             assert np.array_equal(bm, first)
             assert np.array_equal(st.level_counts, st0.level_counts)
+
+
+def test_single_destination(rpq):
+    # SDR(t) = { s : t in SSR(s) } (Sec. 2), checked by running the oracle's
+    # single-source query from every vertex; the GPU runs the reversed,
+    # inverted automaton from t (Sec. 4)
+    rng = np.random.default_rng(21)
+    for case in range(6):
+        g = G.erdos_renyi(120, 420, 3, 100 + case)
+        og = oracle.Graph(g)
+        gg = rpq.Graph(g)
+        text = OC.tiny_expr(rng, g.num_labels, max_leaves=4)
+        nfa = R.compile_regex(text, g.num_labels)
+        nh = rpq.NFA(nfa)
+        reach = np.stack([og.ssr(nfa, s).bitmap for s in range(g.num_vertices)])
+        for t in rng.integers(0, g.num_vertices, size=4):
+            t = int(t)
+            col = (reach[:, t >> 6] >> np.uint64(t & 63)) & np.uint64(1)
+            want = OC.bitmap_of(np.nonzero(col)[0].tolist(), g.num_vertices)
+            for fl in (0, 8, 16):
+                bm, _ = gg.single_destination(nh, t, flags=fl)
+                assert np.array_equal(bm, want), (text, t, fl)
+
+
+def test_autotune_keeps_answers(rpq):
+    # the tuner times its candidates and keeps one; answers under the kept
+    # settings are still the oracle's, on both tuned paths
+    w = C.rmat_workload(scale=12, edge_factor=8, num_labels=8, n_per_template=2)
+    og = oracle.Graph(w.graph)
+    gg = rpq.Graph(w.graph)
+    nh = [rpq.NFA(n) for n in w.nfas]
+    srcs = [int(s) for s in w.sources]
+    rec = gg.autotune(rpq.TUNE_PLAIN, nh, srcs)
+    assert rec["candidates"] >= 22 and rec["best_ms"] <= rec["default_ms"] + 1e-9
+    assert gg.get_option("pull_alpha") == rec["alpha"] and gg.get_option("persistent_grid") == rec["grid"]
+    for h, n, s in zip(nh, w.nfas, srcs):
+        bm, _ = gg.single_source(h, s)
+        assert np.array_equal(bm, og.ssr(n, s).bitmap)
+    rec = gg.autotune(rpq.TUNE_STACKED, nh[:1], srcs * 3)
+    assert gg.get_option("stacked_alpha") == rec["alpha"]
+    bms, _ = gg.multi_source(nh[0], srcs * 3)
+    for i, s in enumerate(srcs * 3):
+        assert np.array_equal(bms[i], og.ssr(w.nfas[0], s).bitmap)
