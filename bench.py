@@ -49,19 +49,37 @@ def build_workload(name: str, scale: int):
     raise SystemExit("unknown workload %r" % name)
 
 
+KERNEL_SOURCES = {
+    "rpq::k_persistent<1>": ("kernels.hip", "device_common.h", "rpq_internal.h"),
+    "rpq::k_stacked<4, 8>": ("stacked.hip", "stacked.h", "device_common.h", "rpq_internal.h"),
+}
+TRAFFIC_FILES = {
+    "rpq::k_persistent<1>": "k_persistent_rmat20_traffic.md",
+    "rpq::k_stacked<4, 8>": "k_stacked_kg20M_traffic.md",
+}
+
+
+def source_sha(kernel: str) -> str:
+    """SHA-256 (first 16 hex digits) of the sources the kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2412_10287_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def committed_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was measured."""
-    import hashlib
+    summary, or None when the kernel's sources changed since it was measured."""
     import re
-    path = os.path.join(ROOT, "profiles", "k_persistent_rmat20_traffic.md")
-    src = os.path.join(ROOT, "paper_2412_10287_amd", "csrc", "kernels.hip")
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES.get(kernel, ""))
     try:
         text = open(path).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    except OSError:
+        sha = source_sha(kernel)
+    except (OSError, KeyError):
         return None
-    m = re.search(r"kernel=(\S+) traffic_bytes_per_launch=(\d+) kernels_hip_sha256_16=(\w+)", text)
+    m = re.search(r"kernel=(.+?) traffic_bytes_per_launch=(\d+) sources_sha256_16=(\w+)", text)
     if not m or m.group(1) != kernel or m.group(3) != sha:
         return None
     return int(m.group(2))
@@ -158,7 +176,8 @@ def bench_batched(args, w):
         kern.append((st.expand_ms, st.expand_launches, st.alg_bytes))
 
     res = {}
-    for name, fn in (("plain", plain_step), ("stacked", stacked_step)):
+    legs = (("stacked", stacked_step),) if args.skip_plain else (("plain", plain_step), ("stacked", stacked_step))
+    for name, fn in legs:
         for _ in range(args.warmup):
             fn()
         rpq.device_synchronize()
@@ -175,6 +194,8 @@ def bench_batched(args, w):
         if lat:
             res[name]["latency_ms_p50"] = percentile(lat, 50) * 1e3
             res[name]["latency_ms_p99"] = percentile(lat, 99) * 1e3
+    kname = "rpq::k_stacked<%d, %d>" % ((B + 63) // 64 if B <= 64 else 1 << ((B + 63) // 64 - 1).bit_length(),
+                                        8 if nfa.num_states <= 8 else 32)
     k_ms = sum(k[0] for k in kern)
     k_launch = sum(k[1] for k in kern)
     k_bytes = sum(k[2] for k in kern)
@@ -183,14 +204,17 @@ def bench_batched(args, w):
     same = bool(np.array_equal(out.to_host().reshape(B, words), plain_ref))
     slat = []
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(0 if args.skip_plain else args.steps):
         tickets = [g.submit(nh, s) for s in srcs]
         for i, t in enumerate(tickets):
             _, st = g.poll(t, timeout_us=-1, out_device_ptr=out.ptr + 8 * i * words)
             slat.append(st.device_ms * 1e-3)
     sdt = time.perf_counter() - t0
-    res["served"] = {"qps": B * args.steps / sdt, "gteps": pe.sum() * args.steps / sdt / 1e9,
-                     "latency_ms_p50": percentile(slat, 50) * 1e3, "latency_ms_p99": percentile(slat, 99) * 1e3}
+    if args.skip_plain:
+        res["plain"] = res["served"] = {}
+    else:
+        res["served"] = {"qps": B * args.steps / sdt, "gteps": pe.sum() * args.steps / sdt / 1e9,
+                         "latency_ms_p50": percentile(slat, 50) * 1e3, "latency_ms_p99": percentile(slat, 99) * 1e3}
     out_json = {
         "metric": "product-graph GTEPS, batched (stacked) path",
         "value": round(res["stacked"]["gteps"], 4),
@@ -205,14 +229,14 @@ def bench_batched(args, w):
         "qps": round(res["stacked"]["qps"], 2),
         "plain": {k: round(v, 4) for k, v in res["plain"].items()},
         "served": {k: round(v, 4) for k, v in res["served"].items()},
-        "stacked_vs_plain_qps": round(res["stacked"]["qps"] / res["plain"]["qps"], 2),
+        "stacked_vs_plain_qps": round(res["stacked"]["qps"] / res["plain"]["qps"], 2) if res["plain"] else None,
         "stacked_same_as_plain": same,
         "stacked_kernel_ms": round(stacked_ms, 3),
         "tuning": tuning,
         "levels_max": int(lv.max()),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                     "kernel": "rpq::k_stacked<%d>" % max(1, 1 << (max(0, (B - 1)) // 64).bit_length()),
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": committed_traffic(kname),
+                     "kernel": kname,
                      "launches": k_launch, "mean_launch_us": round(stacked_ms * 1e3, 1),
                      "alg_bytes_per_launch": round(k_bytes / max(k_launch, 1), 1)},
     }
@@ -344,6 +368,7 @@ def main():
     ap.add_argument("--stacked-alpha", type=int, default=None, help="push->pull threshold of the stacked path")
     ap.add_argument("--levels-only", action="store_true", help="batched workloads: per-level profiles only")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
+    ap.add_argument("--skip-plain", action="store_true", help="batched workloads: time the stacked path only")
     ap.add_argument("--serve-queries", type=int, default=256, help="serve workload: queries in the stream")
     ap.add_argument("--max-slots", type=int, default=0, help="served path: concurrent queries (0 = library default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
