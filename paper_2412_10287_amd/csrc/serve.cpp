@@ -1,4 +1,4 @@
-// Served path: rpq_submit / rpq_poll, and rpq_multi_source on the same engine.
+// Served path: rpq_submit / rpq_poll (continuous batching of independent queries).
 //
 // A scheduler thread owns a multi-query engine (multi.hip). Each admitted
 // query occupies a slot with its own state words; every iteration of the loop
