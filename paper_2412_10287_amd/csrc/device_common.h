@@ -122,6 +122,156 @@ __device__ __forceinline__ bool wave_append4(bool f0, int32_t v0, bool f1, int32
     return ok;
 }
 
+// ------------------------------------------------- workgroup aggregation
+// Atomics on one address are serialised (about 12 ns each on MI355X), so a
+// counter that every wave of the grid updates once per step is a bottleneck
+// at a few thousand waves. The helpers below let a workgroup make one atomic
+// where its waves would make eight. Every thread of the workgroup must call
+// them (workgroup-uniform control flow; blockDim.x == BLOCK).
+constexpr int NWAVE = BLOCK / 64;
+
+__device__ __forceinline__ uint32_t atomic_add_any(uint32_t *p, uint32_t x) { return atomicAdd(p, x); }
+__device__ __forceinline__ uint64_t atomic_add_any(uint64_t *p, uint64_t x) {
+    return atomicAdd(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(x));
+}
+
+// Reserves the workgroup's summed amount on `counter` with one atomic; `wtot`
+// is the calling wave's amount (the same in all its lanes). base receives the
+// wave's first position (its share follows the shares of the lower waves).
+// Also returns whether any lane of the workgroup passed more == true.
+template <typename T>
+__device__ __forceinline__ bool block_reserve(T wtot, bool more, T *counter, T &base) {
+    __shared__ T s_w[NWAVE];
+    __shared__ uint32_t s_more[NWAVE];
+    __shared__ T s_base;
+    const uint32_t wave = threadIdx.x >> 6;
+    const bool wmore = __ballot(more) != 0;
+    if (lane_id() == 0) {
+        s_w[wave] = wtot;
+        s_more[wave] = wmore ? 1u : 0u;
+    }
+    __syncthreads();
+    T off = 0, tot = 0;
+    uint32_t any = 0;
+#pragma unroll
+    for (int k = 0; k < NWAVE; k++) {
+        const T x = s_w[k];
+        if (static_cast<uint32_t>(k) < wave) off += x;
+        tot += x;
+        any |= s_more[k];
+    }
+    if (threadIdx.x == 0 && tot) s_base = atomic_add_any(counter, tot);
+    __syncthreads();
+    base = tot ? s_base + off : T(0);
+    return any != 0;
+}
+
+// block_reserve on two counters at once (same synchronisation cost as one):
+// a 64-bit amount w64 on c64 and a 32-bit amount w32 on c32.
+__device__ __forceinline__ void block_reserve2(uint64_t w64, uint64_t *c64, uint64_t &b64, uint32_t w32,
+                                               uint32_t *c32, uint32_t &b32) {
+    __shared__ uint64_t s_w64[NWAVE], s_b64;
+    __shared__ uint32_t s_w32[NWAVE], s_b32;
+    const uint32_t wave = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        s_w64[wave] = w64;
+        s_w32[wave] = w32;
+    }
+    __syncthreads();
+    uint64_t off64 = 0, tot64 = 0;
+    uint32_t off32 = 0, tot32 = 0;
+#pragma unroll
+    for (int k = 0; k < NWAVE; k++) {
+        const uint64_t x = s_w64[k];
+        const uint32_t y = s_w32[k];
+        if (static_cast<uint32_t>(k) < wave) {
+            off64 += x;
+            off32 += y;
+        }
+        tot64 += x;
+        tot32 += y;
+    }
+    if (threadIdx.x == 0 && tot64) s_b64 = atomic_add_any(c64, tot64);
+    if (threadIdx.x == 64 && tot32) s_b32 = atomic_add_any(c32, tot32);
+    __syncthreads();
+    b64 = tot64 ? s_b64 + off64 : 0ull;
+    b32 = tot32 ? s_b32 + off32 : 0u;
+}
+
+// wave_append4 with one queue reservation per workgroup and step.
+__device__ __forceinline__ bool block_append4(bool f0, int32_t v0, bool f1, int32_t v1, bool f2, int32_t v2, bool f3,
+                                              int32_t v3, int32_t *queue, uint32_t *counter, uint32_t cap) {
+    const uint64_t m0 = __ballot(f0), m1 = __ballot(f1), m2 = __ballot(f2), m3 = __ballot(f3);
+    const uint32_t c0 = static_cast<uint32_t>(__popcll(m0)), c1 = static_cast<uint32_t>(__popcll(m1));
+    const uint32_t c2 = static_cast<uint32_t>(__popcll(m2)), c3 = static_cast<uint32_t>(__popcll(m3));
+    const uint32_t tot = c0 + c1 + c2 + c3;
+    uint32_t base = 0;
+    block_reserve<uint32_t>(tot, false, counter, base);
+    if (tot == 0) return true;
+    const uint64_t below = (1ull << lane_id()) - 1ull;
+    bool ok = true;
+    uint32_t pos;
+    if (f0) {
+        pos = base + static_cast<uint32_t>(__popcll(m0 & below));
+        if (pos < cap) queue[pos] = v0;
+        else ok = false;
+    }
+    if (f1) {
+        pos = base + c0 + static_cast<uint32_t>(__popcll(m1 & below));
+        if (pos < cap) queue[pos] = v1;
+        else ok = false;
+    }
+    if (f2) {
+        pos = base + c0 + c1 + static_cast<uint32_t>(__popcll(m2 & below));
+        if (pos < cap) queue[pos] = v2;
+        else ok = false;
+    }
+    if (f3) {
+        pos = base + c0 + c1 + c2 + static_cast<uint32_t>(__popcll(m3 & below));
+        if (pos < cap) queue[pos] = v3;
+        else ok = false;
+    }
+    return ok;
+}
+
+// wave_append with one queue reservation per workgroup.
+__device__ __forceinline__ bool block_append(bool flag, int32_t value, int32_t *queue, uint32_t *counter,
+                                             uint32_t cap) {
+    const uint64_t m = __ballot(flag);
+    uint32_t base = 0;
+    block_reserve<uint32_t>(static_cast<uint32_t>(__popcll(m)), false, counter, base);
+    if (!flag) return true;
+    const uint32_t pos = base + static_cast<uint32_t>(__popcll(m & ((1ull << lane_id()) - 1ull)));
+    if (pos >= cap) return false;
+    queue[pos] = value;
+    return true;
+}
+
+// Totals over the workgroup of K per-wave values (already reduced over the
+// wave: the same in all its lanes): sums, or ORs for the k with bit k of
+// or_mask set. Thread k < K receives total k, every other thread 0.
+template <int K>
+__device__ __forceinline__ uint64_t block_reduce(const uint64_t (&v)[K], uint32_t or_mask) {
+    __shared__ uint64_t s_part[NWAVE][K];
+    const uint32_t wave = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k++) s_part[wave][k] = v[k];
+    }
+    __syncthreads();
+    uint64_t r = 0;
+    if (threadIdx.x < static_cast<uint32_t>(K)) {
+        const bool use_or = (or_mask >> threadIdx.x) & 1u;
+#pragma unroll
+        for (int w = 0; w < NWAVE; w++) {
+            const uint64_t x = s_part[w][threadIdx.x];
+            r = use_or ? (r | x) : (r + x);
+        }
+    }
+    __syncthreads();  // s_part is free again
+    return r;
+}
+
 // A set of used symbols (up to MAX_SYMS) as SYM_WORDS 64-bit words.
 struct SymSet {
     uint64_t w[SYM_WORDS];

@@ -51,7 +51,7 @@ __device__ __forceinline__ void init_phase(const Params &p) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     const QHeader &h = *p.qv.h;
     LevelRec *r = p.st.rec;
-    r[0] = LevelRec{};
+    rec_clear(r[0]);
     const uint32_t sm = h.smask;
     if (sm) {
         // M_0 = Q_S x {source}, as a candidate that level 0's select adds to P
@@ -70,7 +70,7 @@ __device__ __forceinline__ void init_phase(const Params &p) {
 // reserved per wave with one 64-bit atomic that counts items (high half) and
 // edges (low half) together, so item order and edge numbering agree.
 template <int W>
-__device__ __forceinline__ void select_phase(const Params &p, uint32_t n) {
+__device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32_t bid, uint32_t nblk) {
     const GraphView &g = p.g;
     const QueryView &qv = p.qv;
     const QHeader &h = *qv.h;
@@ -79,11 +79,11 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n) {
     const uint32_t V = static_cast<uint32_t>(g.V);
     uint32_t nq = ld_acq(&R.nq);
     if (nq > V) {
-        if (gthread() == 0) flag_violation(p);
+        if (bid == 0 && threadIdx.x == 0) flag_violation(p);
         nq = V;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        rec[(n + 1) % REC_RING] = LevelRec{};
+    if (bid == 0 && threadIdx.x == 0) {
+        rec_clear(rec[(n + 1) % REC_RING]);
         if (n < LVL_COUNT_CAP) p.st.lvl[static_cast<uint64_t>(n) * LVL_STRIDE + 3] = wall_clock64();
     }
     // frontier words of level n-1 live in the buffer level n writes: clear them
@@ -92,22 +92,33 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n) {
         if (nprev > V) nprev = V;
         uint32_t *Mold = p.st.M[(n + 1) & 1];
         const int32_t *qold = p.st.q[(n + 1) & 1];
-        for (uint32_t i = gthread(); i < nprev; i += gthreads()) {
-            const uint32_t v = static_cast<uint32_t>(qold[i]);
-            if (v < V) st_state<W>(Mold, v, 0);
-            else flag_violation(p);
+        // eight entries per thread and step, all loads before the stores
+        // (one workgroup alone may clear a long queue)
+        const uint32_t stride = nblk * BLOCK;
+        for (uint32_t i0 = bid * BLOCK + threadIdx.x; i0 < nprev; i0 += 8 * stride) {
+            uint32_t vv[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const uint32_t i = i0 + k * stride;
+                vv[k] = i < nprev ? static_cast<uint32_t>(qold[i]) : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                if (i0 + k * stride >= nprev) continue;
+                if (vv[k] < V) st_state<W>(Mold, vv[k], 0);
+                else flag_violation(p);
+            }
         }
     }
     const int32_t *qc = p.st.q[n & 1];
     uint32_t *Mc = p.st.M[n & 1];
     uint32_t *P = p.st.P;
-    const uint32_t lane = lane_id();
-    const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
     const uint32_t nsym = h.nsym;
     uint64_t c_pe = 0, c_sc = 0, c_sd = 0, pairs = 0;
     uint32_t nfront = 0, su = 0;
-    for (uint32_t base = gw * 64; base < nq; base += nw * 64) {
-        const uint32_t i = base + lane;
+    // workgroup-uniform loop: item reservations are made per workgroup
+    for (uint32_t bbase = bid * BLOCK; bbase < nq; bbase += nblk * BLOCK) {
+        const uint32_t i = bbase + threadIdx.x;
         uint32_t v = 0, S = 0;
         if (i < nq) {
             v = static_cast<uint32_t>(qc[i]);
@@ -126,14 +137,17 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n) {
                 v = 0;
             }
         }
-        // only the symbols with a transition out of S can give an item
+        // only the symbols with a transition out of S can give an item; the
+        // rounds continue while any lane of the workgroup has symbols left
         SymSet Rs = symbols_of(qv, S, nsym);
         while (true) {
             uint32_t us[SYM_BATCH], sp[SYM_BATCH], beg[SYM_BATCH], len[SYM_BATCH];
             RankWordD rw[SYM_BATCH];
 #pragma unroll
             for (int j = 0; j < SYM_BATCH; j++) us[j] = symbol_pop(Rs);
-            if (__ballot(us[0] < nsym) == 0) break;
+            bool more = false;
+#pragma unroll
+            for (int k = 0; k < SYM_WORDS; k++) more = more || Rs.w[k] != 0;
 #pragma unroll
             for (int j = 0; j < SYM_BATCH; j++) {
                 sp[j] = us[j] < nsym ? succ_of(qv.succ, us[j], S) : 0u;
@@ -160,13 +174,10 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n) {
             }
             uint64_t wtot;
             const uint64_t ex = wave_excl_scan((static_cast<uint64_t>(cnt) << 32) | tot, wtot);
-            if (wtot == 0) continue;
-            uint64_t old = 0;
-            if (lane == 63)
-                old = atomicAdd(reinterpret_cast<unsigned long long *>(&R.sel), static_cast<unsigned long long>(wtot));
-            old = __shfl(old, 63, 64);
+            uint64_t wbase;
+            const bool bmore = block_reserve<uint64_t>(wtot, more, &R.sel, wbase);
             if (cnt) {
-                const uint64_t mine = old + ex;
+                const uint64_t mine = wbase + ex;
                 uint32_t idx = static_cast<uint32_t>(mine >> 32);
                 uint32_t eb = static_cast<uint32_t>(mine);
 #pragma unroll
@@ -189,28 +200,25 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n) {
                     eb += len[j];
                 }
             }
+            if (!bmore) break;
         }
     }
-    pairs = wave_sum(pairs);
+    // level totals: one atomic per workgroup and field
     const uint64_t nf = wave_sum(static_cast<uint64_t>(nfront));
-    su = wave_or(su);
-    if (lane == 0) {
-        if (pairs) atomicAdd(reinterpret_cast<unsigned long long *>(&R.pairs), static_cast<unsigned long long>(pairs));
-        if (nf) atomicAdd(&R.nfront, static_cast<uint32_t>(nf));
-        if (su) atomicOr(&R.su, su);
+    {
+        const uint64_t v[3] = {wave_sum(pairs), nf, wave_or(su)};
+        const uint64_t t = block_reduce<3>(v, 4u);
+        if (t) {
+            if (threadIdx.x == 0) atomicAdd(reinterpret_cast<unsigned long long *>(&R.pairs), (unsigned long long)t);
+            if (threadIdx.x == 1) atomicAdd(&R.nfront, static_cast<uint32_t>(t));
+            if (threadIdx.x == 2) atomicOr(&R.su, static_cast<uint32_t>(t));
+        }
     }
     if (h.counters) {
-        c_pe = wave_sum(c_pe);
-        c_sc = wave_sum(c_sc);
-        c_sd = wave_sum(c_sd);
-        if (lane == 0) {
-            if (c_pe | c_sc) {
-                atomicAdd(reinterpret_cast<unsigned long long *>(&p.st.cnt[0]), (unsigned long long)c_pe);
-                atomicAdd(reinterpret_cast<unsigned long long *>(&p.st.cnt[1]), (unsigned long long)c_sc);
-                atomicAdd(reinterpret_cast<unsigned long long *>(&p.st.cnt[2]), (unsigned long long)c_sd);
-            }
-            if (nf) atomicAdd(reinterpret_cast<unsigned long long *>(&p.st.cnt[3]), (unsigned long long)nf);
-        }
+        const uint64_t v[4] = {wave_sum(c_pe), wave_sum(c_sc), wave_sum(c_sd), nf};
+        const uint64_t t = block_reduce<4>(v, 0u);
+        if (t && threadIdx.x < 4)
+            atomicAdd(reinterpret_cast<unsigned long long *>(&p.st.cnt[threadIdx.x]), (unsigned long long)t);
     }
 }
 
@@ -292,8 +300,8 @@ __device__ __forceinline__ void push_range(const Params &p, uint32_t n, const ui
         bool first[4];
 #pragma unroll
         for (int k = 0; k < 4; k++) first[k] = cand[k] ? or_state<W>(Mn, w[k], cand[k]) == 0 : false;
-        if (!wave_append4(first[0], static_cast<int32_t>(w[0]), first[1], static_cast<int32_t>(w[1]), first[2],
-                          static_cast<int32_t>(w[2]), first[3], static_cast<int32_t>(w[3]), qn, qlen, V))
+        if (!block_append4(first[0], static_cast<int32_t>(w[0]), first[1], static_cast<int32_t>(w[1]), first[2],
+                           static_cast<int32_t>(w[2]), first[3], static_cast<int32_t>(w[3]), qn, qlen, V))
             flag_violation(p);
     }
 }
@@ -305,13 +313,13 @@ __device__ __forceinline__ void push_range(const Params &p, uint32_t n, const ui
 // workgroups each tile is split into parts of at least a wave's worth.
 template <int W>
 __device__ __forceinline__ void push_phase(const Params &p, uint32_t n, uint32_t *s_eb, uint32_t *s_beg,
-                                           uint32_t *s_mask) {
+                                           uint32_t *s_mask, uint32_t bid, uint32_t nblk) {
     const uint64_t sel = ld_acq(&p.st.rec[n % REC_RING].sel);
     const uint32_t nitems = static_cast<uint32_t>(sel >> 32);
     const uint32_t T = static_cast<uint32_t>(sel);
     if (T == 0 || nitems == 0) return;
     if (nitems > p.st.item_cap) {
-        if (gthread() == 0) flag_violation(p);
+        if (bid == 0 && threadIdx.x == 0) flag_violation(p);
         return;
     }
     const uint32_t tid = threadIdx.x;
@@ -322,9 +330,9 @@ __device__ __forceinline__ void push_phase(const Params &p, uint32_t n, uint32_t
             s_mask[j] = p.st.it_mask[j];
         }
         __syncthreads();
-        uint32_t per = (T + gridDim.x - 1) / gridDim.x;
+        uint32_t per = (T + nblk - 1) / nblk;
         per = (per + 63) & ~63u;
-        const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * per;
+        const uint64_t b0 = static_cast<uint64_t>(bid) * per;
         const uint32_t b1 = b0 + per < T ? static_cast<uint32_t>(b0 + per) : T;
         if (b0 < b1) push_range<W>(p, n, s_eb, s_beg, s_mask, nitems, static_cast<uint32_t>(b0), b1);
         __syncthreads();
@@ -332,9 +340,9 @@ __device__ __forceinline__ void push_phase(const Params &p, uint32_t n, uint32_t
     }
     const uint32_t ntiles = (T + TILE - 1) / TILE;
     uint32_t sub = 1;
-    while (sub < TILE / 64 && ntiles * sub * 2 <= gridDim.x) sub *= 2;
+    while (sub < TILE / 64 && ntiles * sub * 2 <= nblk) sub *= 2;
     const uint32_t part = TILE / sub;
-    for (uint32_t vt = blockIdx.x; vt < ntiles * sub; vt += gridDim.x) {
+    for (uint32_t vt = bid; vt < ntiles * sub; vt += nblk) {
         const uint32_t tile = vt / sub, k = vt % sub;
         uint32_t i0 = tile < p.st.tile_cap ? p.st.tile_first[tile] : 0u;
         uint32_t i1 = (tile + 1 < ntiles && tile + 1 < p.st.tile_cap) ? p.st.tile_first[tile + 1] : nitems - 1;
@@ -422,9 +430,9 @@ __device__ __forceinline__ void pull_phase(const Params &p, uint32_t n, uint32_t
     const uint32_t nsym = h.nsym;
     if (threadIdx.x == 0) *s_hn = 0;
     __syncthreads();
-    const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
-    for (uint32_t base = gw * 64; base < V; base += nw * 64) {
-        const uint32_t w = base + lane;
+    // workgroup-uniform loop: queue reservations are made per workgroup
+    for (uint32_t bbase = blockIdx.x * BLOCK; bbase < V; bbase += gridDim.x * BLOCK) {
+        const uint32_t w = bbase + threadIdx.x;
         uint32_t acc = 0;
         if (w < V) {
             const uint32_t pw = ld_state<W>(P, w);
@@ -473,7 +481,7 @@ __device__ __forceinline__ void pull_phase(const Params &p, uint32_t n, uint32_t
                 if (acc) st_state<W>(Mn, w, acc);  // only unvisited states: the next select adds them to P
             }
         }
-        if (!wave_append(acc != 0, static_cast<int32_t>(w), qn, &RN.nq, V)) flag_violation(p);
+        if (!block_append(acc != 0, static_cast<int32_t>(w), qn, &RN.nq, V)) flag_violation(p);
     }
     __syncthreads();
     // heavy vertices of this workgroup: one wavefront each, 64 neighbours per step
@@ -544,6 +552,54 @@ __device__ __forceinline__ void final_phase(const Params &p, uint32_t nlev) {
     }
 }
 
+// ------------------------------------------------------------ small levels
+// A level with a short queue and few push edges is mostly fixed cost: two
+// grid barriers (about 6 us each) and two dependent chains of loads. Such
+// levels run in workgroup 0 alone, one after the other, with workgroup
+// barriers in place of grid barriers, while the other workgroups wait at a
+// single grid barrier. The phases and every array they touch are the same as
+// in the grid-wide loop; all waves of workgroup 0 share one compute unit, so
+// a workgroup barrier orders their memory accesses.
+constexpr uint32_t SOLO_MAX_QUEUE = 1024;  // candidate queue entries of a small level
+constexpr uint32_t SOLO_MAX_EDGES = 8192;  // push edges of a small level
+constexpr uint32_t SOLO_MAX_RUN = 2048;    // levels per run (the waiting workgroups' barrier times out after 5 s)
+
+__device__ __forceinline__ void solo_sync() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// Runs levels n, n+1, ... in workgroup 0 while they are small. Leaves in
+// bar->solo_n the first level not finished, and in bar->solo_sel whether its
+// select phase is already done (it was too large to push here, or the
+// direction switch chose pull).
+template <int W>
+__device__ __forceinline__ void solo_levels(const Params &p, uint32_t n, uint32_t *s_eb, uint32_t *s_beg,
+                                            uint32_t *s_mask, uint32_t &npush) {
+    uint32_t sel_done = 0;
+    for (uint32_t run = 0; run < SOLO_MAX_RUN; run++) {
+        const uint32_t nq = ld_acq(&p.st.rec[n % REC_RING].nq);
+        if (nq == 0 || nq > SOLO_MAX_QUEUE) break;
+        select_phase<W>(p, n, 0, 1);
+        solo_sync();
+        const uint32_t mode = decide(p, n);
+        const uint64_t T = ld_acq(&p.st.rec[n % REC_RING].sel) & 0xffffffffull;
+        if (mode != 0 || T > SOLO_MAX_EDGES) {
+            sel_done = 1;
+            break;
+        }
+        if (threadIdx.x == 0) record_level(p, n, 0);
+        push_phase<W>(p, n, s_eb, s_beg, s_mask, 0, 1);
+        solo_sync();
+        npush++;
+        n++;
+    }
+    if (threadIdx.x == 0) {
+        p.st.bar->solo_n = n;
+        p.st.bar->solo_sel = sel_done;
+    }
+}
+
 // ---------------------------------------------------------------- kernels
 template <int W>
 __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
@@ -554,14 +610,27 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
     if (!barrier_register(bar, bc)) return;
     init_phase<W>(p);
     if (!grid_barrier(bar, bc)) return;
-    uint32_t n = 0, npush = 0, npull = 0;
+    uint32_t n = 0, npush = 0, npull = 0, solo_at = ~0u;
     while (true) {
-        if (ld_acq(&p.st.rec[n % REC_RING].nq) == 0) break;
-        select_phase<W>(p, n);
-        if (!grid_barrier(bar, bc)) return;
+        const uint32_t nq = ld_acq(&p.st.rec[n % REC_RING].nq);
+        if (nq == 0) break;
+        bool selected = false;
+        if (nq <= SOLO_MAX_QUEUE && n != solo_at) {
+            // a run of small levels in workgroup 0; the rest wait here
+            solo_at = n;
+            if (blockIdx.x == 0) solo_levels<W>(p, n, s_eb, s_beg, s_mask, npush);
+            if (!grid_barrier(bar, bc)) return;
+            n = ld_acq(&bar->solo_n);
+            selected = ld_acq(&bar->solo_sel) != 0;
+            if (!selected) continue;
+        }
+        if (!selected) {
+            select_phase<W>(p, n, blockIdx.x, gridDim.x);
+            if (!grid_barrier(bar, bc)) return;
+        }
         const uint32_t mode = decide(p, n);
         if (blockIdx.x == 0 && threadIdx.x == 0) record_level(p, n, mode);
-        if (mode == 0) push_phase<W>(p, n, s_eb, s_beg, s_mask);
+        if (mode == 0) push_phase<W>(p, n, s_eb, s_beg, s_mask, blockIdx.x, gridDim.x);
         else pull_phase<W>(p, n, s_eb, s_beg, s_mask, &s_hn);
         npush += mode == 0;
         npull += mode != 0;
@@ -583,7 +652,7 @@ __global__ __launch_bounds__(64) void k_init(Params p) {
 
 template <int W>
 __global__ __launch_bounds__(BLOCK) void k_select(Params p, uint32_t n) {
-    select_phase<W>(p, n);
+    select_phase<W>(p, n, blockIdx.x, gridDim.x);
 }
 
 template <int W>
@@ -595,7 +664,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(Params p, uint32_t n) {
         p.st.status[0] = n + 1;
         p.st.status[1 + (mode != 0)] += 1;
     }
-    if (mode == 0) push_phase<W>(p, n, s_eb, s_beg, s_mask);
+    if (mode == 0) push_phase<W>(p, n, s_eb, s_beg, s_mask, blockIdx.x, gridDim.x);
     else pull_phase<W>(p, n, s_eb, s_beg, s_mask, &s_hn);
 }
 

@@ -66,11 +66,10 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
     }
     const uint32_t *qc = p.q[parity];
     uint32_t *Mc = p.M[parity];
-    const uint32_t lane = lane_id();
-    const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
     const GraphView &g = p.g;
-    for (uint32_t base = lo + gw * 64; base < hi; base += nw * 64) {
-        const uint32_t i = base + lane;
+    // workgroup-uniform loop: item reservations are made per workgroup
+    for (uint32_t bbase = lo + blockIdx.x * BLOCK; bbase < hi; bbase += gridDim.x * BLOCK) {
+        const uint32_t i = bbase + threadIdx.x;
         uint32_t s = 0, v = 0, S = 0, nsym = 0;
         QueryView qv{};
         if (i < hi) {
@@ -94,14 +93,16 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
         }
         if (S) atomicAdd(&s_pairs[s < MAX_SLOTS_DEV ? s : 0], static_cast<unsigned long long>(__popc(S)));
         // only the symbols with a transition out of S can give an item; the
-        // loop runs until every lane of the wave is done
+        // rounds continue while any lane of the workgroup has symbols left
         SymSet Rs = symbols_of(qv, S, nsym);
         while (true) {
             uint32_t us[SYM_BATCH], sp[SYM_BATCH], beg[SYM_BATCH], len[SYM_BATCH];
             RankWordD rw[SYM_BATCH];
 #pragma unroll
             for (int j = 0; j < SYM_BATCH; j++) us[j] = symbol_pop(Rs);
-            if (__ballot(us[0] < nsym) == 0) break;
+            bool more = false;
+#pragma unroll
+            for (int k = 0; k < SYM_WORDS; k++) more = more || Rs.w[k] != 0;
 #pragma unroll
             for (int j = 0; j < SYM_BATCH; j++) {
                 sp[j] = us[j] < nsym ? succ_of(qv.succ, us[j], S) : 0u;
@@ -123,12 +124,10 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
             }
             uint64_t wtot;
             const uint64_t ex = wave_excl_scan((static_cast<uint64_t>(cnt) << SEL_SHIFT) | tot, wtot);
-            if (wtot == 0) continue;
-            uint64_t old = 0;
-            if (lane == 63) old = atomicAdd(reinterpret_cast<unsigned long long *>(sel), (unsigned long long)wtot);
-            old = __shfl(old, 63, 64);
+            uint64_t wbase;
+            const bool bmore = block_reserve<uint64_t>(wtot, more, sel, wbase);
             if (cnt) {
-                const uint64_t mine = old + ex;
+                const uint64_t mine = wbase + ex;
                 uint64_t idx = mine >> SEL_SHIFT;
                 uint64_t eb = mine & ((1ull << SEL_SHIFT) - 1);
 #pragma unroll
@@ -151,6 +150,7 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
                     eb += len[j];
                 }
             }
+            if (!bmore) break;
         }
     }
     __syncthreads();
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
 
 // Edges [ubase, uend) of the items staged in LDS (cnt of them), four per
 // thread and step: the loads of col and P for all four, then the atomics,
-// then one queue reservation per wave. The states of an item not yet in P[w]
+// then one queue reservation per workgroup. The states of an item not yet in P[w]
 // are ORed into w's next word; the first writer appends (slot, w).
 __device__ __forceinline__ void multi_push_range(const MultiParams &p, uint32_t parity, const uint64_t *s_eb,
                                                  const uint32_t *s_beg, const uint32_t *s_mask, const uint32_t *s_slot,
@@ -209,11 +209,11 @@ __device__ __forceinline__ void multi_push_range(const MultiParams &p, uint32_t 
         bool first[4];
 #pragma unroll
         for (int k = 0; k < 4; k++) first[k] = cand[k] ? atomicOr(&Mn[sl[k] * p.swords + w[k]], cand[k]) == 0u : false;
-        if (!wave_append4(first[0], static_cast<int32_t>((sl[0] << p.vbits) | w[0]), first[1],
-                          static_cast<int32_t>((sl[1] << p.vbits) | w[1]), first[2],
-                          static_cast<int32_t>((sl[2] << p.vbits) | w[2]), first[3],
-                          static_cast<int32_t>((sl[3] << p.vbits) | w[3]), reinterpret_cast<int32_t *>(qn),
-                          p.qlen[parity ^ 1], static_cast<uint32_t>(p.queue_cap)))
+        if (!block_append4(first[0], static_cast<int32_t>((sl[0] << p.vbits) | w[0]), first[1],
+                           static_cast<int32_t>((sl[1] << p.vbits) | w[1]), first[2],
+                           static_cast<int32_t>((sl[2] << p.vbits) | w[2]), first[3],
+                           static_cast<int32_t>((sl[3] << p.vbits) | w[3]), reinterpret_cast<int32_t *>(qn),
+                           p.qlen[parity ^ 1], static_cast<uint32_t>(p.queue_cap)))
             mviolation(p);
         // the host only asks whether a slot still has a frontier: a plain
         // store of 1 (every writer stores the same value), skipped once this
@@ -283,8 +283,6 @@ __global__ __launch_bounds__(BLOCK) void k_multi_push(MultiParams p, uint32_t pa
     }
 }
 
-// One wavefront per 64-vertex word of each finished slot's answer: the ballot
-// of (P[v] & F != 0) is the word (the product F P of Alg. 1); P is reset.
 // One wavefront per 64-vertex word of each finished slot's answer: the ballot
 // of (P[v] & F != 0) is the word (the product F P of Alg. 1); P is reset.
 // fin holds (slot, result-pool entry) pairs.

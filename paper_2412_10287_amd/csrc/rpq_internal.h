@@ -128,16 +128,37 @@ __host__ __device__ inline QueryView qconst_view(const uint8_t *base, size_t nsy
     return qv;
 }
 
-// One BFS level's bookkeeping (a ring of REC_RING entries).
-struct LevelRec {
+// One BFS level's bookkeeping (a ring of REC_RING entries). Every field that
+// the whole grid updates with atomics sits on a 128-byte line of its own:
+// atomics on one line are serialised (about 12 ns each on MI355X), so fields
+// sharing a line would queue behind each other's updates.
+struct alignas(128) LevelRec {
     uint32_t nq;          // frontier vertices (queue length) of this level
-    uint32_t su;          // union of the frontier's state sets
-    uint64_t pairs;       // |M_n|
+    uint32_t pad_nq[31];
     uint64_t sel;         // select phase: (items << 32) | push edges
+    uint64_t pad_sel[15];
+    uint64_t pairs;       // |M_n|
+    uint64_t pad_pairs[15];
+    uint32_t nfront;      // vertices with a non-empty frontier set
+    uint32_t pad_nfront[31];
+    uint32_t su;          // union of the frontier's state sets
+    uint32_t pad_su[31];
     uint32_t mode;        // 0 push, 1 pull (decided when the level is expanded)
-    uint32_t nfront;      // stacked path: vertices with a non-empty frontier set
+    uint32_t pad_mode;
     uint64_t hsel;        // stacked pull: long rows deferred to the edge-balanced pass, (items << 32) | edges
+    uint64_t pad_hsel[14];
 };
+
+// Resets the fields of a level record (one thread).
+__device__ __forceinline__ void rec_clear(LevelRec &r) {
+    r.nq = 0;
+    r.sel = 0;
+    r.pairs = 0;
+    r.nfront = 0;
+    r.su = 0;
+    r.mode = 0;
+    r.hsel = 0;
+}
 
 // Two-level grid barrier state (see grid_barrier in kernels.hip).
 struct GridBarrier {
@@ -145,7 +166,8 @@ struct GridBarrier {
     uint32_t nreg;                // workgroups registered in total
     uint32_t abort;               // a wait timed out; the launch ends early
     uint32_t gcount, ggen;        // XCD leaders arrived / generation
-    uint32_t pad0[12];
+    uint32_t solo_n, solo_sel;    // where a run of small levels in workgroup 0 stopped
+    uint32_t pad0[10];
     uint32_t lcount[MAX_XCD][16]; // per-XCD arrivals (one 64-byte line each)
     uint32_t lgen[MAX_XCD][16];   // per-XCD generation
 };

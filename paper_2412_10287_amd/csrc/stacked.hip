@@ -112,7 +112,7 @@ __device__ __forceinline__ void put_item(const StackParams &p, uint32_t idx, uin
 
 // ------------------------------------------------------------------ select
 template <int G, int QM>
-__device__ __forceinline__ void st_select(const StackParams &p, uint32_t n) {
+__device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint32_t bid, uint32_t nblk) {
     const GraphView &g = p.g;
     const QueryView &qv = p.qv;
     LevelRec *rec = p.rec;
@@ -120,15 +120,14 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n) {
     const uint32_t nq = queue_len(p, R);
     const uint32_t V = static_cast<uint32_t>(p.V);
     const uint32_t qmask = state_mask(p);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        rec[(n + 1) % REC_RING] = LevelRec{};
+    if (bid == 0 && threadIdx.x == 0) {
+        rec_clear(rec[(n + 1) % REC_RING]);
         if (n < LVL_COUNT_CAP) p.lvl[static_cast<uint64_t>(n) * LVL_STRIDE + 3] = wall_clock64();
     }
     const uint32_t lane = lane_id();
     const uint32_t j = lane % G;
     const uint32_t grp = lane / G;
-    constexpr uint32_t GPW = 64 / G;  // vertices per wave and step
-    const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
+    constexpr uint32_t GPB = BLOCK / G;  // vertices per workgroup and step
     // level n-1's frontier state sets live in the array level n's expansion
     // fills: clear them. Its frontier rows may stay: every bit in them is in P
     // already, so a later select masks them out (it rewrites every row it
@@ -137,10 +136,20 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n) {
         const uint32_t nprev = queue_len(p, rec[(n - 1) % REC_RING]);
         uint32_t *sold = p.sup[(n + 1) & 1];
         const int32_t *qold = p.q[(n + 1) & 1];
-        for (uint32_t i = gthread(); i < nprev; i += gthreads()) {
-            const uint32_t v = static_cast<uint32_t>(qold[i]);
-            if (v < V) sold[v] = 0;
-            else sviol(p);
+        const uint32_t stride = nblk * BLOCK;
+        for (uint32_t i0 = bid * BLOCK + threadIdx.x; i0 < nprev; i0 += 8 * stride) {
+            uint32_t vv[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const uint32_t i = i0 + k * stride;
+                vv[k] = i < nprev ? static_cast<uint32_t>(qold[i]) : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                if (i0 + k * stride >= nprev) continue;
+                if (vv[k] < V) sold[vv[k]] = 0;
+                else sviol(p);
+            }
         }
     }
     const int32_t *qc = p.q[n & 1];
@@ -149,8 +158,9 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n) {
     const uint32_t nsym = qv.h->nsym;
     uint64_t pairs = 0, upd = 0, c_items = 0, c_edges = 0;
     uint32_t nfront = 0, su = 0;
-    for (uint32_t base = gw * GPW; base < nq; base += nw * GPW) {
-        const uint32_t i = base + grp;
+    // workgroup-uniform loop: item reservations are made per workgroup
+    for (uint32_t bbase = bid * GPB; bbase < nq; bbase += nblk * GPB) {
+        const uint32_t i = bbase + threadIdx.x / G;
         uint32_t w = 0, cs = 0;
         bool ok = false;
         if (i < nq) {
@@ -211,7 +221,9 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n) {
             RankWordD rw[SYM_BATCH];
 #pragma unroll
             for (int jj = 0; jj < SYM_BATCH; jj++) us[jj] = symbol_pop(Rs);
-            if (__ballot(us[0] < nsym) == 0) break;
+            bool more = false;
+#pragma unroll
+            for (int k = 0; k < SYM_WORDS; k++) more = more || Rs.w[k] != 0;
 #pragma unroll
             for (int jj = 0; jj < SYM_BATCH; jj++) {
                 const uint32_t u = us[jj];
@@ -242,13 +254,10 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n) {
             }
             uint64_t wtot;
             const uint64_t ex = wave_excl_scan((static_cast<uint64_t>(cnt) << 32) | tot, wtot);
-            if (wtot == 0) continue;
-            uint64_t old = 0;
-            if (lane == 63)
-                old = atomicAdd(reinterpret_cast<unsigned long long *>(&R.sel), static_cast<unsigned long long>(wtot));
-            old = __shfl(old, 63, 64);
+            uint64_t wbase;
+            const bool bmore = block_reserve<uint64_t>(wtot, more, &R.sel, wbase);
             if (cnt) {
-                const uint64_t mine = old + ex;
+                const uint64_t mine = wbase + ex;
                 uint32_t idx = static_cast<uint32_t>(mine >> 32);
                 uint32_t eb = static_cast<uint32_t>(mine);
                 c_items += cnt;
@@ -261,26 +270,24 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n) {
                     eb += len[jj];
                 }
             }
+            if (!bmore) break;
         }
     }
-    pairs = wave_sum(pairs);
-    upd = wave_sum(upd);
-    c_items = wave_sum(c_items);
-    c_edges = wave_sum(c_edges);
+    // level totals and work counters: one atomic per workgroup and field
     const uint64_t nf = wave_sum(nfront);
-    su = wave_or(su);
-    if (lane == 0) {
-        if (pairs) atomicAdd(reinterpret_cast<unsigned long long *>(&R.pairs), static_cast<unsigned long long>(pairs));
-        if (nf) {
-            atomicAdd(&R.nfront, static_cast<uint32_t>(nf));
-            atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[3]), static_cast<unsigned long long>(nf));
+    const uint64_t v[7] = {wave_sum(pairs), nf, wave_or(su), wave_sum(c_items), wave_sum(c_edges), wave_sum(upd), nf};
+    const uint64_t t = block_reduce<7>(v, 4u);
+    if (t) {
+        switch (threadIdx.x) {
+            case 0: atomicAdd(reinterpret_cast<unsigned long long *>(&R.pairs), (unsigned long long)t); break;
+            case 1: atomicAdd(&R.nfront, static_cast<uint32_t>(t)); break;
+            case 2: atomicOr(&R.su, static_cast<uint32_t>(t)); break;
+            case 3: atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[0]), (unsigned long long)t); break;
+            case 4: atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[1]), (unsigned long long)t); break;
+            case 5: atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[2]), (unsigned long long)t); break;
+            case 6: atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[3]), (unsigned long long)t); break;
+            default: break;
         }
-        if (su) atomicOr(&R.su, su);
-        if (c_items) {
-            atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[0]), static_cast<unsigned long long>(c_items));
-            atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[1]), static_cast<unsigned long long>(c_edges));
-        }
-        if (upd) atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[2]), static_cast<unsigned long long>(upd));
     }
 }
 
@@ -395,19 +402,19 @@ __device__ __forceinline__ void unit_scatter(const StackParams &p, uint32_t n, u
 }
 
 // The first writer of the target's candidate state set appends it to the
-// next queue. All 64 lanes of the wave call this.
+// next queue. Every thread of the workgroup calls this.
 template <int G, int QM>
 __device__ __forceinline__ void unit_append(const StackParams &p, uint32_t n, uint32_t j, const UnitC<QM> &U) {
     const uint32_t tg = group_or<G>(U.tb);
     bool first = false;
     if (tg && j == 0) first = atomicOr(&p.sup[(n + 1) & 1][U.dst], tg) == 0u;
-    if (!wave_append(first, static_cast<int32_t>(U.dst), p.q[(n + 1) & 1], &p.rec[(n + 1) % REC_RING].nq,
-                     static_cast<uint32_t>(p.V)))
+    if (!block_append(first, static_cast<int32_t>(U.dst), p.q[(n + 1) & 1], &p.rec[(n + 1) % REC_RING].nq,
+                      static_cast<uint32_t>(p.V)))
         sviol(p);
 }
 
 // Four units' appends with their sup atomics issued together and one queue
-// reservation per wave. All 64 lanes of the wave call this.
+// reservation per workgroup. Every thread of the workgroup calls this.
 template <int G, int QM>
 __device__ __forceinline__ void unit_append4(const StackParams &p, uint32_t n, uint32_t j, const UnitC<QM> &U0,
                                              const UnitC<QM> &U1, const UnitC<QM> &U2, const UnitC<QM> &U3) {
@@ -427,9 +434,9 @@ __device__ __forceinline__ void unit_append4(const StackParams &p, uint32_t n, u
     if (t1 && lead && (o1 & t1) != t1) o1 = atomicOr(&sn[U1.dst], t1);
     if (t2 && lead && (o2 & t2) != t2) o2 = atomicOr(&sn[U2.dst], t2);
     if (t3 && lead && (o3 & t3) != t3) o3 = atomicOr(&sn[U3.dst], t3);
-    if (!wave_append4(o0 == 0, static_cast<int32_t>(U0.dst), o1 == 0, static_cast<int32_t>(U1.dst), o2 == 0,
-                      static_cast<int32_t>(U2.dst), o3 == 0, static_cast<int32_t>(U3.dst), p.q[(n + 1) & 1],
-                      &p.rec[(n + 1) % REC_RING].nq, static_cast<uint32_t>(p.V)))
+    if (!block_append4(o0 == 0, static_cast<int32_t>(U0.dst), o1 == 0, static_cast<int32_t>(U1.dst), o2 == 0,
+                       static_cast<int32_t>(U2.dst), o3 == 0, static_cast<int32_t>(U3.dst), p.q[(n + 1) & 1],
+                       &p.rec[(n + 1) % REC_RING].nq, static_cast<uint32_t>(p.V)))
         sviol(p);
 }
 
@@ -495,12 +502,13 @@ __device__ __forceinline__ void expand_range(const StackParams &p, uint32_t n, c
 
 // Items [0, nitems) with `T` edges (packed in sel) -> units spread over the grid.
 template <int G, int QM, bool PULL>
-__device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, StLds &L, uint64_t sel, uint32_t ns) {
+__device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, StLds &L, uint64_t sel, uint32_t ns,
+                                             uint32_t bid, uint32_t nblk) {
     const uint32_t nitems = static_cast<uint32_t>(sel >> 32);
     const uint32_t T = static_cast<uint32_t>(sel);
     if (T == 0 || nitems == 0) return;
     if (nitems > p.item_cap) {
-        if (gthread() == 0) sviol(p);
+        if (bid == 0 && threadIdx.x == 0) sviol(p);
         return;
     }
     const uint64_t units = static_cast<uint64_t>(T) * G;
@@ -516,9 +524,9 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, S
             L.s[x] = p.it_s[x];
         }
         __syncthreads();
-        uint64_t per = (units + gridDim.x - 1) / gridDim.x;
+        uint64_t per = (units + nblk - 1) / nblk;
         per = (per + 63) & ~63ull;
-        const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * per;
+        const uint64_t b0 = static_cast<uint64_t>(bid) * per;
         const uint64_t b1 = b0 + per < units ? b0 + per : units;
         if (b0 < b1) expand_range<G, QM, PULL>(p, n, L, nitems, b0, b1, ns);
         __syncthreads();
@@ -529,9 +537,9 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, S
     // fewer tiles than workgroups: split each tile into parts of at least a
     // wave's worth of units, so the level still spreads over the grid
     uint32_t sub = 1;
-    while (sub < TILE / 64 && ntiles * sub * 2 <= gridDim.x) sub *= 2;
+    while (sub < TILE / 64 && ntiles * sub * 2 <= nblk) sub *= 2;
     const uint32_t part_units = TILE / sub;
-    for (uint32_t vt = blockIdx.x; vt < ntiles * sub; vt += gridDim.x) {
+    for (uint32_t vt = bid; vt < ntiles * sub; vt += nblk) {
         const uint32_t tile = vt / sub, part = vt % sub;
         uint32_t i0 = tile < p.tile_cap ? p.tile_first[tile] : 0u;
         uint32_t i1 = (tile + 1 < ntiles && tile + 1 < p.tile_cap) ? p.tile_first[tile + 1] : nitems - 1;
@@ -571,9 +579,7 @@ __device__ __forceinline__ void st_pull_rows(const StackParams &p, uint32_t n, u
     const uint32_t nsym = qv.h->nsym;
     const uint32_t lane = lane_id();
     const uint32_t j = lane % G;
-    const uint32_t grp = lane / G;
-    constexpr uint32_t GPW = 64 / G;
-    const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
+    constexpr uint32_t GPB = BLOCK / G;  // rows per workgroup and step
     const uint64_t full = word_full(p.B, j);
     const uint64_t *Mc = p.M[n & 1];
     uint64_t *Mn = p.M[(n + 1) & 1];
@@ -601,8 +607,9 @@ __device__ __forceinline__ void st_pull_rows(const StackParams &p, uint32_t n, u
         if (!pu || !tu) continue;
         const uint64_t rb = qv.pull_r[u];
         const uint32_t rows = qv.pull_n[u];
-        for (uint32_t base = gw * GPW; base < rows; base += nw * GPW) {
-            const uint32_t r = base + grp;
+        // workgroup-uniform loop: reservations are made per workgroup
+        for (uint32_t bbase = blockIdx.x * GPB; bbase < rows; bbase += gridDim.x * GPB) {
+            const uint32_t r = bbase + threadIdx.x / G;
             uint32_t w = V, beg = 0, end = 0;
             if (r < rows) {
                 w = g.rowvert[rb + r];
@@ -626,14 +633,10 @@ __device__ __forceinline__ void st_pull_rows(const StackParams &p, uint32_t n, u
             }
             need = group_or64<G>(need);
             uint32_t tb = 0;
+            bool heavy = false;
             if (need) {
                 if (end - beg > PULL_LIGHT_ROW) {
-                    if (j == 0) {
-                        const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long *>(&R.hsel),
-                                                       (1ull << 32) | static_cast<unsigned long long>(end - beg));
-                        put_item<G>(p, static_cast<uint32_t>(old >> 32), static_cast<uint32_t>(old), beg, end - beg, w,
-                                    u, pu);
-                    }
+                    heavy = true;
                 } else {
                     for (uint32_t e0 = beg; e0 < end && need; e0 += 4) {
                         uint32_t vv[4], sv[4];
@@ -671,10 +674,29 @@ __device__ __forceinline__ void st_pull_rows(const StackParams &p, uint32_t n, u
                     }
                 }
             }
+            // long rows become items of the edge-balanced pass; rows that
+            // gained bits are appended to the next queue (the first writer of
+            // their state set): both reserved together, once per workgroup
+            const bool hl = heavy && j == 0;
+            uint64_t htot;
+            const uint64_t hex =
+                wave_excl_scan(hl ? ((1ull << 32) | static_cast<uint64_t>(end - beg)) : 0ull, htot);
             tb = group_or<G>(tb);
             bool first = false;
             if (tb && j == 0) first = atomicOr(&sn[w], tb) == 0u;
-            if (!wave_append(first, static_cast<int32_t>(w), qn, &RN.nq, V)) sviol(p);
+            const uint64_t fm = __ballot(first);
+            uint64_t hbase;
+            uint32_t qbase;
+            block_reserve2(htot, &R.hsel, hbase, static_cast<uint32_t>(__popcll(fm)), &RN.nq, qbase);
+            if (hl) {
+                const uint64_t at = hbase + hex;
+                put_item<G>(p, static_cast<uint32_t>(at >> 32), static_cast<uint32_t>(at), beg, end - beg, w, u, pu);
+            }
+            if (first) {
+                const uint32_t pos = qbase + static_cast<uint32_t>(__popcll(fm & ((1ull << lane) - 1ull)));
+                if (pos < V) qn[pos] = static_cast<int32_t>(w);
+                else sviol(p);
+            }
         }
     }
 }
@@ -754,6 +776,63 @@ __device__ __forceinline__ void st_final(const StackParams &p, uint32_t nexit, u
 }
 
 // ----------------------------------------------------------------- kernel
+// Level n's record once its select phase is complete (one thread).
+__device__ __forceinline__ void st_record(const StackParams &p, uint32_t n, uint32_t mode) {
+    LevelRec &R = p.rec[n % REC_RING];
+    R.mode = mode;
+    if (n < LVL_COUNT_CAP) {
+        uint64_t *Lv = p.lvl + static_cast<uint64_t>(n) * LVL_STRIDE;
+        Lv[0] = ld_acq(&R.pairs);
+        Lv[1] = ld_acq(&R.nfront);
+        Lv[2] = ld_acq(&R.sel);
+        Lv[4] = wall_clock64();
+    }
+}
+
+// ------------------------------------------------------------ small levels
+// As in the single-query kernel: levels with a short candidate queue and few
+// expansion units run in workgroup 0 alone, with workgroup barriers in place
+// of grid barriers, while the other workgroups wait at one grid barrier.
+constexpr uint32_t ST_SOLO_MAX_UNITS = 4 * TILE;  // expansion units of a small level
+constexpr uint32_t ST_SOLO_MAX_RUN = 2048;        // levels per run (the waiting barrier times out after 5 s)
+
+__device__ __forceinline__ void st_solo_sync() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// Runs levels n, n+1, ... in workgroup 0 while they are small (at most two
+// select steps of the workgroup). Leaves in bar->solo_n the first level not
+// finished and in bar->solo_sel whether its select phase is already done.
+template <int G, int QM>
+__device__ __forceinline__ void st_solo_levels(const StackParams &p, uint32_t n, StLds &L, uint32_t prev,
+                                               uint32_t &npush) {
+    constexpr uint32_t max_queue = 2 * BLOCK / G;
+    uint32_t sel_done = 0;
+    for (uint32_t run = 0; run < ST_SOLO_MAX_RUN; run++) {
+        const uint32_t nq = ld_acq(&p.rec[n % REC_RING].nq);
+        if (nq == 0 || nq > max_queue) break;
+        st_select<G, QM>(p, n, 0, 1);
+        st_solo_sync();
+        const uint32_t mode = st_decide<QM>(p, n, prev);
+        const uint64_t sel = ld_acq(&p.rec[n % REC_RING].sel);
+        if (mode != 0 || (sel & 0xffffffffull) * G > ST_SOLO_MAX_UNITS) {
+            sel_done = 1;
+            break;
+        }
+        if (threadIdx.x == 0) st_record(p, n, 0);
+        expand_items<G, QM, false>(p, n, L, sel, ~0u, 0, 1);
+        st_solo_sync();
+        npush++;
+        prev = 0;
+        n++;
+    }
+    if (threadIdx.x == 0) {
+        p.bar->solo_n = n;
+        p.bar->solo_sel = sel_done;
+    }
+}
+
 template <int G, int QM>
 __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
     __shared__ StLds L;
@@ -761,7 +840,7 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
     BarCtx bc;
     if (!barrier_register(bar, bc)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        p.rec[0] = LevelRec{};
+        rec_clear(p.rec[0]);
         for (int i = 0; i < 4; i++) p.status[i] = 0;
         for (int i = 0; i < 4; i++) p.cnt[i] = 0;
     }
@@ -792,27 +871,36 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
         }
     }
     if (!grid_barrier(bar, bc)) return;
-    uint32_t n = 0, npush = 0, npull = 0, prev = 0;
+    uint32_t n = 0, npush = 0, npull = 0, prev = 0, solo_at = ~0u;
     uint64_t last_pairs = 0;
     while (true) {
-        if (ld_acq(&p.rec[n % REC_RING].nq) == 0) break;
-        st_select<G, QM>(p, n);
-        if (!grid_barrier(bar, bc)) return;
+        const uint32_t nq = ld_acq(&p.rec[n % REC_RING].nq);
+        if (nq == 0) break;
+        bool selected = false;
+        if (nq <= 2 * BLOCK / G && n != solo_at) {
+            // a run of small levels in workgroup 0; the rest wait here
+            solo_at = n;
+            if (blockIdx.x == 0) st_solo_levels<G, QM>(p, n, L, prev, npush);
+            if (!grid_barrier(bar, bc)) return;
+            const uint32_t n2 = ld_acq(&bar->solo_n);
+            if (n2 != n) {
+                prev = 0;  // small levels are pushed
+                last_pairs = ld_acq(&p.rec[(n2 - 1) % REC_RING].pairs);
+            }
+            n = n2;
+            selected = ld_acq(&bar->solo_sel) != 0;
+            if (!selected) continue;
+        }
+        if (!selected) {
+            st_select<G, QM>(p, n, blockIdx.x, gridDim.x);
+            if (!grid_barrier(bar, bc)) return;
+        }
         LevelRec &R = p.rec[n % REC_RING];
         last_pairs = ld_acq(&R.pairs);
         const uint32_t mode = st_decide<QM>(p, n, prev);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            R.mode = mode;
-            if (n < LVL_COUNT_CAP) {
-                uint64_t *Lv = p.lvl + static_cast<uint64_t>(n) * LVL_STRIDE;
-                Lv[0] = last_pairs;
-                Lv[1] = ld_acq(&R.nfront);
-                Lv[2] = ld_acq(&R.sel);
-                Lv[4] = wall_clock64();
-            }
-        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) st_record(p, n, mode);
         if (mode == 0) {
-            expand_items<G, QM, false>(p, n, L, ld_acq(&R.sel), ~0u);
+            expand_items<G, QM, false>(p, n, L, ld_acq(&R.sel), ~0u, blockIdx.x, gridDim.x);
             if (!grid_barrier(bar, bc)) return;
             npush++;
         } else {
@@ -828,7 +916,7 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
                 if (!grid_barrier(bar, bc)) return;
                 const uint64_t hsel = ld_acq(&R.hsel);
                 if (hsel) {
-                    expand_items<G, 8, true>(p, n, L, hsel, ns);
+                    expand_items<G, 8, true>(p, n, L, hsel, ns, blockIdx.x, gridDim.x);
                     if (!grid_barrier(bar, bc)) return;
                 }
             }
