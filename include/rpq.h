@@ -136,6 +136,14 @@ rpq_status rpq_graph_info(const rpq_graph *g, const char *key, int64_t *value);
  *  "max_batch"   largest number of sources stacked in one launch (<= 1024).
  *  "mem_budget"  device bytes the served path may use for query state.
  *  "max_slots"   concurrent queries in the served path.
+ *  "serve_stack_min"  waiting served requests of one NFA handle that run as
+ *                one stacked group (default 32; 0 = never).
+ *  "large_query_pairs", "large_query_slots"  while the moving average of
+ *                the reached (state, vertex) pairs of recently finished
+ *                served queries exceeds large_query_pairs (default 2^21),
+ *                at most large_query_slots (default 8) run at once: the state
+ *                arrays of many large queries thrash the caches, and a few
+ *                of them already fill the GPU.
  * Errors: RPQ_ENOTFOUND for an unknown key, RPQ_EINVAL for a bad value.
  */
 rpq_status rpq_set_option(rpq_graph *g, const char *key, int64_t value);
@@ -203,7 +211,12 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
  * its pool entry freed), RPQ_PENDING if not finished and timeout_us == 0,
  * RPQ_ETIMEDOUT if the wait elapsed, RPQ_ENOTFOUND for an unknown ticket.
  * Finished answers hold their pool entry until polled; while every entry is
- * held, further finished queries keep their slots and new ones wait.
+ * held, further answers are kept in host memory instead.
+ * Requests of one NFA handle that wait together (at least "serve_stack_min"
+ * of them, default 32) run as one stacked multi-source traversal, as
+ * rpq_multi_source would (up to "max_batch" per group); their answers are the
+ * same, and their statistics are the group's (levels, visited pairs) with
+ * batch = the group size.
  */
 rpq_status rpq_submit(rpq_graph *g, const rpq_nfa *n, int32_t source, rpq_ticket *out);
 rpq_status rpq_poll(rpq_graph *g, rpq_ticket t, uint64_t *out_bitmap, uint32_t flags, rpq_stats *stats,

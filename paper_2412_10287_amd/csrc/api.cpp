@@ -408,6 +408,17 @@ rpq_status rpq_set_option(rpq_graph *g, const char *key, int64_t value) {
     } else if (!strcmp(key, "max_slots")) {
         if (value < 1 || value > MAX_SLOTS) return fail(RPQ_EINVAL, "rpq_set_option: max_slots outside [1, %d]", MAX_SLOTS);
         g->max_slots = static_cast<int32_t>(value);
+    } else if (!strcmp(key, "large_query_pairs")) {
+        if (value < 0) return fail(RPQ_EINVAL, "rpq_set_option: large_query_pairs < 0");
+        g->large_pairs = value;
+    } else if (!strcmp(key, "large_query_slots")) {
+        if (value < 1 || value > MAX_SLOTS)
+            return fail(RPQ_EINVAL, "rpq_set_option: large_query_slots outside [1, %d]", MAX_SLOTS);
+        g->large_slots = static_cast<int32_t>(value);
+    } else if (!strcmp(key, "serve_stack_min")) {
+        if (value < 0 || value > MAX_BATCH)
+            return fail(RPQ_EINVAL, "rpq_set_option: serve_stack_min outside [0, %d]", MAX_BATCH);
+        g->serve_stack_min = static_cast<int32_t>(value);
     } else if (!strcmp(key, "grid")) {
         if (value < 0) return fail(RPQ_EINVAL, "rpq_set_option: grid < 0");
         g->grid_override = static_cast<int32_t>(value);
@@ -428,6 +439,9 @@ rpq_status rpq_get_option(const rpq_graph *g, const char *key, int64_t *value) {
     else if (!strcmp(key, "max_batch")) *value = g->max_batch;
     else if (!strcmp(key, "mem_budget")) *value = g->mem_budget;
     else if (!strcmp(key, "max_slots")) *value = g->max_slots;
+    else if (!strcmp(key, "large_query_pairs")) *value = g->large_pairs;
+    else if (!strcmp(key, "large_query_slots")) *value = g->large_slots;
+    else if (!strcmp(key, "serve_stack_min")) *value = g->serve_stack_min;
     else if (!strcmp(key, "grid")) *value = g->grid_override;
     else return fail(RPQ_ENOTFOUND, "rpq_get_option: unknown key '%s'", key);
     return RPQ_OK;

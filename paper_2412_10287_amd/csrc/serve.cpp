@@ -12,9 +12,11 @@
 // scheduling), and one launch carries the work of all of them.
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <memory>
 #include <thread>
 #include <unordered_map>
 
@@ -31,7 +33,9 @@ struct Request {
     int32_t source = 0;
     int32_t nsym = 0;
     uint32_t smask = 0;
-    std::vector<uint8_t> qc;  // query constants (build_qconst layout)
+    uint64_t serial = 0;                // the NFA handle's identity
+    std::shared_ptr<const rpq_nfa> nfa; // a copy of the NFA (for a stacked group)
+    std::vector<uint8_t> qc;            // query constants (build_qconst layout)
     Clock::time_point submitted;
 };
 
@@ -66,6 +70,15 @@ struct ServeState {
     std::string fail_msg;
     rpq_ticket next_ticket = 1;
     size_t running = 0;
+    // size of recent queries (reached pairs, moving average): while they are
+    // large, fewer run at once (the state arrays of many large queries thrash
+    // the caches and the TLB; a few already fill the GPU)
+    double size_avg = 0.0;
+    uint64_t size_n = 0;
+    // stacked groups: staging for their answers; grouping is switched off
+    // after a failure of the stacked path
+    uint64_t *gout = nullptr;
+    bool group_off = false;
     // engine (owned by the worker thread after start)
     MultiParams mp{};
     hipStream_t stream = nullptr;
@@ -333,11 +346,78 @@ static rpq_status retire(rpq_graph *g, ServeState *ss) {
             ss->free_entries.push_back(entry);
         }
         if (spill) k++;
+        ss->size_avg = ss->size_n == 0 ? static_cast<double>(si.pairs)
+                                       : 0.8 * ss->size_avg + 0.2 * static_cast<double>(si.pairs);
+        ss->size_n++;
         si = SlotInfo{};
         ss->free_slots.push_back(sl);
         ss->running--;
     }
     ss->ready.clear();
+    ss->cv_done.notify_all();
+    return RPQ_OK;
+}
+
+// Requests that share one NFA and wait together run as one stacked
+// multi-source traversal (every source one bit of a stacked row: the same
+// answers, one pass over the graph for all of them) into a staging buffer;
+// each answer then moves to a result-pool entry or, when none is free, to
+// host memory. Called by the worker thread without ss->mu held.
+static rpq_status run_group(rpq_graph *g, ServeState *ss, std::vector<Request> &grp) {
+    const int32_t B = static_cast<int32_t>(grp.size());
+    const size_t nw = static_cast<size_t>(g->nwords);
+    if (!ss->gout) {
+        const size_t words = static_cast<size_t>(std::min<int32_t>(g->max_batch, MAX_BATCH)) * nw;
+        ST(salloc(ss, reinterpret_cast<void **>(&ss->gout), 8 * words));
+    }
+    std::vector<int32_t> src(static_cast<size_t>(B));
+    for (int32_t i = 0; i < B; i++) src[i] = grp[i].source;
+    rpq_stats stt{};
+    rpq_status st = rpq_multi_source(g, grp[0].nfa.get(), src.data(), B, ss->gout, RPQ_OUT_DEVICE, &stt);
+    if (st != RPQ_OK) return st;
+    std::vector<uint32_t> entry(static_cast<size_t>(B), ~0u);
+    {
+        std::lock_guard<std::mutex> lk(ss->mu);
+        for (int32_t i = 0; i < B && !ss->free_entries.empty(); i++) {
+            entry[i] = ss->free_entries.back();
+            ss->free_entries.pop_back();
+        }
+    }
+    std::vector<std::vector<uint64_t>> spill(static_cast<size_t>(B));
+    for (int32_t i = 0; i < B; i++) {
+        const uint64_t *from = ss->gout + static_cast<size_t>(i) * nw;
+        if (entry[i] != ~0u) {
+            ST(hipMemcpyAsync(ss->mp.out + static_cast<size_t>(entry[i]) * nw, from, 8 * nw, hipMemcpyDeviceToDevice,
+                              ss->stream));
+        } else {
+            spill[i].resize(nw);
+            ST(hipMemcpyAsync(spill[i].data(), from, 8 * nw, hipMemcpyDeviceToHost, ss->stream));
+        }
+    }
+    ST(hipStreamSynchronize(ss->stream));
+    const Clock::time_point now = Clock::now();
+    std::lock_guard<std::mutex> lk(ss->mu);
+    for (int32_t i = 0; i < B; i++) {
+        auto it = ss->tickets.find(grp[i].id);
+        if (it != ss->tickets.end()) {
+            Ticket &t = it->second;
+            if (entry[i] != ~0u) t.entry = entry[i];
+            else t.spill.swap(spill[i]);
+            // a stacked group's statistics: its level count and total pairs
+            t.stats = rpq_stats{};
+            t.stats.levels = stt.levels;
+            t.stats.push_levels = stt.push_levels;
+            t.stats.pull_levels = stt.pull_levels;
+            t.stats.visited_pairs = stt.visited_pairs;
+            t.stats.device_ms = std::chrono::duration<double, std::milli>(now - grp[i].submitted).count();
+            t.stats.batch = B;
+            t.status = RPQ_OK;
+            t.state = 2;
+        } else if (entry[i] != ~0u) {
+            ss->free_entries.push_back(entry[i]);
+        }
+        ss->running--;
+    }
     ss->cv_done.notify_all();
     return RPQ_OK;
 }
@@ -367,22 +447,70 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
         fail_all(ss, st, rpq_last_error());
         return;
     }
-    std::vector<Request> admit;
+    std::vector<Request> admit, grp;
     while (true) {
         admit.clear();
+        grp.clear();
         {
             std::unique_lock<std::mutex> lk(ss->mu);
+            // a stacked group: at least serve_stack_min waiting requests of one NFA
+            const size_t smin = ss->group_off ? 0 : static_cast<size_t>(std::max<int32_t>(g->serve_stack_min, 0));
+            auto group_serial = [&]() -> uint64_t {
+                if (smin == 0 || ss->pending.size() < smin) return 0;
+                std::unordered_map<uint64_t, size_t> cnt;
+                for (const Request &r : ss->pending)
+                    if (++cnt[r.serial] >= smin) return r.serial;
+                return 0;
+            };
+            // concurrency: every slot, or large_query_slots while recent
+            // queries are large
+            size_t cap = ss->slots;
+            if (ss->size_n && ss->size_avg > static_cast<double>(g->large_pairs))
+                cap = std::min<size_t>(cap, static_cast<size_t>(g->large_slots));
+            auto active = [&] { return static_cast<size_t>(ss->slots) - ss->free_slots.size(); };
             // work: a level to run or a request and a free slot
             ss->cv_work.wait(lk, [&] {
-                return ss->stop || ss->cur_len > 0 || (!ss->pending.empty() && !ss->free_slots.empty());
+                return ss->stop || ss->cur_len > 0 ||
+                       (!ss->pending.empty() && !ss->free_slots.empty() && active() < cap) || group_serial() != 0;
             });
             if (ss->stop && ss->pending.empty() && ss->cur_len == 0) break;
-            while (!ss->pending.empty() && admit.size() < ss->free_slots.size()) {
-                admit.push_back(std::move(ss->pending.front()));
-                ss->pending.pop_front();
-                auto it = ss->tickets.find(admit.back().id);
-                if (it != ss->tickets.end()) it->second.state = 1;
+            const uint64_t gs = ss->stop ? 0 : group_serial();
+            if (gs) {
+                const size_t maxb = static_cast<size_t>(std::min<int32_t>(g->max_batch, MAX_BATCH));
+                for (auto it = ss->pending.begin(); it != ss->pending.end() && grp.size() < maxb;) {
+                    if (it->serial != gs) {
+                        ++it;
+                        continue;
+                    }
+                    grp.push_back(std::move(*it));
+                    it = ss->pending.erase(it);
+                    auto t = ss->tickets.find(grp.back().id);
+                    if (t != ss->tickets.end()) t->second.state = 1;
+                }
+            } else {
+                while (!ss->pending.empty() && admit.size() < ss->free_slots.size() &&
+                       active() + admit.size() < cap) {
+                    admit.push_back(std::move(ss->pending.front()));
+                    ss->pending.pop_front();
+                    auto it = ss->tickets.find(admit.back().id);
+                    if (it != ss->tickets.end()) it->second.state = 1;
+                }
             }
+        }
+        if (!grp.empty()) {
+            if (run_group(g, ss, grp) != RPQ_OK) {
+                // the stacked path failed (for instance no memory for its
+                // state): these requests go back to the queue for the slots,
+                // and grouping stays off
+                std::lock_guard<std::mutex> lk(ss->mu);
+                for (size_t i = grp.size(); i-- > 0;) {
+                    auto t = ss->tickets.find(grp[i].id);
+                    if (t != ss->tickets.end()) t->second.state = 0;
+                    ss->pending.push_front(std::move(grp[i]));
+                }
+                ss->group_off = true;
+            }
+            continue;
         }
         st = engine_step(g, ss, admit);
         if (st != RPQ_OK) {
@@ -435,6 +563,8 @@ rpq_status rpq_submit(rpq_graph *g, const rpq_nfa *n, int32_t source, rpq_ticket
     Request r;
     r.source = source;
     r.smask = n->smask;
+    r.serial = n->serial;
+    r.nfa = std::make_shared<const rpq_nfa>(*n);
     const size_t sz = build_qconst(g, n, 1u, 0u, r.qc, &r.nsym);
     if (r.nsym > MAX_SYMS || sz > QC_STRIDE)
         return fail(RPQ_EINVAL, "rpq_submit: query uses %d symbols; the limit is %d", r.nsym, MAX_SYMS);

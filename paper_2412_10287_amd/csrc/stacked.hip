@@ -801,13 +801,13 @@ __device__ __forceinline__ void st_solo_sync() {
     __syncthreads();
 }
 
-// Runs levels n, n+1, ... in workgroup 0 while they are small (at most two
-// select steps of the workgroup). Leaves in bar->solo_n the first level not
+// Runs levels n, n+1, ... in workgroup 0 while they are small (one select
+// step of the workgroup). Leaves in bar->solo_n the first level not
 // finished and in bar->solo_sel whether its select phase is already done.
 template <int G, int QM>
 __device__ __forceinline__ void st_solo_levels(const StackParams &p, uint32_t n, StLds &L, uint32_t prev,
                                                uint32_t &npush) {
-    constexpr uint32_t max_queue = 2 * BLOCK / G;
+    constexpr uint32_t max_queue = BLOCK / G;
     uint32_t sel_done = 0;
     for (uint32_t run = 0; run < ST_SOLO_MAX_RUN; run++) {
         const uint32_t nq = ld_acq(&p.rec[n % REC_RING].nq);
@@ -877,7 +877,7 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
         const uint32_t nq = ld_acq(&p.rec[n % REC_RING].nq);
         if (nq == 0) break;
         bool selected = false;
-        if (nq <= 2 * BLOCK / G && n != solo_at) {
+        if (nq <= BLOCK / G && n != solo_at) {
             // a run of small levels in workgroup 0; the rest wait here
             solo_at = n;
             if (blockIdx.x == 0) st_solo_levels<G, QM>(p, n, L, prev, npush);

@@ -157,3 +157,48 @@ def test_result_pool_backpressure_and_device_output(rpq):
             assert r is not None, i
             bm = out.to_host()
         assert np.array_equal(bm, want), i
+
+
+def test_large_query_cap(rpq):
+    # every finished query counts as large (threshold 0), so after the first
+    # finishes at most two run at once; answers are unchanged and all arrive
+    w = C.rmat_workload(scale=13, edge_factor=16, num_labels=8, n_per_template=6)
+    og = oracle.Graph(w.graph)
+    gg = rpq.Graph(w.graph)
+    gg.set_option("large_query_pairs", 0)
+    gg.set_option("large_query_slots", 2)
+    assert gg.get_option("large_query_slots") == 2
+    nh = [rpq.NFA(n) for n in w.nfas]
+    for rnd in range(2):
+        res = _poll_all(gg, _submit_all(gg, nh, w.sources))
+        for (bm, st), n, s, text in zip(res, w.nfas, w.sources, w.queries):
+            r = og.ssr(n, int(s))
+            assert np.array_equal(bm, r.bitmap), (rnd, text)
+            assert st.levels == r.levels, (rnd, text)
+        if rnd == 1:
+            assert max(st.batch for _, st in res) <= 2
+
+
+def test_same_nfa_requests_run_as_stacked_groups(rpq):
+    # 80 requests of one NFA handle, submitted together with a few others:
+    # waiting requests of one NFA run as stacked groups (serve_stack_min 16),
+    # the rest through the slots; every answer equals the oracle's
+    w = C.rmat_workload(scale=13, edge_factor=16, num_labels=8, n_per_template=2)
+    og = oracle.Graph(w.graph)
+    gg = rpq.Graph(w.graph)
+    gg.set_option("serve_stack_min", 16)
+    gg.set_option("max_batch", 64)
+    gg.set_option("max_slots", 2)  # most requests wait, so groups form
+    assert gg.get_option("serve_stack_min") == 16
+    shared = rpq.NFA(w.nfas[1])
+    others = [rpq.NFA(n) for n in w.nfas]
+    srcs = np.random.default_rng(8).integers(0, w.graph.num_vertices, size=80)
+    tickets = [(gg.submit(o, int(s)), n, int(s)) for o, n, s in zip(others, w.nfas, w.sources)]
+    tickets += [(gg.submit(shared, int(s)), w.nfas[1], int(s)) for s in srcs]
+    grouped = 0
+    for t, n, s in reversed(tickets):
+        bm, st = gg.poll(t, timeout_us=60_000_000)
+        assert np.array_equal(bm, og.ssr(n, s).bitmap), s
+        grouped += st.batch > 2
+    print("answers from stacked groups:", grouped)
+    assert grouped > 0
