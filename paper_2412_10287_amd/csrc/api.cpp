@@ -5,6 +5,7 @@
 
 #include <stdarg.h>
 #include <stdio.h>
+#include <stddef.h>
 #include <string.h>
 
 #include <algorithm>
@@ -338,9 +339,13 @@ rpq_status rpq::graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32
         RPQ_OK)
         return st;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&g->dev_out), 8 * g->nwords, "out")) != RPQ_OK) return st;
-    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.status), 64, "status")) != RPQ_OK) return st;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.cnt), 64, "cnt")) != RPQ_OK) return st;
-    if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.bar), sizeof(GridBarrier), "barrier")) != RPQ_OK) return st;
+    for (int k = 0; k < 2; k++)
+        if ((st = dev_alloc(g, reinterpret_cast<void **>(&g->bars[k]), sizeof(GridBarrier), "barrier")) != RPQ_OK)
+            return st;
+    sv.bar = g->bars[0];
+    sv.bar_next = g->bars[1];
+    sv.status = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(sv.bar) + offsetof(GridBarrier, status));
     g->qconst_cap = qconst_bytes(MAX_SYMS) + 64;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&g->qconst_dev), g->qconst_cap, "qconst")) != RPQ_OK) return st;
     g->pinned_cap = g->qconst_cap + 4096 + 8 * LVL_STRIDE * (LVL_COUNT_CAP + 1);
@@ -479,12 +484,21 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
         g->q_counters = counters;
         g->q_alpha = g->pull_alpha;
         g->q_beta = g->pull_beta;
-        HIP_TRY(hipStreamSynchronize(s));  // the pinned staging buffer is reused below
+        // no wait here: nothing else writes this staging area before the
+        // synchronisation at the end of the query
     }
     Params p;
     p.g = g->gv;
     p.qv = g->qv;
     p.st = g->sv;
+    // barriers in turn; the status words live in this launch's barrier
+    p.st.bar = g->bars[g->bar_idx];
+    p.st.bar_next = g->bars[g->bar_idx ^ 1];
+    p.st.status = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(p.st.bar) + offsetof(GridBarrier, status));
+    if (g->bars_dirty) {
+        for (GridBarrier *b : g->bars) HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(b), sizeof(GridBarrier) / 4, 0, s));
+        g->bars_dirty = false;
+    }
     p.st.out = (flags & RPQ_OUT_DEVICE) ? out : g->dev_out;
     p.source = source;
     const bool timing = (flags & RPQ_KERNEL_TIMING) != 0;
@@ -496,7 +510,7 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
     if (g->plain_grid) grid_p = std::min(g->plain_grid, grid_p);
     if (g->grid_override) grid_p = std::min(g->grid_override, grid_p);
     if (!(flags & RPQ_HOST_LOOP) && grid_p > 0) {
-        HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(p.st.bar), sizeof(GridBarrier) / 4, 0, s));
+        g->bar_idx ^= 1;  // the next persistent launch uses the barrier this one zeroes
         if (timing) HIP_TRY(hipEventRecord(g->ev[2], s));
         HIP_TRY(launch_persistent(W, p, grid_p, s));
         if (timing) HIP_TRY(hipEventRecord(g->ev[3], s));
@@ -528,14 +542,21 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
     uint8_t *stage = g->pinned + g->qconst_cap;
     uint32_t *status = reinterpret_cast<uint32_t *>(stage);
     uint64_t *cnt = reinterpret_cast<uint64_t *>(stage + 64);
-    HIP_TRY(hipMemcpyAsync(status, p.st.status, 16, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(status + 4, &p.st.bar->abort, 4, hipMemcpyDeviceToHost, s));
+    // status words 0..6 and the abort flag in one copy; the first per-level
+    // records with them (most queries have fewer levels), the rest below
+    static_assert(offsetof(GridBarrier, abort) == offsetof(GridBarrier, status) + 28, "abort follows status");
+    constexpr uint32_t LVL_SPEC = 64;
+    uint64_t *lp = reinterpret_cast<uint64_t *>(stage + 128);
+    HIP_TRY(hipMemcpyAsync(status, p.st.status, 32, hipMemcpyDeviceToHost, s));
     if (counters) HIP_TRY(hipMemcpyAsync(cnt, p.st.cnt, 32, hipMemcpyDeviceToHost, s));
+    if (stats) HIP_TRY(hipMemcpyAsync(lp, p.st.lvl, 8 * LVL_STRIDE * LVL_SPEC, hipMemcpyDeviceToHost, s));
     if (!(flags & RPQ_OUT_DEVICE))
         HIP_TRY(hipMemcpyAsync(out, g->dev_out, 8 * g->nwords, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (status[4] && !(flags & RPQ_HOST_LOOP) && grid_p > 0)
+    if (status[7] && !(flags & RPQ_HOST_LOOP) && grid_p > 0) {
+        g->bars_dirty = true;
         return fail(RPQ_EDEVICE, "persistent traversal aborted: grid barrier timed out");
+    }
     if (status[3]) return fail(RPQ_EDEVICE, "internal invariant violated %u times (index out of range)", status[3]);
     const uint32_t levels = (flags & RPQ_HOST_LOOP || grid_p <= 0) ? nlev : status[0];
     if (stats) {
@@ -551,9 +572,10 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
         }
         stats->expand_ms = timing ? expand_ms : 0.0;
         stats->expand_launches = timing ? launches : 0;
-        uint64_t *lp = reinterpret_cast<uint64_t *>(stage + 128);
         const uint32_t ncopy = std::min<uint32_t>(levels + 1, LVL_COUNT_CAP);
-        HIP_TRY(hipMemcpy(lp, p.st.lvl, 8 * LVL_STRIDE * static_cast<size_t>(ncopy), hipMemcpyDeviceToHost));
+        if (ncopy > LVL_SPEC)
+            HIP_TRY(hipMemcpy(lp + LVL_STRIDE * LVL_SPEC, p.st.lvl + LVL_STRIDE * LVL_SPEC,
+                              8 * LVL_STRIDE * static_cast<size_t>(ncopy - LVL_SPEC), hipMemcpyDeviceToHost));
         stats->visited_pairs = stats_levels(stats, lp, ncopy, levels);
         if (counters) {
             const int64_t w = W;

@@ -56,6 +56,10 @@ struct rpq_graph {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     int pgrid[5] = {0, 0, 0, 0, 0};
     bool dirty = false;
+    // persistent-launch barriers, used in turn: each launch zeroes the other
+    rpq::GridBarrier *bars[2] = {nullptr, nullptr};
+    int bar_idx = 0;
+    bool bars_dirty = true;  // zero both before the next launch (first use, or after an aborted launch)
     // options
     double pull_alpha = 0.0;  // push only until tuned (see rpq_set_option)
     double pull_beta = 24.0;

@@ -606,6 +606,12 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
     // push tiles and pull heavy lists share the workgroup's LDS
     __shared__ uint32_t s_eb[TILE + 1], s_beg[TILE + 1], s_mask[TILE + 1], s_hn;
     GridBarrier *bar = p.st.bar;
+    // the next launch's barrier (not touched by this one) starts zeroed: no
+    // separate clearing launch per query
+    if (blockIdx.x == 0 && p.st.bar_next) {
+        uint32_t *z = reinterpret_cast<uint32_t *>(p.st.bar_next);
+        for (uint32_t i = threadIdx.x; i < sizeof(GridBarrier) / 4; i += BLOCK) z[i] = 0;
+    }
     BarCtx bc;
     if (!barrier_register(bar, bc)) return;
     init_phase<W>(p);

@@ -164,10 +164,11 @@ __device__ __forceinline__ void rec_clear(LevelRec &r) {
 struct GridBarrier {
     uint32_t reg[MAX_XCD];        // workgroups registered per XCD (this launch)
     uint32_t nreg;                // workgroups registered in total
-    uint32_t abort;               // a wait timed out; the launch ends early
     uint32_t gcount, ggen;        // XCD leaders arrived / generation
     uint32_t solo_n, solo_sel;    // where a run of small levels in workgroup 0 stopped
-    uint32_t pad0[10];
+    uint32_t pad0[3];
+    uint32_t status[7];           // the single-query launch's status words (StateView::status)
+    uint32_t abort;               // a wait timed out; the launch ends early (after status: one copy reads both)
     uint32_t lcount[MAX_XCD][16]; // per-XCD arrivals (one 64-byte line each)
     uint32_t lgen[MAX_XCD][16];   // per-XCD generation
 };
@@ -186,7 +187,8 @@ struct StateView {
     uint64_t *out;        // output bitmap (device)
     uint32_t *status;     // [0] levels, [1] push levels, [2] pull levels, [3] invariant violations
     uint64_t *cnt;        // [0] product edges, [1] scans, [2] scanned edges, [3] active
-    GridBarrier *bar;     // persistent-kernel barrier
+    GridBarrier *bar;     // persistent-kernel barrier (zero at launch)
+    GridBarrier *bar_next;  // the barrier of the next launch, zeroed by this one
     uint64_t item_cap;    // entries of the item arrays
     uint64_t tile_cap;    // entries of tile_first
 };
