@@ -63,6 +63,33 @@ __device__ __forceinline__ void init_phase(const Params &p) {
     for (int i = 0; i < 4; i++) p.st.status[i] = 0;
 }
 
+// Zeroes the state words that level k's queue entries point to in M[k & 1]
+// (its candidate and frontier words), eight entries per thread and step with
+// all loads before the stores (one workgroup alone may clear a long queue).
+template <int W>
+__device__ __forceinline__ void clear_level_words(const Params &p, uint32_t k, uint32_t bid, uint32_t nblk) {
+    const uint32_t V = static_cast<uint32_t>(p.g.V);
+    uint32_t nk = ld_acq(&p.st.rec[k % REC_RING].nq);
+    if (nk > V) nk = V;
+    uint32_t *M = p.st.M[k & 1];
+    const int32_t *q = p.st.q[k & 1];
+    const uint32_t stride = nblk * BLOCK;
+    for (uint32_t i0 = bid * BLOCK + threadIdx.x; i0 < nk; i0 += 8 * stride) {
+        uint32_t vv[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const uint32_t i = i0 + j * stride;
+            vv[j] = i < nk ? static_cast<uint32_t>(q[i]) : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            if (i0 + j * stride >= nk) continue;
+            if (vv[j] < V) st_state<W>(M, vv[j], 0);
+            else flag_violation(p);
+        }
+    }
+}
+
 // Candidates -> frontier -> push items. Each candidate w gets its new states
 // S = M[w] & ~P[w] (added to P); for each used symbol u, succ_u(S) is the
 // column w of (N^u)^T M, and when it is non-empty and w has u-neighbours,
@@ -86,30 +113,10 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
         rec_clear(rec[(n + 1) % REC_RING]);
         if (n < LVL_COUNT_CAP) p.st.lvl[static_cast<uint64_t>(n) * LVL_STRIDE + 3] = wall_clock64();
     }
-    // frontier words of level n-1 live in the buffer level n writes: clear them
-    if (n >= 1) {
-        uint32_t nprev = ld_acq(&rec[(n - 1) % REC_RING].nq);
-        if (nprev > V) nprev = V;
-        uint32_t *Mold = p.st.M[(n + 1) & 1];
-        const int32_t *qold = p.st.q[(n + 1) & 1];
-        // eight entries per thread and step, all loads before the stores
-        // (one workgroup alone may clear a long queue)
-        const uint32_t stride = nblk * BLOCK;
-        for (uint32_t i0 = bid * BLOCK + threadIdx.x; i0 < nprev; i0 += 8 * stride) {
-            uint32_t vv[8];
-#pragma unroll
-            for (int k = 0; k < 8; k++) {
-                const uint32_t i = i0 + k * stride;
-                vv[k] = i < nprev ? static_cast<uint32_t>(qold[i]) : 0u;
-            }
-#pragma unroll
-            for (int k = 0; k < 8; k++) {
-                if (i0 + k * stride >= nprev) continue;
-                if (vv[k] < V) st_state<W>(Mold, vv[k], 0);
-                else flag_violation(p);
-            }
-        }
-    }
+    // frontier words of level n-1 live in the buffer level n writes: after a
+    // pull level they are cleared here (after a push level, that level's
+    // push phase has cleared them already)
+    if (n >= 1 && ld_acq(&rec[(n - 1) % REC_RING].mode) != 0) clear_level_words<W>(p, n - 1, bid, nblk);
     const int32_t *qc = p.st.q[n & 1];
     uint32_t *Mc = p.st.M[n & 1];
     uint32_t *P = p.st.P;
@@ -314,6 +321,10 @@ __device__ __forceinline__ void push_range(const Params &p, uint32_t n, const ui
 template <int W>
 __device__ __forceinline__ void push_phase(const Params &p, uint32_t n, uint32_t *s_eb, uint32_t *s_beg,
                                            uint32_t *s_mask, uint32_t bid, uint32_t nblk) {
+    // the push direction never reads this level's words of M[n & 1] again
+    // (items carry the successor sets): clear them now, with stores that
+    // overlap the push; level n+1's expansion writes this buffer
+    clear_level_words<W>(p, n, bid, nblk);
     const uint64_t sel = ld_acq(&p.st.rec[n % REC_RING].sel);
     const uint32_t nitems = static_cast<uint32_t>(sel >> 32);
     const uint32_t T = static_cast<uint32_t>(sel);
