@@ -41,6 +41,34 @@
 
 namespace rpq {
 
+// The running query's tables, for every phase of this file's kernels: a copy
+// in LDS when the block fits (the persistent kernel), else the global block.
+__shared__ QueryView s_qv;
+__shared__ __align__(16) uint8_t s_qc[QC_LDS_BYTES];
+
+// Sets s_qv (copying the block into s_qc when TO_LDS and it fits). Every
+// thread of the workgroup calls it; it ends with a workgroup barrier.
+template <bool TO_LDS>
+__device__ __forceinline__ void qv_setup(const QueryView &qv) {
+    bool fits = false;
+    uint32_t nsym = 0;
+    if constexpr (TO_LDS) {
+        nsym = qv.h->nsym;
+        const size_t qb = qconst_bytes(nsym);
+        fits = qb <= QC_LDS_BYTES;
+        if (fits) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(qv.h);
+            uint4 *dst = reinterpret_cast<uint4 *>(s_qc);
+            for (uint32_t i = threadIdx.x; i < (qb + 15) / 16; i += blockDim.x) dst[i] = src[i];
+        }
+    }
+    if (threadIdx.x == 0) {
+        if constexpr (TO_LDS) s_qv = fits ? qconst_view(s_qc, nsym) : qv;
+        else s_qv = qv;
+    }
+    __syncthreads();
+}
+
 // Records a violated invariant (an index read from device memory out of
 // range); the access is skipped and the host reports the query as failed.
 __device__ __forceinline__ void flag_violation(const Params &p) { atomicAdd(&p.st.status[3], 1u); }
@@ -49,7 +77,7 @@ __device__ __forceinline__ void flag_violation(const Params &p) { atomicAdd(&p.s
 template <int W>
 __device__ __forceinline__ void init_phase(const Params &p) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    const QHeader &h = *p.qv.h;
+    const QHeader &h = *s_qv.h;
     LevelRec *r = p.st.rec;
     rec_clear(r[0]);
     const uint32_t sm = h.smask;
@@ -99,7 +127,7 @@ __device__ __forceinline__ void clear_level_words(const Params &p, uint32_t k, u
 template <int W>
 __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32_t bid, uint32_t nblk) {
     const GraphView &g = p.g;
-    const QueryView &qv = p.qv;
+    const QueryView &qv = s_qv;
     const QHeader &h = *qv.h;
     LevelRec *rec = p.st.rec;
     LevelRec &R = rec[n % REC_RING];
@@ -244,7 +272,7 @@ __device__ __forceinline__ void record_level(const Params &p, uint32_t n, uint32
 
 // push (0) or pull (1) for level n; every workgroup computes the same answer
 __device__ __forceinline__ uint32_t decide(const Params &p, uint32_t n) {
-    const QHeader &h = *p.qv.h;
+    const QHeader &h = *s_qv.h;
     if (h.force == 1) return 0;
     if (h.force == 2) return 1;
     if (!(h.alpha > 0.f)) return 0;
@@ -390,7 +418,7 @@ __device__ __forceinline__ uint32_t pull_rows(const Params &p, uint32_t w, uint3
     // row ranges of w for symbols u0 .. u0+SYM_BATCH-1 in the pull direction;
     // returns the summed length (0 for symbols that cannot reach U)
     const GraphView &g = p.g;
-    const QueryView &qv = p.qv;
+    const QueryView &qv = s_qv;
     const uint32_t nsym = qv.h->nsym;
     uint32_t pu[SYM_BATCH];
     RankWordD rw[SYM_BATCH];
@@ -421,7 +449,7 @@ template <int W>
 __device__ __forceinline__ void pull_phase(const Params &p, uint32_t n, uint32_t *s_hw, uint32_t *s_hu, uint32_t *s_hp,
                            uint32_t *s_hn) {
     const GraphView &g = p.g;
-    const QueryView &qv = p.qv;
+    const QueryView &qv = s_qv;
     const QHeader &h = *qv.h;
     LevelRec *rec = p.st.rec;
     // states that can appear in the next frontier at all
@@ -550,7 +578,7 @@ __device__ __forceinline__ void final_phase(const Params &p, uint32_t nlev) {
             else flag_violation(p);
         }
     }
-    const uint32_t fm = p.qv.h->fmask;
+    const uint32_t fm = s_qv.h->fmask;
     const uint32_t nwords = (V + 63) / 64;
     const uint32_t lane = lane_id();
     const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
@@ -616,6 +644,7 @@ template <int W>
 __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
     // push tiles and pull heavy lists share the workgroup's LDS
     __shared__ uint32_t s_eb[TILE + 1], s_beg[TILE + 1], s_mask[TILE + 1], s_hn;
+    qv_setup<true>(p.qv);
     GridBarrier *bar = p.st.bar;
     // the next launch's barrier (not touched by this one) starts zeroed: no
     // separate clearing launch per query
@@ -664,17 +693,20 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
 
 template <int W>
 __global__ __launch_bounds__(64) void k_init(Params p) {
+    qv_setup<false>(p.qv);
     init_phase<W>(p);
 }
 
 template <int W>
 __global__ __launch_bounds__(BLOCK) void k_select(Params p, uint32_t n) {
+    qv_setup<false>(p.qv);
     select_phase<W>(p, n, blockIdx.x, gridDim.x);
 }
 
 template <int W>
 __global__ __launch_bounds__(BLOCK) void k_expand(Params p, uint32_t n) {
     __shared__ uint32_t s_eb[TILE + 1], s_beg[TILE + 1], s_mask[TILE + 1], s_hn;
+    qv_setup<false>(p.qv);
     const uint32_t mode = decide(p, n);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         record_level(p, n, mode);
@@ -687,6 +719,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(Params p, uint32_t n) {
 
 template <int W>
 __global__ __launch_bounds__(BLOCK) void k_final(Params p, uint32_t nlev) {
+    qv_setup<false>(p.qv);
     final_phase<W>(p, nlev);
 }
 

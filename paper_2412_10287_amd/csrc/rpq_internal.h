@@ -110,7 +110,12 @@ __host__ __device__ inline QOffsets qconst_offsets(size_t nsym) {
 }
 
 // Bytes of the query-constant block for nsym used symbols.
-inline size_t qconst_bytes(size_t nsym) { return qconst_offsets(nsym).end; }
+__host__ __device__ inline size_t qconst_bytes(size_t nsym) { return qconst_offsets(nsym).end; }
+
+// Query-constant blocks up to this size are copied into LDS by the
+// persistent kernels (about 38 used symbols): the select phase's symbol
+// tables are then one LDS access away instead of an L2 round trip.
+constexpr size_t QC_LDS_BYTES = 12 * 1024;
 
 // Table addresses of the block at `base` (host or device address).
 __host__ __device__ inline QueryView qconst_view(const uint8_t *base, size_t nsym) {

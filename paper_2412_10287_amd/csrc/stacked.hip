@@ -34,6 +34,26 @@ namespace rpq {
 
 constexpr uint32_t PULL_LIGHT_ROW = 128;  // longer pull rows are processed edge-balanced
 
+// The query's tables for every phase of the stacked kernel: a copy in LDS
+// when the block fits, else the global block.
+__shared__ QueryView s_qv;
+__shared__ __align__(16) uint8_t s_qc[QC_LDS_BYTES];
+
+// Sets s_qv, copying the block into s_qc when it fits. Every thread of the
+// workgroup calls it; it ends with a workgroup barrier.
+__device__ __forceinline__ void st_qv_setup(const QueryView &qv) {
+    const uint32_t nsym = qv.h->nsym;
+    const size_t qb = qconst_bytes(nsym);
+    const bool fits = qb <= QC_LDS_BYTES;
+    if (fits) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(qv.h);
+        uint4 *dst = reinterpret_cast<uint4 *>(s_qc);
+        for (uint32_t i = threadIdx.x; i < (qb + 15) / 16; i += blockDim.x) dst[i] = src[i];
+    }
+    if (threadIdx.x == 0) s_qv = fits ? qconst_view(s_qc, nsym) : qv;
+    __syncthreads();
+}
+
 __device__ __forceinline__ void sviol(const StackParams &p) { atomicAdd(&p.status[3], 1u); }
 
 template <int G>
@@ -114,7 +134,7 @@ __device__ __forceinline__ void put_item(const StackParams &p, uint32_t idx, uin
 template <int G, int QM>
 __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint32_t bid, uint32_t nblk) {
     const GraphView &g = p.g;
-    const QueryView &qv = p.qv;
+    const QueryView &qv = s_qv;
     LevelRec *rec = p.rec;
     LevelRec &R = rec[n % REC_RING];
     const uint32_t nq = queue_len(p, R);
@@ -329,7 +349,7 @@ __device__ __forceinline__ void unit_gather(const StackParams &p, uint32_t n, co
     if (unit >= uend) return;
     const uint32_t pos = L.beg[lo] + (t - L.eb[lo]);
     const uint32_t iv = L.v[lo], u = L.u[lo];
-    if (pos >= p.g.ncol || iv >= V || u >= p.qv.h->nsym) {
+    if (pos >= p.g.ncol || iv >= V || u >= s_qv.h->nsym) {
         sviol(p);
         return;
     }
@@ -340,7 +360,7 @@ __device__ __forceinline__ void unit_gather(const StackParams &p, uint32_t n, co
     }
     const uint32_t src = PULL ? other : iv;
     const uint32_t w = PULL ? iv : other;
-    const uint32_t *succ = p.qv.succ + u * MAX_STATES;
+    const uint32_t *succ = s_qv.succ + u * MAX_STATES;
     const uint32_t tmask = PULL ? ns : ~0u;
     const uint32_t S = (PULL ? (p.sup[n & 1][src] & L.s[lo]) : L.s[lo]) & state_mask(p);
     U.dst = w;
@@ -574,7 +594,7 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, S
 template <int G>
 __device__ __forceinline__ void st_pull_rows(const StackParams &p, uint32_t n, uint32_t ns) {
     const GraphView &g = p.g;
-    const QueryView &qv = p.qv;
+    const QueryView &qv = s_qv;
     const uint32_t V = static_cast<uint32_t>(p.V);
     const uint32_t nsym = qv.h->nsym;
     const uint32_t lane = lane_id();
@@ -705,7 +725,7 @@ __device__ __forceinline__ void st_pull_rows(const StackParams &p, uint32_t n, u
 // push (0) or pull (1) for level n; every workgroup computes the same answer
 template <int QM>
 __device__ __forceinline__ uint32_t st_decide(const StackParams &p, uint32_t n, uint32_t prev) {
-    const QHeader &h = *p.qv.h;
+    const QHeader &h = *s_qv.h;
     if (QM > 8 || h.force == 1) return 0;
     if (h.force == 2) return 1;
     if (!(h.alpha > 0.f)) return 0;
@@ -748,7 +768,7 @@ __device__ __forceinline__ void st_final(const StackParams &p, uint32_t nexit, u
             if (gthread() == 0 && (words & 1)) p.M[b][words - 1] = 0;
         }
     }
-    const uint32_t fm = p.qv.h->fmask;
+    const uint32_t fm = s_qv.h->fmask;
     const uint64_t nwords = static_cast<uint64_t>(p.nwords);
     const uint64_t total = nwords * G;
     const uint32_t B = static_cast<uint32_t>(p.B);
@@ -836,6 +856,7 @@ __device__ __forceinline__ void st_solo_levels(const StackParams &p, uint32_t n,
 template <int G, int QM>
 __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
     __shared__ StLds L;
+    st_qv_setup(p.qv);
     GridBarrier *bar = p.bar;
     BarCtx bc;
     if (!barrier_register(bar, bc)) return;
@@ -847,7 +868,7 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
     if (!grid_barrier(bar, bc)) return;
     // start pairs M_0 = Q_S x {source}: every source's bit in its start rows,
     // as candidates that level 0's select adds to P
-    const QHeader &h = *p.qv.h;
+    const QHeader &h = *s_qv.h;
     const uint32_t V = static_cast<uint32_t>(p.V);
     for (uint32_t i = gthread(); i < static_cast<uint32_t>(p.B); i += gthreads()) {
         const uint32_t s = static_cast<uint32_t>(p.sources[i]);
