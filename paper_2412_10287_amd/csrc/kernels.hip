@@ -95,9 +95,9 @@ __device__ __forceinline__ void init_phase(const Params &p) {
 // (its candidate and frontier words), eight entries per thread and step with
 // all loads before the stores (one workgroup alone may clear a long queue).
 template <int W>
-__device__ __forceinline__ void clear_level_words(const Params &p, uint32_t k, uint32_t bid, uint32_t nblk) {
+__device__ __forceinline__ void clear_level_words(const Params &p, uint32_t k, uint32_t nk, uint32_t bid,
+                                                  uint32_t nblk) {
     const uint32_t V = static_cast<uint32_t>(p.g.V);
-    uint32_t nk = ld_acq(&p.st.rec[k % REC_RING].nq);
     if (nk > V) nk = V;
     uint32_t *M = p.st.M[k & 1];
     const int32_t *q = p.st.q[k & 1];
@@ -144,7 +144,8 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
     // frontier words of level n-1 live in the buffer level n writes: after a
     // pull level they are cleared here (after a push level, that level's
     // push phase has cleared them already)
-    if (n >= 1 && ld_acq(&rec[(n - 1) % REC_RING].mode) != 0) clear_level_words<W>(p, n - 1, bid, nblk);
+    if (n >= 1 && ld_acq(&rec[(n - 1) % REC_RING].mode) != 0)
+        clear_level_words<W>(p, n - 1, ld_acq(&rec[(n - 1) % REC_RING].nq), bid, nblk);
     const int32_t *qc = p.st.q[n & 1];
     uint32_t *Mc = p.st.M[n & 1];
     uint32_t *P = p.st.P;
@@ -257,31 +258,46 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
     }
 }
 
-// Level n's statistics once its select phase is complete (one thread).
-__device__ __forceinline__ void record_level(const Params &p, uint32_t n, uint32_t mode) {
-    LevelRec &R = p.st.rec[n % REC_RING];
-    R.mode = mode;
+// Level n's totals once its select phase is complete, read by every thread
+// at once (one round trip): its push reservations, pairs, frontier vertices,
+// queue length and the direction of level n-1.
+struct LevelInfo {
+    uint64_t sel, pairs;
+    uint32_t nfront, nq, prev_mode;
+};
+
+__device__ __forceinline__ LevelInfo level_info(const Params &p, uint32_t n) {
+    const LevelRec &R = p.st.rec[n % REC_RING];
+    LevelInfo li;
+    li.sel = ld_acq(&R.sel);
+    li.pairs = ld_acq(&R.pairs);
+    li.nfront = ld_acq(&R.nfront);
+    li.nq = ld_acq(&R.nq);
+    li.prev_mode = n ? ld_acq(&p.st.rec[(n - 1) % REC_RING].mode) : 0u;
+    return li;
+}
+
+// Level n's statistics (one thread).
+__device__ __forceinline__ void record_level(const Params &p, uint32_t n, uint32_t mode, const LevelInfo &li) {
+    p.st.rec[n % REC_RING].mode = mode;
     if (n < LVL_COUNT_CAP) {
         uint64_t *L = p.st.lvl + static_cast<uint64_t>(n) * LVL_STRIDE;
-        L[0] = ld_acq(&R.pairs);
-        L[1] = ld_acq(&R.nfront);
-        L[2] = ld_acq(&R.sel);
+        L[0] = li.pairs;
+        L[1] = li.nfront;
+        L[2] = li.sel;
         L[4] = wall_clock64();
     }
 }
 
 // push (0) or pull (1) for level n; every workgroup computes the same answer
-__device__ __forceinline__ uint32_t decide(const Params &p, uint32_t n) {
+__device__ __forceinline__ uint32_t decide(const Params &p, const LevelInfo &li) {
     const QHeader &h = *s_qv.h;
     if (h.force == 1) return 0;
     if (h.force == 2) return 1;
     if (!(h.alpha > 0.f)) return 0;
-    const LevelRec *rec = p.st.rec;
-    const uint32_t prev = n ? ld_acq(&rec[(n - 1) % REC_RING].mode) : 0u;
-    const uint64_t T = ld_acq(&rec[n % REC_RING].sel) & 0xffffffffull;
-    const uint32_t nq = ld_acq(&rec[n % REC_RING].nfront);
-    if (prev == 0) return static_cast<double>(T) * h.alpha > static_cast<double>(h.e_rel) ? 1u : 0u;
-    return static_cast<double>(nq) * h.beta < static_cast<double>(p.g.V) ? 0u : 1u;
+    const uint64_t T = li.sel & 0xffffffffull;
+    if (li.prev_mode == 0) return static_cast<double>(T) * h.alpha > static_cast<double>(h.e_rel) ? 1u : 0u;
+    return static_cast<double>(li.nfront) * h.beta < static_cast<double>(p.g.V) ? 0u : 1u;
 }
 
 // Edges [ubase, uend) of the items staged in LDS (cnt of them), four per
@@ -347,13 +363,13 @@ __device__ __forceinline__ void push_range(const Params &p, uint32_t n, const ui
 // [k*TILE, (k+1)*TILE) and its items are staged in LDS; with fewer tiles than
 // workgroups each tile is split into parts of at least a wave's worth.
 template <int W>
-__device__ __forceinline__ void push_phase(const Params &p, uint32_t n, uint32_t *s_eb, uint32_t *s_beg,
-                                           uint32_t *s_mask, uint32_t bid, uint32_t nblk) {
+__device__ __forceinline__ void push_phase(const Params &p, uint32_t n, const LevelInfo &li, uint32_t *s_eb,
+                                           uint32_t *s_beg, uint32_t *s_mask, uint32_t bid, uint32_t nblk) {
     // the push direction never reads this level's words of M[n & 1] again
     // (items carry the successor sets): clear them now, with stores that
     // overlap the push; level n+1's expansion writes this buffer
-    clear_level_words<W>(p, n, bid, nblk);
-    const uint64_t sel = ld_acq(&p.st.rec[n % REC_RING].sel);
+    clear_level_words<W>(p, n, li.nq, bid, nblk);
+    const uint64_t sel = li.sel;
     const uint32_t nitems = static_cast<uint32_t>(sel >> 32);
     const uint32_t T = static_cast<uint32_t>(sel);
     if (T == 0 || nitems == 0) return;
@@ -621,14 +637,14 @@ __device__ __forceinline__ void solo_levels(const Params &p, uint32_t n, uint32_
         if (nq == 0 || nq > SOLO_MAX_QUEUE) break;
         select_phase<W>(p, n, 0, 1);
         solo_sync();
-        const uint32_t mode = decide(p, n);
-        const uint64_t T = ld_acq(&p.st.rec[n % REC_RING].sel) & 0xffffffffull;
-        if (mode != 0 || T > SOLO_MAX_EDGES) {
+        const LevelInfo li = level_info(p, n);
+        const uint32_t mode = decide(p, li);
+        if (mode != 0 || (li.sel & 0xffffffffull) > SOLO_MAX_EDGES) {
             sel_done = 1;
             break;
         }
-        if (threadIdx.x == 0) record_level(p, n, 0);
-        push_phase<W>(p, n, s_eb, s_beg, s_mask, 0, 1);
+        if (threadIdx.x == 0) record_level(p, n, 0, li);
+        push_phase<W>(p, n, li, s_eb, s_beg, s_mask, 0, 1);
         solo_sync();
         npush++;
         n++;
@@ -674,9 +690,10 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
             select_phase<W>(p, n, blockIdx.x, gridDim.x);
             if (!grid_barrier(bar, bc)) return;
         }
-        const uint32_t mode = decide(p, n);
-        if (blockIdx.x == 0 && threadIdx.x == 0) record_level(p, n, mode);
-        if (mode == 0) push_phase<W>(p, n, s_eb, s_beg, s_mask, blockIdx.x, gridDim.x);
+        const LevelInfo li = level_info(p, n);
+        const uint32_t mode = decide(p, li);
+        if (blockIdx.x == 0 && threadIdx.x == 0) record_level(p, n, mode, li);
+        if (mode == 0) push_phase<W>(p, n, li, s_eb, s_beg, s_mask, blockIdx.x, gridDim.x);
         else pull_phase<W>(p, n, s_eb, s_beg, s_mask, &s_hn);
         npush += mode == 0;
         npull += mode != 0;
@@ -707,13 +724,14 @@ template <int W>
 __global__ __launch_bounds__(BLOCK) void k_expand(Params p, uint32_t n) {
     __shared__ uint32_t s_eb[TILE + 1], s_beg[TILE + 1], s_mask[TILE + 1], s_hn;
     qv_setup<false>(p.qv);
-    const uint32_t mode = decide(p, n);
+    const LevelInfo li = level_info(p, n);
+    const uint32_t mode = decide(p, li);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        record_level(p, n, mode);
+        record_level(p, n, mode, li);
         p.st.status[0] = n + 1;
         p.st.status[1 + (mode != 0)] += 1;
     }
-    if (mode == 0) push_phase<W>(p, n, s_eb, s_beg, s_mask, blockIdx.x, gridDim.x);
+    if (mode == 0) push_phase<W>(p, n, li, s_eb, s_beg, s_mask, blockIdx.x, gridDim.x);
     else pull_phase<W>(p, n, s_eb, s_beg, s_mask, &s_hn);
 }
 
