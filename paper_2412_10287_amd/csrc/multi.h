@@ -22,7 +22,8 @@ struct MultiParams {
     // control block, copied to the host in one transfer per level:
     //   qlen[2] (queue lengths by parity), status (invariant violations),
     //   next_count[slots] (non-zero when the slot's next frontier is not empty),
-    //   pairs[slots] (reached (state, vertex) pairs per slot, 8-byte aligned)
+    //   pairs[slots * PAIRS_STRIDE] (reached (state, vertex) pairs of slot s at
+    //   s * PAIRS_STRIDE, one line per slot)
     uint32_t *ctl;
     uint32_t *qlen[2];        // next-queue lengths by parity (separate lines)
     uint32_t *status;
@@ -59,7 +60,12 @@ constexpr size_t CTL_NEXT = 3 * CTL_LINE;   // uint32 next_count[slots]
 inline size_t multi_pairs_offset(uint32_t slots) {
     return CTL_NEXT + ((4 * static_cast<size_t>(slots) + CTL_LINE - 1) / CTL_LINE) * CTL_LINE;
 }
-inline size_t multi_ctl_bytes(uint32_t slots) { return multi_pairs_offset(slots) + 8 * static_cast<size_t>(slots); }
+// pairs[] keeps each slot's counter on a line of its own (every workgroup of
+// a select launch adds to the counters of the slots it saw)
+constexpr size_t PAIRS_STRIDE = CTL_LINE / 8;  // uint64 entries per slot
+inline size_t multi_ctl_bytes(uint32_t slots) {
+    return multi_pairs_offset(slots) + CTL_LINE * static_cast<size_t>(slots);
+}
 hipError_t multi_extract(const MultiParams &p, uint32_t nfin, const uint32_t *fin_slots, uint64_t nwords,
                          hipStream_t s);
 

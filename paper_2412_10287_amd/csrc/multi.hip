@@ -28,7 +28,7 @@ __global__ void k_multi_admit(MultiParams p, uint32_t parity, uint32_t n, const 
         return;
     }
     const uint32_t sm = reinterpret_cast<const QHeader *>(p.qconst + static_cast<size_t>(s) * QC_STRIDE)->smask;
-    p.pairs[s] = 0;
+    p.pairs[s * PAIRS_STRIDE] = 0;
     if (!sm) return;
     // M_0 = Q_S x {source} as a candidate: the next select adds it to P
     p.M[parity][s * p.swords + v] = sm;
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < p.slots && i < MAX_SLOTS_DEV; i += BLOCK)
-        if (s_pairs[i]) atomicAdd(reinterpret_cast<unsigned long long *>(&p.pairs[i]), s_pairs[i]);
+        if (s_pairs[i]) atomicAdd(reinterpret_cast<unsigned long long *>(&p.pairs[i * PAIRS_STRIDE]), s_pairs[i]);
 }
 
 // Edges [ubase, uend) of the items staged in LDS (cnt of them), four per

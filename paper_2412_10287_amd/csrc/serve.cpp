@@ -278,7 +278,7 @@ static rpq_status engine_step(rpq_graph *g, ServeState *ss, std::vector<Request>
         if (si.ticket && !si.finished && h_cnt[sl] == 0) {
             si.finished = true;
             si.levels = ss->level - si.admit_level + 1;
-            si.pairs = h_pairs[sl];
+            si.pairs = h_pairs[sl * PAIRS_STRIDE];
             ss->ready.push_back(sl);
         }
     }

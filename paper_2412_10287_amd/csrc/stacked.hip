@@ -132,7 +132,7 @@ __device__ __forceinline__ void put_item(const StackParams &p, uint32_t idx, uin
 
 // ------------------------------------------------------------------ select
 template <int G, int QM>
-__device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint32_t bid, uint32_t nblk) {
+__device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint32_t bid, uint32_t nblk, uint64_t &cacc) {
     const GraphView &g = p.g;
     const QueryView &qv = s_qv;
     LevelRec *rec = p.rec;
@@ -302,10 +302,13 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
             case 0: atomicAdd(reinterpret_cast<unsigned long long *>(&R.pairs), (unsigned long long)t); break;
             case 1: atomicAdd(&R.nfront, static_cast<uint32_t>(t)); break;
             case 2: atomicOr(&R.su, static_cast<uint32_t>(t)); break;
-            case 3: atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[0]), (unsigned long long)t); break;
-            case 4: atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[1]), (unsigned long long)t); break;
-            case 5: atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[2]), (unsigned long long)t); break;
-            case 6: atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[3]), (unsigned long long)t); break;
+            // work counters: kept by threads 3..6 over the whole launch and
+            // added to p.cnt once at its end (one line for all four: per
+            // level, the grid's atomics on it would queue for ~12 us)
+            case 3:
+            case 4:
+            case 5:
+            case 6: cacc += t; break;
             default: break;
         }
     }
@@ -826,13 +829,13 @@ __device__ __forceinline__ void st_solo_sync() {
 // finished and in bar->solo_sel whether its select phase is already done.
 template <int G, int QM>
 __device__ __forceinline__ void st_solo_levels(const StackParams &p, uint32_t n, StLds &L, uint32_t prev,
-                                               uint32_t &npush) {
+                                               uint32_t &npush, uint64_t &cacc) {
     constexpr uint32_t max_queue = BLOCK / G;
     uint32_t sel_done = 0;
     for (uint32_t run = 0; run < ST_SOLO_MAX_RUN; run++) {
         const uint32_t nq = ld_acq(&p.rec[n % REC_RING].nq);
         if (nq == 0 || nq > max_queue) break;
-        st_select<G, QM>(p, n, 0, 1);
+        st_select<G, QM>(p, n, 0, 1, cacc);
         st_solo_sync();
         const uint32_t mode = st_decide<QM>(p, n, prev);
         const uint64_t sel = ld_acq(&p.rec[n % REC_RING].sel);
@@ -893,7 +896,7 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
     }
     if (!grid_barrier(bar, bc)) return;
     uint32_t n = 0, npush = 0, npull = 0, prev = 0, solo_at = ~0u;
-    uint64_t last_pairs = 0;
+    uint64_t last_pairs = 0, cacc = 0;
     while (true) {
         const uint32_t nq = ld_acq(&p.rec[n % REC_RING].nq);
         if (nq == 0) break;
@@ -901,7 +904,7 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
         if (nq <= BLOCK / G && n != solo_at) {
             // a run of small levels in workgroup 0; the rest wait here
             solo_at = n;
-            if (blockIdx.x == 0) st_solo_levels<G, QM>(p, n, L, prev, npush);
+            if (blockIdx.x == 0) st_solo_levels<G, QM>(p, n, L, prev, npush, cacc);
             if (!grid_barrier(bar, bc)) return;
             const uint32_t n2 = ld_acq(&bar->solo_n);
             if (n2 != n) {
@@ -913,7 +916,7 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
             if (!selected) continue;
         }
         if (!selected) {
-            st_select<G, QM>(p, n, blockIdx.x, gridDim.x);
+            st_select<G, QM>(p, n, blockIdx.x, gridDim.x, cacc);
             if (!grid_barrier(bar, bc)) return;
         }
         LevelRec &R = p.rec[n % REC_RING];
@@ -946,6 +949,9 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
         prev = mode;
         n++;
     }
+    // this workgroup's share of the work counters (threads 3..6)
+    if (threadIdx.x >= 3 && threadIdx.x < 7 && cacc)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[threadIdx.x - 3]), static_cast<unsigned long long>(cacc));
     // the last level may have found only visited pairs
     const uint32_t levels = (n > 0 && last_pairs == 0) ? n - 1 : n;
     st_final<G>(p, n, levels);
