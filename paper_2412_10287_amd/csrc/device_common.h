@@ -9,11 +9,13 @@ namespace rpq {
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// State word of vertex v (a device-scope load: see ldc).
 template <int W>
 __device__ __forceinline__ uint32_t ld_state(const uint32_t *a, uint32_t v) {
-    if constexpr (W == 4) return a[v];
-    else if constexpr (W == 2) return reinterpret_cast<const uint16_t *>(a)[v];
-    else return reinterpret_cast<const uint8_t *>(a)[v];
+    if constexpr (W == 4) return __hip_atomic_load(a + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else if constexpr (W == 2)
+        return __hip_atomic_load(reinterpret_cast<const uint16_t *>(a) + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return __hip_atomic_load(reinterpret_cast<const uint8_t *>(a) + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int W>
@@ -38,6 +40,16 @@ __device__ __forceinline__ uint32_t or_state(uint32_t *a, uint32_t v, uint32_t x
 
 template <typename T>
 __device__ __forceinline__ T ld_acq(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Load of data that other workgroups write during a persistent launch
+// (queues, state words, items): a device-scope load, which misses the
+// compute unit's L1. The grid barrier invalidates the L1 only in the XCD
+// leaders (the invalidations of all workgroups queue up in each XCD), so
+// every such read in the persistent kernels goes through here.
+template <typename T>
+__device__ __forceinline__ T ldc(const T *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -430,8 +442,12 @@ __device__ inline bool grid_barrier(GridBarrier *b, BarCtx &c) {
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
             __hip_atomic_store(&b->lgen[c.xcd][0], c.k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
+            // the leader has invalidated the XCD's L2; this compute unit's L1
+            // may hold stale lines, which the persistent kernels never read:
+            // their loads of data written during the launch are device-scope
+            // (ldc, ld_state). The fence only orders the compiler's accesses.
             ok = spin_until_at_least(b, &b->lgen[c.xcd][0], c.k);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
         if (aload(&b->abort)) ok = 0;
         s_ok = ok;

@@ -107,7 +107,7 @@ __device__ __forceinline__ void clear_level_words(const Params &p, uint32_t k, u
 #pragma unroll
         for (int j = 0; j < 8; j++) {
             const uint32_t i = i0 + j * stride;
-            vv[j] = i < nk ? static_cast<uint32_t>(q[i]) : 0u;
+            vv[j] = i < nk ? static_cast<uint32_t>(ldc(&q[i])) : 0u;
         }
 #pragma unroll
         for (int j = 0; j < 8; j++) {
@@ -157,7 +157,7 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
         const uint32_t i = bbase + threadIdx.x;
         uint32_t v = 0, S = 0;
         if (i < nq) {
-            v = static_cast<uint32_t>(qc[i]);
+            v = static_cast<uint32_t>(ldc(&qc[i]));
             if (v < V) {
                 // the complement mask of Alg. 1, then P = P + M
                 const uint32_t c = ld_state<W>(Mc, v);
@@ -380,9 +380,9 @@ __device__ __forceinline__ void push_phase(const Params &p, uint32_t n, const Le
     const uint32_t tid = threadIdx.x;
     if (nitems <= static_cast<uint32_t>(TILE)) {
         for (uint32_t j = tid; j < nitems; j += BLOCK) {
-            s_eb[j] = p.st.it_ebase[j];
-            s_beg[j] = p.st.it_beg[j];
-            s_mask[j] = p.st.it_mask[j];
+            s_eb[j] = ldc(&p.st.it_ebase[j]);
+            s_beg[j] = ldc(&p.st.it_beg[j]);
+            s_mask[j] = ldc(&p.st.it_mask[j]);
         }
         __syncthreads();
         uint32_t per = (T + nblk - 1) / nblk;
@@ -399,17 +399,17 @@ __device__ __forceinline__ void push_phase(const Params &p, uint32_t n, const Le
     const uint32_t part = TILE / sub;
     for (uint32_t vt = bid; vt < ntiles * sub; vt += nblk) {
         const uint32_t tile = vt / sub, k = vt % sub;
-        uint32_t i0 = tile < p.st.tile_cap ? p.st.tile_first[tile] : 0u;
-        uint32_t i1 = (tile + 1 < ntiles && tile + 1 < p.st.tile_cap) ? p.st.tile_first[tile + 1] : nitems - 1;
+        uint32_t i0 = tile < p.st.tile_cap ? ldc(&p.st.tile_first[tile]) : 0u;
+        uint32_t i1 = (tile + 1 < ntiles && tile + 1 < p.st.tile_cap) ? ldc(&p.st.tile_first[tile + 1]) : nitems - 1;
         if (i0 >= nitems || i1 >= nitems || i1 < i0 || i1 - i0 > static_cast<uint32_t>(TILE)) {
             if (tid == 0) flag_violation(p);
             i0 = i1 = 0;
         }
         const uint32_t cnt = i1 - i0 + 1;  // <= TILE + 1
         for (uint32_t j = tid; j < cnt; j += BLOCK) {
-            s_eb[j] = p.st.it_ebase[i0 + j];
-            s_beg[j] = p.st.it_beg[i0 + j];
-            s_mask[j] = p.st.it_mask[i0 + j];
+            s_eb[j] = ldc(&p.st.it_ebase[i0 + j]);
+            s_beg[j] = ldc(&p.st.it_beg[i0 + j]);
+            s_mask[j] = ldc(&p.st.it_mask[i0 + j]);
         }
         __syncthreads();
         const uint32_t u0 = tile * TILE + k * part;
@@ -589,7 +589,7 @@ __device__ __forceinline__ void final_phase(const Params &p, uint32_t nlev) {
         uint32_t *M = p.st.M[D & 1];
         const int32_t *q = p.st.q[D & 1];
         for (uint32_t i = gthread(); i < nq; i += gthreads()) {
-            const uint32_t v = static_cast<uint32_t>(q[i]);
+            const uint32_t v = static_cast<uint32_t>(ldc(&q[i]));
             if (v < V) st_state<W>(M, v, 0);
             else flag_violation(p);
         }

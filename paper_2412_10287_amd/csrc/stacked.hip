@@ -162,7 +162,7 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
 #pragma unroll
             for (int k = 0; k < 8; k++) {
                 const uint32_t i = i0 + k * stride;
-                vv[k] = i < nprev ? static_cast<uint32_t>(qold[i]) : 0u;
+                vv[k] = i < nprev ? static_cast<uint32_t>(ldc(&qold[i])) : 0u;
             }
 #pragma unroll
             for (int k = 0; k < 8; k++) {
@@ -184,9 +184,9 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
         uint32_t w = 0, cs = 0;
         bool ok = false;
         if (i < nq) {
-            w = static_cast<uint32_t>(qc[i]);
+            w = static_cast<uint32_t>(ldc(&qc[i]));
             if (w < V) {
-                cs = sc[w] & qmask;
+                cs = ldc(&sc[w]) & qmask;
                 ok = true;
             } else {
                 if (j == 0) sviol(p);
@@ -200,8 +200,8 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
         for (int k = 0; k < QM; k++) {
             if ((cs >> k) & 1u) {
                 const uint64_t idx = rowi<G>(p, w, k) + j;
-                const uint64_t c = Mc[idx];
-                const uint64_t pv = p.P[idx];
+                const uint64_t c = ldc(&Mc[idx]);
+                const uint64_t pv = ldc(&p.P[idx]);
                 const uint64_t nb = c & ~pv;
                 if (nb) {
                     p.P[idx] = pv | nb;
@@ -365,7 +365,7 @@ __device__ __forceinline__ void unit_gather(const StackParams &p, uint32_t n, co
     const uint32_t w = PULL ? iv : other;
     const uint32_t *succ = s_qv.succ + u * MAX_STATES;
     const uint32_t tmask = PULL ? ns : ~0u;
-    const uint32_t S = (PULL ? (p.sup[n & 1][src] & L.s[lo]) : L.s[lo]) & state_mask(p);
+    const uint32_t S = (PULL ? (ldc(&p.sup[n & 1][src]) & L.s[lo]) : L.s[lo]) & state_mask(p);
     U.dst = w;
     if constexpr (QM <= 8) {
         // y[q'] = OR of the source's rows over the transitions into q'
@@ -375,7 +375,7 @@ __device__ __forceinline__ void unit_gather(const StackParams &p, uint32_t n, co
 #pragma unroll
         for (int kq = 0; kq < QM; kq++) {
             if ((S >> kq) & 1u) {
-                const uint64_t x = Mc[rowi<G>(p, src, kq) + j];
+                const uint64_t x = ldc(&Mc[rowi<G>(p, src, kq) + j]);
                 const uint32_t tq = succ[kq] & tmask;
 #pragma unroll
                 for (int q2 = 0; q2 < QM; q2++)
@@ -384,7 +384,7 @@ __device__ __forceinline__ void unit_gather(const StackParams &p, uint32_t n, co
         }
 #pragma unroll
         for (int q2 = 0; q2 < QM; q2++)
-            if (y[q2]) U.c[q2] = y[q2] & ~p.P[rowi<G>(p, w, q2) + j];
+            if (y[q2]) U.c[q2] = y[q2] & ~ldc(&p.P[rowi<G>(p, w, q2) + j]);
     } else {
         uint32_t SS = S;
         while (SS) {
@@ -392,13 +392,13 @@ __device__ __forceinline__ void unit_gather(const StackParams &p, uint32_t n, co
             SS &= SS - 1;
             uint32_t tq = succ[kq] & tmask;
             if (!tq) continue;
-            const uint64_t x = Mc[rowi<G>(p, src, kq) + j];
+            const uint64_t x = ldc(&Mc[rowi<G>(p, src, kq) + j]);
             if (!x) continue;
             while (tq) {
                 const uint32_t q2 = __ffs(tq) - 1;
                 tq &= tq - 1;
                 const uint64_t idx = rowi<G>(p, w, q2) + j;
-                const uint64_t c = x & ~p.P[idx];
+                const uint64_t c = x & ~ldc(&p.P[idx]);
                 if (c) {
                     atomicOr(reinterpret_cast<unsigned long long *>(Mn + idx), static_cast<unsigned long long>(c));
                     U.tb |= 1u << q2;
@@ -449,10 +449,10 @@ __device__ __forceinline__ void unit_append4(const StackParams &p, uint32_t n, u
     // states (values read during the phase only ever lack bits, never have
     // extra ones), and a load costs far less than an atomic
     uint32_t o0 = 1, o1 = 1, o2 = 1, o3 = 1;
-    if (t0 && lead) o0 = sn[U0.dst];
-    if (t1 && lead) o1 = sn[U1.dst];
-    if (t2 && lead) o2 = sn[U2.dst];
-    if (t3 && lead) o3 = sn[U3.dst];
+    if (t0 && lead) o0 = ldc(&sn[U0.dst]);
+    if (t1 && lead) o1 = ldc(&sn[U1.dst]);
+    if (t2 && lead) o2 = ldc(&sn[U2.dst]);
+    if (t3 && lead) o3 = ldc(&sn[U3.dst]);
     if (t0 && lead && (o0 & t0) != t0) o0 = atomicOr(&sn[U0.dst], t0);
     if (t1 && lead && (o1 & t1) != t1) o1 = atomicOr(&sn[U1.dst], t1);
     if (t2 && lead && (o2 & t2) != t2) o2 = atomicOr(&sn[U2.dst], t2);
@@ -540,11 +540,11 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, S
         // few items: every workgroup stages all of them and takes an even,
         // wave-aligned share of the units, so small levels use the whole chip
         for (uint32_t x = tid; x < nitems; x += BLOCK) {
-            L.eb[x] = p.it_ebase[x];
-            L.beg[x] = p.it_beg[x];
-            L.v[x] = p.it_v[x];
-            L.u[x] = p.it_u[x];
-            L.s[x] = p.it_s[x];
+            L.eb[x] = ldc(&p.it_ebase[x]);
+            L.beg[x] = ldc(&p.it_beg[x]);
+            L.v[x] = ldc(&p.it_v[x]);
+            L.u[x] = ldc(&p.it_u[x]);
+            L.s[x] = ldc(&p.it_s[x]);
         }
         __syncthreads();
         uint64_t per = (units + nblk - 1) / nblk;
@@ -564,19 +564,19 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, S
     const uint32_t part_units = TILE / sub;
     for (uint32_t vt = bid; vt < ntiles * sub; vt += nblk) {
         const uint32_t tile = vt / sub, part = vt % sub;
-        uint32_t i0 = tile < p.tile_cap ? p.tile_first[tile] : 0u;
-        uint32_t i1 = (tile + 1 < ntiles && tile + 1 < p.tile_cap) ? p.tile_first[tile + 1] : nitems - 1;
+        uint32_t i0 = tile < p.tile_cap ? ldc(&p.tile_first[tile]) : 0u;
+        uint32_t i1 = (tile + 1 < ntiles && tile + 1 < p.tile_cap) ? ldc(&p.tile_first[tile + 1]) : nitems - 1;
         if (i0 >= nitems || i1 >= nitems || i1 < i0 || i1 - i0 > TE) {
             if (tid == 0) sviol(p);
             i0 = i1 = 0;
         }
         const uint32_t cnt = i1 - i0 + 1;
         for (uint32_t x = tid; x < cnt; x += BLOCK) {
-            L.eb[x] = p.it_ebase[i0 + x];
-            L.beg[x] = p.it_beg[i0 + x];
-            L.v[x] = p.it_v[i0 + x];
-            L.u[x] = p.it_u[i0 + x];
-            L.s[x] = p.it_s[i0 + x];
+            L.eb[x] = ldc(&p.it_ebase[i0 + x]);
+            L.beg[x] = ldc(&p.it_beg[i0 + x]);
+            L.v[x] = ldc(&p.it_v[i0 + x]);
+            L.u[x] = ldc(&p.it_u[i0 + x]);
+            L.s[x] = ldc(&p.it_s[i0 + x]);
         }
         __syncthreads();
         const uint64_t u0 = static_cast<uint64_t>(tile) * TILE + static_cast<uint64_t>(part) * part_units;
@@ -650,7 +650,7 @@ __device__ __forceinline__ void st_pull_rows(const StackParams &p, uint32_t n, u
                 prow[k] = 0;
                 acc[k] = 0;
                 if (w < V && ((tu >> k) & 1u)) {
-                    prow[k] = p.P[rowi<G>(p, w, k) + j];
+                    prow[k] = ldc(&p.P[rowi<G>(p, w, k) + j]);
                     need |= full & ~prow[k];
                 }
             }
@@ -666,13 +666,13 @@ __device__ __forceinline__ void st_pull_rows(const StackParams &p, uint32_t n, u
 #pragma unroll
                         for (int a = 0; a < 4; a++) vv[a] = e0 + a < end ? g.col[e0 + a] : V;
 #pragma unroll
-                        for (int a = 0; a < 4; a++) sv[a] = vv[a] < V ? (sc[vv[a]] & pu) : 0u;  // pu: states only
+                        for (int a = 0; a < 4; a++) sv[a] = vv[a] < V ? (ldc(&sc[vv[a]]) & pu) : 0u;  // pu: states only
 #pragma unroll
                         for (int a = 0; a < 4; a++) {
 #pragma unroll
                             for (int kq = 0; kq < 8; kq++) {
                                 if ((sv[a] >> kq) & 1u) {
-                                    const uint64_t xw = Mc[rowi<G>(p, vv[a], kq) + j];
+                                    const uint64_t xw = ldc(&Mc[rowi<G>(p, vv[a], kq) + j]);
                                     const uint32_t tq = succ[kq] & tu;
 #pragma unroll
                                     for (int k2 = 0; k2 < 8; k2++)
@@ -758,7 +758,7 @@ __device__ __forceinline__ void st_final(const StackParams &p, uint32_t nexit, u
         uint32_t *sp = p.sup[D & 1];
         const int32_t *q = p.q[D & 1];
         for (uint32_t i = gthread(); i < nq; i += gthreads()) {
-            const uint32_t v = static_cast<uint32_t>(q[i]);
+            const uint32_t v = static_cast<uint32_t>(ldc(&q[i]));
             if (v < V) sp[v] = 0;
             else sviol(p);
         }
@@ -783,7 +783,7 @@ __device__ __forceinline__ void st_final(const StackParams &p, uint32_t nexit, u
         if (v < V) {
             for (uint32_t q = 0; q < Q; q++) {
                 const uint64_t idx = rowi<G>(p, static_cast<uint32_t>(v), q) + j;
-                const uint64_t x = p.P[idx];
+                const uint64_t x = ldc(&p.P[idx]);
                 if (x) {
                     if (fm >> q & 1u) f |= x;
                     p.P[idx] = 0;
