@@ -78,7 +78,9 @@ typedef struct {
        plus ceil(V/8), w the state-word bytes (1, 2, 4 for <= 8, 16, 32 states);
        active = (level, vertex) pairs with a non-empty frontier word. */
     int64_t product_edges, scans, scanned_edges, alg_bytes, active;
-    double device_ms;        /* out: GPU time of the whole call (events) */
+    double device_ms;        /* out: GPU time of the whole call (events); with
+                                RPQ_KERNEL_TIMING on the persistent single-query
+                                path, the kernel's time (= expand_ms) */
     double expand_ms;        /* out, with RPQ_KERNEL_TIMING: summed expansion-kernel time */
     int32_t expand_launches; /* out, with RPQ_KERNEL_TIMING */
     int32_t batch;           /* out: sources evaluated together */

@@ -14,7 +14,6 @@ from __future__ import annotations
 
 import ctypes
 import os
-from dataclasses import dataclass, field
 from typing import Optional, Sequence
 
 import numpy as np
@@ -175,35 +174,47 @@ def bitmap_words(num_vertices: int) -> int:
     return int(lib.rpq_bitmap_words(num_vertices))
 
 
-@dataclass
+_SCALAR_FIELDS = frozenset(k for k, _ in rpq_stats._fields_ if k not in _LEVEL_FIELDS)
+_LEVEL_ARRAYS = {"level_counts": np.int64, "level_us": np.float64, "level_frontier": np.int64,
+                 "level_edges": np.int64, "level_select_us": np.float64}
+
+
 class Stats:
-    levels: int = 0
-    push_levels: int = 0
-    pull_levels: int = 0
-    visited_pairs: int = 0
-    product_edges: int = 0
-    scans: int = 0
-    scanned_edges: int = 0
-    alg_bytes: int = 0
-    active: int = 0
-    device_ms: float = 0.0
-    expand_ms: float = 0.0
-    expand_launches: int = 0
-    batch: int = 0
-    level_counts: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
-    level_us: np.ndarray = field(default_factory=lambda: np.zeros(0, np.float64))
-    level_frontier: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
-    level_edges: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
-    level_select_us: np.ndarray = field(default_factory=lambda: np.zeros(0, np.float64))
+    """Statistics of one call: the fields of rpq_stats as attributes (levels,
+    push_levels, pull_levels, visited_pairs, product_edges, scans,
+    scanned_edges, alg_bytes, active, device_ms, expand_ms, expand_launches,
+    batch), read from the C struct when accessed, and the per-level arrays
+    level_counts, level_us, level_frontier, level_edges, level_select_us
+    (empty unless the call asked for them with level_cap)."""
+
+    __slots__ = ("_s", "_lv", "_cache")
+
+    def __init__(self, s: Optional[rpq_stats] = None, lv: Optional[dict] = None):
+        self._s = s if s is not None else rpq_stats()
+        self._lv = lv
+        self._cache = {}
 
     @classmethod
     def from_c(cls, s: rpq_stats, lv: Optional[dict]):
-        out = cls(**{k: getattr(s, k) for k, _ in rpq_stats._fields_ if k not in _LEVEL_FIELDS})
-        if lv is not None:
-            n = max(s.levels, 0)
-            for k, a in lv.items():
-                setattr(out, k, a[:min(a.size, n)].copy())
-        return out
+        return cls(s, lv)
+
+    def __getattr__(self, k):
+        if k in _SCALAR_FIELDS:
+            return getattr(self._s, k)
+        if k in _LEVEL_ARRAYS:
+            c = self._cache
+            if k not in c:
+                if self._lv is None:
+                    c[k] = np.zeros(0, _LEVEL_ARRAYS[k])
+                else:
+                    a = self._lv[k]
+                    c[k] = a[:min(a.size, max(self._s.levels, 0))].copy()
+            return c[k]
+        raise AttributeError(k)
+
+    def __repr__(self):
+        return "Stats(%s)" % ", ".join("%s=%r" % (k, getattr(self._s, k)) for k, _ in rpq_stats._fields_
+                                       if k in _SCALAR_FIELDS)
 
 
 def _stats_struct(level_cap: int):
