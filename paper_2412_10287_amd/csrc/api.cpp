@@ -552,7 +552,10 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
     uint64_t *lp = reinterpret_cast<uint64_t *>(stage + 128);
     HIP_TRY(hipMemcpyAsync(status, p.st.status, 32, hipMemcpyDeviceToHost, s));
     if (counters) HIP_TRY(hipMemcpyAsync(cnt, p.st.cnt, 32, hipMemcpyDeviceToHost, s));
-    if (stats) HIP_TRY(hipMemcpyAsync(lp, p.st.lvl, 8 * LVL_STRIDE * LVL_SPEC, hipMemcpyDeviceToHost, s));
+    // without per-level outputs the persistent kernel's status words carry |P|
+    const bool persistent = !(flags & RPQ_HOST_LOOP) && grid_p > 0;
+    const bool need_lvl = stats && (stats->level_cap > 0 || !persistent);
+    if (need_lvl) HIP_TRY(hipMemcpyAsync(lp, p.st.lvl, 8 * LVL_STRIDE * LVL_SPEC, hipMemcpyDeviceToHost, s));
     if (!(flags & RPQ_OUT_DEVICE))
         HIP_TRY(hipMemcpyAsync(out, g->dev_out, 8 * g->nwords, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -575,11 +578,15 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
         stats->device_ms = ms;
         stats->expand_ms = timing ? expand_ms : 0.0;
         stats->expand_launches = timing ? launches : 0;
-        const uint32_t ncopy = std::min<uint32_t>(levels + 1, LVL_COUNT_CAP);
-        if (ncopy > LVL_SPEC)
-            HIP_TRY(hipMemcpy(lp + LVL_STRIDE * LVL_SPEC, p.st.lvl + LVL_STRIDE * LVL_SPEC,
-                              8 * LVL_STRIDE * static_cast<size_t>(ncopy - LVL_SPEC), hipMemcpyDeviceToHost));
-        stats->visited_pairs = stats_levels(stats, lp, ncopy, levels);
+        if (need_lvl) {
+            const uint32_t ncopy = std::min<uint32_t>(levels + 1, LVL_COUNT_CAP);
+            if (ncopy > LVL_SPEC)
+                HIP_TRY(hipMemcpy(lp + LVL_STRIDE * LVL_SPEC, p.st.lvl + LVL_STRIDE * LVL_SPEC,
+                                  8 * LVL_STRIDE * static_cast<size_t>(ncopy - LVL_SPEC), hipMemcpyDeviceToHost));
+            stats->visited_pairs = stats_levels(stats, lp, ncopy, levels);
+        } else {
+            stats->visited_pairs = static_cast<int64_t>(status[4]) | (static_cast<int64_t>(status[5]) << 32);
+        }
         if (counters) {
             const int64_t w = W;
             stats->product_edges = static_cast<int64_t>(cnt[0]);

@@ -630,7 +630,7 @@ __device__ __forceinline__ void solo_sync() {
 // direction switch chose pull).
 template <int W>
 __device__ __forceinline__ void solo_levels(const Params &p, uint32_t n, uint32_t *s_eb, uint32_t *s_beg,
-                                            uint32_t *s_mask, uint32_t &npush) {
+                                            uint32_t *s_mask, uint32_t &npush, uint64_t &tpairs) {
     uint32_t sel_done = 0;
     for (uint32_t run = 0; run < SOLO_MAX_RUN; run++) {
         const uint32_t nq = ld_acq(&p.st.rec[n % REC_RING].nq);
@@ -644,6 +644,7 @@ __device__ __forceinline__ void solo_levels(const Params &p, uint32_t n, uint32_
             break;
         }
         if (threadIdx.x == 0) record_level(p, n, 0, li);
+        tpairs += li.pairs;
         push_phase<W>(p, n, li, s_eb, s_beg, s_mask, 0, 1);
         solo_sync();
         npush++;
@@ -673,6 +674,7 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
     init_phase<W>(p);
     if (!grid_barrier(bar, bc)) return;
     uint32_t n = 0, npush = 0, npull = 0, solo_at = ~0u;
+    uint64_t tpairs = 0;  // |P|, summed over the levels (workgroup 0's count is complete)
     while (true) {
         const uint32_t nq = ld_acq(&p.st.rec[n % REC_RING].nq);
         if (nq == 0) break;
@@ -680,7 +682,7 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
         if (nq <= SOLO_MAX_QUEUE && n != solo_at) {
             // a run of small levels in workgroup 0; the rest wait here
             solo_at = n;
-            if (blockIdx.x == 0) solo_levels<W>(p, n, s_eb, s_beg, s_mask, npush);
+            if (blockIdx.x == 0) solo_levels<W>(p, n, s_eb, s_beg, s_mask, npush, tpairs);
             if (!grid_barrier(bar, bc)) return;
             n = ld_acq(&bar->solo_n);
             selected = ld_acq(&bar->solo_sel) != 0;
@@ -693,6 +695,7 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
         const LevelInfo li = level_info(p, n);
         const uint32_t mode = decide(p, li);
         if (blockIdx.x == 0 && threadIdx.x == 0) record_level(p, n, mode, li);
+        tpairs += li.pairs;
         if (mode == 0) push_phase<W>(p, n, li, s_eb, s_beg, s_mask, blockIdx.x, gridDim.x);
         else pull_phase<W>(p, n, s_eb, s_beg, s_mask, &s_hn);
         npush += mode == 0;
@@ -705,6 +708,8 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
         p.st.status[0] = n;
         p.st.status[1] = npush;
         p.st.status[2] = npull;
+        p.st.status[4] = static_cast<uint32_t>(tpairs);
+        p.st.status[5] = static_cast<uint32_t>(tpairs >> 32);
     }
 }
 

@@ -196,6 +196,10 @@ def test_repeat_is_stable(rpq):
             bm, st = gg.single_source(nh, int(s), level_cap=1024)
             assert np.array_equal(bm, first)
             assert np.array_equal(st.level_counts, st0.level_counts)
+        # without per-level outputs |P| comes from the kernel's own sum
+        bm, st = gg.single_source(nh, int(s))
+        assert np.array_equal(bm, first)
+        assert st.visited_pairs == int(st0.level_counts.sum()) and st.levels == st0.levels
 
 
 def test_single_destination(rpq):
