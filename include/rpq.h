@@ -143,9 +143,12 @@ rpq_status rpq_graph_info(const rpq_graph *g, const char *key, int64_t *value);
  *  "large_query_pairs", "large_query_slots"  while the moving average of
  *                the reached (state, vertex) pairs of recently finished
  *                served queries exceeds large_query_pairs (default 2^21),
- *                at most large_query_slots (default 8) run at once: the state
+ *                at most large_query_slots run in slots at once (the state
  *                arrays of many large queries thrash the caches, and a few
- *                of them already fill the GPU.
+ *                of them already fill the GPU); with large_query_slots 0
+ *                (the default) such periods run one request at a time with
+ *                the single-query kernel once the slots have drained (the
+ *                most efficient path per edge for large queries).
  * Errors: RPQ_ENOTFOUND for an unknown key, RPQ_EINVAL for a bad value.
  */
 rpq_status rpq_set_option(rpq_graph *g, const char *key, int64_t value);

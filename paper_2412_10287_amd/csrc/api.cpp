@@ -417,8 +417,8 @@ rpq_status rpq_set_option(rpq_graph *g, const char *key, int64_t value) {
         if (value < 0) return fail(RPQ_EINVAL, "rpq_set_option: large_query_pairs < 0");
         g->large_pairs = value;
     } else if (!strcmp(key, "large_query_slots")) {
-        if (value < 1 || value > MAX_SLOTS)
-            return fail(RPQ_EINVAL, "rpq_set_option: large_query_slots outside [1, %d]", MAX_SLOTS);
+        if (value < 0 || value > MAX_SLOTS)
+            return fail(RPQ_EINVAL, "rpq_set_option: large_query_slots outside [0, %d]", MAX_SLOTS);
         g->large_slots = static_cast<int32_t>(value);
     } else if (!strcmp(key, "serve_stack_min")) {
         if (value < 0 || value > MAX_BATCH)

@@ -69,7 +69,7 @@ struct rpq_graph {
     int64_t mem_budget = 0;  // 0 = a quarter of the free device memory at first use
     int32_t max_slots = 128;
     int64_t large_pairs = 1 << 21;  // served path: queries above this many reached pairs count as large
-    int32_t large_slots = 8;        // concurrent served queries while recent queries are large
+    int32_t large_slots = 0;        // concurrent served queries while recent queries are large (0: one at a time, single-query kernel)
     int32_t serve_stack_min = 32;   // waiting served requests of one NFA that run as one stacked group (0 = never)
     int32_t grid_override = 0;
     int32_t plain_grid = 0;  // persistent single-query launch workgroups (0 = one per CU)

@@ -422,6 +422,64 @@ static rpq_status run_group(rpq_graph *g, ServeState *ss, std::vector<Request> &
     return RPQ_OK;
 }
 
+// A request run alone by the single-query persistent kernel (while recent
+// queries are large: for them it is the most efficient path per edge), its
+// answer written straight into a result-pool entry or, when none is free,
+// into host memory. Called by the worker thread without ss->mu held.
+static void run_one(rpq_graph *g, ServeState *ss, Request &r) {
+    const size_t nw = static_cast<size_t>(g->nwords);
+    uint32_t entry = ~0u;
+    {
+        std::lock_guard<std::mutex> lk(ss->mu);
+        if (!ss->free_entries.empty()) {
+            entry = ss->free_entries.back();
+            ss->free_entries.pop_back();
+        }
+    }
+    std::vector<uint64_t> spill;
+    rpq_stats st{};
+    rpq_status rs;
+    if (entry != ~0u) {
+        rs = rpq_single_source(g, r.nfa.get(), r.source, ss->mp.out + static_cast<size_t>(entry) * nw, RPQ_OUT_DEVICE,
+                               &st);
+    } else {
+        spill.resize(nw);
+        rs = rpq_single_source(g, r.nfa.get(), r.source, spill.data(), 0u, &st);
+    }
+    const std::string err = rs == RPQ_OK ? std::string() : std::string(rpq_last_error());
+    const Clock::time_point now = Clock::now();
+    std::lock_guard<std::mutex> lk(ss->mu);
+    auto it = ss->tickets.find(r.id);
+    if (it != ss->tickets.end()) {
+        Ticket &t = it->second;
+        t.stats = rpq_stats{};
+        if (rs == RPQ_OK) {
+            if (entry != ~0u) t.entry = entry;
+            else t.spill.swap(spill);
+            t.stats.levels = st.levels;
+            t.stats.push_levels = st.push_levels;
+            t.stats.pull_levels = st.pull_levels;
+            t.stats.visited_pairs = st.visited_pairs;
+            t.stats.batch = 1;
+            t.stats.device_ms = std::chrono::duration<double, std::milli>(now - r.submitted).count();
+        } else {
+            t.error = err;
+            if (entry != ~0u) ss->free_entries.push_back(entry);
+        }
+        t.status = rs;
+        t.state = 2;
+    } else if (entry != ~0u) {
+        ss->free_entries.push_back(entry);
+    }
+    if (rs == RPQ_OK) {
+        ss->size_avg = ss->size_n == 0 ? static_cast<double>(st.visited_pairs)
+                                       : 0.8 * ss->size_avg + 0.2 * static_cast<double>(st.visited_pairs);
+        ss->size_n++;
+    }
+    ss->running--;
+    ss->cv_done.notify_all();
+}
+
 static void fail_all(ServeState *ss, rpq_status st, const std::string &msg) {
     std::lock_guard<std::mutex> lk(ss->mu);
     ss->failed = true;
@@ -447,10 +505,11 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
         fail_all(ss, st, rpq_last_error());
         return;
     }
-    std::vector<Request> admit, grp;
+    std::vector<Request> admit, grp, one;
     while (true) {
         admit.clear();
         grp.clear();
+        one.clear();
         {
             std::unique_lock<std::mutex> lk(ss->mu);
             // a stacked group: at least serve_stack_min waiting requests of one NFA
@@ -463,19 +522,29 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
                 return 0;
             };
             // concurrency: every slot, or large_query_slots while recent
-            // queries are large
+            // queries are large; with large_query_slots 0, large-query
+            // periods run one request at a time through the single-query
+            // kernel once the slots have drained
+            const bool large = ss->size_n && ss->size_avg > static_cast<double>(g->large_pairs);
             size_t cap = ss->slots;
-            if (ss->size_n && ss->size_avg > static_cast<double>(g->large_pairs))
-                cap = std::min<size_t>(cap, static_cast<size_t>(g->large_slots));
+            if (large) cap = std::min<size_t>(cap, static_cast<size_t>(g->large_slots));
             auto active = [&] { return static_cast<size_t>(ss->slots) - ss->free_slots.size(); };
-            // work: a level to run or a request and a free slot
+            const bool single = large && g->large_slots == 0;
+            // work: a level to run, a request and a free slot, a group, or a
+            // request to run alone
             ss->cv_work.wait(lk, [&] {
                 return ss->stop || ss->cur_len > 0 ||
-                       (!ss->pending.empty() && !ss->free_slots.empty() && active() < cap) || group_serial() != 0;
+                       (!ss->pending.empty() && !ss->free_slots.empty() && active() < cap) || group_serial() != 0 ||
+                       (single && !ss->pending.empty() && active() == 0);
             });
             if (ss->stop && ss->pending.empty() && ss->cur_len == 0) break;
             const uint64_t gs = ss->stop ? 0 : group_serial();
-            if (gs) {
+            if (!gs && single && ss->cur_len == 0 && active() == 0 && !ss->pending.empty()) {
+                one.push_back(std::move(ss->pending.front()));
+                ss->pending.pop_front();
+                auto t = ss->tickets.find(one.back().id);
+                if (t != ss->tickets.end()) t->second.state = 1;
+            } else if (gs) {
                 const size_t maxb = static_cast<size_t>(std::min<int32_t>(g->max_batch, MAX_BATCH));
                 for (auto it = ss->pending.begin(); it != ss->pending.end() && grp.size() < maxb;) {
                     if (it->serial != gs) {
@@ -496,6 +565,10 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
                     if (it != ss->tickets.end()) it->second.state = 1;
                 }
             }
+        }
+        if (!one.empty()) {
+            run_one(g, ss, one[0]);
+            continue;
         }
         if (!grp.empty()) {
             if (run_group(g, ss, grp) != RPQ_OK) {

@@ -202,3 +202,23 @@ def test_same_nfa_requests_run_as_stacked_groups(rpq):
         grouped += st.batch > 2
     print("answers from stacked groups:", grouped)
     assert grouped > 0
+
+
+def test_large_queries_run_alone(rpq):
+    # threshold 0: after the first answer every query counts as large, and
+    # with large_query_slots 0 the rest run one at a time with the
+    # single-query kernel; answers and level counts are unchanged
+    w = C.rmat_workload(scale=13, edge_factor=16, num_labels=8, n_per_template=4)
+    og = oracle.Graph(w.graph)
+    gg = rpq.Graph(w.graph)
+    gg.set_option("large_query_pairs", 0)
+    gg.set_option("large_query_slots", 0)
+    nh = [rpq.NFA(n) for n in w.nfas]
+    for rnd in range(2):
+        res = _poll_all(gg, _submit_all(gg, nh, w.sources))
+        for (bm, st), n, s, text in zip(res, w.nfas, w.sources, w.queries):
+            r = og.ssr(n, int(s))
+            assert np.array_equal(bm, r.bitmap), (rnd, text)
+            assert st.levels == r.levels and st.visited_pairs == int(r.level_counts.sum()), (rnd, text)
+        if rnd == 1:
+            assert all(st.batch == 1 for _, st in res)
