@@ -384,14 +384,7 @@ __device__ __forceinline__ void unit_gather(const StackParams &p, uint32_t n, co
         }
 #pragma unroll
         for (int q2 = 0; q2 < QM; q2++)
-            if (y[q2]) {
-                // bits already visited, or already in the target's candidate
-                // row (another edge of this level got there first), need no
-                // atomic: both rows are loaded together
-                const uint64_t idx = rowi<G>(p, w, q2) + j;
-                const uint64_t pv = ldc(&p.P[idx]), have = ldc(&Mn[idx]);
-                U.c[q2] = y[q2] & ~pv & ~have;
-            }
+            if (y[q2]) U.c[q2] = y[q2] & ~ldc(&p.P[rowi<G>(p, w, q2) + j]);
     } else {
         uint32_t SS = S;
         while (SS) {
@@ -405,7 +398,7 @@ __device__ __forceinline__ void unit_gather(const StackParams &p, uint32_t n, co
                 const uint32_t q2 = __ffs(tq) - 1;
                 tq &= tq - 1;
                 const uint64_t idx = rowi<G>(p, w, q2) + j;
-                const uint64_t c = x & ~ldc(&p.P[idx]) & ~ldc(&Mn[idx]);
+                const uint64_t c = x & ~ldc(&p.P[idx]);
                 if (c) {
                     atomicOr(reinterpret_cast<unsigned long long *>(Mn + idx), static_cast<unsigned long long>(c));
                     U.tb |= 1u << q2;
