@@ -142,7 +142,7 @@ def bench_batched(args, w):
         g.set_option("stacked_alpha", args.stacked_alpha)
     elif not args.no_tune and args.workload == "kg":
         from paper_2412_10287_amd import autotune
-        tuning = autotune.tune(g, rpq.TUNE_STACKED, [nh], srcs, cache=None)
+        tuning = autotune.tune(g, rpq.TUNE_STACKED, [nh], srcs, cache=args.tune_cache)
         log("autotune (stacked, one batch): %s" % tuning)
     words = g.words
     out = rpq.DeviceBuffer(8 * B * words)
@@ -368,6 +368,9 @@ def main():
     ap.add_argument("--stacked-alpha", type=int, default=None, help="push->pull threshold of the stacked path")
     ap.add_argument("--levels-only", action="store_true", help="batched workloads: per-level profiles only")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file for the autotuner's choices (reused when present, e.g. so that "
+                         "profiler passes run the settings of an earlier timed run)")
     ap.add_argument("--skip-plain", action="store_true", help="batched workloads: time the stacked path only")
     ap.add_argument("--serve-queries", type=int, default=256, help="serve workload: queries in the stream")
     ap.add_argument("--max-slots", type=int, default=0, help="served path: concurrent queries (0 = library default)")
@@ -412,7 +415,7 @@ def main():
         # settings measured on a sample of the queries, before the timed region
         from paper_2412_10287_amd import autotune
         k = min(16, len(nfas))
-        tuning = autotune.tune(g, rpq.TUNE_PLAIN, nfas[:k], [int(s) for s in w.sources[:k]], cache=None)
+        tuning = autotune.tune(g, rpq.TUNE_PLAIN, nfas[:k], [int(s) for s in w.sources[:k]], cache=args.tune_cache)
         log("autotune (plain, %d sample queries): %s" % (k, tuning))
 
     # algorithmic work per query (deterministic; the GPU counters match the oracle's)
