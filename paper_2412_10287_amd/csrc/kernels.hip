@@ -18,7 +18,8 @@
 //          drops the item's states already in P[w] (a load) and ORs the rest
 //          into the next level's word of w with one atomic; the first writer
 //          of that word appends w to the next candidate queue (wave ballot +
-//          popc, one reservation per wave for four edges per lane).
+//          popc, one reservation per workgroup and step of four edges per
+//          lane).
 //  pull    used instead of push on dense levels: every vertex w with states
 //          still unvisited scans its reverse neighbours under the symbols that
 //          can reach those states and stops as soon as all are found.
@@ -122,8 +123,8 @@ __device__ __forceinline__ void clear_level_words(const Params &p, uint32_t k, u
 // S = M[w] & ~P[w] (added to P); for each used symbol u, succ_u(S) is the
 // column w of (N^u)^T M, and when it is non-empty and w has u-neighbours,
 // (w, u) becomes an item carrying the neighbour range and succ_u(S). Items are
-// reserved per wave with one 64-bit atomic that counts items (high half) and
-// edges (low half) together, so item order and edge numbering agree.
+// reserved per workgroup with one 64-bit atomic that counts items (high half)
+// and edges (low half) together, so item order and edge numbering agree.
 template <int W>
 __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32_t bid, uint32_t nblk) {
     const GraphView &g = p.g;
@@ -302,7 +303,7 @@ __device__ __forceinline__ uint32_t decide(const Params &p, const LevelInfo &li)
 
 // Edges [ubase, uend) of the items staged in LDS (cnt of them), four per
 // thread and step: all four loads of col, then of P, then the atomics, then
-// one queue reservation per wave. Per edge (v, w) with successor set S' the
+// one queue reservation per workgroup. Per edge (v, w) with successor set S' the
 // states of S' not yet in P[w] (the complement mask) are ORed into the next
 // level's word of w; the first writer appends w to the candidate queue.
 template <int W>

@@ -50,9 +50,9 @@ hipError_t multi_select(const MultiParams &p, uint32_t parity, uint32_t lo, uint
 hipError_t multi_push(const MultiParams &p, uint32_t parity, uint32_t chunk_id, int grid, hipStream_t s);
 // bytes of the control block for `slots` slots, and the offset of pairs[] in it
 // Control block layout (bytes). Each field that kernels update heavily sits
-// on a cache line of its own: the next queue's length (one atomic per wave
-// and step of every push), the per-slot frontier flags (stored by appending
-// lanes) and the per-slot pair counters (atomics at select time).
+// on a cache line of its own: the next queue's length (one atomic per
+// workgroup and step of every push), the per-slot frontier flags (stored by
+// appending lanes) and the per-slot pair counters (atomics at select time).
 constexpr size_t CTL_LINE = 128;
 constexpr size_t CTL_QLEN = 0;              // uint32 qlen[2], one line each
 constexpr size_t CTL_STATUS = 2 * CTL_LINE; // uint32 invariant violations
