@@ -123,6 +123,26 @@ def test_wide_state_words(rpq):
                 assert np.array_equal(st.level_counts, want.level_counts), (leaves, name)
 
 
+def test_long_chain_runs_of_small_levels(rpq):
+    # a path of 5000 vertices: 5000 levels of one vertex each, all small, so
+    # the levels run in workgroup 0 in runs of at most 2048 (three runs);
+    # a second label hangs a star off the middle so one level is large
+    n = 5000
+    src = list(range(n - 1)) + [2500] * 3000
+    dst = list(range(1, n)) + [n + i for i in range(3000)]
+    lab = [0] * (n - 1) + [1] * 3000
+    g = G.from_triples(n + 3000, 2, np.array(src), np.array(dst), np.array(lab))
+    gg = rpq.Graph(g)
+    og = oracle.Graph(g)
+    for text in ("0*", "(0|1)*", "0* 1"):
+        nfa = R.compile_regex(text, 2)
+        want = og.ssr(nfa, 0)
+        for name in ("auto", "push", "pull"):
+            bm, st = _run(rpq, gg, rpq.NFA(nfa), 0, MODES[name], level_cap=8192)
+            assert np.array_equal(bm, want.bitmap), (text, name)
+            assert np.array_equal(st.level_counts, want.level_counts), (text, name)
+
+
 def test_grid_closed_forms_gpu(rpq):
     side = 48
     g = G.grid(side, 0.0, 0)

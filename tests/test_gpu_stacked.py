@@ -144,6 +144,22 @@ def test_grid_batch(rpq):
             assert np.array_equal(bms[i], want)
 
 
+def test_long_chain_batch(rpq):
+    # 3000 levels of a path with 64 sources along it: runs of small levels
+    # in workgroup 0 (at most 2048 per run) and the grid-wide levels between
+    n = 3000
+    g = G.from_triples(n, 1, np.arange(n - 1), np.arange(1, n), np.zeros(n - 1, dtype=np.int64))
+    gg = rpq.Graph(g)
+    og = oracle.Graph(g)
+    srcs = list(range(0, 64 * 7, 7))
+    nfa = R.compile_regex("0*", 1)
+    for name, fl in STACK_MODES.items():
+        bms, st = gg.multi_source(rpq.NFA(nfa), srcs, flags=fl, level_cap=4096)
+        assert st.levels == n  # from vertex 0 along the whole path
+        for i, s in enumerate(srcs):
+            assert np.array_equal(bms[i], og.ssr(nfa, s).bitmap), (name, s)
+
+
 def test_repeat_and_device_output(rpq):
     g = G.rmat(11, 8, 4, 1.1, 2)
     gg = rpq.Graph(g)
