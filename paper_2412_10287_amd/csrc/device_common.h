@@ -259,6 +259,68 @@ __device__ __forceinline__ bool block_append(bool flag, int32_t value, int32_t *
     return true;
 }
 
+// block_reserve for a cursor that one workgroup alone advances: `running`
+// (the same in every thread) takes the place of the counter in memory, so no
+// atomic is made. base receives the wave's first position.
+template <typename T>
+__device__ __forceinline__ bool block_reserve_local(T wtot, bool more, T &running, T &base) {
+    __shared__ T s_w[NWAVE];
+    __shared__ uint32_t s_more[NWAVE];
+    const uint32_t wave = threadIdx.x >> 6;
+    const bool wmore = __ballot(more) != 0;
+    if (lane_id() == 0) {
+        s_w[wave] = wtot;
+        s_more[wave] = wmore ? 1u : 0u;
+    }
+    __syncthreads();
+    T off = 0, tot = 0;
+    uint32_t any = 0;
+#pragma unroll
+    for (int k = 0; k < NWAVE; k++) {
+        const T x = s_w[k];
+        if (static_cast<uint32_t>(k) < wave) off += x;
+        tot += x;
+        any |= s_more[k];
+    }
+    __syncthreads();  // s_w is read everywhere before the next call writes it
+    base = running + off;
+    running += tot;
+    return any != 0;
+}
+
+// block_append4 for a queue that one workgroup alone fills, kept twice: in
+// `lq` (positions below lcap; the rest are dropped) and in `gq` (positions
+// below gcap; returns false if this lane's slots go beyond). `running` is the
+// queue length, the same in every thread.
+__device__ __forceinline__ bool block_append4_local(bool f0, int32_t v0, bool f1, int32_t v1, bool f2, int32_t v2,
+                                                    bool f3, int32_t v3, int32_t *lq, uint32_t lcap, int32_t *gq,
+                                                    uint32_t gcap, uint32_t &running) {
+    const uint64_t m0 = __ballot(f0), m1 = __ballot(f1), m2 = __ballot(f2), m3 = __ballot(f3);
+    const uint32_t c0 = static_cast<uint32_t>(__popcll(m0)), c1 = static_cast<uint32_t>(__popcll(m1));
+    const uint32_t c2 = static_cast<uint32_t>(__popcll(m2)), c3 = static_cast<uint32_t>(__popcll(m3));
+    const uint32_t tot = c0 + c1 + c2 + c3;
+    uint32_t base = 0;
+    block_reserve_local<uint32_t>(tot, false, running, base);
+    if (tot == 0) return true;
+    const uint64_t below = (1ull << lane_id()) - 1ull;
+    bool ok = true;
+    const bool f[4] = {f0, f1, f2, f3};
+    const int32_t v[4] = {v0, v1, v2, v3};
+    const uint64_t m[4] = {m0, m1, m2, m3};
+    uint32_t pre = base;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        if (f[k]) {
+            const uint32_t pos = pre + static_cast<uint32_t>(__popcll(m[k] & below));
+            if (pos < lcap) lq[pos] = v[k];
+            if (pos < gcap) gq[pos] = v[k];
+            else ok = false;
+        }
+        pre += static_cast<uint32_t>(__popcll(m[k]));
+    }
+    return ok;
+}
+
 // Totals over the workgroup of K per-wave values (already reduced over the
 // wave: the same in all its lanes): sums, or ORs for the k with bit k of
 // or_mask set. Thread k < K receives total k, every other thread 0.

@@ -74,6 +74,20 @@ __device__ __forceinline__ void qv_setup(const QueryView &qv) {
 // range); the access is skipped and the host reports the query as failed.
 __device__ __forceinline__ void flag_violation(const Params &p) { atomicAdd(&p.st.status[3], 1u); }
 
+// Runs of small levels (solo_levels) execute in workgroup 0 alone; their
+// queues, reservation cursors and level totals live in LDS (SoloLds) rather
+// than in the level records, so such a level makes no global atomic and
+// reads nothing global but state words and the graph.
+constexpr uint32_t SOLO_MAX_QUEUE = 1024;  // candidate queue entries of a small level
+constexpr uint32_t SOLO_MAX_EDGES = 8192;  // push edges of a small level
+constexpr uint32_t SOLO_MAX_RUN = 2048;    // levels per run (the waiting workgroups' barrier times out after 5 s)
+
+struct SoloLds {
+    uint64_t sel, pairs;           // the level's reservations ((items << 32) | edges) and pairs
+    uint32_t nfront, su, prev_mode;
+    int32_t q[2][SOLO_MAX_QUEUE];  // candidate queues of levels n and n + 1, by parity
+};
+
 // ---------------------------------------------------------------- phases
 template <int W>
 __device__ __forceinline__ void init_phase(const Params &p) {
@@ -95,9 +109,9 @@ __device__ __forceinline__ void init_phase(const Params &p) {
 // Zeroes the state words that level k's queue entries point to in M[k & 1]
 // (its candidate and frontier words), eight entries per thread and step with
 // all loads before the stores (one workgroup alone may clear a long queue).
-template <int W>
+template <int W, bool LQ = false>
 __device__ __forceinline__ void clear_level_words(const Params &p, uint32_t k, uint32_t nk, uint32_t bid,
-                                                  uint32_t nblk) {
+                                                  uint32_t nblk, const int32_t *lq = nullptr) {
     const uint32_t V = static_cast<uint32_t>(p.g.V);
     if (nk > V) nk = V;
     uint32_t *M = p.st.M[k & 1];
@@ -108,7 +122,8 @@ __device__ __forceinline__ void clear_level_words(const Params &p, uint32_t k, u
 #pragma unroll
         for (int j = 0; j < 8; j++) {
             const uint32_t i = i0 + j * stride;
-            vv[j] = i < nk ? static_cast<uint32_t>(ldc(&q[i])) : 0u;
+            // LQ: the queue's copy in LDS (a solo level's)
+            vv[j] = i < nk ? static_cast<uint32_t>(LQ ? lq[i] : ldc(&q[i])) : 0u;
         }
 #pragma unroll
         for (int j = 0; j < 8; j++) {
@@ -125,15 +140,24 @@ __device__ __forceinline__ void clear_level_words(const Params &p, uint32_t k, u
 // (w, u) becomes an item carrying the neighbour range and succ_u(S). Items are
 // reserved per workgroup with one 64-bit atomic that counts items (high half)
 // and edges (low half) together, so item order and edge numbering agree.
-template <int W>
-__device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32_t bid, uint32_t nblk) {
+//
+// SOLO: workgroup 0 alone runs the level (bid 0, nblk 1). The queue length
+// comes in solo_nq and, when solo_lq, the queue from so->q; reservations
+// advance a cursor in registers; the items are also kept in s_eb, s_beg and
+// s_mask (the first TILE + 1 of them), and the level's totals go to `so` as
+// well as, with plain stores, to its level record.
+template <int W, bool SOLO = false>
+__device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32_t bid, uint32_t nblk,
+                                             SoloLds *so = nullptr, uint32_t solo_nq = 0, bool solo_lq = false,
+                                             uint32_t *s_eb = nullptr, uint32_t *s_beg = nullptr,
+                                             uint32_t *s_mask = nullptr) {
     const GraphView &g = p.g;
     const QueryView &qv = s_qv;
     const QHeader &h = *qv.h;
     LevelRec *rec = p.st.rec;
     LevelRec &R = rec[n % REC_RING];
     const uint32_t V = static_cast<uint32_t>(g.V);
-    uint32_t nq = ld_acq(&R.nq);
+    uint32_t nq = SOLO ? solo_nq : ld_acq(&R.nq);
     if (nq > V) {
         if (bid == 0 && threadIdx.x == 0) flag_violation(p);
         nq = V;
@@ -144,10 +168,12 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
     }
     // frontier words of level n-1 live in the buffer level n writes: after a
     // pull level they are cleared here (after a push level, that level's
-    // push phase has cleared them already)
-    if (n >= 1 && ld_acq(&rec[(n - 1) % REC_RING].mode) != 0)
-        clear_level_words<W>(p, n - 1, ld_acq(&rec[(n - 1) % REC_RING].nq), bid, nblk);
+    // push phase has cleared them already). A solo level after another one
+    // follows a push level.
+    const uint32_t prev_mode = (n >= 1 && !(SOLO && solo_lq)) ? ld_acq(&rec[(n - 1) % REC_RING].mode) : 0u;
+    if (prev_mode != 0) clear_level_words<W>(p, n - 1, ld_acq(&rec[(n - 1) % REC_RING].nq), bid, nblk);
     const int32_t *qc = p.st.q[n & 1];
+    uint64_t run_sel = 0;  // SOLO: the reservation cursor
     uint32_t *Mc = p.st.M[n & 1];
     uint32_t *P = p.st.P;
     const uint32_t nsym = h.nsym;
@@ -158,7 +184,7 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
         const uint32_t i = bbase + threadIdx.x;
         uint32_t v = 0, S = 0;
         if (i < nq) {
-            v = static_cast<uint32_t>(ldc(&qc[i]));
+            v = static_cast<uint32_t>(SOLO && solo_lq ? so->q[n & 1][i] : ldc(&qc[i]));
             if (v < V) {
                 // the complement mask of Alg. 1, then P = P + M
                 const uint32_t c = ld_state<W>(Mc, v);
@@ -212,7 +238,9 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
             uint64_t wtot;
             const uint64_t ex = wave_excl_scan((static_cast<uint64_t>(cnt) << 32) | tot, wtot);
             uint64_t wbase;
-            const bool bmore = block_reserve<uint64_t>(wtot, more, &R.sel, wbase);
+            bool bmore;
+            if constexpr (SOLO) bmore = block_reserve_local<uint64_t>(wtot, more, run_sel, wbase);
+            else bmore = block_reserve<uint64_t>(wtot, more, &R.sel, wbase);
             if (cnt) {
                 const uint64_t mine = wbase + ex;
                 uint32_t idx = static_cast<uint32_t>(mine >> 32);
@@ -226,6 +254,11 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
                         p.st.it_mask[idx] = sp[j];
                     } else {
                         flag_violation(p);
+                    }
+                    if (SOLO && idx <= static_cast<uint32_t>(TILE)) {
+                        s_eb[idx] = eb;
+                        s_beg[idx] = beg[j];
+                        s_mask[idx] = sp[j];
                     }
                     // this item owns the tiles whose first edge falls inside it
                     const uint32_t k1 = (eb + len[j] - 1) / TILE;
@@ -245,7 +278,25 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
     {
         const uint64_t v[3] = {wave_sum(pairs), nf, wave_or(su)};
         const uint64_t t = block_reduce<3>(v, 4u);
-        if (t) {
+        if constexpr (SOLO) {
+            // the only workgroup: plain stores, into the record for the grid
+            // (should it take the level over) and into LDS for workgroup 0
+            if (threadIdx.x == 0) {
+                so->pairs = t;
+                so->sel = run_sel;
+                so->prev_mode = prev_mode;
+                R.pairs = t;
+                R.sel = run_sel;
+            }
+            if (threadIdx.x == 1) {
+                so->nfront = static_cast<uint32_t>(t);
+                R.nfront = static_cast<uint32_t>(t);
+            }
+            if (threadIdx.x == 2) {
+                so->su = static_cast<uint32_t>(t);
+                R.su = static_cast<uint32_t>(t);
+            }
+        } else if (t) {
             if (threadIdx.x == 0) atomicAdd(reinterpret_cast<unsigned long long *>(&R.pairs), (unsigned long long)t);
             if (threadIdx.x == 1) atomicAdd(&R.nfront, static_cast<uint32_t>(t));
             if (threadIdx.x == 2) atomicOr(&R.su, static_cast<uint32_t>(t));
@@ -306,9 +357,12 @@ __device__ __forceinline__ uint32_t decide(const Params &p, const LevelInfo &li)
 // one queue reservation per workgroup. Per edge (v, w) with successor set S' the
 // states of S' not yet in P[w] (the complement mask) are ORed into the next
 // level's word of w; the first writer appends w to the candidate queue.
-template <int W>
-__device__ __forceinline__ void push_range(const Params &p, uint32_t n, const uint32_t *s_eb, const uint32_t *s_beg,
-                                           const uint32_t *s_mask, uint32_t cnt, uint32_t ubase, uint32_t uend) {
+// SOLO (workgroup 0 alone): the queue length is a cursor in registers, the
+// entries also go to lq (the first SOLO_MAX_QUEUE), and the length is returned.
+template <int W, bool SOLO = false>
+__device__ __forceinline__ uint32_t push_range(const Params &p, uint32_t n, const uint32_t *s_eb,
+                                               const uint32_t *s_beg, const uint32_t *s_mask, uint32_t cnt,
+                                               uint32_t ubase, uint32_t uend, int32_t *lq = nullptr) {
     const uint32_t V = static_cast<uint32_t>(p.g.V);
     const uint32_t *P = p.st.P;
     uint32_t *Mn = p.st.M[(n + 1) & 1];
@@ -317,27 +371,35 @@ __device__ __forceinline__ void push_range(const Params &p, uint32_t n, const ui
     const uint32_t *col = p.g.col;
     const uint32_t tid = threadIdx.x;
     static_assert(TILE == 4 * BLOCK, "four edges per thread and step");
+    uint32_t run_q = 0;
+    // the halving steps of the item search depend on cnt alone (the same in
+    // every lane): a uniform loop of ceil(log2(cnt)) steps, no step for one item
+    const uint32_t ucnt = __builtin_amdgcn_readfirstlane(cnt);
     for (uint32_t ub = ubase; ub < uend; ub += TILE) {
-        uint32_t w[4], sp[4];
+        uint32_t w[4], sp[4], lo[4], tt[4];
+        // item holding edge t: the last staged item with s_eb <= t (s_eb[0]
+        // <= ubase); lanes past uend search for uend - 1 and drop the result
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint32_t t = ub + k * BLOCK + tid;
+            tt[k] = t < uend ? t : uend - 1;
+            lo[k] = 0;
+        }
+        for (uint32_t len = ucnt; len > 1;) {
+            const uint32_t half = len >> 1;
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                if (s_eb[lo[k] + half] <= tt[k]) lo[k] += half;
+            len -= half;
+        }
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const uint32_t t = ub + k * BLOCK + tid;
             w[k] = V;
             sp[k] = 0;
-            // item holding edge t: the last staged item with s_eb <= t
-            // (fixed-step search: cnt <= TILE + 1 < 2^12)
-            uint32_t lo = 0, len = cnt;
-#pragma unroll
-            for (int step = 0; step < 12; step++) {
-                const uint32_t half = len >> 1;
-                if (half && t < uend) {
-                    if (s_eb[lo + half] <= t) lo += half;
-                    len -= half;
-                }
-            }
             if (t < uend) {
-                const uint32_t pos = s_beg[lo] + (t - s_eb[lo]);
-                sp[k] = s_mask[lo];
+                const uint32_t pos = s_beg[lo[k]] + (t - s_eb[lo[k]]);
+                sp[k] = s_mask[lo[k]];
                 if (pos < p.g.ncol) w[k] = col[pos];
                 else flag_violation(p);
                 if (w[k] >= V && pos < p.g.ncol) {
@@ -352,10 +414,17 @@ __device__ __forceinline__ void push_range(const Params &p, uint32_t n, const ui
         bool first[4];
 #pragma unroll
         for (int k = 0; k < 4; k++) first[k] = cand[k] ? or_state<W>(Mn, w[k], cand[k]) == 0 : false;
-        if (!block_append4(first[0], static_cast<int32_t>(w[0]), first[1], static_cast<int32_t>(w[1]), first[2],
-                           static_cast<int32_t>(w[2]), first[3], static_cast<int32_t>(w[3]), qn, qlen, V))
-            flag_violation(p);
+        bool ok;
+        if constexpr (SOLO)
+            ok = block_append4_local(first[0], static_cast<int32_t>(w[0]), first[1], static_cast<int32_t>(w[1]),
+                                     first[2], static_cast<int32_t>(w[2]), first[3], static_cast<int32_t>(w[3]), lq,
+                                     SOLO_MAX_QUEUE, qn, V, run_q);
+        else
+            ok = block_append4(first[0], static_cast<int32_t>(w[0]), first[1], static_cast<int32_t>(w[1]), first[2],
+                               static_cast<int32_t>(w[2]), first[3], static_cast<int32_t>(w[3]), qn, qlen, V);
+        if (!ok) flag_violation(p);
     }
+    return run_q;
 }
 
 // Items -> edges, spread evenly over the grid. Few items: every workgroup
@@ -616,41 +685,56 @@ __device__ __forceinline__ void final_phase(const Params &p, uint32_t nlev) {
 // single grid barrier. The phases and every array they touch are the same as
 // in the grid-wide loop; all waves of workgroup 0 share one compute unit, so
 // a workgroup barrier orders their memory accesses.
-constexpr uint32_t SOLO_MAX_QUEUE = 1024;  // candidate queue entries of a small level
-constexpr uint32_t SOLO_MAX_EDGES = 8192;  // push edges of a small level
-constexpr uint32_t SOLO_MAX_RUN = 2048;    // levels per run (the waiting workgroups' barrier times out after 5 s)
-
 __device__ __forceinline__ void solo_sync() {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 }
 
-// Runs levels n, n+1, ... in workgroup 0 while they are small. Leaves in
-// bar->solo_n the first level not finished, and in bar->solo_sel whether its
-// select phase is already done (it was too large to push here, or the
-// direction switch chose pull).
+// Runs levels n, n+1, ... (level n's queue holds nq entries) in workgroup 0
+// while they are small. Leaves in bar->solo_n the first level not finished,
+// and in bar->solo_sel whether its select phase is already done (it was too
+// large to push here, or the direction switch chose pull). The level records,
+// the global queues and the item arrays are kept up to date as well, for the
+// grid to take over from.
 template <int W>
-__device__ __forceinline__ void solo_levels(const Params &p, uint32_t n, uint32_t *s_eb, uint32_t *s_beg,
-                                            uint32_t *s_mask, uint32_t &npush, uint64_t &tpairs) {
+__device__ __forceinline__ void solo_levels(const Params &p, uint32_t n, uint32_t nq, uint32_t *s_eb,
+                                            uint32_t *s_beg, uint32_t *s_mask, uint32_t &npush, uint64_t &tpairs) {
+    __shared__ SoloLds so;
     uint32_t sel_done = 0;
+    bool lq = false;  // level n's queue is in so.q (every level of the run but the first)
     for (uint32_t run = 0; run < SOLO_MAX_RUN; run++) {
-        const uint32_t nq = ld_acq(&p.st.rec[n % REC_RING].nq);
         if (nq == 0 || nq > SOLO_MAX_QUEUE) break;
-        select_phase<W>(p, n, 0, 1);
+        select_phase<W, true>(p, n, 0, 1, &so, nq, lq, s_eb, s_beg, s_mask);
+        // the stores to P and M are complete before the push loads P; the
+        // items and totals are in LDS
         solo_sync();
-        const LevelInfo li = level_info(p, n);
+        LevelInfo li;
+        li.sel = so.sel;
+        li.pairs = so.pairs;
+        li.nfront = so.nfront;
+        li.nq = nq;
+        li.prev_mode = so.prev_mode;
         const uint32_t mode = decide(p, li);
-        if (mode != 0 || (li.sel & 0xffffffffull) > SOLO_MAX_EDGES) {
+        const uint32_t T = static_cast<uint32_t>(li.sel), nitems = static_cast<uint32_t>(li.sel >> 32);
+        if (mode != 0 || T > SOLO_MAX_EDGES || nitems > static_cast<uint32_t>(TILE)) {
             sel_done = 1;
             break;
         }
         if (threadIdx.x == 0) record_level(p, n, 0, li);
         tpairs += li.pairs;
-        push_phase<W>(p, n, li, s_eb, s_beg, s_mask, 0, 1);
-        solo_sync();
+        // as push_phase: this level's words first, then the items' edges
+        if (lq) clear_level_words<W, true>(p, n, nq, 0, 1, so.q[n & 1]);
+        else clear_level_words<W>(p, n, nq, 0, 1);
+        uint32_t nn = 0;
+        if (T && nitems) nn = push_range<W, true>(p, n, s_eb, s_beg, s_mask, nitems, 0, T, so.q[(n + 1) & 1]);
+        if (threadIdx.x == 0) p.st.rec[(n + 1) % REC_RING].nq = nn;
+        __syncthreads();  // level n+1's queue is complete in LDS; the item copies are free
         npush++;
         n++;
+        nq = nn;
+        lq = true;
     }
+    solo_sync();
     if (threadIdx.x == 0) {
         p.st.bar->solo_n = n;
         p.st.bar->solo_sel = sel_done;
@@ -683,7 +767,7 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
         if (nq <= SOLO_MAX_QUEUE && n != solo_at) {
             // a run of small levels in workgroup 0; the rest wait here
             solo_at = n;
-            if (blockIdx.x == 0) solo_levels<W>(p, n, s_eb, s_beg, s_mask, npush, tpairs);
+            if (blockIdx.x == 0) solo_levels<W>(p, n, nq, s_eb, s_beg, s_mask, npush, tpairs);
             if (!grid_barrier(bar, bc)) return;
             n = ld_acq(&bar->solo_n);
             selected = ld_acq(&bar->solo_sel) != 0;

@@ -171,27 +171,37 @@ __device__ __forceinline__ void multi_push_range(const MultiParams &p, uint32_t 
     const uint32_t *col = p.g.col;
     const uint32_t tid = threadIdx.x;
     static_assert(TILE == 4 * BLOCK, "four edges per thread and step");
+    // the halving steps of the item search depend on cnt alone (the same in
+    // every lane): a uniform loop of ceil(log2(cnt)) steps, no step for one item
+    const uint32_t ucnt = __builtin_amdgcn_readfirstlane(cnt);
     for (uint64_t ub = ubase; ub < uend; ub += TILE) {
-        uint32_t w[4], sp[4], sl[4];
+        uint32_t w[4], sp[4], sl[4], lo[4];
+        uint64_t tt[4];
+        // last staged item with s_eb <= t (s_eb[0] <= ubase); lanes past
+        // uend search for uend - 1 and drop the result
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint64_t t = ub + static_cast<uint64_t>(k) * BLOCK + tid;
+            tt[k] = t < uend ? t : uend - 1;
+            lo[k] = 0;
+        }
+        for (uint32_t len = ucnt; len > 1;) {
+            const uint32_t half = len >> 1;
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                if (s_eb[lo[k] + half] <= tt[k]) lo[k] += half;
+            len -= half;
+        }
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const uint64_t t = ub + static_cast<uint64_t>(k) * BLOCK + tid;
             w[k] = V;
             sp[k] = 0;
             sl[k] = 0;
-            uint32_t lo = 0, len = cnt;  // last staged item with s_eb <= t (cnt <= TILE + 1 < 2^12)
-#pragma unroll
-            for (int step = 0; step < 12; step++) {
-                const uint32_t half = len >> 1;
-                if (half && t < uend) {
-                    if (s_eb[lo + half] <= t) lo += half;
-                    len -= half;
-                }
-            }
             if (t < uend) {
-                const uint64_t pos = s_beg[lo] + (t - s_eb[lo]);
-                sp[k] = s_mask[lo];
-                sl[k] = s_slot[lo];
+                const uint64_t pos = s_beg[lo[k]] + (t - s_eb[lo[k]]);
+                sp[k] = s_mask[lo[k]];
+                sl[k] = s_slot[lo[k]];
                 if (pos < p.g.ncol && sl[k] < p.slots) {
                     w[k] = col[pos];
                     if (w[k] >= V) {

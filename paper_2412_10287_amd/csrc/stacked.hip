@@ -326,8 +326,30 @@ struct UnitC {
 // Gather of one unit: locate its item and edge, OR the source's frontier rows
 // over the transitions into each target state, and drop the bits already in
 // P. Wide automata (QM = 32) scatter here, one transition at a time.
+// The staged item of each of K units: the last lo with L.eb[lo] <= the unit's
+// edge. The halving steps depend on cnt alone (the same in every lane), so
+// they run as one uniform loop of ceil(log2(cnt)) steps for all K units; a
+// unit past uend searches for the range's last unit, and its caller drops it.
+template <int G, int K>
+__device__ __forceinline__ void item_search(const StLds &L, uint32_t cnt, const uint64_t (&unit)[K], uint64_t uend,
+                                            uint32_t (&lo)[K]) {
+    uint32_t t[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        t[k] = static_cast<uint32_t>((unit[k] < uend ? unit[k] : uend - 1) / G);
+        lo[k] = 0;
+    }
+    for (uint32_t len = __builtin_amdgcn_readfirstlane(cnt); len > 1;) {
+        const uint32_t half = len >> 1;
+#pragma unroll
+        for (int k = 0; k < K; k++)
+            if (L.eb[lo[k] + half] <= t[k]) lo[k] += half;
+        len -= half;
+    }
+}
+
 template <int G, int QM, bool PULL>
-__device__ __forceinline__ void unit_gather(const StackParams &p, uint32_t n, const StLds &L, uint32_t cnt,
+__device__ __forceinline__ void unit_gather(const StackParams &p, uint32_t n, const StLds &L, uint32_t lo,
                                             uint64_t unit, uint64_t uend, uint32_t ns, UnitC<QM> &U) {
     const uint32_t V = static_cast<uint32_t>(p.V);
     const uint32_t j = static_cast<uint32_t>(unit % G);
@@ -338,17 +360,7 @@ __device__ __forceinline__ void unit_gather(const StackParams &p, uint32_t n, co
 #pragma unroll
     for (int q2 = 0; q2 < (QM <= 8 ? QM : 1); q2++) U.c[q2] = 0;
     const uint32_t t = static_cast<uint32_t>(unit / G);
-    // item holding edge t: the last staged item with L.eb <= t
-    // (fixed-step search: cnt <= TILE + 1 < 2^12)
-    uint32_t lo = 0, len = cnt;
-#pragma unroll
-    for (int step = 0; step < 12; step++) {
-        const uint32_t half = len >> 1;
-        if (half && unit < uend) {
-            if (L.eb[lo + half] <= t) lo += half;
-            len -= half;
-        }
-    }
+    // lo: the staged item holding edge t (item_search)
     if (unit >= uend) return;
     const uint32_t pos = L.beg[lo] + (t - L.eb[lo]);
     const uint32_t iv = L.v[lo], u = L.u[lo];
@@ -498,10 +510,13 @@ __device__ __forceinline__ void expand_range(const StackParams &p, uint32_t n, c
         static_assert(TILE == 4 * BLOCK, "four units per thread and step");
         for (uint64_t ub = ubase; ub < uend; ub += TILE) {
             UnitC<QM> U0, U1, U2, U3;
-            unit_gather<G, QM, PULL>(p, n, L, cnt, ub + tid, uend, ns, U0);
-            unit_gather<G, QM, PULL>(p, n, L, cnt, ub + BLOCK + tid, uend, ns, U1);
-            unit_gather<G, QM, PULL>(p, n, L, cnt, ub + 2 * BLOCK + tid, uend, ns, U2);
-            unit_gather<G, QM, PULL>(p, n, L, cnt, ub + 3 * BLOCK + tid, uend, ns, U3);
+            const uint64_t us[4] = {ub + tid, ub + BLOCK + tid, ub + 2 * BLOCK + tid, ub + 3 * BLOCK + tid};
+            uint32_t lo[4];
+            item_search<G, 4>(L, cnt, us, uend, lo);
+            unit_gather<G, QM, PULL>(p, n, L, lo[0], us[0], uend, ns, U0);
+            unit_gather<G, QM, PULL>(p, n, L, lo[1], us[1], uend, ns, U1);
+            unit_gather<G, QM, PULL>(p, n, L, lo[2], us[2], uend, ns, U2);
+            unit_gather<G, QM, PULL>(p, n, L, lo[3], us[3], uend, ns, U3);
             if constexpr (PULL) {
                 wave_merge<G, QM>(U0);
                 wave_merge<G, QM>(U1);
@@ -517,7 +532,10 @@ __device__ __forceinline__ void expand_range(const StackParams &p, uint32_t n, c
     } else {
         for (uint64_t ub = ubase; ub < uend; ub += BLOCK) {
             UnitC<QM> U0;
-            unit_gather<G, QM, PULL>(p, n, L, cnt, ub + tid, uend, ns, U0);
+            const uint64_t us[1] = {ub + tid};
+            uint32_t lo[1];
+            item_search<G, 1>(L, cnt, us, uend, lo);
+            unit_gather<G, QM, PULL>(p, n, L, lo[0], us[0], uend, ns, U0);
             unit_append<G, QM>(p, n, j, U0);
         }
     }
