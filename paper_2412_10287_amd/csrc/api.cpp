@@ -424,6 +424,9 @@ rpq_status rpq_set_option(rpq_graph *g, const char *key, int64_t value) {
         if (value < 0 || value > MAX_BATCH)
             return fail(RPQ_EINVAL, "rpq_set_option: serve_stack_min outside [0, %d]", MAX_BATCH);
         g->serve_stack_min = static_cast<int32_t>(value);
+    } else if (!strcmp(key, "cooperative_launch")) {
+        if (value != 0 && value != 1) return fail(RPQ_EINVAL, "rpq_set_option: cooperative_launch must be 0 or 1");
+        g->coop_launch = value != 0;
     } else if (!strcmp(key, "grid")) {
         if (value < 0) return fail(RPQ_EINVAL, "rpq_set_option: grid < 0");
         g->grid_override = static_cast<int32_t>(value);
@@ -447,6 +450,7 @@ rpq_status rpq_get_option(const rpq_graph *g, const char *key, int64_t *value) {
     else if (!strcmp(key, "large_query_pairs")) *value = g->large_pairs;
     else if (!strcmp(key, "large_query_slots")) *value = g->large_slots;
     else if (!strcmp(key, "serve_stack_min")) *value = g->serve_stack_min;
+    else if (!strcmp(key, "cooperative_launch")) *value = g->coop_launch ? 1 : 0;
     else if (!strcmp(key, "grid")) *value = g->grid_override;
     else return fail(RPQ_ENOTFOUND, "rpq_get_option: unknown key '%s'", key);
     return RPQ_OK;
@@ -515,7 +519,7 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
     if (!(flags & RPQ_HOST_LOOP) && grid_p > 0) {
         g->bar_idx ^= 1;  // the next persistent launch uses the barrier this one zeroes
         if (timing) HIP_TRY(hipEventRecord(g->ev[2], s));
-        HIP_TRY(launch_persistent(W, p, grid_p, s));
+        HIP_TRY(launch_persistent(W, p, grid_p, g->coop_launch, s));
         if (timing) HIP_TRY(hipEventRecord(g->ev[3], s));
         launches = 1;
     } else {

@@ -73,6 +73,7 @@ struct rpq_graph {
     int32_t serve_stack_min = 32;   // waiting served requests of one NFA that run as one stacked group (0 = never)
     int32_t grid_override = 0;
     int32_t plain_grid = 0;  // persistent single-query launch workgroups (0 = one per CU)
+    bool coop_launch = false;  // hipLaunchCooperativeKernel for the persistent single-query kernel
     std::recursive_mutex mu;
     // cached query constants of the single-query path
     rpq::QueryView qv{};

@@ -838,19 +838,28 @@ __global__ void k_fill(uint32_t *ptr, uint64_t words, uint32_t value) {
 }
 
 // ---------------------------------------------------------------- launchers
+// The grid (persistent_grid) is at most one workgroup per CU and fits the
+// occupancy limit, so on an idle GPU every workgroup is resident at once; an
+// ordinary launch dispatches about 14 us faster than a cooperative one. A
+// workgroup held back by other work longer than the barrier's time-out makes
+// the launch abort (status word), never wait for good.
 template <int W>
-static hipError_t launch_persistent_w(const Params &p, int grid, hipStream_t s) {
+static hipError_t launch_persistent_w(const Params &p, int grid, bool cooperative, hipStream_t s) {
     Params a = p;
-    void *args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_persistent<W>), dim3(grid),
-                                      dim3(BLOCK), args, 0, s);
+    if (cooperative) {
+        void *args[] = {&a};
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_persistent<W>), dim3(grid),
+                                          dim3(BLOCK), args, 0, s);
+    }
+    hipLaunchKernelGGL(k_persistent<W>, dim3(grid), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
 }
 
-hipError_t launch_persistent(int W, const Params &p, int grid, hipStream_t s) {
+hipError_t launch_persistent(int W, const Params &p, int grid, bool cooperative, hipStream_t s) {
     switch (W) {
-        case 1: return launch_persistent_w<1>(p, grid, s);
-        case 2: return launch_persistent_w<2>(p, grid, s);
-        default: return launch_persistent_w<4>(p, grid, s);
+        case 1: return launch_persistent_w<1>(p, grid, cooperative, s);
+        case 2: return launch_persistent_w<2>(p, grid, cooperative, s);
+        default: return launch_persistent_w<4>(p, grid, cooperative, s);
     }
 }
 

@@ -206,7 +206,7 @@ struct Params {
 };
 
 // Launchers (kernels.hip). W is the state-word width in bytes: 1, 2 or 4.
-hipError_t launch_persistent(int W, const Params &p, int grid, hipStream_t s);
+hipError_t launch_persistent(int W, const Params &p, int grid, bool cooperative, hipStream_t s);
 int persistent_grid(int W);          // co-resident workgroups for the persistent kernel
 int occupancy_blocks_per_cu(int W);  // what the occupancy API reports
 hipError_t launch_init(int W, const Params &p, hipStream_t s);

@@ -222,6 +222,24 @@ def test_repeat_is_stable(rpq):
         assert st.visited_pairs == int(st0.level_counts.sum()) and st.levels == st0.levels
 
 
+def test_cooperative_launch_option(rpq):
+    # the persistent kernel started with hipLaunchCooperativeKernel and with
+    # an ordinary launch (the default) gives the oracle's answers either way
+    w = C.rmat_workload(scale=13, edge_factor=16, num_labels=8, n_per_template=2)
+    og = oracle.Graph(w.graph)
+    gg = rpq.Graph(w.graph)
+    assert gg.get_option("cooperative_launch") == 0
+    with pytest.raises(rpq.RPQError):
+        gg.set_option("cooperative_launch", 2)
+    for coop in (1, 0):
+        gg.set_option("cooperative_launch", coop)
+        for nfa, s in zip(w.nfas, w.sources):
+            want = og.ssr(nfa, int(s))
+            bm, st = gg.single_source(rpq.NFA(nfa), int(s), level_cap=1024)
+            assert np.array_equal(bm, want.bitmap), coop
+            assert np.array_equal(st.level_counts, want.level_counts), coop
+
+
 def test_single_destination(rpq):
     # SDR(t) = { s : t in SSR(s) } (Sec. 2), checked by running the oracle's
     # single-source query from every vertex; the GPU runs the reversed,
