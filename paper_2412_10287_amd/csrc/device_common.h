@@ -461,13 +461,22 @@ __device__ __forceinline__ bool spin_until_at_least(const GridBarrier *b, const 
     return true;
 }
 
-// Registration at kernel start: every workgroup counts itself on its XCD.
-__device__ inline bool barrier_register(GridBarrier *b, BarCtx &c) {
-    __shared__ uint32_t s_v[3];
+// Registration at kernel start: every workgroup counts itself on its XCD
+// (barrier_arrive_register), then waits until all have (barrier_wait_register)
+// and learns how many share its XCD and how many XCDs take part. A workgroup
+// may do work of its own between the two calls.
+__device__ __forceinline__ void barrier_arrive_register(GridBarrier *b) {
     if (threadIdx.x == 0) {
         const uint32_t x = xcc_id();
         __hip_atomic_fetch_add(&b->reg[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(&b->nreg, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__device__ inline bool barrier_wait_register(GridBarrier *b, BarCtx &c) {
+    __shared__ uint32_t s_v[3];
+    if (threadIdx.x == 0) {
+        const uint32_t x = xcc_id();
         uint32_t ok = spin_until_at_least(b, &b->nreg, gridDim.x);
         uint32_t nx = 0;
         for (int i = 0; i < MAX_XCD; i++) nx += aload(&b->reg[i]) ? 1u : 0u;
@@ -481,6 +490,11 @@ __device__ inline bool barrier_register(GridBarrier *b, BarCtx &c) {
     c.nxcd = s_v[2];
     c.k = 0;
     return c.nxcd != 0;
+}
+
+__device__ inline bool barrier_register(GridBarrier *b, BarCtx &c) {
+    barrier_arrive_register(b);
+    return barrier_wait_register(b, c);
 }
 
 __device__ inline bool grid_barrier(GridBarrier *b, BarCtx &c) {

@@ -141,23 +141,23 @@ __device__ __forceinline__ void clear_level_words(const Params &p, uint32_t k, u
 // reserved per workgroup with one 64-bit atomic that counts items (high half)
 // and edges (low half) together, so item order and edge numbering agree.
 //
-// SOLO: workgroup 0 alone runs the level (bid 0, nblk 1). The queue length
-// comes in solo_nq and, when solo_lq, the queue from so->q; reservations
-// advance a cursor in registers; the items are also kept in s_eb, s_beg and
-// s_mask (the first TILE + 1 of them), and the level's totals go to `so` as
-// well as, with plain stores, to its level record.
+// nq is the level's queue length (its record's nq).
+//
+// SOLO: workgroup 0 alone runs the level (bid 0, nblk 1). When solo_lq the
+// queue comes from so->q; reservations advance a cursor in registers; the
+// items are also kept in s_eb, s_beg and s_mask (the first TILE + 1 of them),
+// and the level's totals go to `so` as well as, with plain stores, to its
+// level record.
 template <int W, bool SOLO = false>
-__device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32_t bid, uint32_t nblk,
-                                             SoloLds *so = nullptr, uint32_t solo_nq = 0, bool solo_lq = false,
-                                             uint32_t *s_eb = nullptr, uint32_t *s_beg = nullptr,
-                                             uint32_t *s_mask = nullptr) {
+__device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32_t nq, uint32_t bid, uint32_t nblk,
+                                             SoloLds *so = nullptr, bool solo_lq = false, uint32_t *s_eb = nullptr,
+                                             uint32_t *s_beg = nullptr, uint32_t *s_mask = nullptr) {
     const GraphView &g = p.g;
     const QueryView &qv = s_qv;
     const QHeader &h = *qv.h;
     LevelRec *rec = p.st.rec;
     LevelRec &R = rec[n % REC_RING];
     const uint32_t V = static_cast<uint32_t>(g.V);
-    uint32_t nq = SOLO ? solo_nq : ld_acq(&R.nq);
     if (nq > V) {
         if (bid == 0 && threadIdx.x == 0) flag_violation(p);
         nq = V;
@@ -646,14 +646,39 @@ __device__ __forceinline__ void pull_phase(const Params &p, uint32_t n, uint32_t
     }
 }
 
-// Clears the last frontier's words, writes the result bitmap (vertex v has a
-// final state: the product F P of Alg. 1) and resets P for the next query.
+// After nlev levels: the result bitmap (vertex v has a final state: the
+// product F P of Alg. 1) and P reset for the next query. The last level's
+// words in M are cleared here only when that level pulled (clear_last); a push
+// level has cleared them itself.
 template <int W>
-__device__ __forceinline__ void final_phase(const Params &p, uint32_t nlev) {
+__device__ __forceinline__ void final_phase(const Params &p, uint32_t nlev, bool clear_last) {
     const uint32_t V = static_cast<uint32_t>(p.g.V);
     if (blockIdx.x == 0 && threadIdx.x == 0 && nlev < LVL_COUNT_CAP)
         p.st.lvl[static_cast<uint64_t>(nlev) * LVL_STRIDE + 3] = wall_clock64();
-    if (nlev >= 1) {
+    // eight words of P per wave and step, all loaded before any is stored
+    const uint32_t fm = s_qv.h->fmask;
+    const uint32_t nwords = (V + 63) / 64;
+    const uint32_t lane = lane_id();
+    const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
+    for (uint32_t k0 = gw; k0 < nwords; k0 += 8 * nw) {
+        uint32_t pv[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const uint32_t k = k0 + j * nw;
+            const uint32_t v = k * 64 + lane;
+            pv[j] = (k < nwords && v < V) ? ld_state<W>(p.st.P, v) : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const uint32_t k = k0 + j * nw;  // the same in the whole wave
+            const uint64_t b = __ballot((pv[j] & fm) != 0);
+            if (k < nwords) {
+                if (lane == 0) p.st.out[k] = b;
+                if (pv[j]) st_state<W>(p.st.P, k * 64 + lane, 0);
+            }
+        }
+    }
+    if (nlev >= 1 && clear_last) {
         const uint32_t D = nlev - 1;
         const uint32_t nq = ld_acq(&p.st.rec[D % REC_RING].nq);
         uint32_t *M = p.st.M[D & 1];
@@ -663,17 +688,6 @@ __device__ __forceinline__ void final_phase(const Params &p, uint32_t nlev) {
             if (v < V) st_state<W>(M, v, 0);
             else flag_violation(p);
         }
-    }
-    const uint32_t fm = s_qv.h->fmask;
-    const uint32_t nwords = (V + 63) / 64;
-    const uint32_t lane = lane_id();
-    const uint32_t gw = gthread() >> 6, nw = gthreads() >> 6;
-    for (uint32_t k = gw; k < nwords; k += nw) {
-        const uint32_t v = k * 64 + lane;
-        const uint32_t pv = v < V ? ld_state<W>(p.st.P, v) : 0u;
-        const uint64_t b = __ballot((pv & fm) != 0);
-        if (lane == 0) p.st.out[k] = b;
-        if (pv) st_state<W>(p.st.P, v, 0);
     }
 }
 
@@ -704,7 +718,7 @@ __device__ __forceinline__ void solo_levels(const Params &p, uint32_t n, uint32_
     bool lq = false;  // level n's queue is in so.q (every level of the run but the first)
     for (uint32_t run = 0; run < SOLO_MAX_RUN; run++) {
         if (nq == 0 || nq > SOLO_MAX_QUEUE) break;
-        select_phase<W, true>(p, n, 0, 1, &so, nq, lq, s_eb, s_beg, s_mask);
+        select_phase<W, true>(p, n, nq, 0, 1, &so, lq, s_eb, s_beg, s_mask);
         // the stores to P and M are complete before the push loads P; the
         // items and totals are in LDS
         solo_sync();
@@ -754,29 +768,42 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
         uint32_t *z = reinterpret_cast<uint32_t *>(p.st.bar_next);
         for (uint32_t i = threadIdx.x; i < sizeof(GridBarrier) / 4; i += BLOCK) z[i] = 0;
     }
-    BarCtx bc;
-    if (!barrier_register(bar, bc)) return;
-    init_phase<W>(p);
-    if (!grid_barrier(bar, bc)) return;
-    uint32_t n = 0, npush = 0, npull = 0, solo_at = ~0u;
+    barrier_arrive_register(bar);
+    uint32_t n = 0, npush = 0, npull = 0, last_mode = 0;
     uint64_t tpairs = 0;  // |P|, summed over the levels (workgroup 0's count is complete)
+    // Level 0's queue is known without reading memory: M_0 = Q_S x {source},
+    // one entry (none without start states). Workgroup 0 initialises the query
+    // and runs the first small levels while the rest of the grid is still
+    // being dispatched and registering; the others wait at the first barrier.
+    if (blockIdx.x == 0) {
+        init_phase<W>(p);
+        solo_sync();  // level 0's queue and word are in memory before the run reads them
+        solo_levels<W>(p, 0, s_qv.h->smask ? 1u : 0u, s_eb, s_beg, s_mask, npush, tpairs);
+    }
+    BarCtx bc;
+    if (!barrier_wait_register(bar, bc)) return;
+    if (!grid_barrier(bar, bc)) return;
+    n = ld_acq(&bar->solo_n);
+    bool selected = ld_acq(&bar->solo_sel) != 0;  // level n's select is done
+    uint32_t solo_at = 0;
     while (true) {
-        const uint32_t nq = ld_acq(&p.st.rec[n % REC_RING].nq);
-        if (nq == 0) break;
-        bool selected = false;
-        if (nq <= SOLO_MAX_QUEUE && n != solo_at) {
-            // a run of small levels in workgroup 0; the rest wait here
-            solo_at = n;
-            if (blockIdx.x == 0) solo_levels<W>(p, n, nq, s_eb, s_beg, s_mask, npush, tpairs);
-            if (!grid_barrier(bar, bc)) return;
-            n = ld_acq(&bar->solo_n);
-            selected = ld_acq(&bar->solo_sel) != 0;
-            if (!selected) continue;
-        }
         if (!selected) {
-            select_phase<W>(p, n, blockIdx.x, gridDim.x);
+            const uint32_t nq = ld_acq(&p.st.rec[n % REC_RING].nq);
+            if (nq == 0) break;
+            if (nq <= SOLO_MAX_QUEUE && n != solo_at) {
+                // a run of small levels in workgroup 0; the rest wait here
+                solo_at = n;
+                if (blockIdx.x == 0) solo_levels<W>(p, n, nq, s_eb, s_beg, s_mask, npush, tpairs);
+                if (!grid_barrier(bar, bc)) return;
+                n = ld_acq(&bar->solo_n);
+                selected = ld_acq(&bar->solo_sel) != 0;
+                last_mode = 0;  // solo levels push (a level it left selected is expanded next)
+                continue;
+            }
+            select_phase<W>(p, n, nq, blockIdx.x, gridDim.x);
             if (!grid_barrier(bar, bc)) return;
         }
+        selected = false;
         const LevelInfo li = level_info(p, n);
         const uint32_t mode = decide(p, li);
         if (blockIdx.x == 0 && threadIdx.x == 0) record_level(p, n, mode, li);
@@ -785,10 +812,11 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
         else pull_phase<W>(p, n, s_eb, s_beg, s_mask, &s_hn);
         npush += mode == 0;
         npull += mode != 0;
+        last_mode = mode;
         if (!grid_barrier(bar, bc)) return;
         n++;
     }
-    final_phase<W>(p, n);
+    final_phase<W>(p, n, last_mode != 0);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         p.st.status[0] = n;
         p.st.status[1] = npush;
@@ -807,7 +835,7 @@ __global__ __launch_bounds__(64) void k_init(Params p) {
 template <int W>
 __global__ __launch_bounds__(BLOCK) void k_select(Params p, uint32_t n) {
     qv_setup<false>(p.qv);
-    select_phase<W>(p, n, blockIdx.x, gridDim.x);
+    select_phase<W>(p, n, ld_acq(&p.st.rec[n % REC_RING].nq), blockIdx.x, gridDim.x);
 }
 
 template <int W>
@@ -828,7 +856,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(Params p, uint32_t n) {
 template <int W>
 __global__ __launch_bounds__(BLOCK) void k_final(Params p, uint32_t nlev) {
     qv_setup<false>(p.qv);
-    final_phase<W>(p, nlev);
+    final_phase<W>(p, nlev, nlev >= 1 && ld_acq(&p.st.rec[(nlev - 1) % REC_RING].mode) != 0);
 }
 
 __global__ void k_fill(uint32_t *ptr, uint64_t words, uint32_t value) {
