@@ -179,13 +179,23 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
     const uint32_t nsym = h.nsym;
     uint64_t c_pe = 0, c_sc = 0, c_sd = 0, pairs = 0;
     uint32_t nfront = 0, su = 0;
+    // With at most SYM_BATCH used symbols, all of them are looked up in one
+    // round, and their rank words are loaded together with the state words
+    // (before S is known): one dependent round trip less per level.
+    const bool few_sym = nsym <= static_cast<uint32_t>(SYM_BATCH);
     // workgroup-uniform loop: item reservations are made per workgroup
     for (uint32_t bbase = bid * BLOCK; bbase < nq; bbase += nblk * BLOCK) {
         const uint32_t i = bbase + threadIdx.x;
         uint32_t v = 0, S = 0;
+        RankWordD rwp[SYM_BATCH];
         if (i < nq) {
             v = static_cast<uint32_t>(SOLO && solo_lq ? so->q[n & 1][i] : ldc(&qc[i]));
             if (v < V) {
+                if (few_sym) {
+#pragma unroll
+                    for (int j = 0; j < SYM_BATCH; j++)
+                        if (static_cast<uint32_t>(j) < nsym) rwp[j] = g.rankw[qv.push_w[j] + (v >> 6)];
+                }
                 // the complement mask of Alg. 1, then P = P + M
                 const uint32_t c = ld_state<W>(Mc, v);
                 const uint32_t pv = ld_state<W>(P, v);
@@ -202,19 +212,29 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
         }
         // only the symbols with a transition out of S can give an item; the
         // rounds continue while any lane of the workgroup has symbols left
-        SymSet Rs = symbols_of(qv, S, nsym);
+        SymSet Rs;
+        if (!few_sym) Rs = symbols_of(qv, S, nsym);
         while (true) {
             uint32_t us[SYM_BATCH], sp[SYM_BATCH], beg[SYM_BATCH], len[SYM_BATCH];
             RankWordD rw[SYM_BATCH];
-#pragma unroll
-            for (int j = 0; j < SYM_BATCH; j++) us[j] = symbol_pop(Rs);
             bool more = false;
+            if (few_sym) {
 #pragma unroll
-            for (int k = 0; k < SYM_WORDS; k++) more = more || Rs.w[k] != 0;
+                for (int j = 0; j < SYM_BATCH; j++) {
+                    us[j] = static_cast<uint32_t>(j) < nsym ? static_cast<uint32_t>(j) : nsym;
+                    sp[j] = us[j] < nsym ? succ_of(qv.succ, us[j], S) : 0u;
+                    if (sp[j]) rw[j] = rwp[j];
+                }
+            } else {
 #pragma unroll
-            for (int j = 0; j < SYM_BATCH; j++) {
-                sp[j] = us[j] < nsym ? succ_of(qv.succ, us[j], S) : 0u;
-                if (sp[j]) rw[j] = g.rankw[qv.push_w[us[j]] + (v >> 6)];
+                for (int j = 0; j < SYM_BATCH; j++) us[j] = symbol_pop(Rs);
+#pragma unroll
+                for (int k = 0; k < SYM_WORDS; k++) more = more || Rs.w[k] != 0;
+#pragma unroll
+                for (int j = 0; j < SYM_BATCH; j++) {
+                    sp[j] = us[j] < nsym ? succ_of(qv.succ, us[j], S) : 0u;
+                    if (sp[j]) rw[j] = g.rankw[qv.push_w[us[j]] + (v >> 6)];
+                }
             }
             uint32_t cnt = 0, tot = 0;
 #pragma unroll
@@ -449,17 +469,18 @@ __device__ __forceinline__ void push_phase(const Params &p, uint32_t n, const Le
     }
     const uint32_t tid = threadIdx.x;
     if (nitems <= static_cast<uint32_t>(TILE)) {
+        uint32_t per = (T + nblk - 1) / nblk;
+        per = (per + 63) & ~63u;
+        const uint64_t b0 = static_cast<uint64_t>(bid) * per;
+        if (b0 >= T) return;  // no edges for this workgroup: nothing to stage
+        const uint32_t b1 = b0 + per < T ? static_cast<uint32_t>(b0 + per) : T;
         for (uint32_t j = tid; j < nitems; j += BLOCK) {
             s_eb[j] = ldc(&p.st.it_ebase[j]);
             s_beg[j] = ldc(&p.st.it_beg[j]);
             s_mask[j] = ldc(&p.st.it_mask[j]);
         }
         __syncthreads();
-        uint32_t per = (T + nblk - 1) / nblk;
-        per = (per + 63) & ~63u;
-        const uint64_t b0 = static_cast<uint64_t>(bid) * per;
-        const uint32_t b1 = b0 + per < T ? static_cast<uint32_t>(b0 + per) : T;
-        if (b0 < b1) push_range<W>(p, n, s_eb, s_beg, s_mask, nitems, static_cast<uint32_t>(b0), b1);
+        push_range<W>(p, n, s_eb, s_beg, s_mask, nitems, static_cast<uint32_t>(b0), b1);
         __syncthreads();
         return;
     }
