@@ -424,16 +424,19 @@ __device__ __forceinline__ bool row_range(const GraphView &g, const RankWordD &r
 }
 
 // ------------------------------------------------------------ grid barrier
-// Two-level barrier for the persistent kernel (every workgroup is resident:
-// cooperative launch). Each XCD has its own L2. Workgroups first meet on a
+// Two-level barrier for the persistent kernels, whose grids are sized to be
+// resident at once. Each XCD has its own L2. Workgroups first meet on a
 // per-XCD counter; their stores are already in that XCD's L2 (every wave
 // waits for its memory operations first). The last one on an XCD writes the
-// L2 back once (device-scope release) and meets the other XCDs' leaders on a
-// global counter; then every workgroup drops stale cached lines (device-scope
-// acquire). Counters only grow within a launch (barrier k completes at
-// k * members), and the host zeroes them before each launch. A wait longer
+// L2 back once (device-scope release), meets the other XCDs' leaders on a
+// global counter, invalidates its L2 (device-scope acquire) and releases the
+// XCD's other workgroups, whose reads of data written during the launch are
+// device-scope loads. Counters only grow within a launch (barrier k
+// completes at k * members) and start at zero (the host clears the block
+// before a launch; a single-query launch clears the next one's block). A wait longer
 // than BARRIER_TIMEOUT ticks of the 100 MHz wall clock sets `abort`, and
-// every workgroup leaves the kernel at its next barrier.
+// every workgroup leaves the kernel at its next barrier, so a workgroup that
+// never becomes resident ends the launch instead of hanging it.
 constexpr uint64_t BARRIER_TIMEOUT = 5ull * 100000000ull;  // 5 s
 
 struct BarCtx {
