@@ -346,8 +346,8 @@ rpq_status rpq::graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32
     sv.bar = g->bars[0];
     sv.bar_next = g->bars[1];
     sv.status = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(sv.bar) + offsetof(GridBarrier, status));
-    g->qconst_cap = qconst_bytes(MAX_SYMS) + 64;
-    if ((st = dev_alloc(g, reinterpret_cast<void **>(&g->qconst_dev), g->qconst_cap, "qconst")) != RPQ_OK) return st;
+    g->qconst_cap = qconst_bytes(MAX_SYMS) + 64;  // one query's constants at most
+    if ((st = dev_alloc(g, reinterpret_cast<void **>(&g->qconst_dev), QARENA_BYTES, "qconst")) != RPQ_OK) return st;
     g->pinned_cap = g->qconst_cap + 4096 + 8 * LVL_STRIDE * (LVL_COUNT_CAP + 1);
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&g->pinned), g->pinned_cap, hipHostMallocDefault));
     HIP_TRY(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
@@ -473,16 +473,36 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
     g->dirty = true;  // until this query completes
     const uint32_t force = (flags & RPQ_FORCE_PUSH) ? 1u : (flags & RPQ_FORCE_PULL) ? 2u : 0u;
     const uint32_t counters = (flags & RPQ_COUNTERS) ? 1u : 0u;
-    // query constants: rebuilt when the NFA or the settings change
+    // query constants: from the device cache, else built and uploaded into it
     if (g->q_serial != n->serial || g->q_force != force || g->q_counters != counters ||
         g->q_alpha != g->pull_alpha || g->q_beta != g->pull_beta) {
-        int32_t nsym = 0;
-        const size_t sz = build_qconst(g, n, force, counters, g->qbuf, &nsym);
-        if (nsym > MAX_SYMS) return fail(RPQ_EINVAL, "query uses %d symbols; the limit is %d", nsym, MAX_SYMS);
-        if (sz > g->qconst_cap) return fail(RPQ_EINVAL, "query constants too large");
-        memcpy(g->pinned, g->qbuf.data(), sz);
-        HIP_TRY(hipMemcpyAsync(g->qconst_dev, g->pinned, sz, hipMemcpyHostToDevice, s));
-        g->qv = query_view(g->qconst_dev, nsym);
+        auto it = g->qcache.find(n->serial);
+        if (it != g->qcache.end() && (it->second.force != force || it->second.counters != counters ||
+                                      it->second.alpha != g->pull_alpha || it->second.beta != g->pull_beta)) {
+            g->qcache.erase(it);
+            it = g->qcache.end();
+        }
+        if (it != g->qcache.end()) {
+            g->qv = query_view(g->qconst_dev + it->second.off, it->second.nsym);
+        } else {
+            int32_t nsym = 0;
+            const size_t sz = build_qconst(g, n, force, counters, g->qbuf, &nsym);
+            if (nsym > MAX_SYMS) return fail(RPQ_EINVAL, "query uses %d symbols; the limit is %d", nsym, MAX_SYMS);
+            if (sz > g->qconst_cap) return fail(RPQ_EINVAL, "query constants too large");
+            const size_t need = (sz + 255) & ~static_cast<size_t>(255);
+            if (g->qarena_used + need > QARENA_BYTES) {
+                // full: start over (every call is complete before the next
+                // begins, so no launch still reads the old entries)
+                g->qcache.clear();
+                g->qarena_used = 0;
+            }
+            const size_t off = g->qarena_used;
+            g->qarena_used += need;
+            memcpy(g->pinned, g->qbuf.data(), sz);
+            HIP_TRY(hipMemcpyAsync(g->qconst_dev + off, g->pinned, sz, hipMemcpyHostToDevice, s));
+            g->qcache[n->serial] = rpq_graph::QEntry{force, counters, g->pull_alpha, g->pull_beta, off, nsym};
+            g->qv = query_view(g->qconst_dev + off, nsym);
+        }
         g->q_serial = n->serial;
         g->q_force = force;
         g->q_counters = counters;

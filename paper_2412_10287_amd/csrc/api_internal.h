@@ -4,11 +4,16 @@
 #include <atomic>
 #include <mutex>
 #include <new>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/rpq.h"
 #include "graph_build.h"
 #include "rpq_internal.h"
+
+// Device bytes per graph handle for cached single-query constants (at least
+// 50 queries of the largest kind, thousands of typical ones).
+constexpr size_t QARENA_BYTES = size_t(4) << 20;
 
 namespace rpq {
 
@@ -81,6 +86,17 @@ struct rpq_graph {
     uint64_t q_serial = 0;
     uint32_t q_force = ~0u, q_counters = ~0u;
     double q_alpha = -1, q_beta = -1;
+    // Query constants of recent single-query calls stay in device memory
+    // (qconst_dev is a bump arena of qconst_cap bytes, emptied when full), so
+    // a query repeated with the same NFA handle and settings uploads nothing.
+    struct QEntry {
+        uint32_t force, counters;
+        double alpha, beta;
+        size_t off;
+        int32_t nsym;
+    };
+    std::unordered_map<uint64_t, QEntry> qcache;  // by NFA serial
+    size_t qarena_used = 0;
     // batched and served paths
     rpq::BatchState *batch = nullptr;
     rpq::ServeState *serve = nullptr;

@@ -240,6 +240,31 @@ def test_cooperative_launch_option(rpq):
             assert np.array_equal(st.level_counts, want.level_counts), coop
 
 
+def test_query_constant_cache(rpq):
+    # automata over most of the 128 symbols (constant blocks of about 36 KB,
+    # beyond the LDS copy) from 160 handles, queried twice in opposite
+    # orders: the device cache of query constants fills, starts over and
+    # serves repeats; every answer stays the oracle's
+    L = 64
+    g = G.erdos_renyi(3000, 20000, L, seed=5)
+    og = oracle.Graph(g)
+    gg = rpq.Graph(g)
+    rng = np.random.default_rng(7)
+    cases = []
+    for k in range(160):
+        syms = rng.permutation(2 * L)
+        tr = [(0, int(a), 1) for a in syms[:100]] + [(1, int(a), 1) for a in syms[100:128]]
+        tr += [(1, int(a), 2) for a in rng.choice(2 * L, size=20, replace=False)]
+        nfa = R.nfa_from_triples(3, L, tr, [0], [2])
+        cases.append((nfa, rpq.NFA(nfa), int(rng.integers(0, 3000))))
+    want = [og.ssr(nfa, s).bitmap for nfa, _, s in cases]
+    for order in (list(range(len(cases))), list(reversed(range(len(cases))))):
+        for i in order:
+            _, nh, s = cases[i]
+            bm, _ = gg.single_source(nh, s)
+            assert np.array_equal(bm, want[i]), i
+
+
 def test_single_destination(rpq):
     # SDR(t) = { s : t in SSR(s) } (Sec. 2), checked by running the oracle's
     # single-source query from every vertex; the GPU runs the reversed,
