@@ -143,6 +143,36 @@ def test_long_chain_runs_of_small_levels(rpq):
             assert np.array_equal(st.level_counts, want.level_counts), (text, name)
 
 
+def test_small_level_handoffs(rpq):
+    # Workgroup 0 runs small levels from the start of a query and hands a
+    # level to the grid once it is too large. Here the hand-off happens
+    # (a) at level 0, from a hub with 20000 out-edges (more push edges than a
+    # small level may have), and (b) at level 1, where 1000 vertices with
+    # three labelled out-edges each give 3000 items (more than one LDS tile
+    # holds) but only 3000 edges.
+    hub, m = 0, 1000
+    src = [hub] * 20000 + [hub] * m
+    dst = [1 + m + i for i in range(20000)] + [1 + i for i in range(m)]
+    lab = [3] * 20000 + [0] * m
+    base = 1 + m + 20000
+    for i in range(m):
+        for k in (1, 2, 3):
+            src.append(1 + i)
+            dst.append(base + (3 * i + k) % 4000)
+            lab.append(k)
+    g = G.from_triples(base + 4000, 4, np.array(src), np.array(dst), np.array(lab))
+    gg = rpq.Graph(g)
+    og = oracle.Graph(g)
+    for text in ("3", "3*", "(3|0)+", "0 (1|2|3)", "0 (1|2|3) ^3", "(0|1|2|3)*"):
+        nfa = R.compile_regex(text, 4)
+        want = og.ssr(nfa, hub)
+        for name in ("auto", "push", "pull", "hostloop"):
+            bm, st = _run(rpq, gg, rpq.NFA(nfa), hub, MODES[name], level_cap=64)
+            assert np.array_equal(bm, want.bitmap), (text, name)
+            assert np.array_equal(st.level_counts, want.level_counts), (text, name)
+            assert st.levels == want.levels, (text, name)
+
+
 def test_grid_closed_forms_gpu(rpq):
     side = 48
     g = G.grid(side, 0.0, 0)
