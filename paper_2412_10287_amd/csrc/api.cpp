@@ -222,6 +222,7 @@ static void destroy(rpq_graph *g) {
     for (hipEvent_t e : g->ev)
         if (e) (void)hipEventDestroy(e);
     if (g->pinned) (void)hipHostFree(g->pinned);
+    if (g->hstat) (void)hipHostFree(g->hstat);
     for (void *p : g->allocs) (void)hipFree(p);
     batch_free(g);
     delete g;
@@ -350,6 +351,9 @@ rpq_status rpq::graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&g->qconst_dev), QARENA_BYTES, "qconst")) != RPQ_OK) return st;
     g->pinned_cap = g->qconst_cap + 4096 + 8 * LVL_STRIDE * (LVL_COUNT_CAP + 1);
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&g->pinned), g->pinned_cap, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&g->hstat), 64, hipHostMallocDefault));
+    HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void **>(&g->hstat_dev), g->hstat, 0));
+    memset(g->hstat, 0, 64);
     HIP_TRY(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
     g->own_stream = true;
     for (int k = 0; k < 4; k++) HIP_TRY(hipEventCreate(&g->ev[k]));
@@ -536,7 +540,21 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
     uint32_t nlev = 0;
     float expand_ms = 0.f;
     int32_t launches = 0;
-    if (!(flags & RPQ_HOST_LOOP) && grid_p > 0) {
+    const bool persistent = !(flags & RPQ_HOST_LOOP) && grid_p > 0;
+    p.st.hstat = nullptr;
+    p.st.hserial = 0;
+    if (persistent) {
+        // the kernel writes its status words to pinned host memory: no copy
+        // back in the common case (the flags are cleared before the launch
+        // is enqueued; the kernel only ever sets them)
+        if (++g->hserial == 0) g->hserial = 1;
+        g->hstat[3] = 0;
+        g->hstat[6] = 0;
+        g->hstat[7] = 0;
+        p.st.hstat = g->hstat_dev;
+        p.st.hserial = g->hserial;
+    }
+    if (persistent) {
         g->bar_idx ^= 1;  // the next persistent launch uses the barrier this one zeroes
         if (timing) HIP_TRY(hipEventRecord(g->ev[2], s));
         HIP_TRY(launch_persistent(W, p, grid_p, g->coop_launch, s));
@@ -574,16 +592,31 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
     static_assert(offsetof(GridBarrier, abort) == offsetof(GridBarrier, status) + 28, "abort follows status");
     constexpr uint32_t LVL_SPEC = 64;
     uint64_t *lp = reinterpret_cast<uint64_t *>(stage + 128);
-    HIP_TRY(hipMemcpyAsync(status, p.st.status, 32, hipMemcpyDeviceToHost, s));
+    if (!persistent) HIP_TRY(hipMemcpyAsync(status, p.st.status, 32, hipMemcpyDeviceToHost, s));
     if (counters) HIP_TRY(hipMemcpyAsync(cnt, p.st.cnt, 32, hipMemcpyDeviceToHost, s));
     // without per-level outputs the persistent kernel's status words carry |P|
-    const bool persistent = !(flags & RPQ_HOST_LOOP) && grid_p > 0;
     const bool need_lvl = stats && (stats->level_cap > 0 || !persistent);
     if (need_lvl) HIP_TRY(hipMemcpyAsync(lp, p.st.lvl, 8 * LVL_STRIDE * LVL_SPEC, hipMemcpyDeviceToHost, s));
     if (!(flags & RPQ_OUT_DEVICE))
         HIP_TRY(hipMemcpyAsync(out, g->dev_out, 8 * g->nwords, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (status[7] && !(flags & RPQ_HOST_LOOP) && grid_p > 0) {
+    if (persistent) {
+        const volatile uint32_t *h = g->hstat;
+        if (h[3] || h[6] || h[7] != g->hserial) {
+            // a violation, an abort or no final status: the device's own
+            // words (the violation count, the barrier's abort flag)
+            HIP_TRY(hipMemcpy(status, p.st.status, 32, hipMemcpyDeviceToHost));
+            if (h[6]) status[7] = 1;
+            if (h[3] && !status[3]) status[3] = 1;
+            if (h[7] != g->hserial && !status[7] && !status[3])
+                return fail(RPQ_EDEVICE, "persistent traversal ended without its status");
+        } else {
+            for (int k = 0; k < 8; k++) status[k] = h[k];
+            status[3] = 0;
+            status[7] = 0;
+        }
+    }
+    if (status[7] && persistent) {
         g->bars_dirty = true;
         return fail(RPQ_EDEVICE, "persistent traversal aborted: grid barrier timed out");
     }

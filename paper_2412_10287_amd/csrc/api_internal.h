@@ -55,6 +55,9 @@ struct rpq_graph {
     size_t qconst_cap = 0;
     uint8_t *pinned = nullptr;
     size_t pinned_cap = 0;
+    uint32_t *hstat = nullptr;      // pinned status words the single-query kernel writes (StateView::hstat)
+    uint32_t *hstat_dev = nullptr;  // the same memory as the device addresses it
+    uint32_t hserial = 0;           // serial of the last single-query launch
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t user_stream = nullptr;

@@ -72,7 +72,15 @@ __device__ __forceinline__ void qv_setup(const QueryView &qv) {
 
 // Records a violated invariant (an index read from device memory out of
 // range); the access is skipped and the host reports the query as failed.
-__device__ __forceinline__ void flag_violation(const Params &p) { atomicAdd(&p.st.status[3], 1u); }
+// Host-visible status word k (pinned host memory; see StateView::hstat).
+__device__ __forceinline__ void hstat_store(const Params &p, int k, uint32_t v) {
+    if (p.st.hstat) __hip_atomic_store(p.st.hstat + k, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ void flag_violation(const Params &p) {
+    atomicAdd(&p.st.status[3], 1u);
+    hstat_store(p, 3, 1u);
+}
 
 // Runs of small levels (solo_levels) execute in workgroup 0 alone; their
 // queues, reservation cursors and level totals live in LDS (SoloLds) rather
@@ -777,6 +785,12 @@ __device__ __forceinline__ void solo_levels(const Params &p, uint32_t n, uint32_
 }
 
 // ---------------------------------------------------------------- kernels
+// A workgroup leaving the persistent kernel because a barrier timed out
+// tells the host so.
+__device__ __forceinline__ void leave_aborted(const Params &p) {
+    if (threadIdx.x == 0) hstat_store(p, 6, 1u);
+}
+
 template <int W>
 __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
     // push tiles and pull heavy lists share the workgroup's LDS
@@ -802,8 +816,8 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
         solo_levels<W>(p, 0, s_qv.h->smask ? 1u : 0u, s_eb, s_beg, s_mask, npush, tpairs);
     }
     BarCtx bc;
-    if (!barrier_wait_register(bar, bc)) return;
-    if (!grid_barrier(bar, bc)) return;
+    if (!barrier_wait_register(bar, bc)) return leave_aborted(p);
+    if (!grid_barrier(bar, bc)) return leave_aborted(p);
     n = ld_acq(&bar->solo_n);
     bool selected = ld_acq(&bar->solo_sel) != 0;  // level n's select is done
     uint32_t solo_at = 0;
@@ -815,14 +829,14 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
                 // a run of small levels in workgroup 0; the rest wait here
                 solo_at = n;
                 if (blockIdx.x == 0) solo_levels<W>(p, n, nq, s_eb, s_beg, s_mask, npush, tpairs);
-                if (!grid_barrier(bar, bc)) return;
+                if (!grid_barrier(bar, bc)) return leave_aborted(p);
                 n = ld_acq(&bar->solo_n);
                 selected = ld_acq(&bar->solo_sel) != 0;
                 last_mode = 0;  // solo levels push (a level it left selected is expanded next)
                 continue;
             }
             select_phase<W>(p, n, nq, blockIdx.x, gridDim.x);
-            if (!grid_barrier(bar, bc)) return;
+            if (!grid_barrier(bar, bc)) return leave_aborted(p);
         }
         selected = false;
         const LevelInfo li = level_info(p, n);
@@ -834,7 +848,7 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
         npush += mode == 0;
         npull += mode != 0;
         last_mode = mode;
-        if (!grid_barrier(bar, bc)) return;
+        if (!grid_barrier(bar, bc)) return leave_aborted(p);
         n++;
     }
     final_phase<W>(p, n, last_mode != 0);
@@ -844,6 +858,13 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
         p.st.status[2] = npull;
         p.st.status[4] = static_cast<uint32_t>(tpairs);
         p.st.status[5] = static_cast<uint32_t>(tpairs >> 32);
+        // the same words for the host, and the launch's serial last
+        hstat_store(p, 0, n);
+        hstat_store(p, 1, npush);
+        hstat_store(p, 2, npull);
+        hstat_store(p, 4, static_cast<uint32_t>(tpairs));
+        hstat_store(p, 5, static_cast<uint32_t>(tpairs >> 32));
+        hstat_store(p, 7, p.st.hserial);
     }
 }
 

@@ -196,6 +196,11 @@ struct StateView {
     GridBarrier *bar_next;  // the barrier of the next launch, zeroed by this one
     uint64_t item_cap;    // entries of the item arrays
     uint64_t tile_cap;    // entries of tile_first
+    // Host-visible status (pinned host memory, or null): [0] levels, [1] push
+    // levels, [2] pull levels, [3] 1 after an invariant violation, [4..5] |P|,
+    // [6] 1 after a barrier abort, [7] hserial once the launch has finished.
+    uint32_t *hstat;
+    uint32_t hserial;
 };
 
 struct Params {
