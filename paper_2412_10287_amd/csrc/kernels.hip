@@ -102,7 +102,9 @@ __device__ __forceinline__ void init_phase(const Params &p) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     const QHeader &h = *s_qv.h;
     LevelRec *r = p.st.rec;
+    // records are cleared two levels ahead (select_phase): levels 0 and 1 here
     rec_clear(r[0]);
+    rec_clear(r[1]);
     const uint32_t sm = h.smask;
     if (sm) {
         // M_0 = Q_S x {source}, as a candidate that level 0's select adds to P
@@ -142,6 +144,58 @@ __device__ __forceinline__ void clear_level_words(const Params &p, uint32_t k, u
     }
 }
 
+template <int W, bool SOLO = false>
+__device__ __forceinline__ uint32_t push_range(const Params &p, uint32_t n, const uint32_t *s_eb,
+                                               const uint32_t *s_beg, const uint32_t *s_mask, uint32_t cnt,
+                                               uint32_t ubase, uint32_t uend, int32_t *lq = nullptr);
+
+// A mid-size level after a push level is fused: each workgroup pushes the
+// edges of its own items right after selecting them (from LDS, up to
+// FUSE_LOCAL_EDGES edges and TILE + 1 items), and only the items beyond that
+// budget are reserved globally and pushed over the grid after the barrier.
+// One grid barrier less per such level; the level is always pushed.
+constexpr uint32_t FUSE_LOCAL_EDGES = 2 * TILE;
+constexpr uint32_t FUSE_V_DIV = 32;  // fused while the queue holds at most V / 32 candidates
+
+// The reservation of one select round of a fused level: the round goes to
+// the workgroup's own items (cursor `local`, in registers) while they fit
+// the budget, else to the level's global items (counter `glob`). Packed
+// (items << 32) | edges as in block_reserve; `is_local` tells which.
+__device__ __forceinline__ bool block_reserve_fused(uint64_t wtot, bool more, uint64_t &local, uint64_t *glob,
+                                                    uint64_t &base, bool &is_local) {
+    __shared__ uint64_t s_w[NWAVE];
+    __shared__ uint32_t s_more[NWAVE];
+    __shared__ uint64_t s_base;
+    const uint32_t wave = threadIdx.x >> 6;
+    const bool wmore = __ballot(more) != 0;
+    if (lane_id() == 0) {
+        s_w[wave] = wtot;
+        s_more[wave] = wmore ? 1u : 0u;
+    }
+    __syncthreads();
+    uint64_t off = 0, tot = 0;
+    uint32_t any = 0;
+#pragma unroll
+    for (int k = 0; k < NWAVE; k++) {
+        const uint64_t x = s_w[k];
+        if (static_cast<uint32_t>(k) < wave) off += x;
+        tot += x;
+        any |= s_more[k];
+    }
+    const uint64_t after = local + tot;
+    is_local = (after >> 32) <= static_cast<uint64_t>(TILE) + 1 && static_cast<uint32_t>(after) <= FUSE_LOCAL_EDGES &&
+               static_cast<uint32_t>(after) >= static_cast<uint32_t>(local);
+    if (!is_local && threadIdx.x == 0 && tot) s_base = atomic_add_any(glob, tot);
+    __syncthreads();  // s_w read everywhere, s_base published
+    if (is_local) {
+        base = local + off;
+        local = after;
+    } else {
+        base = tot ? s_base + off : 0ull;
+    }
+    return any != 0;
+}
+
 // Candidates -> frontier -> push items. Each candidate w gets its new states
 // S = M[w] & ~P[w] (added to P); for each used symbol u, succ_u(S) is the
 // column w of (N^u)^T M, and when it is non-empty and w has u-neighbours,
@@ -156,10 +210,17 @@ __device__ __forceinline__ void clear_level_words(const Params &p, uint32_t k, u
 // items are also kept in s_eb, s_beg and s_mask (the first TILE + 1 of them),
 // and the level's totals go to `so` as well as, with plain stores, to its
 // level record.
-template <int W, bool SOLO = false>
+//
+// FUSED (grid, a mid-size level that is pushed): rounds that fit the
+// workgroup's budget keep their items in s_eb, s_beg and s_mask (local
+// numbering) and are pushed at the end by this workgroup; the frontier words
+// are cleared at once (a pushed level never reads them again); the local
+// items and edges are added to the record's hsel for the statistics.
+template <int W, bool SOLO = false, bool FUSED = false>
 __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32_t nq, uint32_t bid, uint32_t nblk,
                                              SoloLds *so = nullptr, bool solo_lq = false, uint32_t *s_eb = nullptr,
                                              uint32_t *s_beg = nullptr, uint32_t *s_mask = nullptr) {
+    static_assert(!(SOLO && FUSED), "one mode");
     const GraphView &g = p.g;
     const QueryView &qv = s_qv;
     const QHeader &h = *qv.h;
@@ -171,7 +232,9 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
         nq = V;
     }
     if (bid == 0 && threadIdx.x == 0) {
-        rec_clear(rec[(n + 1) % REC_RING]);
+        // the record of level n+2: level n+1's is already clear (a fused level's
+        // pushes append to it while other workgroups still select)
+        rec_clear(rec[(n + 2) % REC_RING]);
         if (n < LVL_COUNT_CAP) p.st.lvl[static_cast<uint64_t>(n) * LVL_STRIDE + 3] = wall_clock64();
     }
     // frontier words of level n-1 live in the buffer level n writes: after a
@@ -181,7 +244,7 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
     const uint32_t prev_mode = (n >= 1 && !(SOLO && solo_lq)) ? ld_acq(&rec[(n - 1) % REC_RING].mode) : 0u;
     if (prev_mode != 0) clear_level_words<W>(p, n - 1, ld_acq(&rec[(n - 1) % REC_RING].nq), bid, nblk);
     const int32_t *qc = p.st.q[n & 1];
-    uint64_t run_sel = 0;  // SOLO: the reservation cursor
+    uint64_t run_sel = 0;  // SOLO: the reservation cursor; FUSED: the workgroup's own items
     uint32_t *Mc = p.st.M[n & 1];
     uint32_t *P = p.st.P;
     const uint32_t nsym = h.nsym;
@@ -191,12 +254,24 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
     // round, and their rank words are loaded together with the state words
     // (before S is known): one dependent round trip less per level.
     const bool few_sym = nsym <= static_cast<uint32_t>(SYM_BATCH);
+    // Candidates [q0, q1) of this workgroup, BLOCK per round, every
+    // nblk * BLOCK (the grid and one workgroup). A fused level spreads its
+    // candidates over the whole grid in wave-sized chunks instead, so each
+    // workgroup's own push stays short.
+    uint32_t q0 = bid * BLOCK, q1 = nq, qstep = nblk * BLOCK;
+    if constexpr (FUSED) {
+        uint32_t chunk = (nq + nblk - 1) / nblk;
+        chunk = (chunk + 63) & ~63u;
+        q0 = bid * chunk < nq ? bid * chunk : nq;
+        q1 = q0 + chunk < nq ? q0 + chunk : nq;
+        qstep = BLOCK;
+    }
     // workgroup-uniform loop: item reservations are made per workgroup
-    for (uint32_t bbase = bid * BLOCK; bbase < nq; bbase += nblk * BLOCK) {
+    for (uint32_t bbase = q0; bbase < q1; bbase += qstep) {
         const uint32_t i = bbase + threadIdx.x;
         uint32_t v = 0, S = 0;
         RankWordD rwp[SYM_BATCH];
-        if (i < nq) {
+        if (i < q1) {
             v = static_cast<uint32_t>(SOLO && solo_lq ? so->q[n & 1][i] : ldc(&qc[i]));
             if (v < V) {
                 if (few_sym) {
@@ -209,7 +284,11 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
                 const uint32_t pv = ld_state<W>(P, v);
                 S = c & ~pv;
                 if (S) st_state<W>(P, v, pv | S);
-                if (S != c) st_state<W>(Mc, v, S);
+                if constexpr (FUSED) {
+                    if (c) st_state<W>(Mc, v, 0u);
+                } else if (S != c) {
+                    st_state<W>(Mc, v, S);
+                }
                 pairs += __popc(S);
                 nfront += S != 0;
                 su |= S;
@@ -266,10 +345,29 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
             uint64_t wtot;
             const uint64_t ex = wave_excl_scan((static_cast<uint64_t>(cnt) << 32) | tot, wtot);
             uint64_t wbase;
-            bool bmore;
+            bool bmore, to_lds = SOLO;
             if constexpr (SOLO) bmore = block_reserve_local<uint64_t>(wtot, more, run_sel, wbase);
+            else if constexpr (FUSED) bmore = block_reserve_fused(wtot, more, run_sel, &R.sel, wbase, to_lds);
             else bmore = block_reserve<uint64_t>(wtot, more, &R.sel, wbase);
-            if (cnt) {
+            if (FUSED && to_lds && cnt) {
+                // this workgroup's own items (local numbering, within the budget)
+                const uint64_t mine = wbase + ex;
+                uint32_t idx = static_cast<uint32_t>(mine >> 32);
+                uint32_t eb = static_cast<uint32_t>(mine);
+#pragma unroll
+                for (int j = 0; j < SYM_BATCH; j++) {
+                    if (!len[j]) continue;
+                    if (idx <= static_cast<uint32_t>(TILE)) {
+                        s_eb[idx] = eb;
+                        s_beg[idx] = beg[j];
+                        s_mask[idx] = sp[j];
+                    } else {
+                        flag_violation(p);
+                    }
+                    idx++;
+                    eb += len[j];
+                }
+            } else if (cnt) {
                 const uint64_t mine = wbase + ex;
                 uint32_t idx = static_cast<uint32_t>(mine >> 32);
                 uint32_t eb = static_cast<uint32_t>(mine);
@@ -336,6 +434,16 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
         if (t && threadIdx.x < 4)
             atomicAdd(reinterpret_cast<unsigned long long *>(&p.st.cnt[threadIdx.x]), (unsigned long long)t);
     }
+    if constexpr (FUSED) {
+        // this workgroup's own items: their edges pushed now
+        if (run_sel >> 32) {
+            __syncthreads();  // the items are in LDS
+            push_range<W>(p, n, s_eb, s_beg, s_mask, static_cast<uint32_t>(run_sel >> 32), 0u,
+                          static_cast<uint32_t>(run_sel));
+            if (threadIdx.x == 0) atomic_add_any(&R.hsel, run_sel);
+            __syncthreads();  // the LDS items are free again
+        }
+    }
 }
 
 // Level n's totals once its select phase is complete, read by every thread
@@ -387,10 +495,10 @@ __device__ __forceinline__ uint32_t decide(const Params &p, const LevelInfo &li)
 // level's word of w; the first writer appends w to the candidate queue.
 // SOLO (workgroup 0 alone): the queue length is a cursor in registers, the
 // entries also go to lq (the first SOLO_MAX_QUEUE), and the length is returned.
-template <int W, bool SOLO = false>
+template <int W, bool SOLO>
 __device__ __forceinline__ uint32_t push_range(const Params &p, uint32_t n, const uint32_t *s_eb,
                                                const uint32_t *s_beg, const uint32_t *s_mask, uint32_t cnt,
-                                               uint32_t ubase, uint32_t uend, int32_t *lq = nullptr) {
+                                               uint32_t ubase, uint32_t uend, int32_t *lq) {
     const uint32_t V = static_cast<uint32_t>(p.g.V);
     const uint32_t *P = p.st.P;
     uint32_t *Mn = p.st.M[(n + 1) & 1];
@@ -462,11 +570,13 @@ __device__ __forceinline__ uint32_t push_range(const Params &p, uint32_t n, cons
 // workgroups each tile is split into parts of at least a wave's worth.
 template <int W>
 __device__ __forceinline__ void push_phase(const Params &p, uint32_t n, const LevelInfo &li, uint32_t *s_eb,
-                                           uint32_t *s_beg, uint32_t *s_mask, uint32_t bid, uint32_t nblk) {
+                                           uint32_t *s_beg, uint32_t *s_mask, uint32_t bid, uint32_t nblk,
+                                           bool clear = true) {
     // the push direction never reads this level's words of M[n & 1] again
     // (items carry the successor sets): clear them now, with stores that
-    // overlap the push; level n+1's expansion writes this buffer
-    clear_level_words<W>(p, n, li.nq, bid, nblk);
+    // overlap the push; level n+1's expansion writes this buffer (a fused
+    // level's select has cleared them already)
+    if (clear) clear_level_words<W>(p, n, li.nq, bid, nblk);
     const uint64_t sel = li.sel;
     const uint32_t nitems = static_cast<uint32_t>(sel >> 32);
     const uint32_t T = static_cast<uint32_t>(sel);
@@ -833,6 +943,28 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
                 n = ld_acq(&bar->solo_n);
                 selected = ld_acq(&bar->solo_sel) != 0;
                 last_mode = 0;  // solo levels push (a level it left selected is expanded next)
+                continue;
+            }
+            if (last_mode == 0 && s_qv.h->force != 2 && nq <= static_cast<uint32_t>(p.g.V) / FUSE_V_DIV) {
+                // a fused level: select and push of each workgroup's own items,
+                // then one barrier (and a grid-wide push of what exceeded the
+                // workgroups' budgets, if anything did)
+                select_phase<W, false, true>(p, n, nq, blockIdx.x, gridDim.x, nullptr, false, s_eb, s_beg, s_mask);
+                if (!grid_barrier(bar, bc)) return leave_aborted(p);
+                const LevelInfo li = level_info(p, n);  // sel: the global items only
+                if (blockIdx.x == 0 && threadIdx.x == 0) {
+                    LevelInfo all = li;
+                    all.sel += ld_acq(&p.st.rec[n % REC_RING].hsel);
+                    record_level(p, n, 0, all);
+                }
+                tpairs += li.pairs;
+                if (li.sel >> 32) {
+                    push_phase<W>(p, n, li, s_eb, s_beg, s_mask, blockIdx.x, gridDim.x, false);
+                    if (!grid_barrier(bar, bc)) return leave_aborted(p);
+                }
+                npush++;
+                last_mode = 0;
+                n++;
                 continue;
             }
             select_phase<W>(p, n, nq, blockIdx.x, gridDim.x);

@@ -150,7 +150,8 @@ struct alignas(128) LevelRec {
     uint32_t pad_su[31];
     uint32_t mode;        // 0 push, 1 pull (decided when the level is expanded)
     uint32_t pad_mode;
-    uint64_t hsel;        // stacked pull: long rows deferred to the edge-balanced pass, (items << 32) | edges
+    uint64_t hsel;        // (items << 32) | edges: stacked pull, the long rows deferred to the edge-balanced
+                          // pass; single-query fused level, the workgroups' own items (statistics)
     uint64_t pad_hsel[14];
 };
 

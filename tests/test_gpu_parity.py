@@ -173,6 +173,31 @@ def test_small_level_handoffs(rpq):
             assert st.levels == want.levels, (text, name)
 
 
+def test_fused_mid_size_levels(rpq):
+    # With 2^17 vertices, levels of 1025 to 4096 candidates after a push level
+    # are fused: each workgroup pushes its own items, and rounds beyond its
+    # budget (hubs of this R-MAT graph) are pushed over the grid after the
+    # barrier. Wide state words (11 and 19 states) take the same path.
+    w = C.rmat_workload(scale=17, edge_factor=16, num_labels=16, n_per_template=3)
+    og = oracle.Graph(w.graph)
+    gg = rpq.Graph(w.graph)
+    extra = ["(0|1|2|3|4|5|6|7|8|9)*", "(0|^1|2|^3|4|5|6|7|8|9|10|11|12|13|14|15|^0|1 2)*"]
+    cases = list(zip(w.queries, w.nfas, w.sources))
+    cases += [(t, R.compile_regex(t, 16), int(w.sources[k])) for k, t in enumerate(extra)]
+    for text, nfa, s in cases:
+        want = og.ssr(nfa, int(s))
+        nh = rpq.NFA(nfa)
+        for name in ("auto", "push"):
+            bm, st = _run(rpq, gg, nh, int(s), MODES[name] | rpq.COUNTERS, level_cap=4096)
+            assert np.array_equal(bm, want.bitmap), (text, name)
+            assert np.array_equal(st.level_counts, want.level_counts), (text, name)
+            assert (st.product_edges, st.scans, st.scanned_edges, st.active, st.alg_bytes) == \
+                (want.product_edges, want.scans, want.scanned_edges, want.active, want.alg_bytes), (text, name)
+            bm2, st2 = _run(rpq, gg, nh, int(s), MODES[name])
+            assert np.array_equal(bm2, want.bitmap), (text, name)
+            assert st2.visited_pairs == int(want.level_counts.sum()), (text, name)
+
+
 def test_grid_closed_forms_gpu(rpq):
     side = 48
     g = G.grid(side, 0.0, 0)
