@@ -155,7 +155,7 @@ __device__ __forceinline__ uint32_t push_range(const Params &p, uint32_t n, cons
 // budget are reserved globally and pushed over the grid after the barrier.
 // One grid barrier less per such level; the level is always pushed.
 constexpr uint32_t FUSE_LOCAL_EDGES = 2 * TILE;
-constexpr uint32_t FUSE_V_DIV = 32;  // fused while the queue holds at most V / 32 candidates
+constexpr uint32_t FUSE_V_DIV = 8;  // fused while the queue holds at most V / 8 candidates
 
 // The reservation of one select round of a fused level: the round goes to
 // the workgroup's own items (cursor `local`, in registers) while they fit
@@ -985,6 +985,15 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
     }
     final_phase<W>(p, n, last_mode != 0);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // A fused level's pushes may read P before other workgroups' selects
+        // of the same level add to it, so its candidates may turn out to hold
+        // only visited states: the next frontier is then empty and yields no
+        // items, which makes it the last level. It is not counted.
+        if (n >= 1 && ld_acq(&p.st.rec[(n - 1) % REC_RING].pairs) == 0) {
+            n--;
+            if (last_mode == 0) npush--;
+            else npull--;
+        }
         p.st.status[0] = n;
         p.st.status[1] = npush;
         p.st.status[2] = npull;
