@@ -931,9 +931,11 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
     n = ld_acq(&bar->solo_n);
     bool selected = ld_acq(&bar->solo_sel) != 0;  // level n's select is done
     uint32_t solo_at = 0;
+    uint32_t nq_known = ~0u;  // level n's queue length when already loaded
     while (true) {
         if (!selected) {
-            const uint32_t nq = ld_acq(&p.st.rec[n % REC_RING].nq);
+            const uint32_t nq = nq_known != ~0u ? nq_known : ld_acq(&p.st.rec[n % REC_RING].nq);
+            nq_known = ~0u;
             if (nq == 0) break;
             if (nq <= SOLO_MAX_QUEUE && n != solo_at) {
                 // a run of small levels in workgroup 0; the rest wait here
@@ -952,6 +954,9 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
                 select_phase<W, false, true>(p, n, nq, blockIdx.x, gridDim.x, nullptr, false, s_eb, s_beg, s_mask);
                 if (!grid_barrier(bar, bc)) return leave_aborted(p);
                 const LevelInfo li = level_info(p, n);  // sel: the global items only
+                // the next queue's length, loaded with the totals (final
+                // unless the grid push below still appends)
+                const uint32_t nq_next = ld_acq(&p.st.rec[(n + 1) % REC_RING].nq);
                 if (blockIdx.x == 0 && threadIdx.x == 0) {
                     LevelInfo all = li;
                     all.sel += ld_acq(&p.st.rec[n % REC_RING].hsel);
@@ -961,6 +966,8 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
                 if (li.sel >> 32) {
                     push_phase<W>(p, n, li, s_eb, s_beg, s_mask, blockIdx.x, gridDim.x, false);
                     if (!grid_barrier(bar, bc)) return leave_aborted(p);
+                } else {
+                    nq_known = nq_next;
                 }
                 npush++;
                 last_mode = 0;
