@@ -155,7 +155,7 @@ __device__ __forceinline__ uint32_t push_range(const Params &p, uint32_t n, cons
 // budget are reserved globally and pushed over the grid after the barrier.
 // One grid barrier less per such level; the level is always pushed.
 constexpr uint32_t FUSE_LOCAL_EDGES = 2 * TILE;
-constexpr uint32_t FUSE_V_DIV = 8;  // fused while the queue holds at most V / 8 candidates
+constexpr uint32_t FUSE_V_DIV = 32;  // fused while the queue holds at most V / 32 candidates
 
 // The reservation of one select round of a fused level: the round goes to
 // the workgroup's own items (cursor `local`, in registers) while they fit
