@@ -43,8 +43,12 @@ struct MultiParams {
     int32_t V;
 };
 
-hipError_t multi_admit(const MultiParams &p, uint32_t parity, uint32_t n, const uint32_t *slot_src,
-                       hipStream_t s);
+// Admission of n requests from one staging upload: `stage` starts with n
+// records (slot, source, byte offset of the request's query constants in
+// stage, their size); the admit kernel copies each block into its slot's
+// constants and sets the slot's start pairs.
+constexpr size_t ADMIT_TABLE_BYTES = 16 * static_cast<size_t>(MAX_SLOTS_DEV);
+hipError_t multi_admit(const MultiParams &p, uint32_t parity, uint32_t n, const uint8_t *stage, hipStream_t s);
 hipError_t multi_select(const MultiParams &p, uint32_t parity, uint32_t lo, uint32_t hi, uint32_t clear_n,
                         int first_chunk, uint32_t chunk_id, int grid, hipStream_t s);
 hipError_t multi_push(const MultiParams &p, uint32_t parity, uint32_t chunk_id, int grid, hipStream_t s);
@@ -66,7 +70,14 @@ constexpr size_t PAIRS_STRIDE = CTL_LINE / 8;  // uint64 entries per slot
 inline size_t multi_ctl_bytes(uint32_t slots) {
     return multi_pairs_offset(slots) + CTL_LINE * static_cast<size_t>(slots);
 }
-hipError_t multi_extract(const MultiParams &p, uint32_t nfin, const uint32_t *fin_slots, uint64_t nwords,
-                         hipStream_t s);
+// (slot, result-pool entry) pairs of the finished queries, passed by value
+struct FinList {
+    uint32_t n;
+    uint32_t e[2 * MAX_SLOTS_DEV];
+};
+hipError_t multi_extract(const MultiParams &p, const FinList &fin, uint64_t nwords, hipStream_t s);
+// Copies the control block (`words` 32-bit words) into host memory that the
+// device addresses as `host` (pinned), on the stream of the level's kernels.
+hipError_t multi_publish(const MultiParams &p, uint32_t *host, uint32_t words, hipStream_t s);
 
 }  // namespace rpq

@@ -19,15 +19,23 @@ __device__ __forceinline__ QueryView slot_view(const MultiParams &p, uint32_t s)
     return qconst_view(base, reinterpret_cast<const QHeader *>(base)->nsym);
 }
 
-__global__ void k_multi_admit(MultiParams p, uint32_t parity, uint32_t n, const uint32_t *ss) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+// One workgroup per admitted request: its query constants from the staging
+// upload into the slot's block, then the start pairs.
+__global__ void k_multi_admit(MultiParams p, uint32_t parity, uint32_t n, const uint8_t *stage) {
+    const uint32_t i = blockIdx.x;
     if (i >= n) return;
-    const uint32_t s = ss[2 * i], v = ss[2 * i + 1];
-    if (s >= p.slots || v >= static_cast<uint32_t>(p.V)) {
-        mviolation(p);
+    const uint32_t *rec = reinterpret_cast<const uint32_t *>(stage) + 4 * i;
+    const uint32_t s = rec[0], v = rec[1], off = rec[2], bytes = rec[3];
+    if (s >= p.slots || v >= static_cast<uint32_t>(p.V) || bytes < sizeof(QHeader) || bytes > QC_STRIDE ||
+        off % 16 != 0 || off < ADMIT_TABLE_BYTES || off > ADMIT_TABLE_BYTES + QC_STRIDE * p.slots - bytes) {
+        if (threadIdx.x == 0) mviolation(p);
         return;
     }
-    const uint32_t sm = reinterpret_cast<const QHeader *>(p.qconst + static_cast<size_t>(s) * QC_STRIDE)->smask;
+    const uint4 *src = reinterpret_cast<const uint4 *>(stage + off);
+    uint4 *dst = reinterpret_cast<uint4 *>(const_cast<uint8_t *>(p.qconst) + static_cast<size_t>(s) * QC_STRIDE);
+    for (uint32_t k = threadIdx.x; k < (bytes + 15) / 16; k += blockDim.x) dst[k] = src[k];
+    if (threadIdx.x != 0) return;
+    const uint32_t sm = reinterpret_cast<const QHeader *>(stage + off)->smask;
     p.pairs[s * PAIRS_STRIDE] = 0;
     if (!sm) return;
     // M_0 = Q_S x {source} as a candidate: the next select adds it to P
@@ -296,15 +304,15 @@ __global__ __launch_bounds__(BLOCK) void k_multi_push(MultiParams p, uint32_t pa
 // One wavefront per 64-vertex word of each finished slot's answer: the ballot
 // of (P[v] & F != 0) is the word (the product F P of Alg. 1); P is reset.
 // fin holds (slot, result-pool entry) pairs.
-__global__ __launch_bounds__(BLOCK) void k_multi_extract(MultiParams p, uint32_t nfin, const uint32_t *fin,
-                                                         uint64_t nwords) {
+__global__ __launch_bounds__(BLOCK) void k_multi_extract(MultiParams p, FinList fin, uint64_t nwords) {
     const uint32_t V = static_cast<uint32_t>(p.V);
     const uint32_t lane = lane_id();
+    const uint32_t nfin = fin.n <= MAX_SLOTS_DEV ? fin.n : MAX_SLOTS_DEV;
     const uint64_t total = static_cast<uint64_t>(nfin) * nwords;
     for (uint64_t gw = gthread() >> 6; gw < total; gw += gthreads() >> 6) {
         const uint32_t f = static_cast<uint32_t>(gw / nwords);
         const uint64_t k = gw % nwords;
-        const uint32_t s = fin[2 * f], entry = fin[2 * f + 1];
+        const uint32_t s = fin.e[2 * f], entry = fin.e[2 * f + 1];
         if (s >= p.slots || entry >= 3 * p.slots) {
             if (lane == 0) mviolation(p);
             continue;
@@ -319,9 +327,21 @@ __global__ __launch_bounds__(BLOCK) void k_multi_extract(MultiParams p, uint32_t
     }
 }
 
-hipError_t multi_admit(const MultiParams &p, uint32_t parity, uint32_t n, const uint32_t *slot_src, hipStream_t s) {
+hipError_t multi_admit(const MultiParams &p, uint32_t parity, uint32_t n, const uint8_t *stage, hipStream_t s) {
     if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_multi_admit, dim3((n + 255) / 256), dim3(256), 0, s, p, parity, n, slot_src);
+    hipLaunchKernelGGL(k_multi_admit, dim3(n), dim3(256), 0, s, p, parity, n, stage);
+    return hipGetLastError();
+}
+
+// Device-scope loads of the block the level's kernels wrote, system-scope
+// stores into the pinned host copy.
+__global__ void k_multi_publish(const uint32_t *ctl, uint32_t *host, uint32_t words) {
+    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x)
+        __hip_atomic_store(host + i, ldc(ctl + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t multi_publish(const MultiParams &p, uint32_t *host, uint32_t words, hipStream_t s) {
+    hipLaunchKernelGGL(k_multi_publish, dim3(1), dim3(1024), 0, s, p.ctl, host, words);
     return hipGetLastError();
 }
 
@@ -337,14 +357,12 @@ hipError_t multi_push(const MultiParams &p, uint32_t parity, uint32_t chunk_id, 
     return hipGetLastError();
 }
 
-hipError_t multi_extract(const MultiParams &p, uint32_t nfin, const uint32_t *fin_slots, uint64_t nwords,
-                         hipStream_t s) {
-    if (!nfin) return hipSuccess;
-    uint64_t waves = static_cast<uint64_t>(nfin) * nwords;
+hipError_t multi_extract(const MultiParams &p, const FinList &fin, uint64_t nwords, hipStream_t s) {
+    if (!fin.n || fin.n > MAX_SLOTS_DEV) return fin.n ? hipErrorInvalidValue : hipSuccess;
+    uint64_t waves = static_cast<uint64_t>(fin.n) * nwords;
     uint64_t blocks = (waves + (BLOCK / 64) - 1) / (BLOCK / 64);
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_multi_extract, dim3(static_cast<uint32_t>(blocks)), dim3(BLOCK), 0, s, p, nfin, fin_slots,
-                       nwords);
+    hipLaunchKernelGGL(k_multi_extract, dim3(static_cast<uint32_t>(blocks)), dim3(BLOCK), 0, s, p, fin, nwords);
     return hipGetLastError();
 }
 

@@ -91,7 +91,9 @@ struct ServeState {
     uint32_t level = 0;
     uint32_t chunk_id = 0;
     uint32_t cur_len = 0, prev_len = 0;
-    uint32_t *d_admit = nullptr, *d_fin = nullptr;
+    uint8_t *d_stage = nullptr;  // admission upload: records, then query constants (stage_bytes)
+    size_t stage_bytes = 0;
+    uint32_t *d_hctl = nullptr;  // h_ctl as the device addresses it
     // result pool: finished queries' bitmaps stay on the device until polled
     // (entries [0, pool_n)); entries [pool_n, pool_n + slots) stage answers
     // that spill to host memory while every pool entry is held
@@ -101,10 +103,9 @@ struct ServeState {
     hipStream_t copy_stream = nullptr;   // rpq_poll's copies out of the pool
     std::mutex copy_mu;
     // pinned host staging
-    uint32_t *h_admit = nullptr;  // 2 * slots
     uint32_t *h_fin = nullptr;    // 2 * slots: (slot, pool entry)
-    uint8_t *h_ctl = nullptr;     // control block
-    uint8_t *h_qc = nullptr;      // slots * QC_STRIDE
+    uint8_t *h_ctl = nullptr;     // control block (written by the publish kernel)
+    uint8_t *h_stage = nullptr;   // admission upload (stage_bytes)
     int grid = 1024;
 };
 
@@ -186,21 +187,25 @@ static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
     SA(p.tile_first, 4 * p.tile_cap);
     ss->pool_n = 2 * slots;
     SA(p.out, 8 * g->nwords * (ss->pool_n + slots));
-    SA(ss->d_admit, 8 * slots);
-    SA(ss->d_fin, 8 * slots);
+    ss->stage_bytes = ADMIT_TABLE_BYTES + QC_STRIDE * static_cast<size_t>(slots);
+    SA(ss->d_stage, ss->stage_bytes);
 #undef SA
     const size_t ctl_b = (multi_ctl_bytes(slots) + 63) & ~static_cast<size_t>(63);
-    ss->pinned_bytes = 8 * slots + 8 * slots + ctl_b + QC_STRIDE * slots + 256;
+    ss->pinned_bytes = ss->stage_bytes + ctl_b + 8 * slots + 256;
     if ((e = hipHostMalloc(reinterpret_cast<void **>(&ss->pinned), ss->pinned_bytes, hipHostMallocDefault)) != hipSuccess)
         return fail(RPQ_ENOMEM, "served path: hipHostMalloc: %s", hipGetErrorString(e));
     uint8_t *hp = ss->pinned;
-    ss->h_qc = hp;
-    hp += QC_STRIDE * slots;
+    ss->h_stage = hp;
+    hp += ss->stage_bytes;
     ss->h_ctl = hp;
     hp += ctl_b;
-    ss->h_admit = reinterpret_cast<uint32_t *>(hp);
-    hp += 8 * slots;
     ss->h_fin = reinterpret_cast<uint32_t *>(hp);
+    {
+        uint8_t *dp = nullptr;
+        if ((e = hipHostGetDevicePointer(reinterpret_cast<void **>(&dp), ss->pinned, 0)) != hipSuccess)
+            return hip_fail(e, "hipHostGetDevicePointer");
+        ss->d_hctl = reinterpret_cast<uint32_t *>(dp + (ss->h_ctl - ss->pinned));
+    }
     if ((e = hipStreamCreateWithFlags(&ss->stream, hipStreamNonBlocking)) != hipSuccess)
         return hip_fail(e, "hipStreamCreate");
     if ((e = hipStreamCreateWithFlags(&ss->copy_stream, hipStreamNonBlocking)) != hipSuccess)
@@ -234,23 +239,28 @@ static rpq_status engine_step(rpq_graph *g, ServeState *ss, std::vector<Request>
     MultiParams &p = ss->mp;
     hipStream_t s = ss->stream;
     const uint32_t parity = ss->level & 1;
-    // 1. admission: query constants per slot, then the start pairs
+    // 1. admission: one upload of the requests' records and query constants;
+    //    the admit kernel moves the constants into the slots and sets the
+    //    start pairs
     if (!admit.empty()) {
         uint32_t k = 0;
+        uint32_t *table = reinterpret_cast<uint32_t *>(ss->h_stage);
+        size_t off = ADMIT_TABLE_BYTES;
         for (Request &r : admit) {
             const uint32_t sl = ss->free_slots.back();
             ss->free_slots.pop_back();
             ss->slot[sl] = SlotInfo{r.id, r.nsym, ss->level, r.submitted};
-            uint8_t *stage = ss->h_qc + static_cast<size_t>(sl) * QC_STRIDE;
-            memcpy(stage, r.qc.data(), r.qc.size());
-            ST(hipMemcpyAsync(const_cast<uint8_t *>(p.qconst) + static_cast<size_t>(sl) * QC_STRIDE, stage,
-                              r.qc.size(), hipMemcpyHostToDevice, s));
-            ss->h_admit[2 * k] = sl;
-            ss->h_admit[2 * k + 1] = static_cast<uint32_t>(r.source);
+            // admit.size() <= free slots <= slots, each block <= QC_STRIDE: it fits
+            memcpy(ss->h_stage + off, r.qc.data(), r.qc.size());
+            table[4 * k] = sl;
+            table[4 * k + 1] = static_cast<uint32_t>(r.source);
+            table[4 * k + 2] = static_cast<uint32_t>(off);
+            table[4 * k + 3] = static_cast<uint32_t>(r.qc.size());
+            off += (r.qc.size() + 15) & ~static_cast<size_t>(15);
             k++;
         }
-        ST(hipMemcpyAsync(ss->d_admit, ss->h_admit, 8 * k, hipMemcpyHostToDevice, s));
-        ST(multi_admit(p, parity, k, ss->d_admit, s));
+        ST(hipMemcpyAsync(ss->d_stage, ss->h_stage, off, hipMemcpyHostToDevice, s));
+        ST(multi_admit(p, parity, k, ss->d_stage, s));
         ss->cur_len += k;  // every admitted request has a start state (checked at submit)
     }
     if (ss->cur_len == 0) return retire(g, ss);
@@ -265,7 +275,7 @@ static rpq_status engine_step(rpq_graph *g, ServeState *ss, std::vector<Request>
         ST(multi_push(p, parity, ss->chunk_id, ss->grid, s));
         ss->chunk_id++;
     }
-    ST(hipMemcpyAsync(ss->h_ctl, p.ctl, multi_ctl_bytes(ss->slots), hipMemcpyDeviceToHost, s));
+    ST(multi_publish(p, ss->d_hctl, static_cast<uint32_t>(multi_ctl_bytes(ss->slots) / 4), s));
     ST(hipStreamSynchronize(s));
     const uint32_t h_status = *reinterpret_cast<const uint32_t *>(ss->h_ctl + CTL_STATUS);
     const uint32_t *h_cnt = reinterpret_cast<const uint32_t *>(ss->h_ctl + CTL_NEXT);
@@ -310,8 +320,12 @@ static rpq_status retire(rpq_graph *g, ServeState *ss) {
             }
         }
     }
-    ST(hipMemcpyAsync(ss->d_fin, ss->h_fin, 8 * nfin, hipMemcpyHostToDevice, s));
-    ST(multi_extract(p, nfin, ss->d_fin, static_cast<uint64_t>(g->nwords), s));
+    {
+        FinList fl;
+        fl.n = nfin;
+        memcpy(fl.e, ss->h_fin, 8 * static_cast<size_t>(nfin));
+        ST(multi_extract(p, fl, static_cast<uint64_t>(g->nwords), s));
+    }
     ST(hipStreamSynchronize(s));
     std::vector<std::vector<uint64_t>> spilled(nspill);
     for (uint32_t f = 0, k = 0; f < nfin; f++) {
