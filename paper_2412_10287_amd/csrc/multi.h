@@ -76,6 +76,13 @@ struct FinList {
     uint32_t e[2 * MAX_SLOTS_DEV];
 };
 hipError_t multi_extract(const MultiParams &p, const FinList &fin, uint64_t nwords, hipStream_t s);
+// Copies nwords 64-bit words from src to dst (device memory) and then stores
+// seq into *flag (pinned host memory, as the device addresses it) once the
+// copy is visible to every agent, so that a host can wait by polling the
+// flag. done (device memory, zero between launches) counts finished
+// workgroups.
+hipError_t copy_signal(const uint64_t *src, uint64_t *dst, uint64_t nwords, uint32_t *done, uint32_t *flag,
+                       uint32_t seq, hipStream_t s);
 // Copies the control block (`words` 32-bit words) into host memory that the
 // device addresses as `host` (pinned), on the stream of the level's kernels.
 hipError_t multi_publish(const MultiParams &p, uint32_t *host, uint32_t words, hipStream_t s);

@@ -340,6 +340,33 @@ __global__ void k_multi_publish(const uint32_t *ctl, uint32_t *host, uint32_t wo
         __hip_atomic_store(host + i, ldc(ctl + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+__global__ void k_copy_signal(const uint64_t *src, uint64_t *dst, uint64_t nwords, uint32_t *done, uint32_t *flag,
+                              uint32_t seq) {
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < nwords;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        dst[i] = src[i];
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores are in L2
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system scope: the L2 is written back
+        const uint32_t prev = __hip_atomic_fetch_add(done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (prev == gridDim.x - 1) {
+            __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+}
+
+hipError_t copy_signal(const uint64_t *src, uint64_t *dst, uint64_t nwords, uint32_t *done, uint32_t *flag,
+                       uint32_t seq, hipStream_t s) {
+    uint64_t blocks = (nwords + 4095) / 4096;  // 1024 threads, 4 words each
+    if (blocks < 1) blocks = 1;
+    if (blocks > 64) blocks = 64;
+    hipLaunchKernelGGL(k_copy_signal, dim3(static_cast<uint32_t>(blocks)), dim3(1024), 0, s, src, dst, nwords, done,
+                       flag, seq);
+    return hipGetLastError();
+}
+
 hipError_t multi_publish(const MultiParams &p, uint32_t *host, uint32_t words, hipStream_t s) {
     hipLaunchKernelGGL(k_multi_publish, dim3(1), dim3(1024), 0, s, p.ctl, host, words);
     return hipGetLastError();

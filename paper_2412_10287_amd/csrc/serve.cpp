@@ -94,6 +94,12 @@ struct ServeState {
     uint8_t *d_stage = nullptr;  // admission upload: records, then query constants (stage_bytes)
     size_t stage_bytes = 0;
     uint32_t *d_hctl = nullptr;  // h_ctl as the device addresses it
+    // rpq_poll's copies out of the pool signal completion through a pinned
+    // word (h_copy_flag; d_copy_flag as the device addresses it)
+    uint32_t *d_copy_done = nullptr;
+    uint32_t *d_copy_flag = nullptr;
+    volatile uint32_t *h_copy_flag = nullptr;
+    uint32_t copy_seq = 0;  // guarded by copy_mu
     // result pool: finished queries' bitmaps stay on the device until polled
     // (entries [0, pool_n)); entries [pool_n, pool_n + slots) stage answers
     // that spill to host memory while every pool entry is held
@@ -189,6 +195,7 @@ static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
     SA(p.out, 8 * g->nwords * (ss->pool_n + slots));
     ss->stage_bytes = ADMIT_TABLE_BYTES + QC_STRIDE * static_cast<size_t>(slots);
     SA(ss->d_stage, ss->stage_bytes);
+    SA(ss->d_copy_done, 64);
 #undef SA
     const size_t ctl_b = (multi_ctl_bytes(slots) + 63) & ~static_cast<size_t>(63);
     ss->pinned_bytes = ss->stage_bytes + ctl_b + 8 * slots + 256;
@@ -200,11 +207,15 @@ static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
     ss->h_ctl = hp;
     hp += ctl_b;
     ss->h_fin = reinterpret_cast<uint32_t *>(hp);
+    hp += 8 * slots;
+    ss->h_copy_flag = reinterpret_cast<volatile uint32_t *>(hp);
+    *ss->h_copy_flag = 0;
     {
         uint8_t *dp = nullptr;
         if ((e = hipHostGetDevicePointer(reinterpret_cast<void **>(&dp), ss->pinned, 0)) != hipSuccess)
             return hip_fail(e, "hipHostGetDevicePointer");
         ss->d_hctl = reinterpret_cast<uint32_t *>(dp + (ss->h_ctl - ss->pinned));
+        ss->d_copy_flag = reinterpret_cast<uint32_t *>(dp + (reinterpret_cast<uint8_t *>(hp) - ss->pinned));
     }
     if ((e = hipStreamCreateWithFlags(&ss->stream, hipStreamNonBlocking)) != hipSuccess)
         return hip_fail(e, "hipStreamCreate");
@@ -213,6 +224,7 @@ static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
     for (uint32_t *a : {p.P, p.M[0], p.M[1]})
         if ((e = launch_fill(a, swords * slots, 0, ss->stream)) != hipSuccess) return hip_fail(e, "fill");
     if ((e = launch_fill(p.ctl, multi_ctl_bytes(slots) / 4, 0, ss->stream)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_fill(ss->d_copy_done, 16, 0, ss->stream)) != hipSuccess) return hip_fail(e, "fill");
     if ((e = launch_fill(reinterpret_cast<uint32_t *>(p.sel), 4, 0, ss->stream)) != hipSuccess)
         return hip_fail(e, "fill");
     if ((e = hipStreamSynchronize(ss->stream)) != hipSuccess) return hip_fail(e, "sync");
@@ -721,10 +733,26 @@ rpq_status rpq_poll(rpq_graph *g, rpq_ticket t, uint64_t *out_bitmap, uint32_t f
     } else if (entry < 0) {
         if (dev) e = hipMemcpy(out_bitmap, spill.data(), bytes, hipMemcpyHostToDevice);
         else memcpy(out_bitmap, spill.data(), bytes);
+    } else if (dev) {
+        // a copy kernel that stores a sequence number into pinned memory once
+        // the copy is visible everywhere: the host polls that word for up to
+        // 200 us (a stream synchronisation wakes up tens of microseconds
+        // late), then waits on the stream
+        std::lock_guard<std::mutex> ck(ss->copy_mu);
+        const uint32_t seq = ++ss->copy_seq;
+        e = copy_signal(ss->mp.out + static_cast<size_t>(entry) * g->nwords, out_bitmap,
+                        static_cast<uint64_t>(g->nwords), ss->d_copy_done, ss->d_copy_flag, seq, ss->copy_stream);
+        if (e == hipSuccess) {
+            const Clock::time_point t0 = Clock::now();
+            bool seen = false;
+            while (!(seen = (*ss->h_copy_flag == seq)) && Clock::now() - t0 < std::chrono::microseconds(200)) {
+            }
+            if (!seen) e = hipStreamSynchronize(ss->copy_stream);
+        }
     } else {
         std::lock_guard<std::mutex> ck(ss->copy_mu);
         e = hipMemcpyAsync(out_bitmap, ss->mp.out + static_cast<size_t>(entry) * g->nwords, bytes,
-                           dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ss->copy_stream);
+                           hipMemcpyDeviceToHost, ss->copy_stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ss->copy_stream);
     }
     {
