@@ -32,9 +32,13 @@
 // the graph store holds both directions, and the label -> symbol tables map an
 // IN segment to the inverse symbol of its label.
 //
-// The whole traversal runs as one cooperative launch with grid barriers
+// The whole traversal runs as one persistent launch with grid barriers
 // between phases (no host round trip per level); the same phase code is also
-// launched kernel by kernel for the host-driven loop.
+// launched kernel by kernel for the host-driven loop. Inside the persistent
+// launch, runs of small levels execute in workgroup 0 alone (solo_levels),
+// and a mid-size level after a push level is fused: each workgroup pushes
+// the edges of its own items right after selecting them, one grid barrier
+// per level (block_reserve_fused).
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
