@@ -91,7 +91,7 @@ __device__ __forceinline__ void flag_violation(const Params &p) {
 // than in the level records, so such a level makes no global atomic and
 // reads nothing global but state words and the graph.
 constexpr uint32_t SOLO_MAX_QUEUE = 1024;  // candidate queue entries of a small level
-constexpr uint32_t SOLO_MAX_EDGES = 2048;  // push edges of a small level (one tile: more take one CU longer than the grid)
+constexpr uint32_t SOLO_MAX_EDGES = 1024;  // push edges of a small level (more take one CU longer than the grid)
 constexpr uint32_t SOLO_MAX_RUN = 2048;    // levels per run (the waiting workgroups' barrier times out after 5 s)
 
 struct SoloLds {
