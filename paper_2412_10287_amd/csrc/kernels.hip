@@ -90,7 +90,7 @@ __device__ __forceinline__ void flag_violation(const Params &p) {
 // queues, reservation cursors and level totals live in LDS (SoloLds) rather
 // than in the level records, so such a level makes no global atomic and
 // reads nothing global but state words and the graph.
-constexpr uint32_t SOLO_MAX_QUEUE = 1024;  // candidate queue entries of a small level
+constexpr uint32_t SOLO_MAX_QUEUE = 512;  // candidate queue entries of a small level
 constexpr uint32_t SOLO_MAX_EDGES = 1024;  // push edges of a small level (more take one CU longer than the grid)
 constexpr uint32_t SOLO_MAX_RUN = 2048;    // levels per run (the waiting workgroups' barrier times out after 5 s)
 
