@@ -38,6 +38,8 @@ typedef struct {
        pairs, sorted by (label, neighbour), duplicates removed */
     int64_t *out_off, *in_off;
     int32_t *out_lab, *out_nbr, *in_lab, *in_nbr;
+    /* has_edges[l] = 1 if at least one edge carries label l */
+    uint8_t *has_edges;
 } og_graph;
 
 /* stable counting sort of idx[0..m) by key[idx[i]] in [0, nkeys) */
@@ -87,6 +89,7 @@ void og_free(og_graph *g) {
     if (!g) return;
     free(g->out_off); free(g->in_off);
     free(g->out_lab); free(g->out_nbr); free(g->in_lab); free(g->in_nbr);
+    free(g->has_edges);
     free(g);
 }
 
@@ -107,6 +110,9 @@ og_graph *og_new(int32_t nv, int32_t nl, const int64_t *label_ptr, const int32_t
     og_graph *g = (og_graph *)calloc(1, sizeof(og_graph));
     if (!g) { free(lab); return NULL; }
     g->nv = nv; g->nl = nl;
+    g->has_edges = (uint8_t *)calloc((size_t)(nl > 0 ? nl : 1), 1);
+    if (!g->has_edges) { free(lab); og_free(g); return NULL; }
+    for (int32_t l = 0; l < nl; l++) g->has_edges[l] = label_ptr[l + 1] > label_ptr[l];
     if (build_dir(nv, nl, m, src, dst, lab, &g->out_off, &g->out_lab, &g->out_nbr) ||
         build_dir(nv, nl, m, dst, src, lab, &g->in_off, &g->in_lab, &g->in_nbr)) {
         free(lab); og_free(g); return NULL;
@@ -144,7 +150,12 @@ int64_t og_num_edges(const og_graph *g, int inv) {
  *   level_counts (nullable): level_counts[n] = |M_n| for n < level_cap.
  *   counters (nullable, 5 int64): product edges out of the reached pairs,
  *        scans, graph edges scanned, algorithmic bytes for state words of
- *        word_bytes bytes, active (level, vertex) pairs.
+ *        word_bytes bytes, active (level, vertex) pairs. A scan is a
+ *        (level n, vertex v, used symbol a) with succ_a(S_n(v)) non-empty,
+ *        S_n(v) the states first reached at v at level n, whether or not v
+ *        has a-neighbours: the byte model charges every scan the 8 bytes of
+ *        the row-pointer pair that finds its neighbour range, plus 4 + w
+ *        bytes per neighbour, plus 2w + 8 bytes per active (n, v).
  * Returns the number of levels (max distance + 1), or -1 on invalid input
  * or allocation failure.
  */
@@ -235,12 +246,12 @@ int32_t og_ssr(const og_graph *g, int32_t nq, int32_t nfa_nl, const int64_t *sym
     }
     if (counters) {
         /* successor sets per (symbol, state) for the symbols the NFA uses and
-           the graph has */
+           some edge of the graph carries */
         int32_t *used = (int32_t *)malloc((size_t)(nsym > 0 ? nsym : 1) * sizeof(int32_t));
         int32_t nused = 0;
         for (int32_t s = 0; s < nsym; s++) {
             int32_t l = s >= nfa_nl ? s - nfa_nl : s;
-            if (sym_ptr[s + 1] > sym_ptr[s] && l < g->nl) used[nused++] = s;
+            if (sym_ptr[s + 1] > sym_ptr[s] && l < g->nl && g->has_edges[l]) used[nused++] = s;
         }
         uint64_t *succ = (uint64_t *)calloc((size_t)(nused > 0 ? nused : 1) * nq, sizeof(uint64_t));
         for (int32_t u = 0; u < nused; u++)
@@ -268,7 +279,6 @@ int32_t og_ssr(const og_graph *g, int32_t nq, int32_t nfa_nl, const int64_t *sym
                 int64_t lo, hi;
                 nbr_range(g, v, inv ? s - nfa_nl : s, inv, &lo, &hi);
                 int64_t deg = hi - lo;
-                if (deg == 0) continue;
                 for (int32_t j = 0; j < nd; j++) {
                     uint64_t img = 0;
                     for (int32_t q = 0; q < nq; q++)

@@ -196,6 +196,36 @@ def test_counters_match_python():
         assert (r.product_edges, r.scans, r.scanned_edges, r.alg_bytes, r.active) == want
 
 
+def oracle_counters(g, nfa, src):
+    r = oracle.ssr(g, nfa, src)
+    return r.product_edges, r.scans, r.scanned_edges, r.alg_bytes, r.active, r.level_counts
+
+
+def test_counters_explicit_product_graph():
+    # counters and level counts against the explicit product automaton of
+    # Def. 2.5 (networkx), on tiny graphs with multi-labelled and repeated edges
+    OC.check_counters_product(oracle_counters, np.random.default_rng(41), n_cases=150)
+
+
+def test_counters_closed_form_star():
+    rng = np.random.default_rng(43)
+    OC.check_counters_star(oracle_counters, rng, G.erdos_renyi(1500, 5000, 4, 13))
+    OC.check_counters_star(oracle_counters, rng, G.rmat(10, 6, 5, 1.1, 17))
+
+
+def test_counters_closed_form_grid():
+    OC.check_counters_grid(oracle_counters, 17, np.random.default_rng(47), n=6)
+
+
+def test_grid_counter_closed_form_by_hand():
+    # the closed form itself, against a count done by hand on a 2 x 2 grid
+    # from (0, 0): (0,(0,0)) has an east and a north edge, (1,(1,0)) a north
+    # edge, (2,(0,1)) an east edge, the two pairs at (1,1) none: 4 product
+    # edges; 4 active vertices, 8 scans (each reached vertex, both symbols),
+    # 4 scanned edges
+    assert OC.grid_star_counters(2, 0, 0) == (4, 8, 4, 10 * 4 + 8 * 8 + 5 * 4 + 1, 4)
+
+
 def test_input_edge_cases():
     g = G.from_triples(1, 1, [], [], [])
     og = oracle.Graph(g)
@@ -208,3 +238,7 @@ def test_input_edge_cases():
     assert og.ssr(nfa, 0).vertices().tolist() == [0]
     with pytest.raises(ValueError):
         og.ssr(R.compile_regex("0", 1), 2)
+
+
+def test_stacked_counters_explicit_product_graph():
+    OC.check_stacked_counters_product(np.random.default_rng(53), n_cases=40)
