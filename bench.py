@@ -208,7 +208,7 @@ def bench_batched(args, w):
         tickets = [g.submit(nh, s) for s in srcs]
         for i, t in enumerate(tickets):
             _, st = g.poll(t, timeout_us=-1, out_device_ptr=out.ptr + 8 * i * words)
-            slat.append(st.device_ms * 1e-3)
+            slat.append(st.latency_ms * 1e-3)
     sdt = time.perf_counter() - t0
     if args.skip_plain:
         res["plain"] = res["served"] = {}
@@ -311,7 +311,7 @@ def bench_serve(args):
     for _ in range(N):
         i, tk, lag = tq.get()
         _, st = g.poll(tk, timeout_us=-1, out_device_ptr=out.ptr)
-        lat[i] = lag + st.device_ms * 1e-3
+        lat[i] = lag + st.latency_ms * 1e-3
     th.join()
     served_span = max(arr[i] + lat[i] for i in range(N)) - arr[0]
     log("served open loop done")
@@ -468,7 +468,7 @@ def main():
         for i, t in enumerate(tickets):
             _, st = g.poll(t, timeout_us=-1, out_device_ptr=base_ptr + i * row_bytes)
             if lat is not None:
-                lat.append(st.device_ms * 1e-3)
+                lat.append(st.latency_ms * 1e-3)
     for _ in range(args.warmup):
         served_step()
     slat = []

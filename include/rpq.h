@@ -72,8 +72,10 @@ typedef struct {
     int64_t visited_pairs;   /* out: |P|, reached (state, vertex) pairs */
     /* out, only with RPQ_COUNTERS (algorithmic work, independent of direction):
        product_edges = sum over reached (q,v) and symbols a of |succ_a(q)|*deg_a(v);
-       scans = (level, vertex, symbol) triples with a non-empty successor set
-       and at least one neighbour; scanned_edges = their neighbours;
+       scans = (level, vertex, used symbol) triples with a non-empty
+       successor set, whether or not the vertex has neighbours under the
+       symbol (a used symbol has a transition and a label some edge
+       carries); scanned_edges = their neighbours;
        alg_bytes = sum over levels of (2w+8)*active + (8+(4+w)*deg) per scan,
        plus ceil(V/8), w the state-word bytes (1, 2, 4 for <= 8, 16, 32 states);
        active = (level, vertex) pairs with a non-empty frontier word. */
@@ -98,6 +100,23 @@ typedef struct {
     int64_t *level_frontier;
     int64_t *level_edges;
     double *level_select_us;
+    /* out, rpq_multi_source: (edge, transition, non-zero 64-bit source word)
+       updates the stacked expansion made (always filled; 0 elsewhere). With
+       RPQ_COUNTERS the other work counters of a stacked call follow the
+       batched model: scans are (level, vertex, used symbol) triples with a
+       non-empty successor set of the union of the sources' frontier states
+       at the vertex, active = (level, vertex) pairs with a non-empty frontier
+       column, product_edges is summed over the sources, and alg_bytes =
+       sum over active (level, v) of 8 + 2 W(v) plus 8 per scan plus
+       (4 + W(v)) per scanned edge, plus B ceil(V/8), where W(v) is 4 bytes
+       per non-zero 32-bit word of v's frontier column (source b in word
+       b / 32 of each state's row). */
+    int64_t updates;
+    /* out, rpq_poll: host wall time from rpq_submit to the answer being
+       ready, in milliseconds (0 elsewhere). A served query shares its
+       launches with other queries, so it has no device time of its own and
+       device_ms is 0 for it. */
+    double latency_ms;
 } rpq_stats;
 
 /* Number of uint64 words of a reachable-vertex bitmap over V vertices. */
@@ -200,6 +219,33 @@ rpq_status rpq_single_source(rpq_graph *g, const rpq_nfa *n, int32_t source,
  */
 rpq_status rpq_single_destination(rpq_graph *g, const rpq_nfa *n, int32_t target, uint64_t *out_bitmap,
                                   uint32_t flags, rpq_stats *stats);
+
+/*
+ * Lengths of the shortest accepted walks from one source (the other semirings
+ * Sec. 6 names as future work: min over walk lengths instead of the Boolean
+ * OR). out_lengths receives num_vertices int32 (host memory, or device memory
+ * with RPQ_OUT_DEVICE): entry v is the least length n of a two-way walk from
+ * `source` to v whose word the NFA accepts, i.e. the least level n of Alg. 1
+ * with v holding a final state in M_n (min over final states q_f of the
+ * product-graph distance of (q_f, v); App. A: M_n holds exactly the pairs at
+ * distance n), or -1 when no such walk exists. Entry v is >= 0 exactly when
+ * rpq_single_source would set bit v. Other flags, stats and errors as
+ * rpq_single_source.
+ */
+rpq_status rpq_single_source_lengths(rpq_graph *g, const rpq_nfa *n, int32_t source, int32_t *out_lengths,
+                                     uint32_t flags, rpq_stats *stats);
+
+/*
+ * Reachability from a set of sources (Def. 2.6 allows a start set V_s): every
+ * vertex u such that a two-way walk from some s in V_s to u spells a word the
+ * NFA accepts, i.e. the union of the single-source answers. One traversal
+ * starting from M_0 = Q_S x V_s; sources (host memory, n_sources entries)
+ * may repeat. Level counts are those of that traversal (|M_n| = pairs at
+ * distance n from the nearest start pair). Output, flags and errors as
+ * rpq_single_source, plus RPQ_EINVAL for n_sources < 1.
+ */
+rpq_status rpq_source_set(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
+                          uint64_t *out_bitmap, uint32_t flags, rpq_stats *stats);
 
 /*
  * Many sources under one NFA, stacked into one traversal (the multiple-source

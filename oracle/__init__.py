@@ -49,6 +49,11 @@ def load_library(path: str):
     lib.og_ssr.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, ctypes.c_int32,
                            P, ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int32, P,
                            ctypes.c_int32]
+    if hasattr(lib, "og_ssr_from"):
+        lib.og_ssr_from.restype = ctypes.c_int32
+        lib.og_ssr_from.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, ctypes.c_int32,
+                                    P, ctypes.c_int32, P, ctypes.c_int32, P, P, P, ctypes.c_int32, P,
+                                    ctypes.c_int32]
     return lib
 
 
@@ -72,9 +77,24 @@ class Result:
     alg_bytes: int
     active: int
     dist: Optional[np.ndarray] = None  # (Q, V) int32
+    final: Optional[np.ndarray] = None  # the NFA's final states
 
     def vertices(self) -> np.ndarray:
         return bitmap_to_vertices(self.bitmap)
+
+    def lengths(self) -> np.ndarray:
+        """Per vertex, the length of the shortest accepted walk: the least
+        distance of a final state at the vertex, -1 where none (needs the
+        distances, keep_dist=True)."""
+        if self.dist is None:
+            raise ValueError("lengths need keep_dist=True")
+        V = self.dist.shape[1]
+        if self.final is None or len(self.final) == 0:
+            return np.full(V, -1, np.int32)
+        d = self.dist[np.asarray(self.final, dtype=np.int64)].astype(np.int64)
+        d[d < 0] = np.iinfo(np.int64).max
+        m = d.min(axis=0)
+        return np.where(m == np.iinfo(np.int64).max, -1, m).astype(np.int32)
 
 
 def bitmap_to_vertices(bm: np.ndarray) -> np.ndarray:
@@ -109,6 +129,14 @@ class Graph:
         return int(self._lib.og_num_edges(self._h, int(inverse)))
 
     def ssr(self, nfa, source: int, keep_dist: bool = False, level_cap: int = 1 << 16) -> Result:
+        return self._run(nfa, [int(source)], keep_dist, level_cap, single=True)
+
+    def ssr_set(self, nfa, sources, keep_dist: bool = False, level_cap: int = 1 << 16) -> Result:
+        """The query from the start set V_s = sources (Def. 2.6): one search
+        from every pair of Q_S x V_s."""
+        return self._run(nfa, [int(s) for s in sources], keep_dist, level_cap, single=False)
+
+    def _run(self, nfa, sources, keep_dist, level_cap, single) -> Result:
         lib = self._lib
         V = self.num_vertices
         Q = int(nfa.num_states)
@@ -121,13 +149,19 @@ class Graph:
         to = np.ascontiguousarray(nfa.to, dtype=np.int32)
         st = np.ascontiguousarray(nfa.start, dtype=np.int32)
         fi = np.ascontiguousarray(nfa.final, dtype=np.int32)
-        n = lib.og_ssr(self._h, Q, int(nfa.num_labels), _ptr(sp), _ptr(fr), _ptr(to), _ptr(st),
-                       int(st.size), _ptr(fi), int(fi.size), int(source), _ptr(bm), _ptr(dist),
-                       _ptr(lc), level_cap, _ptr(ctr), word_bytes(Q))
+        if single:
+            n = lib.og_ssr(self._h, Q, int(nfa.num_labels), _ptr(sp), _ptr(fr), _ptr(to), _ptr(st),
+                           int(st.size), _ptr(fi), int(fi.size), sources[0], _ptr(bm), _ptr(dist),
+                           _ptr(lc), level_cap, _ptr(ctr), word_bytes(Q))
+        else:
+            srcs = np.ascontiguousarray(sources, dtype=np.int32)
+            n = lib.og_ssr_from(self._h, Q, int(nfa.num_labels), _ptr(sp), _ptr(fr), _ptr(to), _ptr(st),
+                                int(st.size), _ptr(fi), int(fi.size), _ptr(srcs), int(srcs.size), _ptr(bm),
+                                _ptr(dist), _ptr(lc), level_cap, _ptr(ctr), word_bytes(Q))
         if n < 0:
             raise ValueError("oracle rejected the query")
         return Result(bm, int(n), lc[:min(max(n, 0), level_cap)].copy(), int(ctr[0]), int(ctr[1]),
-                      int(ctr[2]), int(ctr[3]), int(ctr[4]), dist)
+                      int(ctr[2]), int(ctr[3]), int(ctr[4]), dist, fi.copy())
 
 
 def ssr(g, nfa, source: int, keep_dist: bool = False, lib=None) -> Result:

@@ -27,6 +27,10 @@
  *  - NFA symbols whose label the graph does not have contribute nothing
  *    (the intersection of alphabets in Alg. 1's update);
  *  - at most 64 NFA states (the work counters use 64-bit state sets).
+ *
+ * Besides the answer it returns dist (the product-graph distance of every
+ * (state, vertex) pair), from which the shortest accepted walk to v is the
+ * least dist over the final states at v.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -141,7 +145,10 @@ int64_t og_num_edges(const og_graph *g, int inv) {
 }
 
 /*
- * One single-source query.
+ * One query from the start set V_s = sources[0..nsources) (Def. 2.6; a
+ * single-source query has V_s = {source}): the search starts from every pair
+ * of Q_S x V_s at distance 0, so dist is the distance from the nearest start
+ * pair and the answer is the union of the sources' single-source answers.
  *   NFA: nq states; symbols s < nfa_nl are labels, s >= nfa_nl inverse labels
  *        of s - nfa_nl; transitions of symbol s are
  *        (tfrom[i] -> tto[i]), i in [sym_ptr[s], sym_ptr[s+1]).
@@ -159,13 +166,14 @@ int64_t og_num_edges(const og_graph *g, int inv) {
  * Returns the number of levels (max distance + 1), or -1 on invalid input
  * or allocation failure.
  */
-int32_t og_ssr(const og_graph *g, int32_t nq, int32_t nfa_nl, const int64_t *sym_ptr,
-               const int32_t *tfrom, const int32_t *tto, const int32_t *start, int32_t nstart,
-               const int32_t *fin, int32_t nfin, int32_t source, uint64_t *bitmap,
-               int32_t *dist_out, int64_t *level_counts, int32_t level_cap, int64_t *counters,
-               int32_t word_bytes) {
-    if (!g || nq < 1 || nq > 64 || nfa_nl < 0 || !sym_ptr || source < 0 || source >= g->nv)
-        return -1;
+int32_t og_ssr_from(const og_graph *g, int32_t nq, int32_t nfa_nl, const int64_t *sym_ptr,
+                    const int32_t *tfrom, const int32_t *tto, const int32_t *start, int32_t nstart,
+                    const int32_t *fin, int32_t nfin, const int32_t *sources, int32_t nsources,
+                    uint64_t *bitmap, int32_t *dist_out, int64_t *level_counts, int32_t level_cap,
+                    int64_t *counters, int32_t word_bytes) {
+    if (!g || nq < 1 || nq > 64 || nfa_nl < 0 || !sym_ptr || !sources || nsources < 1) return -1;
+    for (int32_t i = 0; i < nsources; i++)
+        if (sources[i] < 0 || sources[i] >= g->nv) return -1;
     const int32_t nv = g->nv;
     const int32_t nsym = 2 * nfa_nl;
     const int64_t nt = sym_ptr[nsym];
@@ -201,10 +209,13 @@ int32_t og_ssr(const og_graph *g, int32_t nq, int32_t nfa_nl, const int64_t *sym
 
     for (int64_t i = 0; i < cells; i++) dist[i] = -1;
     int64_t head = 0, tail = 0;
-    for (int32_t i = 0; i < nstart; i++) {
-        int64_t c = (int64_t)start[i] * nv + source;
-        if (dist[c] < 0) { dist[c] = 0; fifo[tail++] = c; }
-    }
+    /* the start pairs Q_S x V_s at distance 0 (V_s = {source} for a
+       single-source query; a repeated pair is queued once) */
+    for (int32_t k = 0; k < nsources; k++)
+        for (int32_t i = 0; i < nstart; i++) {
+            int64_t c = (int64_t)start[i] * nv + sources[k];
+            if (dist[c] < 0) { dist[c] = 0; fifo[tail++] = c; }
+        }
     int32_t maxd = tail > 0 ? 0 : -1;
     while (head < tail) {
         int64_t c = fifo[head++];
@@ -305,4 +316,14 @@ int32_t og_ssr(const og_graph *g, int32_t nq, int32_t nfa_nl, const int64_t *sym
     free(toff); free(tsym); free(ttgt);
     if (!dist_out) free(dist);
     return nlev;
+}
+
+/* The single-source query: og_ssr_from with V_s = {source}. */
+int32_t og_ssr(const og_graph *g, int32_t nq, int32_t nfa_nl, const int64_t *sym_ptr,
+               const int32_t *tfrom, const int32_t *tto, const int32_t *start, int32_t nstart,
+               const int32_t *fin, int32_t nfin, int32_t source, uint64_t *bitmap,
+               int32_t *dist_out, int64_t *level_counts, int32_t level_cap, int64_t *counters,
+               int32_t word_bytes) {
+    return og_ssr_from(g, nq, nfa_nl, sym_ptr, tfrom, tto, start, nstart, fin, nfin, &source, 1, bitmap,
+                       dist_out, level_counts, level_cap, counters, word_bytes);
 }

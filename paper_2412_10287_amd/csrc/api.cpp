@@ -223,6 +223,7 @@ static void destroy(rpq_graph *g) {
         if (e) (void)hipEventDestroy(e);
     if (g->pinned) (void)hipHostFree(g->pinned);
     if (g->hstat) (void)hipHostFree(g->hstat);
+    if (g->pin_srcset) (void)hipHostFree(g->pin_srcset);
     for (void *p : g->allocs) (void)hipFree(p);
     batch_free(g);
     delete g;
@@ -464,7 +465,7 @@ rpq_status rpq_get_option(const rpq_graph *g, const char *key, int64_t *value) {
 static int word_width(int32_t Q) { return Q <= 8 ? 1 : Q <= 16 ? 2 : 4; }
 
 rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint64_t *out, uint32_t flags,
-                           rpq_stats *stats) {
+                           rpq_stats *stats, const SingleExtra *ex) {
     hipStream_t s = g->user_stream ? g->user_stream : g->stream;
     const int W = word_width(n->Q);
     if (g->dirty) {
@@ -529,6 +530,20 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
     }
     p.st.out = (flags & RPQ_OUT_DEVICE) ? out : g->dev_out;
     p.source = source;
+    p.nsrc = 0;
+    p.srcset = nullptr;
+    p.dist = nullptr;
+    if (ex) {
+        p.dist = ex->dist;
+        if (ex->nsrc > 0) {
+            // the start set's vertices go up on this stream before the launch
+            // (the staging buffer is not written again before the call ends)
+            HIP_TRY(hipMemcpyAsync(g->dev_srcset, g->pin_srcset, 4 * static_cast<size_t>(ex->nsrc),
+                                   hipMemcpyHostToDevice, s));
+            p.nsrc = static_cast<uint32_t>(ex->nsrc);
+            p.srcset = g->dev_srcset;
+        }
+    }
     const bool timing = (flags & RPQ_KERNEL_TIMING) != 0;
     int grid_p = g->pgrid[W];
     if (g->plain_grid) grid_p = std::min(g->plain_grid, grid_p);
@@ -695,4 +710,63 @@ rpq_status rpq_single_destination(rpq_graph *g, const rpq_nfa *n, int32_t target
     std::lock_guard<std::recursive_mutex> lk(g->mu);
     HIP_TRY(hipSetDevice(g->device));
     return run_single(g, &rev, target, out_bitmap, flags, stats);
+}
+
+// Lengths of the shortest accepted walks (the future-work semirings of Sec. 6,
+// min over walk lengths in place of the Boolean OR): the same traversal, with
+// each vertex's first level that reaches it in a final state recorded by the
+// select (by the FIFO-level invariant of App. A that level is the length).
+rpq_status rpq_single_source_lengths(rpq_graph *g, const rpq_nfa *n, int32_t source, int32_t *out_lengths,
+                                     uint32_t flags, rpq_stats *stats) {
+    if (!g || !n || !out_lengths) return fail(RPQ_EINVAL, "rpq_single_source_lengths: NULL argument");
+    if (source < 0 || source >= g->V)
+        return fail(RPQ_EINVAL, "rpq_single_source_lengths: source %d outside [0, %d)", source, g->V);
+    if ((flags & RPQ_FORCE_PUSH) && (flags & RPQ_FORCE_PULL))
+        return fail(RPQ_EINVAL, "rpq_single_source_lengths: RPQ_FORCE_PUSH and RPQ_FORCE_PULL together");
+    std::lock_guard<std::recursive_mutex> lk(g->mu);
+    HIP_TRY(hipSetDevice(g->device));
+    const bool dev = (flags & RPQ_OUT_DEVICE) != 0;
+    if (!dev && !g->dev_dist) {
+        const rpq_status st = dev_alloc(g, reinterpret_cast<void **>(&g->dev_dist), 4 * static_cast<size_t>(g->V), "lengths");
+        if (st != RPQ_OK) return st;
+    }
+    SingleExtra ex;
+    ex.dist = dev ? out_lengths : g->dev_dist;
+    const rpq_status r = run_single(g, n, source, g->dev_out, flags | RPQ_OUT_DEVICE, stats, &ex);
+    if (r != RPQ_OK) return r;
+    if (!dev) {
+        hipStream_t s = g->user_stream ? g->user_stream : g->stream;
+        HIP_TRY(hipMemcpyAsync(out_lengths, g->dev_dist, 4 * static_cast<size_t>(g->V), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    return RPQ_OK;
+}
+
+// Reachability from a set of sources (Def. 2.6 with a start set V_s): the
+// traversal starts from M_0 = Q_S x V_s, and F P is the union of the sources'
+// single-source answers.
+rpq_status rpq_source_set(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
+                          uint64_t *out_bitmap, uint32_t flags, rpq_stats *stats) {
+    if (!g || !n || !sources || !out_bitmap) return fail(RPQ_EINVAL, "rpq_source_set: NULL argument");
+    if (n_sources < 1) return fail(RPQ_EINVAL, "rpq_source_set: n_sources < 1");
+    for (int32_t i = 0; i < n_sources; i++)
+        if (sources[i] < 0 || sources[i] >= g->V)
+            return fail(RPQ_EINVAL, "rpq_source_set: source %d outside [0, %d)", sources[i], g->V);
+    if ((flags & RPQ_FORCE_PUSH) && (flags & RPQ_FORCE_PULL))
+        return fail(RPQ_EINVAL, "rpq_source_set: RPQ_FORCE_PUSH and RPQ_FORCE_PULL together");
+    // distinct vertices: the level-0 queue holds each start vertex once
+    std::vector<int32_t> vs(sources, sources + n_sources);
+    std::sort(vs.begin(), vs.end());
+    vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
+    std::lock_guard<std::recursive_mutex> lk(g->mu);
+    HIP_TRY(hipSetDevice(g->device));
+    if (!g->dev_srcset) {
+        const rpq_status st = dev_alloc(g, reinterpret_cast<void **>(&g->dev_srcset), 4 * static_cast<size_t>(g->V), "start set");
+        if (st != RPQ_OK) return st;
+    }
+    if (!g->pin_srcset) HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&g->pin_srcset), 4 * static_cast<size_t>(g->V), hipHostMallocDefault));
+    memcpy(g->pin_srcset, vs.data(), 4 * vs.size());
+    SingleExtra ex;
+    ex.nsrc = static_cast<int32_t>(vs.size());
+    return run_single(g, n, vs[0], out_bitmap, flags, stats, &ex);
 }

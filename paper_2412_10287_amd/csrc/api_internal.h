@@ -51,6 +51,9 @@ struct rpq_graph {
     int64_t device_bytes = 0;
     int64_t nwords = 0;
     uint64_t *dev_out = nullptr;
+    int32_t *dev_dist = nullptr;    // V lengths for rpq_single_source_lengths with host output (lazy)
+    int32_t *dev_srcset = nullptr;  // a start set's distinct vertices for rpq_source_set (lazy, V entries)
+    int32_t *pin_srcset = nullptr;  // pinned staging of the same (lazy, V entries)
     uint8_t *qconst_dev = nullptr;
     size_t qconst_cap = 0;
     uint8_t *pinned = nullptr;
@@ -113,8 +116,15 @@ size_t build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, uint32
                     std::vector<uint8_t> &buf, int32_t *nsym_out);
 QueryView query_view(uint8_t *base, int32_t nsym);
 rpq_status graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32_t *src, const int32_t *dst);
+// Optional parts of a single-query call: a start set instead of one source
+// (nsrc distinct vertices, already in g->pin_srcset) and the shortest-length
+// output (V int32, device memory).
+struct SingleExtra {
+    int32_t nsrc = 0;
+    int32_t *dist = nullptr;
+};
 rpq_status run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint64_t *out, uint32_t flags,
-                      rpq_stats *stats);
+                      rpq_stats *stats, const SingleExtra *ex = nullptr);
 void serve_shutdown(rpq_graph *g);
 bool serve_pending(rpq_graph *g);
 void batch_free(rpq_graph *g);

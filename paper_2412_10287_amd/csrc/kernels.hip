@@ -101,23 +101,44 @@ struct SoloLds {
 };
 
 // ---------------------------------------------------------------- phases
+// Run by every thread of workgroup 0 (the caller orders its stores before
+// level 0 reads them).
 template <int W>
 __device__ __forceinline__ void init_phase(const Params &p) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    if (blockIdx.x != 0) return;
     const QHeader &h = *s_qv.h;
     LevelRec *r = p.st.rec;
-    // records are cleared two levels ahead (select_phase): levels 0 and 1 here
-    rec_clear(r[0]);
-    rec_clear(r[1]);
     const uint32_t sm = h.smask;
-    if (sm) {
-        // M_0 = Q_S x {source}, as a candidate that level 0's select adds to P
-        st_state<W>(p.st.M[0], p.source, sm);
-        p.st.q[0][0] = p.source;
-        r[0].nq = 1;
+    if (threadIdx.x == 0) {
+        // records are cleared two levels ahead (select_phase): levels 0 and 1 here
+        rec_clear(r[0]);
+        rec_clear(r[1]);
+        for (int i = 0; i < 4; i++) p.st.cnt[i] = 0;
+        for (int i = 0; i < 4; i++) p.st.status[i] = 0;
     }
-    for (int i = 0; i < 4; i++) p.st.cnt[i] = 0;
-    for (int i = 0; i < 4; i++) p.st.status[i] = 0;
+    if (!sm) return;
+    // M_0 = Q_S x V_s (V_s = {source}, or the distinct vertices of a source
+    // set), as candidates that level 0's select adds to P
+    if (p.nsrc == 0) {
+        if (threadIdx.x == 0) {
+            st_state<W>(p.st.M[0], p.source, sm);
+            p.st.q[0][0] = p.source;
+            r[0].nq = 1;
+        }
+        return;
+    }
+    const uint32_t V = static_cast<uint32_t>(p.g.V);
+    for (uint32_t i = threadIdx.x; i < p.nsrc; i += blockDim.x) {
+        const uint32_t v = static_cast<uint32_t>(p.srcset[i]);
+        if (v < V) {
+            st_state<W>(p.st.M[0], v, sm);
+            p.st.q[0][i] = static_cast<int32_t>(v);
+        } else {
+            flag_violation(p);
+            p.st.q[0][i] = 0;
+        }
+    }
+    if (threadIdx.x == 0) r[0].nq = p.nsrc;
 }
 
 // Zeroes the state words that level k's queue entries point to in M[k & 1]
@@ -288,6 +309,9 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
                 const uint32_t pv = ld_state<W>(P, v);
                 S = c & ~pv;
                 if (S) st_state<W>(P, v, pv | S);
+                // shortest accepted walk: the first level at which v holds a
+                // final state (levels only grow, so the first is the least)
+                if (p.dist && (S & h.fmask) && !(pv & h.fmask)) p.dist[v] = static_cast<int32_t>(n);
                 if constexpr (FUSED) {
                     if (c) st_state<W>(Mc, v, 0u);
                 } else if (S != c) {
@@ -327,11 +351,12 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
                     if (sp[j]) rw[j] = g.rankw[qv.push_w[us[j]] + (v >> 6)];
                 }
             }
-            uint32_t cnt = 0, tot = 0;
+            uint32_t cnt = 0, tot = 0, nscan = 0;
 #pragma unroll
             for (int j = 0; j < SYM_BATCH; j++) {
                 len[j] = 0;
                 uint32_t e;
+                nscan += sp[j] != 0;
                 if (sp[j] && row_range(g, rw[j], qv.push_r[us[j]], v, beg[j], e)) {
                     if (e > beg[j] && e <= g.ncol) len[j] = e - beg[j];
                     else if (e != beg[j]) flag_violation(p);
@@ -343,7 +368,9 @@ __device__ __forceinline__ void select_phase(const Params &p, uint32_t n, uint32
                 }
             }
             if (h.counters) {
-                c_sc += cnt;
+                // a scan is charged its row-pointer lookup whether or not the
+                // row exists
+                c_sc += nscan;
                 c_sd += tot;
             }
             uint64_t wtot;
@@ -818,6 +845,9 @@ __device__ __forceinline__ void final_phase(const Params &p, uint32_t nlev, bool
             if (k < nwords) {
                 if (lane == 0) p.st.out[k] = b;
                 if (pv[j]) st_state<W>(p.st.P, k * 64 + lane, 0);
+                // no accepted walk reaches v: its length is -1 (the others
+                // were written by the select of their first final level)
+                if (p.dist && !(pv[j] & fm) && k * 64 + lane < V) p.dist[k * 64 + lane] = -1;
             }
         }
     }
@@ -926,8 +956,9 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Params p) {
     // being dispatched and registering; the others wait at the first barrier.
     if (blockIdx.x == 0) {
         init_phase<W>(p);
-        solo_sync();  // level 0's queue and word are in memory before the run reads them
-        solo_levels<W>(p, 0, s_qv.h->smask ? 1u : 0u, s_eb, s_beg, s_mask, npush, tpairs);
+        solo_sync();  // level 0's queue and words are in memory before the run reads them
+        const uint32_t nq0 = s_qv.h->smask ? (p.nsrc ? p.nsrc : 1u) : 0u;
+        solo_levels<W>(p, 0, nq0, s_eb, s_beg, s_mask, npush, tpairs);
     }
     BarCtx bc;
     if (!barrier_wait_register(bar, bc)) return leave_aborted(p);

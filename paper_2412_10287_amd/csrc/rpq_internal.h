@@ -209,6 +209,9 @@ struct Params {
     QueryView qv;
     StateView st;
     int32_t source;
+    uint32_t nsrc;          // 0: one source (`source`); else the start set srcset[0..nsrc), distinct vertices
+    const int32_t *srcset;  // device
+    int32_t *dist;          // null, or V lengths of the shortest accepted walks (device; -1 = none)
 };
 
 // Launchers (kernels.hip). W is the state-word width in bytes: 1, 2 or 4.

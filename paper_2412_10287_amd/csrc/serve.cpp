@@ -364,7 +364,7 @@ static rpq_status retire(rpq_graph *g, ServeState *ss) {
             t.stats.levels = static_cast<int32_t>(si.levels);
             t.stats.push_levels = t.stats.levels;
             t.stats.visited_pairs = static_cast<int64_t>(si.pairs);
-            t.stats.device_ms = std::chrono::duration<double, std::milli>(now - si.submitted).count();
+            t.stats.latency_ms = std::chrono::duration<double, std::milli>(now - si.submitted).count();
             t.stats.batch = static_cast<int32_t>(ss->slots - ss->free_slots.size());
             t.status = RPQ_OK;
             t.state = 2;
@@ -435,7 +435,7 @@ static rpq_status run_group(rpq_graph *g, ServeState *ss, std::vector<Request> &
             t.stats.push_levels = stt.push_levels;
             t.stats.pull_levels = stt.pull_levels;
             t.stats.visited_pairs = stt.visited_pairs;
-            t.stats.device_ms = std::chrono::duration<double, std::milli>(now - grp[i].submitted).count();
+            t.stats.latency_ms = std::chrono::duration<double, std::milli>(now - grp[i].submitted).count();
             t.stats.batch = B;
             t.status = RPQ_OK;
             t.state = 2;
@@ -487,7 +487,8 @@ static void run_one(rpq_graph *g, ServeState *ss, Request &r) {
             t.stats.pull_levels = st.pull_levels;
             t.stats.visited_pairs = st.visited_pairs;
             t.stats.batch = 1;
-            t.stats.device_ms = std::chrono::duration<double, std::milli>(now - r.submitted).count();
+            t.stats.device_ms = st.device_ms;  // the query ran alone in its own launch
+            t.stats.latency_ms = std::chrono::duration<double, std::milli>(now - r.submitted).count();
         } else {
             t.error = err;
             if (entry != ~0u) ss->free_entries.push_back(entry);

@@ -14,6 +14,18 @@ namespace rpq {
 // q[n&1]. Level n's select then masks every candidate row by P, adds the new
 // bits to P, and leaves in M[n&1][w] the frontier rows M_n and in sup[n&1][w]
 // the frontier's state set (0 when every candidate bit was already visited).
+// Work counters of one launch (p.cnt), filled when the query constants ask
+// for counters; word updates are always counted.
+enum {
+    ST_CNT_SCANS = 0,   // (level, vertex, used symbol) with a non-empty successor set of the union state set
+    ST_CNT_EDGES = 1,   // neighbours of those scans
+    ST_CNT_UPDATES = 2, // (edge, transition, non-zero 64-bit source word) updates
+    ST_CNT_ACTIVE = 3,  // (level, vertex) with a non-empty frontier column
+    ST_CNT_WBYTES = 4,  // sum over active (level, v) of W(v) * (2 + neighbours scanned at v)
+    ST_CNT_PE = 5,      // product edges summed over the sources
+    ST_NCNT = 6
+};
+
 struct StackParams {
     GraphView g;
     QueryView qv;
@@ -28,7 +40,7 @@ struct StackParams {
     LevelRec *rec;
     GridBarrier *bar;
     uint32_t *status;        // [0] levels, [1] push levels, [2] pull levels, [3] invariant violations
-    uint64_t *cnt;           // [0] items, [1] scanned edges, [2] word updates, [3] active vertices
+    uint64_t *cnt;           // ST_NCNT work counters (ST_CNT_*), summed over the launch
     uint64_t *lvl;           // per-level statistics (LVL_STRIDE words), pairs summed over sources
     uint64_t *out;           // B bitmaps of nwords words
     const int32_t *sources;  // B vertex ids

@@ -95,6 +95,13 @@ __device__ __forceinline__ uint32_t group_or(uint32_t x) {
 }
 
 template <int G>
+__device__ __forceinline__ uint32_t group_sum(uint32_t x) {
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) x += static_cast<uint32_t>(__shfl_xor(static_cast<int>(x), d, 64));
+    return x;
+}
+
+template <int G>
 __device__ __forceinline__ uint64_t group_or64(uint64_t x) {
 #pragma unroll
     for (int d = 1; d < G; d <<= 1) x |= __shfl_xor(x, d, 64);
@@ -176,8 +183,9 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
     uint64_t *Mc = p.M[n & 1];
     uint32_t *sc = p.sup[n & 1];
     const uint32_t nsym = qv.h->nsym;
-    uint64_t pairs = 0, upd = 0, c_items = 0, c_edges = 0;
+    uint64_t pairs = 0, upd = 0, c_scans = 0, c_edges = 0, c_wb = 0, c_pe = 0;
     uint32_t nfront = 0, su = 0;
+    const bool counters = qv.h->counters != 0;
     // workgroup-uniform loop: item reservations are made per workgroup
     for (uint32_t bbase = bid * GPB; bbase < nq; bbase += nblk * GPB) {
         const uint32_t i = bbase + threadIdx.x / G;
@@ -195,9 +203,11 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
         }
         // mask the candidate rows by P (Alg. 1's complement mask), add the new
         // bits to P; rows that gained nothing are cleared
-        uint32_t S = 0, nzm = 0;
+        uint32_t S = 0, nzm = 0, halves = 0;
+        uint32_t pk[QM];  // new source bits per state in this lane's word (counters only)
 #pragma unroll
         for (int k = 0; k < QM; k++) {
+            pk[k] = 0;
             if ((cs >> k) & 1u) {
                 const uint64_t idx = rowi<G>(p, w, k) + j;
                 const uint64_t c = ldc(&Mc[idx]);
@@ -206,12 +216,24 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
                 if (nb) {
                     p.P[idx] = pv | nb;
                     nzm |= 1u << k;
-                    pairs += __popcll(nb);
+                    pk[k] = static_cast<uint32_t>(__popcll(nb));
+                    pairs += pk[k];
+                    halves += (static_cast<uint32_t>(nb) != 0u) + (static_cast<uint32_t>(nb >> 32) != 0u);
                 }
                 if (nb != c) Mc[idx] = nb;
             }
         }
         S = group_or<G>(nzm);
+        // work counters: W = 4 bytes per non-zero 32-bit word of the vertex's
+        // frontier column (all states, all sources), and the frontier's pairs
+        // per state over the group's words (for the product edges)
+        uint32_t Wv = 0;
+        if (counters) {
+            Wv = 4u * group_sum<G>(halves);
+#pragma unroll
+            for (int k = 0; k < QM; k++) pk[k] = group_sum<G>(pk[k]);
+            if (j == 0) c_wb += 2ull * Wv;
+        }
         if (ok && j == 0) {
             sc[w] = S;
             if (S) nfront++;
@@ -256,18 +278,31 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
                 const uint32_t u = us[jj];
                 len[jj] = 0;
                 uint32_t e;
+                c_scans += tu[jj] != 0u;
                 if (tu[jj] && row_range(g, rw[jj], qv.push_r[u], w, beg[jj], e)) {
                     if (e > beg[jj] && e <= g.ncol) len[jj] = e - beg[jj];
                     else if (e != beg[jj]) sviol(p);
                 }
                 if (len[jj]) {
-                    // (edge, transition, word) updates this item carries
+                    // (edge, transition, word) updates this item carries and,
+                    // with the counters, its product edges: |succ_u(q)| per
+                    // pair (q, source) of the frontier, per edge
                     const uint32_t *su_tab = qv.succ + u * MAX_STATES;
                     uint32_t c = 0;
+                    uint64_t pe = 0;
 #pragma unroll
-                    for (int k = 0; k < QM; k++)
-                        if ((S >> k) & 1u) c += static_cast<uint32_t>(__popc(su_tab[k])) * nzc[k];
+                    for (int k = 0; k < QM; k++) {
+                        if ((S >> k) & 1u) {
+                            const uint32_t ns = static_cast<uint32_t>(__popc(su_tab[k]));
+                            c += ns * nzc[k];
+                            pe += static_cast<uint64_t>(ns) * pk[k];
+                        }
+                    }
                     upd += static_cast<uint64_t>(c) * len[jj];
+                    if (counters) {
+                        c_pe += pe * len[jj];
+                        c_wb += static_cast<uint64_t>(Wv) * len[jj];
+                    }
                     cnt++;
                     tot += len[jj];
                 }
@@ -280,7 +315,6 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
                 const uint64_t mine = wbase + ex;
                 uint32_t idx = static_cast<uint32_t>(mine >> 32);
                 uint32_t eb = static_cast<uint32_t>(mine);
-                c_items += cnt;
                 c_edges += tot;
 #pragma unroll
                 for (int jj = 0; jj < SYM_BATCH; jj++) {
@@ -295,21 +329,21 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
     }
     // level totals and work counters: one atomic per workgroup and field
     const uint64_t nf = wave_sum(nfront);
-    const uint64_t v[7] = {wave_sum(pairs), nf, wave_or(su), wave_sum(c_items), wave_sum(c_edges), wave_sum(upd), nf};
-    const uint64_t t = block_reduce<7>(v, 4u);
+    const uint64_t v[3 + ST_NCNT] = {wave_sum(pairs),  nf,           wave_or(su),       wave_sum(c_scans),
+                                     wave_sum(c_edges), wave_sum(upd), nf,               wave_sum(c_wb),
+                                     wave_sum(c_pe)};
+    const uint64_t t = block_reduce<3 + ST_NCNT>(v, 4u);
     if (t) {
         switch (threadIdx.x) {
             case 0: atomicAdd(reinterpret_cast<unsigned long long *>(&R.pairs), (unsigned long long)t); break;
             case 1: atomicAdd(&R.nfront, static_cast<uint32_t>(t)); break;
             case 2: atomicOr(&R.su, static_cast<uint32_t>(t)); break;
-            // work counters: kept by threads 3..6 over the whole launch and
-            // added to p.cnt once at its end (one line for all four: per
+            // work counters: kept by threads 3..8 over the whole launch and
+            // added to p.cnt once at its end (one line for all of them: per
             // level, the grid's atomics on it would queue for ~12 us)
-            case 3:
-            case 4:
-            case 5:
-            case 6: cacc += t; break;
-            default: break;
+            default:
+                if (threadIdx.x < 3 + ST_NCNT) cacc += t;
+                break;
         }
     }
 }
@@ -884,7 +918,7 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         rec_clear(p.rec[0]);
         for (int i = 0; i < 4; i++) p.status[i] = 0;
-        for (int i = 0; i < 4; i++) p.cnt[i] = 0;
+        for (int i = 0; i < ST_NCNT; i++) p.cnt[i] = 0;
     }
     if (!grid_barrier(bar, bc)) return;
     // start pairs M_0 = Q_S x {source}: every source's bit in its start rows,
@@ -967,8 +1001,8 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
         prev = mode;
         n++;
     }
-    // this workgroup's share of the work counters (threads 3..6)
-    if (threadIdx.x >= 3 && threadIdx.x < 7 && cacc)
+    // this workgroup's share of the work counters (threads 3..8)
+    if (threadIdx.x >= 3 && threadIdx.x < 3 + ST_NCNT && cacc)
         atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[threadIdx.x - 3]), static_cast<unsigned long long>(cacc));
     // the last level may have found only visited pairs
     const uint32_t levels = (n > 0 && last_pairs == 0) ? n - 1 : n;

@@ -122,7 +122,7 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
     if ((flags & RPQ_FORCE_PUSH) && (flags & RPQ_FORCE_PULL))
         return fail(RPQ_EINVAL, "rpq_multi_source: RPQ_FORCE_PUSH and RPQ_FORCE_PULL together");
     const uint32_t force = (flags & RPQ_FORCE_PUSH) ? 1u : (flags & RPQ_FORCE_PULL) ? 2u : 0u;
-    const size_t qsz = build_qconst(g, n, force, 0u, qbuf, &nsym);
+    const size_t qsz = build_qconst(g, n, force, (flags & RPQ_COUNTERS) ? 1u : 0u, qbuf, &nsym);
     if (nsym > MAX_SYMS || qsz > g->qconst_cap)
         return fail(RPQ_EINVAL, "rpq_multi_source: query uses %d symbols; the limit is %d", nsym, MAX_SYMS);
     {
@@ -136,7 +136,7 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
     const int QM = n->Q <= 8 ? 8 : 32;
     int32_t push_levels = 0, pull_levels = 0;
     int32_t levels = 0;
-    int64_t pairs = 0, items = 0, edges = 0, updates = 0, active = 0, bytes = 0;
+    int64_t pairs = 0, scans = 0, edges = 0, updates = 0, active = 0, bytes = 0, pedges = 0;
     float total_ms = 0.f;
     std::vector<uint64_t> lvl_host;
     uint32_t lvl_nrec = 0, lvl_levels = 0;
@@ -171,7 +171,7 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         uint32_t *hst = reinterpret_cast<uint32_t *>(bs->pinned + bs->qconst_cap + 4 * 1024);
         uint64_t *hcnt = reinterpret_cast<uint64_t *>(bs->pinned + bs->qconst_cap + 4 * 1024 + 64);
         BT(hipMemcpyAsync(hst, p.status, 16, hipMemcpyDeviceToHost, s));
-        BT(hipMemcpyAsync(hcnt, p.cnt, 32, hipMemcpyDeviceToHost, s));
+        BT(hipMemcpyAsync(hcnt, p.cnt, 8 * ST_NCNT, hipMemcpyDeviceToHost, s));
         BT(hipMemcpyAsync(hst + 4, &p.bar->abort, 4, hipMemcpyDeviceToHost, s));
         if (!(flags & RPQ_OUT_DEVICE))
             BT(hipMemcpyAsync(out_bitmaps + static_cast<size_t>(b0) * g->nwords, bs->out,
@@ -197,17 +197,20 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         lvl_nrec = nrec;
         lvl_levels = hst[0];
         pairs += stats_levels(nullptr, lvl_host.data(), nrec, hst[0]);
-        // algorithmic bytes of the stacked traversal: 8 B of row pointers per
-        // item, 4 B per scanned edge, a read and a write of one 8-byte source
-        // word per (edge, transition, word) with a non-empty source word, the
-        // Q*G frontier words of every active vertex read and cleared, and the
-        // B result bitmaps
-        items += static_cast<int64_t>(hcnt[0]);
-        edges += static_cast<int64_t>(hcnt[1]);
-        updates += static_cast<int64_t>(hcnt[2]);
-        active += static_cast<int64_t>(hcnt[3]);
-        bytes += 8 * static_cast<int64_t>(hcnt[0]) + 4 * static_cast<int64_t>(hcnt[1]) +
-                 16 * static_cast<int64_t>(hcnt[2]) + 16 * static_cast<int64_t>(n->Q) * G * static_cast<int64_t>(hcnt[3]) +
+        // algorithmic bytes of the stacked traversal, levels in lockstep:
+        // per active (level, vertex) its queue entry read and written (8 B)
+        // and its frontier column read and written (2W, W = 4 B per non-zero
+        // 32-bit word of the column over all states and sources); per scan
+        // its row-pointer pair (8 B); per scanned edge its 4-byte index and
+        // the column's W bytes delivered to the neighbour; and the B result
+        // bitmaps
+        scans += static_cast<int64_t>(hcnt[ST_CNT_SCANS]);
+        edges += static_cast<int64_t>(hcnt[ST_CNT_EDGES]);
+        updates += static_cast<int64_t>(hcnt[ST_CNT_UPDATES]);
+        active += static_cast<int64_t>(hcnt[ST_CNT_ACTIVE]);
+        pedges += static_cast<int64_t>(hcnt[ST_CNT_PE]);
+        bytes += 8 * static_cast<int64_t>(hcnt[ST_CNT_ACTIVE]) + 8 * static_cast<int64_t>(hcnt[ST_CNT_SCANS]) +
+                 4 * static_cast<int64_t>(hcnt[ST_CNT_EDGES]) + static_cast<int64_t>(hcnt[ST_CNT_WBYTES]) +
                  static_cast<int64_t>(B) * ((static_cast<int64_t>(g->V) + 7) / 8);
     }
     if (stats) {
@@ -221,11 +224,14 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         stats->device_ms = total_ms;
         stats->expand_ms = total_ms;
         stats->expand_launches = (n_sources + maxb - 1) / maxb;
-        stats->scans = items;
-        stats->scanned_edges = edges;
-        stats->active = active;
-        stats->alg_bytes = bytes;
-        stats->product_edges = updates;  // (edge, transition, 64-source word) updates
+        stats->updates = updates;
+        if (flags & RPQ_COUNTERS) {
+            stats->scans = scans;
+            stats->scanned_edges = edges;
+            stats->active = active;
+            stats->alg_bytes = bytes;
+            stats->product_edges = pedges;
+        }
     }
     return RPQ_OK;
 }

@@ -30,7 +30,8 @@ OUT_DEVICE, COUNTERS, KERNEL_TIMING, FORCE_PUSH, FORCE_PULL, HOST_LOOP = 1, 2, 4
 
 EXPORTS = ("rpq_bitmap_words", "rpq_graph_load", "rpq_graph_free", "rpq_graph_info", "rpq_set_option",
            "rpq_get_option", "rpq_nfa_load", "rpq_nfa_free", "rpq_single_source", "rpq_single_destination",
-           "rpq_multi_source", "rpq_submit", "rpq_poll", "rpq_autotune", "rpq_last_error")
+           "rpq_single_source_lengths", "rpq_source_set", "rpq_multi_source", "rpq_submit", "rpq_poll",
+           "rpq_autotune", "rpq_last_error")
 
 TUNE_PLAIN, TUNE_STACKED = 0, 1
 
@@ -61,6 +62,8 @@ class rpq_stats(ctypes.Structure):
         ("level_frontier", ctypes.POINTER(ctypes.c_int64)),
         ("level_edges", ctypes.POINTER(ctypes.c_int64)),
         ("level_select_us", ctypes.POINTER(ctypes.c_double)),
+        ("updates", ctypes.c_int64),
+        ("latency_ms", ctypes.c_double),
     ]
 
 _LEVEL_FIELDS = ("level_counts", "level_cap", "level_us", "level_frontier", "level_edges", "level_select_us")
@@ -88,6 +91,8 @@ def load_library(path: str = LIB_PATH):
         "rpq_nfa_free": (ctypes.c_int, [P]),
         "rpq_single_source": (ctypes.c_int, [P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
         "rpq_single_destination": (ctypes.c_int, [P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
+        "rpq_single_source_lengths": (ctypes.c_int, [P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
+        "rpq_source_set": (ctypes.c_int, [P, P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
         "rpq_multi_source": (ctypes.c_int, [P, P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
         "rpq_submit": (ctypes.c_int, [P, P, i32, ctypes.POINTER(u64)]),
         "rpq_poll": (ctypes.c_int, [P, u64, P, u32, ctypes.POINTER(rpq_stats), i64]),
@@ -183,7 +188,7 @@ class Stats:
     """Statistics of one call: the fields of rpq_stats as attributes (levels,
     push_levels, pull_levels, visited_pairs, product_edges, scans,
     scanned_edges, alg_bytes, active, device_ms, expand_ms, expand_launches,
-    batch), read from the C struct when accessed, and the per-level arrays
+    batch, updates, latency_ms), read from the C struct when accessed, and the per-level arrays
     level_counts, level_us, level_frontier, level_edges, level_select_us
     (empty unless the call asked for them with level_cap)."""
 
@@ -312,6 +317,34 @@ class Graph:
         st, lc = _stats_struct(level_cap)
         bm = np.zeros(self.words, dtype=np.uint64)
         check(lib.rpq_single_destination(self.h, nfa.h, int(target), _p(bm), flags, ctypes.byref(st)))
+        return bm, Stats.from_c(st, lc)
+
+    def single_source_lengths(self, nfa: NFA, source: int, flags: int = 0, level_cap: int = 0,
+                              out_device_ptr: Optional[int] = None):
+        """Shortest accepted walk length per vertex (-1 where none): (int32
+        array or None, Stats). With out_device_ptr the lengths go to that
+        device address (RPQ_OUT_DEVICE) and None is returned."""
+        st, lc = _stats_struct(level_cap)
+        if out_device_ptr is not None:
+            check(lib.rpq_single_source_lengths(self.h, nfa.h, int(source), ctypes.c_void_p(out_device_ptr),
+                                                flags | OUT_DEVICE, ctypes.byref(st)))
+            return None, Stats.from_c(st, lc)
+        d = np.empty(self.num_vertices, dtype=np.int32)
+        check(lib.rpq_single_source_lengths(self.h, nfa.h, int(source), _p(d), flags, ctypes.byref(st)))
+        return d, Stats.from_c(st, lc)
+
+    def source_set(self, nfa: NFA, sources: Sequence[int], flags: int = 0, level_cap: int = 0,
+                   out_device_ptr: Optional[int] = None):
+        """Vertices reached from any of `sources` (one traversal from
+        Q_S x sources): (bitmap or None, Stats)."""
+        src = np.ascontiguousarray(sources, dtype=np.int32)
+        st, lc = _stats_struct(level_cap)
+        if out_device_ptr is not None:
+            check(lib.rpq_source_set(self.h, nfa.h, _p(src), int(src.size), ctypes.c_void_p(out_device_ptr),
+                                     flags | OUT_DEVICE, ctypes.byref(st)))
+            return None, Stats.from_c(st, lc)
+        bm = np.zeros(self.words, dtype=np.uint64)
+        check(lib.rpq_source_set(self.h, nfa.h, _p(src), int(src.size), _p(bm), flags, ctypes.byref(st)))
         return bm, Stats.from_c(st, lc)
 
     def multi_source(self, nfa: NFA, sources: Sequence[int], flags: int = 0,

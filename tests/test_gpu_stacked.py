@@ -176,3 +176,37 @@ def test_repeat_and_device_output(rpq):
     for i, s in enumerate(srcs[:5]):
         gg.single_source(nfa, int(s), out_device_ptr=out.ptr + 8 * i * gg.words)
     assert np.array_equal(out.to_host().reshape(len(srcs), gg.words)[:5], first[:5])
+
+
+def test_batched_counters(rpq):
+    # the stacked call's work counters with RPQ_COUNTERS follow the batched
+    # model, recomputed here from each source's oracle distances: scans over
+    # the union of the sources' frontier states, scanned edges, active
+    # (level, vertex) pairs, algorithmic bytes (word-granular columns) and
+    # word updates; product edges are the oracle's summed over the sources
+    g = G.rmat(10, 8, 5, 1.1, 77)
+    gg = rpq.Graph(g)
+    og = oracle.Graph(g)
+    rng = np.random.default_rng(12)
+    texts = ["(0|^1)* 2 3*", "0 ^1 (2|4)*", "(0|1|2|3|4)+"]
+    nfas = [R.compile_regex(t, 5) for t in texts]
+    nfas.append(R.glushkov(R.random_ast(rng, 14, lambda r: r.integers(0, 5), 0.3), 5))  # > 8 states
+    for nfa in nfas:
+        for B, maxb in ((1, 1024), (40, 1024), (100, 1024), (300, 1024), (300, 128)):
+            # a call of more than max_batch sources runs in batches of
+            # max_batch, each its own lockstep pass; the counters add up
+            gg.set_option("max_batch", maxb)
+            srcs = [int(x) for x in rng.integers(0, g.num_vertices, size=B)]
+            res = [og.ssr(nfa, s, keep_dist=True) for s in srcs]
+            want = np.zeros(5, np.int64)
+            for b0 in range(0, B, maxb):
+                want += OC.stacked_counters(g, nfa, srcs[b0:b0 + maxb], [r.dist for r in res[b0:b0 + maxb]])
+            scans, scanned, active, byt, upd = (int(x) for x in want)
+            pe = sum(int(r.product_edges) for r in res)
+            for name, fl in STACK_MODES.items():
+                print(nfa.text, B, maxb, name, flush=True)
+                bms, st = gg.multi_source(rpq.NFA(nfa), srcs, flags=fl | rpq.COUNTERS)
+                for i, r in enumerate(res):
+                    assert np.array_equal(bms[i], r.bitmap), (nfa.text, B, name, i)
+                got = (st.scans, st.scanned_edges, st.active, st.alg_bytes, st.updates, st.product_edges)
+                assert got == (scans, scanned, active, byt, upd, pe), (nfa.text, B, maxb, name, got)

@@ -242,3 +242,70 @@ def test_input_edge_cases():
 
 def test_stacked_counters_explicit_product_graph():
     OC.check_stacked_counters_product(np.random.default_rng(53), n_cases=40)
+
+
+def test_lengths_brute_force():
+    # the shortest accepted walk per vertex (least distance of a final state
+    # at the vertex) equals the brute-force enumeration's shortest matching
+    # walk, which never builds an automaton
+    import brute
+    rng = np.random.default_rng(2024)
+    checked = 0
+    for _ in range(60):
+        g = OC.tiny_graph(rng)
+        text = OC.tiny_expr(rng, g.num_labels)
+        nfa = R.compile_regex(text, g.num_labels)
+        src = int(rng.integers(0, g.num_vertices))
+        r = oracle.ssr(g, nfa, src, keep_dist=True)
+        try:
+            best = brute.min_match_len(g, text, src, nfa.num_states * g.num_vertices - 1, max_pairs=300_000)
+        except RuntimeError:
+            continue
+        assert np.array_equal(r.lengths(), best), (text, src)
+        checked += 1
+    assert checked >= 30
+
+
+def test_lengths_grid_manhattan():
+    # (0|1)* on the grid without shortcuts: the shortest walk east/north from
+    # (x0, y0) to (x, y) has length (x - x0) + (y - y0); -1 outside the
+    # upper-right quadrant
+    side = 24
+    g = G.grid(side, 0.0, 0)
+    og = oracle.Graph(g)
+    nfa = R.compile_regex("(0|1)*", 4)
+    xs, ys = np.meshgrid(np.arange(side), np.arange(side))
+    for x0, y0 in ((0, 0), (5, 17), (23, 23), (11, 2)):
+        got = og.ssr(nfa, y0 * side + x0, keep_dist=True).lengths()
+        want = np.where((xs >= x0) & (ys >= y0), (xs - x0) + (ys - y0), -1).ravel()
+        assert np.array_equal(got, want), (x0, y0)
+
+
+def test_source_set_union_and_nearest_source():
+    # a query from a start set V_s (Def. 2.6): the answer is the union of the
+    # single-source answers, and a pair's distance is its least distance from
+    # any source (breadth-first search from a set); repeats change nothing
+    rng = np.random.default_rng(99)
+    cases = []
+    for _ in range(40):
+        g = OC.tiny_graph(rng)
+        cases.append((g, R.compile_regex(OC.tiny_expr(rng, g.num_labels), g.num_labels)))
+    w = C.er_workload(n=600, m=2400, num_labels=4, n_queries=6)
+    cases += [(w.graph, nfa) for nfa in w.nfas]
+    for g, nfa in cases:
+        og = oracle.Graph(g)
+        k = int(rng.integers(1, min(6, g.num_vertices) + 1))
+        srcs = [int(x) for x in rng.integers(0, g.num_vertices, size=k)]
+        srcs.append(srcs[0])
+        got = og.ssr_set(nfa, srcs, keep_dist=True)
+        ones = [og.ssr(nfa, s, keep_dist=True) for s in srcs]
+        bm = np.zeros_like(got.bitmap)
+        for r in ones:
+            bm |= r.bitmap
+        assert np.array_equal(got.bitmap, bm), nfa.text
+        big = np.iinfo(np.int64).max
+        d = np.stack([np.where(r.dist < 0, big, r.dist.astype(np.int64)) for r in ones]).min(axis=0)
+        d = np.where(d == big, -1, d)
+        assert np.array_equal(got.dist, d), nfa.text
+        assert got.levels == int(d.max()) + 1
+        assert np.array_equal(got.level_counts, np.bincount(d[d >= 0].ravel(), minlength=got.levels))
