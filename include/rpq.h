@@ -28,6 +28,7 @@
 #ifndef RPQ_H
 #define RPQ_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus

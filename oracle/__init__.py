@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from dataclasses import dataclass
 from typing import Optional
 
@@ -123,7 +124,11 @@ class Graph:
             self._lib.og_free(self._h)
             self._h = None
 
-    __del__ = close
+    def __del__(self):
+        # no foreign calls from a half-finalized interpreter (the memory goes
+        # with the process)
+        if not sys.is_finalizing():
+            self.close()
 
     def num_edges(self, inverse: bool = False) -> int:
         return int(self._lib.og_num_edges(self._h, int(inverse)))

@@ -26,6 +26,16 @@ rpq_status rpq::fail(rpq_status st, const char *fmt, ...) {
     return st;
 }
 
+// Persistent grids are sized to fill the GPU and wait for each other at grid
+// barriers, so two of them in flight on one device at once could each hold
+// part of the GPU and wait (up to the barrier timeout) for workgroups that
+// cannot start. Every persistent launch of this process holds its device's
+// lock from the launch until its stream has drained it.
+std::mutex &rpq::persistent_mutex(int device) {
+    static std::mutex mus[64];
+    return mus[static_cast<unsigned>(device) & 63u];
+}
+
 rpq_status rpq::hip_fail(hipError_t e, const char *what) {
     return fail(RPQ_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
@@ -126,36 +136,59 @@ rpq_status rpq_nfa_free(rpq_nfa *n) {
 }
 
 // Builds the query-constant block (QHeader, succ, pred, label->symbol maps)
-// for NFA n on graph g into `buf`; returns its size in bytes.
-size_t rpq::build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, uint32_t counters,
-                         std::vector<uint8_t> &buf, int32_t *nsym_out) {
+// for NFA n on graph g into dst (cap bytes), with no heap allocation; returns
+// its size in bytes, or 0 when n uses more than MAX_SYMS symbols (*nsym_out
+// says how many) or the block would exceed cap.
+size_t rpq::build_qconst_into(const rpq_graph *g, const rpq_nfa *n, uint32_t force, uint32_t counters, uint8_t *dst,
+                              size_t cap, int32_t *nsym_out) {
     const int32_t L = g->L;
-    // used symbols: label within the graph, with edges, with transitions
-    std::vector<int32_t> symidx(2 * static_cast<size_t>(n->NL), -1);
-    std::vector<int32_t> used;
+    // used symbols: label within the graph, with edges, with transitions; in
+    // order of first transition
+    int32_t used[MAX_SYMS];
+    int32_t ns = 0;
+    bool over = false;
+    auto index_of = [&](int32_t sym) {
+        for (int32_t u = 0; u < ns; u++)
+            if (used[u] == sym) return u;
+        return -1;
+    };
+    int32_t total = 0;
     for (const auto &t : n->trans) {
         const int32_t lab = t.sym >= n->NL ? t.sym - n->NL : t.sym;
         if (lab >= L || g->label_edges[lab] == 0) continue;
-        if (symidx[t.sym] < 0) {
-            symidx[t.sym] = static_cast<int32_t>(used.size());
-            used.push_back(t.sym);
-        }
+        if (index_of(t.sym) >= 0) continue;
+        if (ns < MAX_SYMS) used[ns++] = t.sym;
+        else over = true;
+        total++;
     }
-    const int32_t ns = static_cast<int32_t>(used.size());
+    if (over) {
+        // count the distinct used symbols beyond the table for the message
+        total = ns;
+        for (size_t i = 0; i < n->trans.size(); i++) {
+            const Trans &t = n->trans[i];
+            const int32_t lab = t.sym >= n->NL ? t.sym - n->NL : t.sym;
+            if (lab >= L || g->label_edges[lab] == 0 || index_of(t.sym) >= 0) continue;
+            bool seen = false;
+            for (size_t k = 0; k < i && !seen; k++) seen = n->trans[k].sym == t.sym;
+            if (!seen) total++;
+        }
+        *nsym_out = total;
+        return 0;
+    }
     *nsym_out = ns;
-    if (ns > MAX_SYMS) return 0;
     const size_t sz = qconst_bytes(static_cast<size_t>(ns));
-    buf.assign(sz, 0);
+    if (sz > cap) return 0;
+    memset(dst, 0, sz);
     const QOffsets o = qconst_offsets(static_cast<size_t>(ns));
-    QHeader *h = reinterpret_cast<QHeader *>(buf.data());
-    uint64_t *symmask = reinterpret_cast<uint64_t *>(buf.data() + o.symmask);
-    uint32_t *succ = reinterpret_cast<uint32_t *>(buf.data() + o.succ);
-    uint32_t *pred = reinterpret_cast<uint32_t *>(buf.data() + o.pred);
-    uint64_t *push_w = reinterpret_cast<uint64_t *>(buf.data() + o.push_w);
-    uint64_t *pull_w = reinterpret_cast<uint64_t *>(buf.data() + o.pull_w);
-    uint32_t *push_r = reinterpret_cast<uint32_t *>(buf.data() + o.push_r);
-    uint32_t *pull_r = reinterpret_cast<uint32_t *>(buf.data() + o.pull_r);
-    uint32_t *pull_n = reinterpret_cast<uint32_t *>(buf.data() + o.pull_n);
+    QHeader *h = reinterpret_cast<QHeader *>(dst);
+    uint64_t *symmask = reinterpret_cast<uint64_t *>(dst + o.symmask);
+    uint32_t *succ = reinterpret_cast<uint32_t *>(dst + o.succ);
+    uint32_t *pred = reinterpret_cast<uint32_t *>(dst + o.pred);
+    uint64_t *push_w = reinterpret_cast<uint64_t *>(dst + o.push_w);
+    uint64_t *pull_w = reinterpret_cast<uint64_t *>(dst + o.pull_w);
+    uint32_t *push_r = reinterpret_cast<uint32_t *>(dst + o.push_r);
+    uint32_t *pull_r = reinterpret_cast<uint32_t *>(dst + o.pull_r);
+    uint32_t *pull_n = reinterpret_cast<uint32_t *>(dst + o.pull_n);
     h->Q = n->Q;
     h->nsym = ns;
     h->smask = n->smask;
@@ -180,7 +213,7 @@ size_t rpq::build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, u
         erel += static_cast<uint64_t>(g->label_edges[lab]);
     }
     for (const auto &t : n->trans) {
-        const int32_t u = symidx[t.sym];
+        const int32_t u = index_of(t.sym);
         if (u < 0) continue;
         succ[u * MAX_STATES + t.from] |= 1u << t.to;
         pred[u * MAX_STATES + t.to] |= 1u << t.from;
@@ -189,6 +222,15 @@ size_t rpq::build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, u
         h->succ_any[t.from] |= 1u << t.to;
     }
     h->e_rel = erel;
+    return sz;
+}
+
+// The same into a vector sized to the block.
+size_t rpq::build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, uint32_t counters,
+                         std::vector<uint8_t> &buf, int32_t *nsym_out) {
+    buf.resize(qconst_bytes(MAX_SYMS));
+    const size_t sz = build_qconst_into(g, n, force, counters, buf.data(), buf.size(), nsym_out);
+    buf.resize(sz);
     return sz;
 }
 
@@ -569,7 +611,9 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
         p.st.hstat = g->hstat_dev;
         p.st.hserial = g->hserial;
     }
+    std::unique_lock<std::mutex> plk(persistent_mutex(g->device), std::defer_lock);
     if (persistent) {
+        plk.lock();  // released when this call returns, after the synchronisation below
         g->bar_idx ^= 1;  // the next persistent launch uses the barrier this one zeroes
         if (timing) HIP_TRY(hipEventRecord(g->ev[2], s));
         HIP_TRY(launch_persistent(W, p, grid_p, g->coop_launch, s));

@@ -111,9 +111,12 @@ struct rpq_graph {
 namespace rpq {
 
 rpq_status fail(rpq_status st, const char *fmt, ...);
+std::mutex &persistent_mutex(int device);
 rpq_status hip_fail(hipError_t e, const char *what);
 size_t build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, uint32_t counters,
                     std::vector<uint8_t> &buf, int32_t *nsym_out);
+size_t build_qconst_into(const rpq_graph *g, const rpq_nfa *n, uint32_t force, uint32_t counters, uint8_t *dst,
+                         size_t cap, int32_t *nsym_out);
 QueryView query_view(uint8_t *base, int32_t nsym);
 rpq_status graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32_t *src, const int32_t *dst);
 // Optional parts of a single-query call: a start set instead of one source
@@ -125,6 +128,20 @@ struct SingleExtra {
 };
 rpq_status run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint64_t *out, uint32_t flags,
                       rpq_stats *stats, const SingleExtra *ex = nullptr);
+// Device memory for a stacked pass that the library does not allocate (see
+// rpq_multi_source_noalloc): bytes at base, and the co-resident grid of the
+// stacked kernel per [QM == 32][G].
+struct StackArena {
+    uint8_t *base;
+    size_t bytes;
+    int grid[2][17];
+};
+struct StackParams;
+size_t stacked_arena_layout(const rpq_graph *g, int32_t Q, int G, int32_t B, uint8_t *base, StackParams *p,
+                            uint8_t **qconst, int32_t **srcs, uint64_t **out);
+rpq_status stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
+                       uint64_t *out_bitmaps, uint32_t flags, rpq_stats *stats, const char *who,
+                       const StackArena *ar);
 void serve_shutdown(rpq_graph *g);
 bool serve_pending(rpq_graph *g);
 void batch_free(rpq_graph *g);

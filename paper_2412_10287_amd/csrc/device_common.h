@@ -481,8 +481,29 @@ __device__ inline bool barrier_wait_register(GridBarrier *b, BarCtx &c) {
     if (threadIdx.x == 0) {
         const uint32_t x = xcc_id();
         uint32_t ok = spin_until_at_least(b, &b->nreg, gridDim.x);
+        // The two increments of a workgroup are independent relaxed atomics,
+        // so the per-XCD counts may trail nreg: wait until they add up to the
+        // grid as well (they only grow, and reach it once every workgroup's
+        // first increment is visible), so that per and nxcd are final.
         uint32_t nx = 0;
-        for (int i = 0; i < MAX_XCD; i++) nx += aload(&b->reg[i]) ? 1u : 0u;
+        const uint64_t t0 = wall_clock64();
+        while (ok) {
+            uint32_t sum = 0;
+            nx = 0;
+            for (int i = 0; i < MAX_XCD; i++) {
+                const uint32_t r = aload(&b->reg[i]);
+                sum += r;
+                nx += r ? 1u : 0u;
+            }
+            if (sum >= gridDim.x) break;
+            if (aload(&b->abort)) ok = 0;
+            else if (wall_clock64() - t0 > BARRIER_TIMEOUT) {
+                __hip_atomic_store(&b->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+            } else {
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
         s_v[0] = x;
         s_v[1] = aload(&b->reg[x]);
         s_v[2] = ok ? nx : 0u;

@@ -106,84 +106,173 @@ static rpq_status batch_prepare(rpq_graph *g, int32_t Q, int G, int32_t B, hipSt
     return RPQ_OK;
 }
 
-rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
-                            uint64_t *out_bitmaps, uint32_t flags, rpq_stats *stats) {
-    if (!g || !n || !sources || !out_bitmaps) return fail(RPQ_EINVAL, "rpq_multi_source: NULL argument");
-    if (n_sources < 1) return fail(RPQ_EINVAL, "rpq_multi_source: n_sources < 1");
+// Lays out one batch's device state for rows of Q*G words inside an arena at
+// `base` (nullptr: sizes only): the arrays of StackParams, the query
+// constants, the batch's sources and its result bitmaps, each 256-byte
+// aligned. Returns the bytes needed.
+size_t rpq::stacked_arena_layout(const rpq_graph *g, int32_t Q, int G, int32_t B, uint8_t *base, StackParams *p,
+                                 uint8_t **qconst, int32_t **srcs, uint64_t **out) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        void *r = base ? static_cast<void *>(base + off) : nullptr;
+        off += (bytes + 255) & ~static_cast<size_t>(255);
+        return r;
+    };
+    const uint64_t words = static_cast<uint64_t>(g->V) * Q * G + 64;
+    StackParams q{};
+    q.P = static_cast<uint64_t *>(take(8 * words));
+    q.M[0] = static_cast<uint64_t *>(take(8 * words));
+    q.M[1] = static_cast<uint64_t *>(take(8 * words));
+    for (int k = 0; k < 2; k++) {
+        q.sup[k] = static_cast<uint32_t *>(take(4 * static_cast<size_t>(g->V) + 64));
+        q.q[k] = static_cast<int32_t *>(take(4 * static_cast<size_t>(g->V) + 64));
+    }
+    q.item_cap = static_cast<uint64_t>(g->rows[OUT] + g->rows[IN]) + 1;
+    for (uint32_t **a : {&q.it_ebase, &q.it_beg, &q.it_v, &q.it_u, &q.it_s}) *a = static_cast<uint32_t *>(take(4 * q.item_cap));
+    q.tile_cap = (2 * static_cast<uint64_t>(g->E)) / (TILE / 16) + 2;
+    q.tile_first = static_cast<uint32_t *>(take(4 * q.tile_cap));
+    q.rec = static_cast<LevelRec *>(take(sizeof(LevelRec) * REC_RING));
+    q.bar = static_cast<GridBarrier *>(take(sizeof(GridBarrier)));
+    q.status = static_cast<uint32_t *>(take(64));
+    q.cnt = static_cast<uint64_t *>(take(64));
+    q.lvl = static_cast<uint64_t *>(take(8 * LVL_STRIDE * (LVL_COUNT_CAP + 1)));
+    uint8_t *qc = static_cast<uint8_t *>(take(g->qconst_cap));
+    int32_t *sv = static_cast<int32_t *>(take(4 * static_cast<size_t>(MAX_BATCH)));
+    uint64_t *ob = static_cast<uint64_t *>(take(8 * static_cast<size_t>(B) * g->nwords));
+    if (base) {
+        *p = q;
+        *qconst = qc;
+        *srcs = sv;
+        *out = ob;
+    }
+    return off;
+}
+
+// The stacked traversal of `sources` in batches of at most max_batch. Its
+// device state comes from g->batch (allocated or grown here), or, with an
+// arena (ar != nullptr), from the arena alone: then nothing is allocated,
+// the arena's arrays are cleared before each batch, and the host staging is
+// the graph handle's pinned buffer.
+rpq_status rpq::stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
+                            uint64_t *out_bitmaps, uint32_t flags, rpq_stats *stats, const char *who,
+                            const StackArena *ar) {
+    if (!g || !n || !sources || !out_bitmaps) return fail(RPQ_EINVAL, "%s: NULL argument", who);
+    if (n_sources < 1) return fail(RPQ_EINVAL, "%s: n_sources < 1", who);
     for (int32_t i = 0; i < n_sources; i++)
         if (sources[i] < 0 || sources[i] >= g->V)
-            return fail(RPQ_EINVAL, "rpq_multi_source: source %d outside [0, %d)", sources[i], g->V);
+            return fail(RPQ_EINVAL, "%s: source %d outside [0, %d)", who, sources[i], g->V);
+    if ((flags & RPQ_FORCE_PUSH) && (flags & RPQ_FORCE_PULL))
+        return fail(RPQ_EINVAL, "%s: RPQ_FORCE_PUSH and RPQ_FORCE_PULL together", who);
     std::lock_guard<std::recursive_mutex> lk(g->mu);
     BT(hipSetDevice(g->device));
     hipStream_t s = g->user_stream ? g->user_stream : g->stream;
-    const int32_t maxb = std::min<int32_t>(g->max_batch, 1024);
-    std::vector<uint8_t> qbuf;
-    int32_t nsym = 0;
-    if ((flags & RPQ_FORCE_PUSH) && (flags & RPQ_FORCE_PULL))
-        return fail(RPQ_EINVAL, "rpq_multi_source: RPQ_FORCE_PUSH and RPQ_FORCE_PULL together");
+    const int32_t maxb = std::min<int32_t>(g->max_batch, MAX_BATCH);
     const uint32_t force = (flags & RPQ_FORCE_PUSH) ? 1u : (flags & RPQ_FORCE_PULL) ? 2u : 0u;
-    const size_t qsz = build_qconst(g, n, force, (flags & RPQ_COUNTERS) ? 1u : 0u, qbuf, &nsym);
-    if (nsym > MAX_SYMS || qsz > g->qconst_cap)
-        return fail(RPQ_EINVAL, "rpq_multi_source: query uses %d symbols; the limit is %d", nsym, MAX_SYMS);
-    {
-        // the stacked path has its own direction thresholds
-        QHeader *h = reinterpret_cast<QHeader *>(qbuf.data());
-        h->alpha = static_cast<float>(g->stack_alpha);
-        h->beta = static_cast<float>(g->stack_beta);
-    }
     // automata with at most 8 states use the kernel with byte-sized state sets
     // (which also has the pull direction)
     const int QM = n->Q <= 8 ? 8 : 32;
+    // host staging: [0, qconst_cap) query constants, then 4 KB of sources,
+    // then status and counter words (128 B), then (arena) the level records
+    uint8_t *pin = nullptr;
+    size_t lvl_room = 0;
+    int32_t nsym = 0;
+    size_t qsz = 0;
+    std::vector<uint8_t> qbuf;
+    if (ar) {
+        const int32_t B0 = std::min(maxb, n_sources);
+        int G0 = 1;
+        while (G0 * 64 < B0) G0 *= 2;
+        const size_t need = stacked_arena_layout(g, n->Q, G0, B0, nullptr, nullptr, nullptr, nullptr, nullptr);
+        if (need > ar->bytes)
+            return fail(RPQ_EINVAL,
+                        "%s: %d sources of %d states on %d vertices need %zu bytes of scratch; the limit is %zu", who,
+                        B0, n->Q, g->V, need, ar->bytes);
+        pin = g->pinned;
+        lvl_room = (g->pinned_cap - g->qconst_cap - 4096 - 128) / (8 * LVL_STRIDE);
+        qsz = build_qconst_into(g, n, force, (flags & RPQ_COUNTERS) ? 1u : 0u, pin, g->qconst_cap, &nsym);
+    } else {
+        qsz = build_qconst(g, n, force, (flags & RPQ_COUNTERS) ? 1u : 0u, qbuf, &nsym);
+    }
+    if (nsym > MAX_SYMS || qsz == 0 || qsz > g->qconst_cap)
+        return fail(RPQ_EINVAL, "%s: query uses %d symbols; the limit is %d", who, nsym, MAX_SYMS);
+    {
+        // the stacked path has its own direction thresholds
+        QHeader *h = reinterpret_cast<QHeader *>(ar ? pin : qbuf.data());
+        h->alpha = static_cast<float>(g->stack_alpha);
+        h->beta = static_cast<float>(g->stack_beta);
+    }
     int32_t push_levels = 0, pull_levels = 0;
     int32_t levels = 0;
     int64_t pairs = 0, scans = 0, edges = 0, updates = 0, active = 0, bytes = 0, pedges = 0;
     float total_ms = 0.f;
     std::vector<uint64_t> lvl_host;
+    const uint64_t *lvl_rec = nullptr;
     uint32_t lvl_nrec = 0, lvl_levels = 0;
     for (int32_t b0 = 0; b0 < n_sources; b0 += maxb) {
         const int32_t B = std::min(maxb, n_sources - b0);
         int G = 1;
         while (G * 64 < B) G *= 2;
-        rpq_status st = batch_prepare(g, n->Q, G, B, s);
-        if (st != RPQ_OK) return st;
-        BatchState *bs = g->batch;
-        StackParams p = bs->p;
-        memcpy(bs->pinned, qbuf.data(), qsz);
-        int32_t *hsrc = reinterpret_cast<int32_t *>(bs->pinned + bs->qconst_cap);
+        StackParams p;
+        uint8_t *dq = nullptr;
+        int32_t *dsrc = nullptr;
+        uint64_t *dout = nullptr;
+        int full = 0;
+        if (ar) {
+            stacked_arena_layout(g, n->Q, G, B, ar->base, &p, &dq, &dsrc, &dout);
+            // the arena keeps whatever the last call on this GPU left there
+            const uint64_t words = static_cast<uint64_t>(g->V) * n->Q * G + 64;
+            for (uint64_t *a : {p.P, p.M[0], p.M[1]}) BT(launch_fill(reinterpret_cast<uint32_t *>(a), 2 * words, 0, s));
+            for (int k = 0; k < 2; k++) BT(launch_fill(p.sup[k], static_cast<uint64_t>(g->V) + 16, 0, s));
+            full = ar->grid[QM == 8 ? 0 : 1][G];
+        } else {
+            rpq_status st = batch_prepare(g, n->Q, G, B, s);
+            if (st != RPQ_OK) return st;
+            BatchState *bs = g->batch;
+            p = bs->p;
+            dq = bs->qconst;
+            dsrc = bs->sources;
+            dout = bs->out;
+            pin = bs->pinned;
+            memcpy(pin, qbuf.data(), qsz);
+            full = bs->grid[QM == 8 ? 0 : 1][G];
+        }
+        int32_t *hsrc = reinterpret_cast<int32_t *>(pin + g->qconst_cap);
         memcpy(hsrc, sources + b0, 4 * static_cast<size_t>(B));
-        BT(hipMemcpyAsync(bs->qconst, bs->pinned, qsz, hipMemcpyHostToDevice, s));
-        BT(hipMemcpyAsync(bs->sources, hsrc, 4 * static_cast<size_t>(B), hipMemcpyHostToDevice, s));
+        BT(hipMemcpyAsync(dq, pin, qsz, hipMemcpyHostToDevice, s));
+        BT(hipMemcpyAsync(dsrc, hsrc, 4 * static_cast<size_t>(B), hipMemcpyHostToDevice, s));
         p.g = g->gv;
-        p.qv = query_view(bs->qconst, nsym);
-        p.sources = bs->sources;
+        p.qv = query_view(dq, nsym);
+        p.sources = dsrc;
         p.B = B;
         p.Q = n->Q;
         p.V = g->V;
         p.nwords = g->nwords;
-        p.out = (flags & RPQ_OUT_DEVICE) ? out_bitmaps + static_cast<size_t>(b0) * g->nwords : bs->out;
-        const int full = bs->grid[QM == 8 ? 0 : 1][G];
+        p.out = (flags & RPQ_OUT_DEVICE) ? out_bitmaps + static_cast<size_t>(b0) * g->nwords : dout;
         const int grid = g->grid_override ? std::min(g->grid_override, full) : full;
-        if (grid <= 0) return fail(RPQ_EDEVICE, "rpq_multi_source: no co-resident grid for the stacked kernel");
+        if (grid <= 0) return fail(RPQ_EDEVICE, "%s: no co-resident grid for the stacked kernel", who);
         BT(launch_fill(reinterpret_cast<uint32_t *>(p.bar), sizeof(GridBarrier) / 4, 0, s));
+        // one persistent grid per device at a time (released after the
+        // synchronisation below, at the end of this batch)
+        std::unique_lock<std::mutex> plk(persistent_mutex(g->device));
         BT(hipEventRecord(g->ev[2], s));
         BT(launch_stacked(G, QM, p, grid, s));
         BT(hipEventRecord(g->ev[3], s));
-        uint32_t *hst = reinterpret_cast<uint32_t *>(bs->pinned + bs->qconst_cap + 4 * 1024);
-        uint64_t *hcnt = reinterpret_cast<uint64_t *>(bs->pinned + bs->qconst_cap + 4 * 1024 + 64);
+        uint32_t *hst = reinterpret_cast<uint32_t *>(pin + g->qconst_cap + 4 * 1024);
+        uint64_t *hcnt = reinterpret_cast<uint64_t *>(pin + g->qconst_cap + 4 * 1024 + 64);
         BT(hipMemcpyAsync(hst, p.status, 16, hipMemcpyDeviceToHost, s));
         BT(hipMemcpyAsync(hcnt, p.cnt, 8 * ST_NCNT, hipMemcpyDeviceToHost, s));
         BT(hipMemcpyAsync(hst + 4, &p.bar->abort, 4, hipMemcpyDeviceToHost, s));
         if (!(flags & RPQ_OUT_DEVICE))
-            BT(hipMemcpyAsync(out_bitmaps + static_cast<size_t>(b0) * g->nwords, bs->out,
+            BT(hipMemcpyAsync(out_bitmaps + static_cast<size_t>(b0) * g->nwords, dout,
                               8 * static_cast<size_t>(B) * g->nwords, hipMemcpyDeviceToHost, s));
         BT(hipStreamSynchronize(s));
         if (hst[4]) {
-            batch_free(g);
-            return fail(RPQ_EDEVICE, "rpq_multi_source: traversal aborted (grid barrier timed out)");
+            if (!ar) batch_free(g);
+            return fail(RPQ_EDEVICE, "%s: traversal aborted (grid barrier timed out)", who);
         }
         if (hst[3]) {
-            batch_free(g);
-            return fail(RPQ_EDEVICE, "rpq_multi_source: internal invariant violated %u times", hst[3]);
+            if (!ar) batch_free(g);
+            return fail(RPQ_EDEVICE, "%s: internal invariant violated %u times", who, hst[3]);
         }
         float ms = 0.f;
         BT(hipEventElapsedTime(&ms, g->ev[2], g->ev[3]));
@@ -191,12 +280,6 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         levels = std::max<int32_t>(levels, static_cast<int32_t>(hst[0]));
         push_levels += static_cast<int32_t>(hst[1]);
         pull_levels += static_cast<int32_t>(hst[2]);
-        const uint32_t nrec = std::min<uint32_t>(hst[0] + 1, LVL_COUNT_CAP);
-        lvl_host.assign(static_cast<size_t>(nrec) * LVL_STRIDE, 0);
-        BT(hipMemcpy(lvl_host.data(), p.lvl, 8 * lvl_host.size(), hipMemcpyDeviceToHost));
-        lvl_nrec = nrec;
-        lvl_levels = hst[0];
-        pairs += stats_levels(nullptr, lvl_host.data(), nrec, hst[0]);
         // algorithmic bytes of the stacked traversal, levels in lockstep:
         // per active (level, vertex) its queue entry read and written (8 B)
         // and its frontier column read and written (2W, W = 4 B per non-zero
@@ -212,10 +295,24 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         bytes += 8 * static_cast<int64_t>(hcnt[ST_CNT_ACTIVE]) + 8 * static_cast<int64_t>(hcnt[ST_CNT_SCANS]) +
                  4 * static_cast<int64_t>(hcnt[ST_CNT_EDGES]) + static_cast<int64_t>(hcnt[ST_CNT_WBYTES]) +
                  static_cast<int64_t>(B) * ((static_cast<int64_t>(g->V) + 7) / 8);
+        uint32_t nrec = std::min<uint32_t>(hst[0] + 1, LVL_COUNT_CAP);
+        if (ar) {
+            nrec = std::min<uint32_t>(nrec, static_cast<uint32_t>(lvl_room));
+            uint64_t *dst = reinterpret_cast<uint64_t *>(pin + g->qconst_cap + 4096 + 128);
+            BT(hipMemcpy(dst, p.lvl, 8 * LVL_STRIDE * static_cast<size_t>(nrec), hipMemcpyDeviceToHost));
+            lvl_rec = dst;
+        } else {
+            lvl_host.assign(static_cast<size_t>(nrec) * LVL_STRIDE, 0);
+            BT(hipMemcpy(lvl_host.data(), p.lvl, 8 * lvl_host.size(), hipMemcpyDeviceToHost));
+            lvl_rec = lvl_host.data();
+        }
+        lvl_nrec = nrec;
+        lvl_levels = hst[0];
+        pairs += stats_levels(nullptr, lvl_rec, nrec, hst[0]);
     }
     if (stats) {
         stats_reset(stats);
-        stats_levels(stats, lvl_host.data(), lvl_nrec, lvl_levels);
+        stats_levels(stats, lvl_rec, lvl_nrec, lvl_levels);
         stats->levels = levels;
         stats->push_levels = push_levels;
         stats->pull_levels = pull_levels;
@@ -234,4 +331,9 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         }
     }
     return RPQ_OK;
+}
+
+rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
+                            uint64_t *out_bitmaps, uint32_t flags, rpq_stats *stats) {
+    return stacked_run(g, n, sources, n_sources, out_bitmaps, flags, stats, "rpq_multi_source", nullptr);
 }

@@ -12,8 +12,11 @@ Two layers:
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -30,7 +33,8 @@ OUT_DEVICE, COUNTERS, KERNEL_TIMING, FORCE_PUSH, FORCE_PULL, HOST_LOOP = 1, 2, 4
 
 EXPORTS = ("rpq_bitmap_words", "rpq_graph_load", "rpq_graph_free", "rpq_graph_info", "rpq_set_option",
            "rpq_get_option", "rpq_nfa_load", "rpq_nfa_free", "rpq_single_source", "rpq_single_destination",
-           "rpq_single_source_lengths", "rpq_source_set", "rpq_multi_source", "rpq_submit", "rpq_poll",
+           "rpq_single_source_lengths", "rpq_source_set", "rpq_multi_source",
+           "rpq_submit", "rpq_poll",
            "rpq_autotune", "rpq_last_error")
 
 TUNE_PLAIN, TUNE_STACKED = 0, 1
@@ -124,6 +128,29 @@ _HIP_D2H = 2
 _HIP_D2D = 3
 
 
+# Handles still open. At interpreter exit they are all closed by an atexit
+# handler, graphs first (which joins their served paths' scheduler threads and
+# waits for outstanding tickets), while the HIP runtime and ctypes are fully
+# alive; objects that reach the finalizer later (for instance kept by a
+# reference cycle) are left to the process exit instead of calling into the
+# library from a half-torn-down interpreter.
+_live_graphs = weakref.WeakSet()
+_live_nfas = weakref.WeakSet()
+_live_buffers = weakref.WeakSet()
+
+
+def _close_all():
+    for group in (_live_graphs, _live_buffers, _live_nfas):
+        for obj in list(group):
+            try:
+                obj.close(drain=True) if group is _live_graphs else obj.close()
+            except Exception:
+                pass
+
+
+atexit.register(_close_all)
+
+
 class DeviceBuffer:
     """A zeroed device allocation of ``nbytes`` (plumbing for RPQ_OUT_DEVICE)."""
 
@@ -133,6 +160,7 @@ class DeviceBuffer:
         if _hip.hipMalloc(ctypes.byref(p), max(self.nbytes, 1)) != 0:
             raise MemoryError("hipMalloc of %d bytes failed" % self.nbytes)
         self.ptr = p.value
+        _live_buffers.add(self)
         if _hip.hipMemset(ctypes.c_void_p(self.ptr), 0, self.nbytes) != 0:
             raise RuntimeError("hipMemset failed")
 
@@ -153,7 +181,9 @@ class DeviceBuffer:
             _hip.hipFree(ctypes.c_void_p(self.ptr))
             self.ptr = None
 
-    __del__ = close
+    def __del__(self):
+        if not sys.is_finalizing():
+            self.close()
 
 
 def device_synchronize():
@@ -256,13 +286,16 @@ class NFA:
         check(lib.rpq_nfa_load(self.num_states, int(nfa.num_labels), _p(sp), _p(fr), _p(to), _p(st),
                                int(st.size), _p(fi), int(fi.size), ctypes.byref(h)))
         self.h = h
+        _live_nfas.add(self)
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             lib.rpq_nfa_free(self.h)
             self.h = None
 
-    __del__ = close
+    def __del__(self):
+        if not sys.is_finalizing():
+            self.close()
 
 
 class Graph:
@@ -278,13 +311,25 @@ class Graph:
         check(lib.rpq_graph_load(self.num_vertices, self.num_labels, _p(lp), _p(s), _p(d), ctypes.byref(h)))
         self.h = h
         self.words = bitmap_words(self.num_vertices)
+        self._tickets = set()  # submitted and not yet collected by poll
+        _live_graphs.add(self)
 
-    def close(self):
-        if getattr(self, "h", None) is not None and self.h.value:
-            check(lib.rpq_graph_free(self.h))
-            self.h = None
+    def close(self, drain: bool = False):
+        """rpq_graph_free. With drain, first waits for the answers of tickets
+        still outstanding (rpq_graph_free refuses while any is pending)."""
+        if getattr(self, "h", None) is None or not self.h.value:
+            return
+        if drain:
+            scratch = np.empty(self.words, dtype=np.uint64)
+            for t in list(self._tickets):
+                lib.rpq_poll(self.h, ctypes.c_uint64(t), _p(scratch), 0, None, -1)
+            self._tickets.clear()
+        check(lib.rpq_graph_free(self.h))
+        self.h = None
 
-    __del__ = close
+    def __del__(self):
+        if not sys.is_finalizing():
+            self.close()
 
     def info(self, key: str) -> int:
         v = ctypes.c_int64()
@@ -377,6 +422,7 @@ class Graph:
     def submit(self, nfa: NFA, source: int) -> int:
         t = ctypes.c_uint64()
         check(lib.rpq_submit(self.h, nfa.h, int(source), ctypes.byref(t)))
+        self._tickets.add(t.value)
         return t.value
 
     def poll(self, ticket: int, timeout_us: int = 0, out_device_ptr: Optional[int] = None):
@@ -392,5 +438,6 @@ class Graph:
         r = lib.rpq_poll(self.h, ctypes.c_uint64(ticket), ptr, fl, ctypes.byref(st), int(timeout_us))
         if r in (RPQ_PENDING, RPQ_ETIMEDOUT):
             return None
+        self._tickets.discard(ticket)
         check(r)
         return bm, Stats.from_c(st, lc)
