@@ -260,6 +260,33 @@ rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
                             rpq_stats *stats);
 
 /*
+ * rpq_multi_source without allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). The same traversal, answers and statistics as
+ * rpq_multi_source, but every piece of per-call device state (frontier,
+ * visited and candidate rows, queues, work items, level records, barrier,
+ * status words, query constants, the batch's sources, and the result bitmaps
+ * when out_bitmaps is host memory) lives in one fixed array of
+ * RPQ_NOALLOC_SCRATCH_BYTES bytes of device memory that the library owns:
+ * each GPU holds its own copy from the first call on it until the process
+ * ends. The call makes no hipMalloc, hipFree or other allocating call (the
+ * graph store and its pinned staging buffer come from rpq_graph_load).
+ * Every call on a GPU reuses that GPU's array and clears what must start at
+ * zero; calls on one GPU are serialized inside the process (calls that
+ * overlapped on one array would race). A batch needs
+ * 3 * 8 * V * Q * G bytes of state rows (G = 64-source words per row, a power
+ * of two >= ceil(B / 64), B = min(n_sources, max_batch)) plus about
+ * 20 (V + rows) bytes of queues and work items, 2.7 MB of level records and
+ * B * ceil(V / 64) * 8 bytes of results; a call whose first batch exceeds
+ * the array fails with RPQ_EINVAL before any device work, and the message
+ * gives both sizes. Other arguments, flags and errors as rpq_multi_source.
+ */
+#define RPQ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+rpq_status rpq_multi_source_noalloc(rpq_graph *g, const rpq_nfa *n, const int32_t *sources,
+                                    int32_t n_sources, uint64_t *out_bitmaps, uint32_t flags,
+                                    rpq_stats *stats);
+
+/*
  * Served path. rpq_submit copies what it needs (the NFA may be freed after it
  * returns) and queues the query; a scheduler thread admits queued queries into
  * free slots while memory allows, advances all admitted queries level by level

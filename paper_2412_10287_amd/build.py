@@ -18,7 +18,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["kernels.hip", "multi.hip", "stacked.hip", "graph_build.cpp", "api.cpp", "serve.cpp", "stacked_host.cpp",
-           "tune.cpp"]
+           "tune.cpp", "noalloc.cpp"]
 
 COMMON = [
     "--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-Wall",

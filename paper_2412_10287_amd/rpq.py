@@ -33,7 +33,7 @@ OUT_DEVICE, COUNTERS, KERNEL_TIMING, FORCE_PUSH, FORCE_PULL, HOST_LOOP = 1, 2, 4
 
 EXPORTS = ("rpq_bitmap_words", "rpq_graph_load", "rpq_graph_free", "rpq_graph_info", "rpq_set_option",
            "rpq_get_option", "rpq_nfa_load", "rpq_nfa_free", "rpq_single_source", "rpq_single_destination",
-           "rpq_single_source_lengths", "rpq_source_set", "rpq_multi_source",
+           "rpq_single_source_lengths", "rpq_source_set", "rpq_multi_source", "rpq_multi_source_noalloc",
            "rpq_submit", "rpq_poll",
            "rpq_autotune", "rpq_last_error")
 
@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH):
         "rpq_single_source_lengths": (ctypes.c_int, [P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
         "rpq_source_set": (ctypes.c_int, [P, P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
         "rpq_multi_source": (ctypes.c_int, [P, P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
+        "rpq_multi_source_noalloc": (ctypes.c_int, [P, P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
         "rpq_submit": (ctypes.c_int, [P, P, i32, ctypes.POINTER(u64)]),
         "rpq_poll": (ctypes.c_int, [P, u64, P, u32, ctypes.POINTER(rpq_stats), i64]),
         "rpq_autotune": (ctypes.c_int, [P, i32, P, P, i32, ctypes.POINTER(rpq_tuning)]),
@@ -402,6 +403,20 @@ class Graph:
             return None, Stats.from_c(st, lc)
         bm = np.zeros((src.size, self.words), dtype=np.uint64)
         check(lib.rpq_multi_source(self.h, nfa.h, _p(src), int(src.size), _p(bm), flags, ctypes.byref(st)))
+        return bm, Stats.from_c(st, lc)
+
+    def multi_source_noalloc(self, nfa: NFA, sources: Sequence[int], flags: int = 0,
+                             out_device_ptr: Optional[int] = None, level_cap: int = 0):
+        """rpq_multi_source_noalloc: as multi_source, with the call's device
+        state in the library's fixed scratch array (no allocation)."""
+        src = np.ascontiguousarray(sources, dtype=np.int32)
+        st, lc = _stats_struct(level_cap)
+        if out_device_ptr is not None:
+            check(lib.rpq_multi_source_noalloc(self.h, nfa.h, _p(src), int(src.size), ctypes.c_void_p(out_device_ptr),
+                                               flags | OUT_DEVICE, ctypes.byref(st)))
+            return None, Stats.from_c(st, lc)
+        bm = np.zeros((src.size, self.words), dtype=np.uint64)
+        check(lib.rpq_multi_source_noalloc(self.h, nfa.h, _p(src), int(src.size), _p(bm), flags, ctypes.byref(st)))
         return bm, Stats.from_c(st, lc)
 
     def autotune(self, path: int, nfas: Sequence[NFA], sources: Sequence[int]) -> dict:
