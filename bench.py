@@ -136,11 +136,13 @@ class OracleRuns:
         self.threads = threads
         self.mem_budget = mem_budget
         self._og = None
-        self._out = None
+        self._out = [] if not queries else None
         self._err = None
+        self.build_s = self.wall_s = 0.0
         self._go = threading.Event()
         self._th = threading.Thread(target=self._run, args=(graph,), daemon=True)
-        self._th.start()
+        if queries:
+            self._th.start()
 
     def go(self):
         self._go.set()
@@ -187,13 +189,16 @@ class OracleRuns:
 
     def results(self):
         self._go.set()
-        self._th.join()
+        if self.queries:
+            self._th.join()
         if self._err is not None:
             raise self._err
         return self._out
 
     def baseline(self, what: str):
         out = self.results()
+        if not out:
+            return None
         lat = [o[3] for o in out]
         pe = sum(o[1] for o in out)
         return {"value": round(pe / self.wall_s / 1e9, 6), "unit": "GTEPS", "cores": self.threads,
@@ -415,6 +420,18 @@ def bench_kg(args):
 
     # the same queries one at a time (plain) and through the served path
     cmp_steps = max(1, min(args.steps, args.compare_steps))
+    if args.skip_compare:
+        g.close()
+        out.close()
+        want = [r[0] for r in runs.results()]
+        res = {"metric": "product-graph GTEPS; queries/s + p50/p99 latency, batched vs plain, 1 GPU",
+               "value": round(pe_total * args.steps / dt / 1e9, 3), "unit": "GTEPS", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
+               "note": "stacked leg only (profiling run)", "mean_launch_us": round(k_ms * 1e3, 1),
+               "alg_bytes_per_launch": int(alg_bytes),
+               "parity": {"stacked": parity_of(stacked_rows[sample], want)}}
+        print(json.dumps(res), flush=True)
+        return 1 if parity_failed(res["parity"]) else 0
     plain_lat = []
 
     def plain_step(lat=None):
@@ -741,6 +758,7 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="kg: leave out the R-MAT plain secondary")
     ap.add_argument("--parity-sample", type=int, default=32, help="kg: batch queries checked against the oracle")
     ap.add_argument("--compare-steps", type=int, default=3, help="kg: steps of the plain and served legs")
+    ap.add_argument("--skip-compare", action="store_true", help="kg: stacked leg only (for profiler runs)")
     ap.add_argument("--grid-oracle", type=int, default=8, help="grid: sources checked against the oracle")
     ap.add_argument("--host-loop", action="store_true", help="plain path: drive levels from the host")
     ap.add_argument("--stacked-alpha", type=int, default=None, help="push->pull threshold of the stacked path")

@@ -57,6 +57,9 @@ typedef uint64_t rpq_ticket;
 #define RPQ_FORCE_PUSH 8u   /* never use the pull direction (testing / tuning) */
 #define RPQ_FORCE_PULL 16u  /* use the pull direction from level 1 on (testing / tuning) */
 #define RPQ_HOST_LOOP 32u   /* drive levels from the host instead of one persistent launch */
+#define RPQ_GRAPH_LEVELS 64u /* single-query paths: levels as replays of a captured HIP graph of
+                                16 levels (select, expansion, advance kernels), the end checked
+                                once per replay; the graph is captured at first use per handle */
 
 /*
  * Statistics of one query (or one batch). Input fields: level_counts may point
@@ -139,7 +142,9 @@ int64_t rpq_bitmap_words(int32_t num_vertices);
 rpq_status rpq_graph_load(int32_t num_vertices, int32_t num_labels, const int64_t *label_ptr,
                           const int32_t *src, const int32_t *dst, rpq_graph **out);
 rpq_status rpq_graph_free(rpq_graph *g);
-/* Graph facts: "num_vertices", "num_labels", "num_edges" (distinct), "device_bytes". */
+/* Graph facts: "num_vertices", "num_labels", "num_edges" (distinct), "device_bytes";
+   "serve_slots": queries the served path holds at once, as its memory budget
+   allowed when it started (0 before the first rpq_submit has been admitted). */
 rpq_status rpq_graph_info(const rpq_graph *g, const char *key, int64_t *value);
 
 /*
@@ -152,7 +157,8 @@ rpq_status rpq_graph_info(const rpq_graph *g, const char *key, int64_t *value);
  *                than num_vertices / beta vertices.
  *  "persistent_grid"  workgroups of the persistent single-query launch
  *                (0 = one per CU; larger values are capped at that).
- *  "cooperative_launch"  1: start the persistent single-query kernel with
+ *  "cooperative_launch"  1: start the persistent kernels (single-query and
+ *                stacked multi-source) with
  *                hipLaunchCooperativeKernel, which guarantees that all its
  *                workgroups are resident at once; 0 (default): an ordinary
  *                launch, about 14 us faster per query on MI355X. The grid is

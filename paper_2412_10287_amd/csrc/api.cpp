@@ -260,6 +260,9 @@ static rpq_status upload(rpq_graph *g, T **dst, const std::vector<T> &src, const
 static void destroy(rpq_graph *g) {
     if (!g) return;
     serve_shutdown(g);
+    for (hipGraphExec_t &ex : g->lgraph)
+        if (ex) (void)hipGraphExecDestroy(ex);
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
     for (hipEvent_t e : g->ev)
         if (e) (void)hipEventDestroy(e);
@@ -426,6 +429,7 @@ rpq_status rpq_graph_info(const rpq_graph *g, const char *key, int64_t *value) {
     else if (!strcmp(key, "rows_in")) *value = g->rows[IN];
     else if (!strcmp(key, "persistent_grid")) *value = g->pgrid[1];
     else if (!strcmp(key, "occupancy_blocks_per_cu")) *value = occupancy_blocks_per_cu(1);
+    else if (!strcmp(key, "serve_slots")) *value = serve_slots(const_cast<rpq_graph *>(g));
     else return fail(RPQ_ENOTFOUND, "rpq_graph_info: unknown key '%s'", key);
     return RPQ_OK;
 }
@@ -505,6 +509,78 @@ rpq_status rpq_get_option(const rpq_graph *g, const char *key, int64_t *value) {
 
 // ------------------------------------------------------------------ plain query
 static int word_width(int32_t Q) { return Q <= 8 ? 1 : Q <= 16 ? 2 : 4; }
+
+// Levels per replay of a captured level graph.
+constexpr int GRAPH_LEVELS_PER_REPLAY = 16;
+
+// RPQ_GRAPH_LEVELS: the host loop's phases captured once per graph handle
+// (and state-word width and grid) as a HIP graph of GRAPH_LEVELS_PER_REPLAY
+// levels that reads the query's Params from device memory; each replay
+// advances up to that many levels, and the host checks for the end once per
+// replay instead of once per level. Writes the level count to *nlev and
+// runs the extract phase.
+static rpq_status run_graph_levels(rpq_graph *g, Params &p, int W, bool has_start, hipStream_t s, uint32_t *nlev) {
+    const int grid = g->grid_override ? g->grid_override : 1024;
+    if (!g->gctl) {
+        if (dev_alloc(g, reinterpret_cast<void **>(&g->gctl), 64, "level control") != RPQ_OK ||
+            dev_alloc(g, reinterpret_cast<void **>(&g->pdev), sizeof(Params), "params") != RPQ_OK)
+            return RPQ_ENOMEM;
+    }
+    p.st.gctl = g->gctl;
+    HIP_TRY(launch_init(W, p, s));
+    HIP_TRY(launch_fill(g->gctl, 16, 0, s));
+    // the Params block goes up through pinned staging (beyond the status
+    // words and the first level records; the copy completes before the first
+    // replay is waited for)
+    static_assert(sizeof(Params) <= 1024, "params staging");
+    uint8_t *stage = g->pinned + g->qconst_cap;
+    memcpy(stage + 2688, &p, sizeof(Params));
+    HIP_TRY(hipMemcpyAsync(g->pdev, stage + 2688, sizeof(Params), hipMemcpyHostToDevice, s));
+    hipGraphExec_t &ex = g->lgraph[W];
+    if (ex && g->lgraph_grid[W] != grid) {
+        (void)hipGraphExecDestroy(ex);
+        ex = nullptr;
+    }
+    if (!ex) {
+        if (!g->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < GRAPH_LEVELS_PER_REPLAY && e == hipSuccess; k++)
+            e = launch_level_g(W, g->pdev, grid, g->cap_stream);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(g->cap_stream, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(e != hipSuccess ? e : e2, "capturing the level graph");
+        }
+        e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            ex = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        g->lgraph_grid[W] = grid;
+    }
+    *nlev = 0;
+    if (has_start) {
+        uint32_t *gc = reinterpret_cast<uint32_t *>(stage + 3712);
+        // levels are bounded by |Q| |V| (App. A); a replay count beyond that
+        // means the device words are wrong
+        const uint64_t cap = (static_cast<uint64_t>(MAX_STATES) * static_cast<uint64_t>(g->V)) / GRAPH_LEVELS_PER_REPLAY + 2;
+        for (uint64_t r = 0;; r++) {
+            HIP_TRY(hipGraphLaunch(ex, s));
+            HIP_TRY(hipMemcpyAsync(gc, g->gctl, 16, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (gc[1]) {
+                *nlev = gc[2];
+                break;
+            }
+            if (r > cap) return fail(RPQ_EDEVICE, "level graph did not terminate");
+        }
+    }
+    HIP_TRY(launch_final(W, p, *nlev, grid, s));
+    return RPQ_OK;
+}
 
 rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint64_t *out, uint32_t flags,
                            rpq_stats *stats, const SingleExtra *ex) {
@@ -597,7 +673,8 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
     uint32_t nlev = 0;
     float expand_ms = 0.f;
     int32_t launches = 0;
-    const bool persistent = !(flags & RPQ_HOST_LOOP) && grid_p > 0;
+    const bool graph_levels = (flags & RPQ_GRAPH_LEVELS) != 0;
+    const bool persistent = !(flags & (RPQ_HOST_LOOP | RPQ_GRAPH_LEVELS)) && grid_p > 0;
     p.st.hstat = nullptr;
     p.st.hserial = 0;
     if (persistent) {
@@ -619,6 +696,9 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
         HIP_TRY(launch_persistent(W, p, grid_p, g->coop_launch, s));
         if (timing) HIP_TRY(hipEventRecord(g->ev[3], s));
         launches = 1;
+    } else if (graph_levels) {
+        const rpq_status r = run_graph_levels(g, p, W, n->smask != 0, s, &nlev);
+        if (r != RPQ_OK) return r;
     } else {
         const int grid = g->grid_override ? g->grid_override : 1024;
         HIP_TRY(launch_init(W, p, s));
@@ -680,7 +760,7 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
         return fail(RPQ_EDEVICE, "persistent traversal aborted: grid barrier timed out");
     }
     if (status[3]) return fail(RPQ_EDEVICE, "internal invariant violated %u times (index out of range)", status[3]);
-    const uint32_t levels = (flags & RPQ_HOST_LOOP || grid_p <= 0) ? nlev : status[0];
+    const uint32_t levels = persistent ? status[0] : nlev;
     if (stats) {
         stats->levels = static_cast<int32_t>(levels);
         stats->push_levels = static_cast<int32_t>(status[1]);

@@ -65,6 +65,14 @@ struct rpq_graph {
     bool own_stream = false;
     hipStream_t user_stream = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // RPQ_GRAPH_LEVELS: device copy of the query's Params, level control
+    // words, the captured level graphs per state-word width (and their grid),
+    // and the stream they are captured on (all made at first use)
+    rpq::Params *pdev = nullptr;
+    uint32_t *gctl = nullptr;
+    hipGraphExec_t lgraph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int lgraph_grid[5] = {0, 0, 0, 0, 0};
+    hipStream_t cap_stream = nullptr;
     int pgrid[5] = {0, 0, 0, 0, 0};
     bool dirty = false;
     // persistent-launch barriers, used in turn: each launch zeroes the other
@@ -144,6 +152,8 @@ rpq_status stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, i
                        const StackArena *ar);
 void serve_shutdown(rpq_graph *g);
 bool serve_pending(rpq_graph *g);
+// Slots the served path's engine admits queries into (0 before it exists).
+int64_t serve_slots(rpq_graph *g);
 void batch_free(rpq_graph *g);
 // Clears the outputs of *st and keeps its caller-supplied input fields.
 void stats_reset(rpq_stats *st);

@@ -1078,6 +1078,50 @@ __global__ __launch_bounds__(BLOCK) void k_expand(Params p, uint32_t n) {
     else pull_phase<W>(p, n, s_eb, s_beg, s_mask, &s_hn);
 }
 
+// Levels in a captured graph: the same phases as k_select / k_expand, with
+// the Params block in device memory (one graph serves every query of the
+// handle) and the level number in gctl, advanced on the device; once a level
+// ends the traversal, the later nodes of the replay return at once. The done
+// flag only changes between kernels, so each workgroup reads one value.
+template <int W>
+__global__ __launch_bounds__(BLOCK) void k_select_g(const Params *pp) {
+    const Params &p = *pp;
+    if (ld_acq(&p.st.gctl[1])) return;
+    qv_setup<false>(p.qv);
+    const uint32_t n = ld_acq(&p.st.gctl[0]);
+    select_phase<W>(p, n, ld_acq(&p.st.rec[n % REC_RING].nq), blockIdx.x, gridDim.x);
+}
+
+template <int W>
+__global__ __launch_bounds__(BLOCK) void k_expand_g(const Params *pp) {
+    __shared__ uint32_t s_eb[TILE + 1], s_beg[TILE + 1], s_mask[TILE + 1], s_hn;
+    const Params &p = *pp;
+    if (ld_acq(&p.st.gctl[1])) return;
+    qv_setup<false>(p.qv);
+    const uint32_t n = ld_acq(&p.st.gctl[0]);
+    const LevelInfo li = level_info(p, n);
+    const uint32_t mode = decide(p, li);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        record_level(p, n, mode, li);
+        p.st.status[0] = n + 1;
+        p.st.status[1 + (mode != 0)] += 1;
+    }
+    if (mode == 0) push_phase<W>(p, n, li, s_eb, s_beg, s_mask, blockIdx.x, gridDim.x);
+    else pull_phase<W>(p, n, s_eb, s_beg, s_mask, &s_hn);
+}
+
+__global__ void k_advance_g(const Params *pp) {
+    const Params &p = *pp;
+    if (threadIdx.x != 0 || ld_acq(&p.st.gctl[1])) return;
+    const uint32_t n = ld_acq(&p.st.gctl[0]);
+    if (ld_acq(&p.st.rec[(n + 1) % REC_RING].nq) == 0) {
+        p.st.gctl[2] = n + 1;
+        p.st.gctl[1] = 1;
+    } else {
+        p.st.gctl[0] = n + 1;
+    }
+}
+
 template <int W>
 __global__ __launch_bounds__(BLOCK) void k_final(Params p, uint32_t nlev) {
     qv_setup<false>(p.qv);
@@ -1150,6 +1194,13 @@ int persistent_grid(int W) {
 
 hipError_t launch_init(int W, const Params &p, hipStream_t s) {
     RPQ_DISPATCH_W(W, hipLaunchKernelGGL(k_init<WW>, dim3(1), dim3(64), 0, s, p));
+    return hipGetLastError();
+}
+
+hipError_t launch_level_g(int W, const Params *pdev, int grid, hipStream_t s) {
+    RPQ_DISPATCH_W(W, hipLaunchKernelGGL(k_select_g<WW>, dim3(grid), dim3(BLOCK), 0, s, pdev));
+    RPQ_DISPATCH_W(W, hipLaunchKernelGGL(k_expand_g<WW>, dim3(grid), dim3(BLOCK), 0, s, pdev));
+    hipLaunchKernelGGL(k_advance_g, dim3(1), dim3(64), 0, s, pdev);
     return hipGetLastError();
 }
 

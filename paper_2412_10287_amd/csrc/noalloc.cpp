@@ -18,17 +18,17 @@ using namespace rpq;
 
 namespace {
 
-// The array. Every GPU the library runs on holds its own copy (at its own
-// address) from the first call on that GPU until the process ends.
+// The array itself (RPQ_NOALLOC_SCRATCH_BYTES) lives in stacked.hip, beside
+// the kernels that use it. Every GPU the library runs on holds its own copy
+// (at its own address) from the first call on that GPU until the process
+// ends.
 constexpr size_t SCRATCH_BYTES = RPQ_NOALLOC_SCRATCH_BYTES;
-static __device__ __align__(256) uint8_t scratch[SCRATCH_BYTES];
 
 constexpr int MAX_DEVICES = 64;
 
-// Per device: the array's device address (from hipGetSymbolAddress with that
-// device current; the host-side name `scratch` is not a device address), the
-// stacked kernel's co-resident grids, and a lock: calls on one GPU share its
-// array, so they run one at a time in this process.
+// Per device: the array's device address (noalloc_scratch_address, with that
+// device current), the stacked kernel's co-resident grids, and a lock: calls
+// on one GPU share its array, so they run one at a time in this process.
 struct DevScratch {
     std::mutex mu;
     bool ready = false;
@@ -40,7 +40,7 @@ DevScratch g_dev[MAX_DEVICES];
 // Once per device, with that device current.
 rpq_status setup(DevScratch &d) {
     void *ptr = nullptr;
-    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    const hipError_t e = noalloc_scratch_address(&ptr);
     if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
     for (int G : {1, 2, 4, 8, 16}) {
         d.grid[0][G] = stacked_grid(G, 8);

@@ -202,6 +202,10 @@ struct StateView {
     // [6] 1 after a barrier abort, [7] hserial once the launch has finished.
     uint32_t *hstat;
     uint32_t hserial;
+    // Levels in captured graphs (RPQ_GRAPH_LEVELS): [0] the level the next
+    // select runs, [1] 1 once a level's expansion produced no candidates,
+    // [2] the number of levels then.
+    uint32_t *gctl;
 };
 
 struct Params {
@@ -222,6 +226,10 @@ hipError_t launch_init(int W, const Params &p, hipStream_t s);
 hipError_t launch_select(int W, const Params &p, uint32_t level, int grid, hipStream_t s);
 hipError_t launch_expand(int W, const Params &p, uint32_t level, int grid, hipStream_t s);
 hipError_t launch_final(int W, const Params &p, uint32_t nlevels, int grid, hipStream_t s);
+// One captured level (select, expansion, advance) reading its Params from
+// device memory and its level from p->st.gctl; every kernel of a level after
+// the last returns at once.
+hipError_t launch_level_g(int W, const Params *pdev, int grid, hipStream_t s);
 hipError_t launch_fill(uint32_t *ptr, uint64_t words, uint32_t value, hipStream_t s);
 
 }  // namespace rpq

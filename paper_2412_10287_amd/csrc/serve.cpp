@@ -156,7 +156,10 @@ static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
                     (long long)budget, (unsigned long long)(fixed + per_slot));
     slots = static_cast<uint32_t>(std::min<uint64_t>(slots, (budget - fixed) / per_slot));
     if (slots < 1) slots = 1;
-    ss->slots = slots;
+    {
+        std::lock_guard<std::mutex> lk(ss->mu);
+        ss->slots = slots;
+    }
     MultiParams &p = ss->mp;
     p.g = g->gv;
     p.slots = slots;
@@ -645,6 +648,13 @@ void rpq::serve_shutdown(rpq_graph *g) {
     for (void *p : ss->allocs) (void)hipFree(p);
     delete ss;
     g->serve = nullptr;
+}
+
+int64_t rpq::serve_slots(rpq_graph *g) {
+    ServeState *ss = g->serve;
+    if (!ss) return 0;
+    std::lock_guard<std::mutex> lk(ss->mu);
+    return static_cast<int64_t>(ss->slots);
 }
 
 bool rpq::serve_pending(rpq_graph *g) {

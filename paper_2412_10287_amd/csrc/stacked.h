@@ -51,7 +51,10 @@ struct StackParams {
 
 // QM is the state bound the kernel is compiled for: 8 (every state set fits a
 // byte; enables the pull direction) or 32.
-hipError_t launch_stacked(int G, int QM, const StackParams &p, int grid, hipStream_t s);
+hipError_t launch_stacked(int G, int QM, const StackParams &p, int grid, bool cooperative, hipStream_t s);
 int stacked_grid(int G, int QM);
+// Device address of the fixed scratch array (RPQ_NOALLOC_SCRATCH_BYTES) on
+// the current device.
+hipError_t noalloc_scratch_address(void **ptr);
 
 }  // namespace rpq

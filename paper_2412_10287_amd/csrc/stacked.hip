@@ -27,6 +27,7 @@
 //           edge-balanced pass after a barrier.
 // After the last level an extract phase turns the rows of final states into
 // one result bitmap per source and resets P.
+#include "../../include/rpq.h"
 #include "device_common.h"
 #include "stacked.h"
 
@@ -77,6 +78,25 @@ __device__ __forceinline__ uint32_t queue_len(const StackParams &p, const LevelR
         return V;
     }
     return nq;
+}
+
+// Candidate and frontier state sets, one 32-bit word per vertex. (A byte per
+// vertex for automata of up to 8 states was measured: 3 ms slower per kg
+// launch, the atomics on words that four vertices share collide.)
+template <int QM>
+__device__ __forceinline__ uint32_t sup_ld(const uint32_t *a, uint32_t v) {
+    return ldc(a + v);
+}
+
+template <int QM>
+__device__ __forceinline__ void sup_st(uint32_t *a, uint32_t v, uint32_t x) {
+    a[v] = x;
+}
+
+// OR x into v's set; returns the set before.
+template <int QM>
+__device__ __forceinline__ uint32_t sup_or(uint32_t *a, uint32_t v, uint32_t x) {
+    return atomicOr(a + v, x);
 }
 
 // Bits of source word j that belong to real sources.
@@ -155,13 +175,13 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
     const uint32_t j = lane % G;
     const uint32_t grp = lane / G;
     constexpr uint32_t GPB = BLOCK / G;  // vertices per workgroup and step
+    uint32_t *sold = p.sup[(n + 1) & 1];
     // level n-1's frontier state sets live in the array level n's expansion
-    // fills: clear them. Its frontier rows may stay: every bit in them is in P
-    // already, so a later select masks them out (it rewrites every row it
-    // reads), and the extract phase clears both row buffers.
+    // fills: clear them. Its frontier rows may stay: every bit in them is in
+    // P already, so a later select masks them out (it rewrites every row it
+    // reads), and the extract phase clears them with P.
     if (n >= 1) {
         const uint32_t nprev = queue_len(p, rec[(n - 1) % REC_RING]);
-        uint32_t *sold = p.sup[(n + 1) & 1];
         const int32_t *qold = p.q[(n + 1) & 1];
         const uint32_t stride = nblk * BLOCK;
         for (uint32_t i0 = bid * BLOCK + threadIdx.x; i0 < nprev; i0 += 8 * stride) {
@@ -174,7 +194,7 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
 #pragma unroll
             for (int k = 0; k < 8; k++) {
                 if (i0 + k * stride >= nprev) continue;
-                if (vv[k] < V) sold[vv[k]] = 0;
+                if (vv[k] < V) sup_st<QM>(sold, vv[k], 0u);
                 else sviol(p);
             }
         }
@@ -194,7 +214,7 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
         if (i < nq) {
             w = static_cast<uint32_t>(ldc(&qc[i]));
             if (w < V) {
-                cs = ldc(&sc[w]) & qmask;
+                cs = sup_ld<QM>(sc, w) & qmask;
                 ok = true;
             } else {
                 if (j == 0) sviol(p);
@@ -235,7 +255,7 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
             if (j == 0) c_wb += 2ull * Wv;
         }
         if (ok && j == 0) {
-            sc[w] = S;
+            sup_st<QM>(sc, w, S);
             if (S) nfront++;
             su |= S;
         }
@@ -411,7 +431,7 @@ __device__ __forceinline__ void unit_gather(const StackParams &p, uint32_t n, co
     const uint32_t w = PULL ? iv : other;
     const uint32_t *succ = s_qv.succ + u * MAX_STATES;
     const uint32_t tmask = PULL ? ns : ~0u;
-    const uint32_t S = (PULL ? (ldc(&p.sup[n & 1][src]) & L.s[lo]) : L.s[lo]) & state_mask(p);
+    const uint32_t S = (PULL ? (sup_ld<QM>(p.sup[n & 1], src) & L.s[lo]) : L.s[lo]) & state_mask(p);
     U.dst = w;
     if constexpr (QM <= 8) {
         // y[q'] = OR of the source's rows over the transitions into q'
@@ -476,7 +496,7 @@ template <int G, int QM>
 __device__ __forceinline__ void unit_append(const StackParams &p, uint32_t n, uint32_t j, const UnitC<QM> &U) {
     const uint32_t tg = group_or<G>(U.tb);
     bool first = false;
-    if (tg && j == 0) first = atomicOr(&p.sup[(n + 1) & 1][U.dst], tg) == 0u;
+    if (tg && j == 0) first = sup_or<QM>(p.sup[(n + 1) & 1], U.dst, tg) == 0u;
     if (!block_append(first, static_cast<int32_t>(U.dst), p.q[(n + 1) & 1], &p.rec[(n + 1) % REC_RING].nq,
                       static_cast<uint32_t>(p.V)))
         sviol(p);
@@ -495,14 +515,14 @@ __device__ __forceinline__ void unit_append4(const StackParams &p, uint32_t n, u
     // states (values read during the phase only ever lack bits, never have
     // extra ones), and a load costs far less than an atomic
     uint32_t o0 = 1, o1 = 1, o2 = 1, o3 = 1;
-    if (t0 && lead) o0 = ldc(&sn[U0.dst]);
-    if (t1 && lead) o1 = ldc(&sn[U1.dst]);
-    if (t2 && lead) o2 = ldc(&sn[U2.dst]);
-    if (t3 && lead) o3 = ldc(&sn[U3.dst]);
-    if (t0 && lead && (o0 & t0) != t0) o0 = atomicOr(&sn[U0.dst], t0);
-    if (t1 && lead && (o1 & t1) != t1) o1 = atomicOr(&sn[U1.dst], t1);
-    if (t2 && lead && (o2 & t2) != t2) o2 = atomicOr(&sn[U2.dst], t2);
-    if (t3 && lead && (o3 & t3) != t3) o3 = atomicOr(&sn[U3.dst], t3);
+    if (t0 && lead) o0 = sup_ld<QM>(sn, U0.dst);
+    if (t1 && lead) o1 = sup_ld<QM>(sn, U1.dst);
+    if (t2 && lead) o2 = sup_ld<QM>(sn, U2.dst);
+    if (t3 && lead) o3 = sup_ld<QM>(sn, U3.dst);
+    if (t0 && lead && (o0 & t0) != t0) o0 = sup_or<QM>(sn, U0.dst, t0);
+    if (t1 && lead && (o1 & t1) != t1) o1 = sup_or<QM>(sn, U1.dst, t1);
+    if (t2 && lead && (o2 & t2) != t2) o2 = sup_or<QM>(sn, U2.dst, t2);
+    if (t3 && lead && (o3 & t3) != t3) o3 = sup_or<QM>(sn, U3.dst, t3);
     if (!block_append4(o0 == 0, static_cast<int32_t>(U0.dst), o1 == 0, static_cast<int32_t>(U1.dst), o2 == 0,
                        static_cast<int32_t>(U2.dst), o3 == 0, static_cast<int32_t>(U3.dst), p.q[(n + 1) & 1],
                        &p.rec[(n + 1) % REC_RING].nq, static_cast<uint32_t>(p.V)))
@@ -718,7 +738,7 @@ __device__ __forceinline__ void st_pull_rows(const StackParams &p, uint32_t n, u
 #pragma unroll
                         for (int a = 0; a < 4; a++) vv[a] = e0 + a < end ? g.col[e0 + a] : V;
 #pragma unroll
-                        for (int a = 0; a < 4; a++) sv[a] = vv[a] < V ? (ldc(&sc[vv[a]]) & pu) : 0u;  // pu: states only
+                        for (int a = 0; a < 4; a++) sv[a] = vv[a] < V ? (sup_ld<8>(sc, vv[a]) & pu) : 0u;  // pu: states only
 #pragma unroll
                         for (int a = 0; a < 4; a++) {
 #pragma unroll
@@ -758,7 +778,7 @@ __device__ __forceinline__ void st_pull_rows(const StackParams &p, uint32_t n, u
                 wave_excl_scan(hl ? ((1ull << 32) | static_cast<uint64_t>(end - beg)) : 0ull, htot);
             tb = group_or<G>(tb);
             bool first = false;
-            if (tb && j == 0) first = atomicOr(&sn[w], tb) == 0u;
+            if (tb && j == 0) first = sup_or<8>(sn, w, tb) == 0u;
             const uint64_t fm = __ballot(first);
             uint64_t hbase;
             uint32_t qbase;
@@ -795,7 +815,7 @@ __device__ __forceinline__ uint32_t st_decide(const StackParams &p, uint32_t n, 
 // Result: source b reaches v iff some final state's row at v has bit b. One
 // wavefront per (64-vertex block, word): 64 ballots transpose the block into
 // one output word per source. P and the last frontier are reset.
-template <int G>
+template <int G, int QM>
 __device__ __forceinline__ void st_final(const StackParams &p, uint32_t nexit, uint32_t levels) {
     const uint32_t V = static_cast<uint32_t>(p.V);
     const uint32_t Q = static_cast<uint32_t>(p.Q);
@@ -811,18 +831,13 @@ __device__ __forceinline__ void st_final(const StackParams &p, uint32_t nexit, u
         const int32_t *q = p.q[D & 1];
         for (uint32_t i = gthread(); i < nq; i += gthreads()) {
             const uint32_t v = static_cast<uint32_t>(ldc(&q[i]));
-            if (v < V) sp[v] = 0;
+            if (v < V) sup_st<QM>(sp, v, 0u);
             else sviol(p);
         }
     }
-    {
-        const uint64_t words = static_cast<uint64_t>(V) * Q * G;  // both buffers hold words + 64 entries
-        for (int b = 0; b < 2; b++) {
-            uint4 *m4 = reinterpret_cast<uint4 *>(p.M[b]);
-            for (uint64_t i = gthread(); i < words / 2; i += gthreads()) m4[i] = make_uint4(0, 0, 0, 0);
-            if (gthread() == 0 && (words & 1)) p.M[b][words - 1] = 0;
-        }
-    }
+    // Row words of M are cleared below with P's: every bit an expansion ORs
+    // into M is added to P by the next select (or was there already), so M
+    // is zero wherever P is.
     const uint32_t fm = s_qv.h->fmask;
     const uint64_t nwords = static_cast<uint64_t>(p.nwords);
     const uint64_t total = nwords * G;
@@ -839,6 +854,8 @@ __device__ __forceinline__ void st_final(const StackParams &p, uint32_t nexit, u
                 if (x) {
                     if (fm >> q & 1u) f |= x;
                     p.P[idx] = 0;
+                    p.M[0][idx] = 0;
+                    p.M[1][idx] = 0;
                 }
             }
         }
@@ -940,7 +957,7 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
             atomicOr(reinterpret_cast<unsigned long long *>(p.M[0] + rowi<G>(p, s, q) + (i >> 6)),
                      static_cast<unsigned long long>(bit));
         }
-        if (atomicOr(&p.sup[0][s], h.smask) == 0) {
+        if (sup_or<QM>(p.sup[0], s, h.smask) == 0) {
             const uint32_t pos = atomicAdd(&p.rec[0].nq, 1u);
             if (pos < V) p.q[0][pos] = static_cast<int32_t>(s);
             else sviol(p);
@@ -1006,7 +1023,7 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
         atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[threadIdx.x - 3]), static_cast<unsigned long long>(cacc));
     // the last level may have found only visited pairs
     const uint32_t levels = (n > 0 && last_pairs == 0) ? n - 1 : n;
-    st_final<G>(p, n, levels);
+    st_final<G, QM>(p, n, levels);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         p.status[0] = levels;
         p.status[1] = npush;
@@ -1014,12 +1031,20 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
     }
 }
 
+// The grid is sized to be resident on an otherwise idle GPU and the process
+// runs one persistent grid per device at a time, so an ordinary launch
+// suffices; hipLaunchCooperativeKernel (which also guarantees residency
+// against other processes) is the option.
 template <int G, int QM>
-static hipError_t launch_g(const StackParams &p, int grid, hipStream_t s) {
+static hipError_t launch_g(const StackParams &p, int grid, bool cooperative, hipStream_t s) {
     StackParams a = p;
-    void *args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_stacked<G, QM>), dim3(grid), dim3(BLOCK),
-                                      args, 0, s);
+    if (cooperative) {
+        void *args[] = {&a};
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_stacked<G, QM>), dim3(grid), dim3(BLOCK),
+                                          args, 0, s);
+    }
+    hipLaunchKernelGGL((k_stacked<G, QM>), dim3(grid), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
 }
 
 #define RPQ_STACKED_DISPATCH(G, QM, CALL8, CALL32)             \
@@ -1041,11 +1066,22 @@ static hipError_t launch_g(const StackParams &p, int grid, hipStream_t s) {
         }                                                      \
     }
 
-hipError_t launch_stacked(int G, int QM, const StackParams &p, int grid, hipStream_t s) {
+hipError_t launch_stacked(int G, int QM, const StackParams &p, int grid, bool cooperative, hipStream_t s) {
     hipError_t e = hipSuccess;
-    RPQ_STACKED_DISPATCH(G, QM, (e = launch_g<GG, 8>(p, grid, s)), (e = launch_g<GG, 32>(p, grid, s)));
+    RPQ_STACKED_DISPATCH(G, QM, (e = launch_g<GG, 8>(p, grid, cooperative, s)),
+                         (e = launch_g<GG, 32>(p, grid, cooperative, s)));
     return e;
 }
+
+// The fixed device array behind rpq_multi_source_noalloc, in the module of
+// the kernels that use it (so no module of its own is registered). Host code
+// never passes `scratch` itself to a kernel: in host code the name is a
+// host-side stand-in, and the device address comes from hipGetSymbolAddress
+// below, once per device with that device current (each GPU holds its own
+// copy at its own address from then until the process ends).
+static __device__ __align__(256) uint8_t scratch[RPQ_NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch_address(void **ptr) { return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch)); }
 
 int stacked_grid(int G, int QM) {
     int dev = 0, ncu = 0, per = 0;

@@ -255,7 +255,7 @@ rpq_status rpq::stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         // synchronisation below, at the end of this batch)
         std::unique_lock<std::mutex> plk(persistent_mutex(g->device));
         BT(hipEventRecord(g->ev[2], s));
-        BT(launch_stacked(G, QM, p, grid, s));
+        BT(launch_stacked(G, QM, p, grid, g->coop_launch, s));
         BT(hipEventRecord(g->ev[3], s));
         uint32_t *hst = reinterpret_cast<uint32_t *>(pin + g->qconst_cap + 4 * 1024);
         uint64_t *hcnt = reinterpret_cast<uint64_t *>(pin + g->qconst_cap + 4 * 1024 + 64);

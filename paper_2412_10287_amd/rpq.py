@@ -22,14 +22,16 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librpq.so")
+# The in-tree build; RPQ_LIB names another build of the same library (for
+# instance to compare two builds in one process environment).
+LIB_PATH = os.environ.get("RPQ_LIB") or os.path.join(HERE, "librpq.so")
 
 RPQ_OK, RPQ_PENDING = 0, 1
 RPQ_EINVAL, RPQ_ENOMEM, RPQ_EDEVICE, RPQ_EAGAIN, RPQ_ENOTFOUND, RPQ_ETIMEDOUT = -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "RPQ_OK", 1: "RPQ_PENDING", -1: "RPQ_EINVAL", -2: "RPQ_ENOMEM", -3: "RPQ_EDEVICE",
                 -4: "RPQ_EAGAIN", -5: "RPQ_ENOTFOUND", -6: "RPQ_ETIMEDOUT"}
 
-OUT_DEVICE, COUNTERS, KERNEL_TIMING, FORCE_PUSH, FORCE_PULL, HOST_LOOP = 1, 2, 4, 8, 16, 32
+OUT_DEVICE, COUNTERS, KERNEL_TIMING, FORCE_PUSH, FORCE_PULL, HOST_LOOP, GRAPH_LEVELS = 1, 2, 4, 8, 16, 32, 64
 
 EXPORTS = ("rpq_bitmap_words", "rpq_graph_load", "rpq_graph_free", "rpq_graph_info", "rpq_set_option",
            "rpq_get_option", "rpq_nfa_load", "rpq_nfa_free", "rpq_single_source", "rpq_single_destination",

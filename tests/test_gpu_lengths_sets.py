@@ -18,7 +18,8 @@ from workloads import graphs as G
 from workloads import regex as R
 import oracle_cases as OC
 
-MODES = {"auto": 0, "push": 8, "pull": 16, "hostloop": 32, "hostloop-pull": 32 | 16}
+MODES = {"auto": 0, "push": 8, "pull": 16, "hostloop": 32, "hostloop-pull": 32 | 16, "graph": 64,
+         "graph-pull": 64 | 16}
 
 
 @pytest.fixture(scope="module")

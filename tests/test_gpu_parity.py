@@ -19,7 +19,8 @@ def rpq():
     return mod
 
 
-MODES = {"auto": 0, "push": 8, "pull": 16, "hostloop": 32, "hostloop-pull": 32 | 16}
+MODES = {"auto": 0, "push": 8, "pull": 16, "hostloop": 32, "hostloop-pull": 32 | 16, "graph": 64,
+         "graph-pull": 64 | 16}
 
 
 def _run(rpq, gg, nfa_h, src, flags=0, level_cap=0):

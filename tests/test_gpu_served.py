@@ -222,3 +222,37 @@ def test_large_queries_run_alone(rpq):
             assert st.levels == r.levels and st.visited_pairs == int(r.level_counts.sum()), (rnd, text)
         if rnd == 1:
             assert all(st.batch == 1 for _, st in res)
+
+
+def test_memory_budget_admission(rpq):
+    # budgets that hold one or two slots (each slot costs about 144 KB of
+    # state and query constants on this 3000-vertex graph, plus about 88 KB
+    # shared): the engine admits that many queries at once, the rest wait in
+    # the queue, and every answer is the oracle's; a budget below one slot
+    # fails every ticket with RPQ_ENOMEM and the handle can still be freed
+    w = C.er_workload(n=3000, m=12000, num_labels=4, n_queries=24)
+    og = oracle.Graph(w.graph)
+    want = [og.ssr(n, int(s)).bitmap for n, s in zip(w.nfas, w.sources)]
+    for budget, lo, hi in ((500 << 10, 1, 2), (300 << 10, 1, 1)):
+        gg = rpq.Graph(w.graph)
+        gg.set_option("serve_stack_min", 0)
+        gg.set_option("mem_budget", budget)
+        nh = [rpq.NFA(n) for n in w.nfas]
+        tickets = [gg.submit(h, int(s)) for h, s in zip(nh, w.sources)]
+        got = [gg.poll(t, timeout_us=30_000_000) for t in tickets]
+        slots = gg.info("serve_slots")
+        print("budget", budget, "slots", slots, flush=True)
+        assert lo <= slots <= hi, (budget, slots)
+        for i, r in enumerate(got):
+            assert r is not None and np.array_equal(r[0], want[i]), (budget, i)
+        gg.close()
+    gg = rpq.Graph(w.graph)
+    gg.set_option("mem_budget", 200 << 10)
+    nh = rpq.NFA(w.nfas[0])
+    # the engine starts with the first submit; its failure reaches that
+    # ticket's poll, or the submit itself when the engine failed first
+    with pytest.raises(rpq.RPQError) as e:
+        t = gg.submit(nh, int(w.sources[0]))
+        gg.poll(t, timeout_us=30_000_000)
+    assert e.value.status in (rpq.RPQ_ENOMEM, rpq.RPQ_EDEVICE) and "budget" in str(e.value)
+    gg.close()
