@@ -565,19 +565,29 @@ def bench_grid(args):
             rpq.device_synchronize()
             dt = (time.perf_counter() - t0) / args.steps
             rows = out.to_host().reshape(B, words)
-            # plain on the first 4 sources (each pays every level alone)
+            # plain on the first 4 sources (each pays every level alone), and
+            # the same queries with levels driven from the host, one launch
+            # per phase or as replays of a captured graph of 16 levels
             pt = []
             for s in srcs[:4]:
                 t = time.perf_counter()
                 g.single_source(nh, s, out_device_ptr=out.ptr)
                 pt.append(time.perf_counter() - t)
+            modes = {}
+            for mname, fl in (("persistent", 0), ("graph_levels", rpq.GRAPH_LEVELS), ("host_loop", rpq.HOST_LOOP)):
+                g.single_source(nh, srcs[1], flags=fl, out_device_ptr=out.ptr)  # warm-up (captures the graph)
+                t = time.perf_counter()
+                _, sm = g.single_source(nh, srcs[1], flags=fl, out_device_ptr=out.ptr)
+                dtm = time.perf_counter() - t
+                modes[mname] = {"ms": round(dtm * 1e3, 3), "levels": int(sm.levels),
+                                "us_per_level": round(dtm * 1e6 / max(sm.levels, 1), 2)}
             key = "%s %s" % ("shortcuts-1%" if frac else "no-shortcuts", text)
             variants[key] = {"levels": int(lv), "batch_ms": round(dt * 1e3, 3),
                              "kernel_ms": round(float(np.mean(kms)), 3),
                              "us_per_level": round(float(np.mean(kms)) * 1e3 / max(lv, 1), 2),
                              "levels_per_s": round(lv / (float(np.mean(kms)) * 1e-3), 1),
                              "qps": round(B / dt, 2), "gteps": round(pe / dt / 1e9, 4),
-                             "plain_qps": round(len(pt) / sum(pt), 2),
+                             "plain_qps": round(len(pt) / sum(pt), 2), "plain_modes": modes,
                              "alg_bytes_per_launch": int(st.alg_bytes)}
             if frac == 0.0:
                 bad = 0
@@ -714,13 +724,24 @@ def bench_serve(args):
     for h, s in zip(handles, srcs):
         g.single_source(h, int(s), out_device_ptr=out.ptr)
     plain_sat = N / (time.perf_counter() - t)
-    slots = g.get_option("max_slots")
+    # the same stream through the plain path with the rare-end plan allowed
+    # (queries with at most 1024 candidate endpoints run backwards from them)
+    g.set_option("rare_end_max", 1024)
+    plans = 0
+    t = time.perf_counter()
+    for i, (h, s) in enumerate(zip(handles, srcs)):
+        _, st = g.single_source(h, int(s), out_device_ptr=dst(i))
+        plans += st.plan
+    rare_sat = N / (time.perf_counter() - t)
+    rare_rows = keep.to_host().reshape(-1, words)[:len(sample)].copy()
+    g.set_option("rare_end_max", 0)
+    slots = g.info("serve_slots")
     g.close()
     out.close()
     keep.close()
     want = [r[0] for r in runs.results()]
     parity = {"served_saturated": parity_of(sat_rows, want), "served_open_loop": parity_of(open_rows, want),
-              "plain": parity_of(plain_rows, want),
+              "plain": parity_of(plain_rows, want), "plain_rare_end": parity_of(rare_rows, want),
               "sample": "%d of the %d queries (seeded), bitmaps against the oracle" % (len(sample), N)}
     res = {
         "metric": "queries/s and p50/p99 latency, served path under Poisson arrivals",
@@ -738,6 +759,9 @@ def bench_serve(args):
                   "latency_ms_p50": round(percentile(plat, 50) * 1e3, 3),
                   "latency_ms_p99": round(percentile(plat, 99) * 1e3, 3),
                   "saturated_qps": round(plain_sat, 2)},
+        "plain_rare_end": {"saturated_qps": round(rare_sat, 2), "queries_on_rare_end_plan": int(plans),
+                           "note": "plain path with rare_end_max 1024: queries with at most 1024 candidate "
+                                   "endpoints run as one reversed stacked traversal from them"},
         "arrival_qps": round(rate, 2),
         "parity": parity,
     }
@@ -768,7 +792,7 @@ def main():
                     help="JSON file for the autotuner's choices (reused when present, e.g. so that "
                          "profiler passes run the settings of an earlier timed run)")
     ap.add_argument("--serve-queries", type=int, default=2000, help="serve: queries in the stream")
-    ap.add_argument("--serve-parity", type=int, default=512, help="serve: queries checked against the oracle")
+    ap.add_argument("--serve-parity", type=int, default=128, help="serve: queries checked against the oracle")
     ap.add_argument("--max-slots", type=int, default=0, help="served path: concurrent queries (0 = library default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (for traffic-counter calibration)")

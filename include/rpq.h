@@ -57,6 +57,8 @@ typedef uint64_t rpq_ticket;
 #define RPQ_FORCE_PUSH 8u   /* never use the pull direction (testing / tuning) */
 #define RPQ_FORCE_PULL 16u  /* use the pull direction from level 1 on (testing / tuning) */
 #define RPQ_HOST_LOOP 32u   /* drive levels from the host instead of one persistent launch */
+#define RPQ_RARE_END 128u   /* rpq_single_source: the rare-end plan (see "rare_end_max"); RPQ_EINVAL
+                                when it does not apply */
 #define RPQ_GRAPH_LEVELS 64u /* single-query paths: levels as replays of a captured HIP graph of
                                 16 levels (select, expansion, advance kernels), the end checked
                                 once per replay; the graph is captured at first use per handle */
@@ -121,6 +123,12 @@ typedef struct {
        launches with other queries, so it has no device time of its own and
        device_ms is 0 for it. */
     double latency_ms;
+    /* out, rpq_single_source: 0 = the forward traversal from the source;
+       1 = the rare-end plan (RPQ_RARE_END or option "rare_end_max"): one
+       stacked traversal of the reversed automaton from the candidate
+       endpoints; levels, push/pull levels, visited_pairs and times then
+       describe that traversal and batch is the number of candidates. */
+    int32_t plan;
 } rpq_stats;
 
 /* Number of uint64 words of a reachable-vertex bitmap over V vertices. */
@@ -172,6 +180,16 @@ rpq_status rpq_graph_info(const rpq_graph *g, const char *key, int64_t *value);
  *  "max_batch"   largest number of sources stacked in one launch (<= 1024).
  *  "mem_budget"  device bytes the served path may use for query state.
  *  "max_slots"   concurrent queries in the served path.
+ *  "rare_end_max"  rpq_single_source evaluates from the rare end when the
+ *                query's candidate endpoints number at most this many (<=
+ *                1024; default 0 = never): every vertex other than the source
+ *                that a query can return is an endpoint of an edge whose
+ *                symbol leads into a final state; when those vertices are
+ *                few, one stacked traversal of the reversed automaton from
+ *                all of them (Sec. 4's reversal; the evaluation-order hybrid
+ *                of Secs 5.5 and 6) finds which of them reach the source. The
+ *                answer is identical; the plan is not taken with per-level
+ *                outputs, counters, or direction and level-driver flags.
  *  "serve_stack_min"  waiting served requests of one NFA handle that run as
  *                one stacked group (default 32; 0 = never).
  *  "large_query_pairs", "large_query_slots"  while the moving average of

@@ -471,6 +471,9 @@ rpq_status rpq_set_option(rpq_graph *g, const char *key, int64_t value) {
         if (value < 0 || value > MAX_SLOTS)
             return fail(RPQ_EINVAL, "rpq_set_option: large_query_slots outside [0, %d]", MAX_SLOTS);
         g->large_slots = static_cast<int32_t>(value);
+    } else if (!strcmp(key, "rare_end_max")) {
+        if (value < 0 || value > MAX_BATCH) return fail(RPQ_EINVAL, "rpq_set_option: rare_end_max outside [0, %d]", MAX_BATCH);
+        g->rare_end_max = value;
     } else if (!strcmp(key, "serve_stack_min")) {
         if (value < 0 || value > MAX_BATCH)
             return fail(RPQ_EINVAL, "rpq_set_option: serve_stack_min outside [0, %d]", MAX_BATCH);
@@ -501,6 +504,7 @@ rpq_status rpq_get_option(const rpq_graph *g, const char *key, int64_t *value) {
     else if (!strcmp(key, "large_query_pairs")) *value = g->large_pairs;
     else if (!strcmp(key, "large_query_slots")) *value = g->large_slots;
     else if (!strcmp(key, "serve_stack_min")) *value = g->serve_stack_min;
+    else if (!strcmp(key, "rare_end_max")) *value = g->rare_end_max;
     else if (!strcmp(key, "cooperative_launch")) *value = g->coop_launch ? 1 : 0;
     else if (!strcmp(key, "grid")) *value = g->grid_override;
     else return fail(RPQ_ENOTFOUND, "rpq_get_option: unknown key '%s'", key);
@@ -797,6 +801,106 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
     return RPQ_OK;
 }
 
+static void reverse_nfa(const rpq_nfa *n, rpq_nfa &rev);
+
+// The rare-end plan (the evaluation-order hybrid Sec. 5.5 and Sec. 6 call
+// for on rare labels). A walk the NFA accepts ends either at the source
+// (the zero-length walk, when a start state is final) or with a step into a
+// final state, so every answer vertex other than the source is an endpoint
+// of an edge under a symbol of some transition into a final state: the
+// candidates T. When T is small, the answer is the candidates t from which
+// the reversed automaton reaches the source (t in SSR(s, R) iff s in
+// SSR(t, R reversed)), found by one stacked traversal from all of T that
+// only reports, per candidate, whether the source was reached in a final
+// state. The answer is identical to the forward traversal's.
+// Sets *used when the plan ran; returns an error only when it was forced and
+// does not apply, or when it failed.
+static rpq_status rare_end(rpq_graph *g, const rpq_nfa *n, int32_t source, uint64_t *out, uint32_t flags,
+                           rpq_stats *stats, bool *used) {
+    *used = false;
+    const bool forced = (flags & RPQ_RARE_END) != 0;
+    const int64_t limit = forced ? MAX_BATCH : std::min<int64_t>(g->rare_end_max, MAX_BATCH);
+    if (limit <= 0) return RPQ_OK;
+    const uint32_t excl = RPQ_HOST_LOOP | RPQ_GRAPH_LEVELS | RPQ_COUNTERS | RPQ_FORCE_PUSH | RPQ_FORCE_PULL;
+    if ((flags & excl) || (stats && stats->level_cap > 0)) {
+        if (forced)
+            return fail(RPQ_EINVAL, "rpq_single_source: RPQ_RARE_END excludes per-level outputs, counters and "
+                                    "direction or level-driver flags");
+        return RPQ_OK;
+    }
+    const int32_t L = g->L;
+    // (direction, label) whose rows are the candidate endpoints
+    std::vector<uint64_t> parts;
+    int64_t total = 0;
+    for (const Trans &t : n->trans) {
+        if (!((n->fmask >> t.to) & 1u)) continue;
+        const bool inv = t.sym >= n->NL;
+        const int32_t lab = inv ? t.sym - n->NL : t.sym;
+        if (lab >= L || g->label_edges[lab] == 0) continue;
+        // a step with label l ends at the head of an l-edge (a row of the
+        // transposed direction); with its inverse at the tail (a row of G^l)
+        const uint64_t key = static_cast<uint64_t>(inv ? OUT : IN) * L + lab;
+        if (std::find(parts.begin(), parts.end(), key) != parts.end()) continue;
+        parts.push_back(key);
+        total += g->label_rows[inv ? OUT : IN][lab];
+    }
+    if (total > limit) {
+        if (forced)
+            return fail(RPQ_EINVAL, "rpq_single_source: %lld candidate endpoints exceed the %d of RPQ_RARE_END",
+                        (long long)total, MAX_BATCH);
+        return RPQ_OK;
+    }
+    hipStream_t s = g->user_stream ? g->user_stream : g->stream;
+    std::vector<int32_t> cand(static_cast<size_t>(total));
+    size_t at = 0;
+    for (uint64_t key : parts) {
+        const int dir = static_cast<int>(key / L);
+        const int32_t lab = static_cast<int32_t>(key % L);
+        const int64_t rows = g->label_rows[dir][lab];
+        if (rows)
+            HIP_TRY(hipMemcpy(cand.data() + at, g->gv.rowvert + g->rbase[key], 4 * static_cast<size_t>(rows),
+                              hipMemcpyDeviceToHost));
+        at += static_cast<size_t>(rows);
+    }
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    for (int32_t v : cand)
+        if (v < 0 || v >= g->V) return fail(RPQ_EDEVICE, "rpq_single_source: corrupt row vertex %d", v);
+    std::vector<uint64_t> ans(static_cast<size_t>(g->nwords), 0ull);
+    rpq_stats st2{};
+    if (!cand.empty()) {
+        rpq_nfa rev;
+        reverse_nfa(n, rev);
+        uint64_t hit[MAX_BATCH / 64];
+        const rpq_status r = stacked_run(g, &rev, cand.data(), static_cast<int32_t>(cand.size()), hit, 0, &st2,
+                                         "rpq_single_source (rare-end plan)", nullptr, source);
+        if (r != RPQ_OK) return r;
+        for (size_t i = 0; i < cand.size(); i++)
+            if ((hit[i >> 6] >> (i & 63)) & 1ull) ans[static_cast<size_t>(cand[i]) >> 6] |= 1ull << (cand[i] & 63);
+    }
+    if (n->smask & n->fmask) ans[static_cast<size_t>(source) >> 6] |= 1ull << (source & 63);
+    if (flags & RPQ_OUT_DEVICE) {
+        HIP_TRY(hipMemcpyAsync(out, ans.data(), 8 * ans.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    } else {
+        memcpy(out, ans.data(), 8 * ans.size());
+    }
+    if (stats) {
+        stats_reset(stats);
+        stats->levels = st2.levels;
+        stats->push_levels = st2.push_levels;
+        stats->pull_levels = st2.pull_levels;
+        stats->visited_pairs = st2.visited_pairs;
+        stats->device_ms = st2.device_ms;
+        stats->expand_ms = st2.expand_ms;
+        stats->expand_launches = st2.expand_launches;
+        stats->batch = static_cast<int32_t>(cand.size());
+        stats->plan = 1;
+    }
+    *used = true;
+    return RPQ_OK;
+}
+
 rpq_status rpq_single_source(rpq_graph *g, const rpq_nfa *n, int32_t source, uint64_t *out_bitmap,
                              uint32_t flags, rpq_stats *stats) {
     if (!g || !n || !out_bitmap) return fail(RPQ_EINVAL, "rpq_single_source: NULL argument");
@@ -806,13 +910,34 @@ rpq_status rpq_single_source(rpq_graph *g, const rpq_nfa *n, int32_t source, uin
         return fail(RPQ_EINVAL, "rpq_single_source: RPQ_FORCE_PUSH and RPQ_FORCE_PULL together");
     std::lock_guard<std::recursive_mutex> lk(g->mu);
     HIP_TRY(hipSetDevice(g->device));
-    return run_single(g, n, source, out_bitmap, flags, stats);
+    bool used = false;
+    const rpq_status r = rare_end(g, n, source, out_bitmap, flags, stats, &used);
+    if (r != RPQ_OK || used) return r;
+    return run_single(g, n, source, out_bitmap, flags & ~RPQ_RARE_END, stats);
 }
 
 // Single-destination reachability (Sec. 2, the SDR map; Sec. 4 evaluates it
 // as the single-source query of the reversed automaton): every transition
 // turned around with its symbol inverted (a walk read backwards crosses each
 // edge the other way), start and final sets swapped.
+// The reversed automaton (reading of Sec. 4's reversal with a two-way
+// alphabet): every transition turned around with its symbol inverted (a walk
+// read backwards crosses each edge the other way), start and final sets
+// swapped.
+static void reverse_nfa(const rpq_nfa *n, rpq_nfa &rev) {
+    rev.Q = n->Q;
+    rev.NL = n->NL;
+    rev.smask = n->fmask;
+    rev.fmask = n->smask;
+    rev.serial = n->serial | (1ull << 63);  // the reversal of n, cached under its own key
+    rev.trans.clear();
+    rev.trans.reserve(n->trans.size());
+    for (const Trans &t : n->trans) {
+        const int32_t inv = t.sym < n->NL ? t.sym + n->NL : t.sym - n->NL;
+        rev.trans.push_back({inv, t.to, t.from});
+    }
+}
+
 rpq_status rpq_single_destination(rpq_graph *g, const rpq_nfa *n, int32_t target, uint64_t *out_bitmap,
                                   uint32_t flags, rpq_stats *stats) {
     if (!g || !n || !out_bitmap) return fail(RPQ_EINVAL, "rpq_single_destination: NULL argument");
@@ -821,16 +946,7 @@ rpq_status rpq_single_destination(rpq_graph *g, const rpq_nfa *n, int32_t target
     if ((flags & RPQ_FORCE_PUSH) && (flags & RPQ_FORCE_PULL))
         return fail(RPQ_EINVAL, "rpq_single_destination: RPQ_FORCE_PUSH and RPQ_FORCE_PULL together");
     rpq_nfa rev;
-    rev.Q = n->Q;
-    rev.NL = n->NL;
-    rev.smask = n->fmask;
-    rev.fmask = n->smask;
-    rev.serial = n->serial | (1ull << 63);  // the reversal of n, cached under its own key
-    rev.trans.reserve(n->trans.size());
-    for (const Trans &t : n->trans) {
-        const int32_t inv = t.sym < n->NL ? t.sym + n->NL : t.sym - n->NL;
-        rev.trans.push_back({inv, t.to, t.from});
-    }
+    reverse_nfa(n, rev);
     std::lock_guard<std::recursive_mutex> lk(g->mu);
     HIP_TRY(hipSetDevice(g->device));
     return run_single(g, &rev, target, out_bitmap, flags, stats);

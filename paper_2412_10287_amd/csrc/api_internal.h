@@ -90,6 +90,7 @@ struct rpq_graph {
     int64_t large_pairs = 1 << 21;  // served path: queries above this many reached pairs count as large
     int32_t large_slots = 0;        // concurrent served queries while recent queries are large (0: one at a time, single-query kernel)
     int32_t serve_stack_min = 32;   // waiting served requests of one NFA that run as one stacked group (0 = never)
+    int64_t rare_end_max = 0;       // rare-end plan of rpq_single_source for at most this many candidate endpoints (0 = off)
     int32_t grid_override = 0;
     int32_t plain_grid = 0;  // persistent single-query launch workgroups (0 = one per CU)
     bool coop_launch = false;  // hipLaunchCooperativeKernel for the persistent single-query kernel
@@ -113,7 +114,10 @@ struct rpq_graph {
     size_t qarena_used = 0;
     // batched and served paths
     rpq::BatchState *batch = nullptr;
-    rpq::ServeState *serve = nullptr;
+    // created by the first rpq_submit under serve_mu (not mu: a query the
+    // scheduler runs holds mu, and submits must not wait for it)
+    std::atomic<rpq::ServeState *> serve{nullptr};
+    std::mutex serve_mu;
 };
 
 namespace rpq {
@@ -147,9 +151,12 @@ struct StackArena {
 struct StackParams;
 size_t stacked_arena_layout(const rpq_graph *g, int32_t Q, int G, int32_t B, uint8_t *base, StackParams *p,
                             uint8_t **qconst, int32_t **srcs, uint64_t **out);
+// With probe >= 0 (at most MAX_BATCH sources, one batch): out_bitmaps is
+// host memory that receives ceil(n_sources / 64) words, bit i set when source
+// i reaches the vertex `probe` in a final state, instead of the bitmaps.
 rpq_status stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
                        uint64_t *out_bitmaps, uint32_t flags, rpq_stats *stats, const char *who,
-                       const StackArena *ar);
+                       const StackArena *ar, int32_t probe = -1);
 void serve_shutdown(rpq_graph *g);
 bool serve_pending(rpq_graph *g);
 // Slots the served path's engine admits queries into (0 before it exists).

@@ -624,12 +624,14 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
 }
 
 static ServeState *serve_get(rpq_graph *g) {
-    // called with g->mu held
-    if (!g->serve) {
-        g->serve = new ServeState();
-        g->serve->worker = std::thread(worker_main, g, g->serve);
+    std::lock_guard<std::mutex> lk(g->serve_mu);
+    ServeState *ss = g->serve.load();
+    if (!ss) {
+        ss = new ServeState();
+        ss->worker = std::thread(worker_main, g, ss);
+        g->serve.store(ss);
     }
-    return g->serve;
+    return ss;
 }
 
 void rpq::serve_shutdown(rpq_graph *g) {
@@ -679,7 +681,9 @@ rpq_status rpq_submit(rpq_graph *g, const rpq_nfa *n, int32_t source, rpq_ticket
     if (r.nsym > MAX_SYMS || sz > QC_STRIDE)
         return fail(RPQ_EINVAL, "rpq_submit: query uses %d symbols; the limit is %d", r.nsym, MAX_SYMS);
     r.submitted = Clock::now();
-    std::lock_guard<std::recursive_mutex> glk(g->mu);
+    // no g->mu here: the scheduler holds it while it runs a query through
+    // the single-query or stacked path, and a submit must not wait for that
+    // (requests queue up while one runs, and can then run as a group)
     ServeState *ss = serve_get(g);
     std::lock_guard<std::mutex> lk(ss->mu);
     if (ss->failed) return fail(RPQ_EDEVICE, "served path failed earlier: %s", ss->fail_msg.c_str());

@@ -42,7 +42,8 @@ struct StackParams {
     uint32_t *status;        // [0] levels, [1] push levels, [2] pull levels, [3] invariant violations
     uint64_t *cnt;           // ST_NCNT work counters (ST_CNT_*), summed over the launch
     uint64_t *lvl;           // per-level statistics (LVL_STRIDE words), pairs summed over sources
-    uint64_t *out;           // B bitmaps of nwords words
+    uint64_t *out;           // B bitmaps of nwords words; with a probe, G words: bit b = source b reaches the probe
+    uint32_t probe;          // a vertex < V: only whether each source reaches it (in a final state) is written
     const int32_t *sources;  // B vertex ids
     uint64_t item_cap, tile_cap;
     int64_t nwords;

@@ -842,12 +842,29 @@ __device__ __forceinline__ void st_final(const StackParams &p, uint32_t nexit, u
     const uint64_t nwords = static_cast<uint64_t>(p.nwords);
     const uint64_t total = nwords * G;
     const uint32_t B = static_cast<uint32_t>(p.B);
+    // With a probe vertex only its final-state rows are read, by workgroup
+    // 0 (which also clears them; the loop below clears every other row).
+    const bool probing = p.probe < V;
+    if (probing && blockIdx.x == 0 && threadIdx.x < static_cast<uint32_t>(G)) {
+        uint64_t f = 0;
+        for (uint32_t q = 0; q < Q; q++) {
+            const uint64_t idx = rowi<G>(p, p.probe, q) + threadIdx.x;
+            const uint64_t x = ldc(&p.P[idx]);
+            if (x) {
+                if (fm >> q & 1u) f |= x;
+                p.P[idx] = 0;
+                p.M[0][idx] = 0;
+                p.M[1][idx] = 0;
+            }
+        }
+        p.out[threadIdx.x] = f & word_full(p.B, threadIdx.x);
+    }
     for (uint64_t gw = gthread() >> 6; gw < total; gw += gthreads() >> 6) {
         const uint64_t k = gw / G;
         const uint32_t j = static_cast<uint32_t>(gw % G);
         const uint64_t v = k * 64 + lane;
         uint64_t f = 0;
-        if (v < V) {
+        if (v < V && !(probing && v == p.probe)) {
             for (uint32_t q = 0; q < Q; q++) {
                 const uint64_t idx = rowi<G>(p, static_cast<uint32_t>(v), q) + j;
                 const uint64_t x = ldc(&p.P[idx]);
@@ -859,6 +876,7 @@ __device__ __forceinline__ void st_final(const StackParams &p, uint32_t nexit, u
                 }
             }
         }
+        if (probing) continue;  // uniform: the probe is a launch parameter
         for (uint32_t i = 0; i < 64; i++) {
             const uint64_t b = __ballot((f >> i) & 1ull);
             const uint32_t src = j * 64 + i;

@@ -155,7 +155,7 @@ size_t rpq::stacked_arena_layout(const rpq_graph *g, int32_t Q, int G, int32_t B
 // the graph handle's pinned buffer.
 rpq_status rpq::stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
                             uint64_t *out_bitmaps, uint32_t flags, rpq_stats *stats, const char *who,
-                            const StackArena *ar) {
+                            const StackArena *ar, int32_t probe) {
     if (!g || !n || !sources || !out_bitmaps) return fail(RPQ_EINVAL, "%s: NULL argument", who);
     if (n_sources < 1) return fail(RPQ_EINVAL, "%s: n_sources < 1", who);
     for (int32_t i = 0; i < n_sources; i++)
@@ -166,7 +166,9 @@ rpq_status rpq::stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
     std::lock_guard<std::recursive_mutex> lk(g->mu);
     BT(hipSetDevice(g->device));
     hipStream_t s = g->user_stream ? g->user_stream : g->stream;
-    const int32_t maxb = std::min<int32_t>(g->max_batch, MAX_BATCH);
+    if (probe >= 0 && (n_sources > MAX_BATCH || probe >= g->V))
+        return fail(RPQ_EINVAL, "%s: a probe needs at most %d sources and a vertex id", who, MAX_BATCH);
+    const int32_t maxb = probe >= 0 ? MAX_BATCH : std::min<int32_t>(g->max_batch, MAX_BATCH);
     const uint32_t force = (flags & RPQ_FORCE_PUSH) ? 1u : (flags & RPQ_FORCE_PULL) ? 2u : 0u;
     // automata with at most 8 states use the kernel with byte-sized state sets
     // (which also has the pull direction)
@@ -225,7 +227,7 @@ rpq_status rpq::stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
             for (int k = 0; k < 2; k++) BT(launch_fill(p.sup[k], static_cast<uint64_t>(g->V) + 16, 0, s));
             full = ar->grid[QM == 8 ? 0 : 1][G];
         } else {
-            rpq_status st = batch_prepare(g, n->Q, G, B, s);
+            rpq_status st = batch_prepare(g, n->Q, G, probe >= 0 ? 1 : B, s);
             if (st != RPQ_OK) return st;
             BatchState *bs = g->batch;
             p = bs->p;
@@ -247,7 +249,8 @@ rpq_status rpq::stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         p.Q = n->Q;
         p.V = g->V;
         p.nwords = g->nwords;
-        p.out = (flags & RPQ_OUT_DEVICE) ? out_bitmaps + static_cast<size_t>(b0) * g->nwords : dout;
+        p.out = (flags & RPQ_OUT_DEVICE) && probe < 0 ? out_bitmaps + static_cast<size_t>(b0) * g->nwords : dout;
+        p.probe = probe >= 0 ? static_cast<uint32_t>(probe) : static_cast<uint32_t>(g->V);
         const int grid = g->grid_override ? std::min(g->grid_override, full) : full;
         if (grid <= 0) return fail(RPQ_EDEVICE, "%s: no co-resident grid for the stacked kernel", who);
         BT(launch_fill(reinterpret_cast<uint32_t *>(p.bar), sizeof(GridBarrier) / 4, 0, s));
@@ -262,7 +265,9 @@ rpq_status rpq::stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         BT(hipMemcpyAsync(hst, p.status, 16, hipMemcpyDeviceToHost, s));
         BT(hipMemcpyAsync(hcnt, p.cnt, 8 * ST_NCNT, hipMemcpyDeviceToHost, s));
         BT(hipMemcpyAsync(hst + 4, &p.bar->abort, 4, hipMemcpyDeviceToHost, s));
-        if (!(flags & RPQ_OUT_DEVICE))
+        if (probe >= 0)
+            BT(hipMemcpyAsync(out_bitmaps, dout, 8 * static_cast<size_t>((B + 63) / 64), hipMemcpyDeviceToHost, s));
+        else if (!(flags & RPQ_OUT_DEVICE))
             BT(hipMemcpyAsync(out_bitmaps + static_cast<size_t>(b0) * g->nwords, dout,
                               8 * static_cast<size_t>(B) * g->nwords, hipMemcpyDeviceToHost, s));
         BT(hipStreamSynchronize(s));

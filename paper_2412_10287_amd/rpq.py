@@ -31,7 +31,8 @@ RPQ_EINVAL, RPQ_ENOMEM, RPQ_EDEVICE, RPQ_EAGAIN, RPQ_ENOTFOUND, RPQ_ETIMEDOUT = 
 STATUS_NAMES = {0: "RPQ_OK", 1: "RPQ_PENDING", -1: "RPQ_EINVAL", -2: "RPQ_ENOMEM", -3: "RPQ_EDEVICE",
                 -4: "RPQ_EAGAIN", -5: "RPQ_ENOTFOUND", -6: "RPQ_ETIMEDOUT"}
 
-OUT_DEVICE, COUNTERS, KERNEL_TIMING, FORCE_PUSH, FORCE_PULL, HOST_LOOP, GRAPH_LEVELS = 1, 2, 4, 8, 16, 32, 64
+OUT_DEVICE, COUNTERS, KERNEL_TIMING, FORCE_PUSH, FORCE_PULL, HOST_LOOP, GRAPH_LEVELS, RARE_END = \
+    1, 2, 4, 8, 16, 32, 64, 128
 
 EXPORTS = ("rpq_bitmap_words", "rpq_graph_load", "rpq_graph_free", "rpq_graph_info", "rpq_set_option",
            "rpq_get_option", "rpq_nfa_load", "rpq_nfa_free", "rpq_single_source", "rpq_single_destination",
@@ -70,6 +71,7 @@ class rpq_stats(ctypes.Structure):
         ("level_select_us", ctypes.POINTER(ctypes.c_double)),
         ("updates", ctypes.c_int64),
         ("latency_ms", ctypes.c_double),
+        ("plan", ctypes.c_int32),
     ]
 
 _LEVEL_FIELDS = ("level_counts", "level_cap", "level_us", "level_frontier", "level_edges", "level_select_us")
@@ -221,7 +223,7 @@ class Stats:
     """Statistics of one call: the fields of rpq_stats as attributes (levels,
     push_levels, pull_levels, visited_pairs, product_edges, scans,
     scanned_edges, alg_bytes, active, device_ms, expand_ms, expand_launches,
-    batch, updates, latency_ms), read from the C struct when accessed, and the per-level arrays
+    batch, updates, latency_ms, plan), read from the C struct when accessed, and the per-level arrays
     level_counts, level_us, level_frontier, level_edges, level_select_us
     (empty unless the call asked for them with level_cap)."""
 

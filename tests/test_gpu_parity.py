@@ -362,3 +362,53 @@ def test_autotune_keeps_answers(rpq):
     bms, _ = gg.multi_source(nh[0], srcs * 3)
     for i, s in enumerate(srcs * 3):
         assert np.array_equal(bms[i], og.ssr(w.nfas[0], s).bitmap)
+
+
+def test_rare_end_plan(rpq):
+    # the rare-end plan (one stacked traversal of the reversed automaton from
+    # every candidate endpoint, reporting only whether each reaches the
+    # source) returns the forward traversal's answer: forced, and chosen
+    # automatically under rare_end_max; queries ending in rare labels, in
+    # inverse labels, accepting the empty word, and with no candidates
+    g = G.rmat(12, 8, 16, 1.3, 77)
+    og = oracle.Graph(g)
+    gg = rpq.Graph(g)
+    counts = g.label_counts()
+    rare = [int(l) for l in np.argsort(counts)[:6]]
+    common = [int(l) for l in np.argsort(counts)[-3:]]
+    rng = np.random.default_rng(19)
+    texts = ["%d* %d" % (common[0], rare[0]), "(%d|%d)* ^%d" % (common[0], common[1], rare[1]),
+             "%d+ (%d|%d)" % (common[2], rare[2], rare[3]), "%d*" % rare[4], "%d ^%d*" % (common[1], rare[5]),
+             "(%d|^%d)* %d" % (common[0], common[0], rare[0]), "15 14", "^%d" % rare[2]]
+    used = 0
+    for text in texts:
+        nfa = R.compile_regex(text, 16)
+        nh = rpq.NFA(nfa)
+        for s in rng.integers(0, g.num_vertices, size=6):
+            want = og.ssr(nfa, int(s)).bitmap
+            try:
+                bm, st = gg.single_source(nh, int(s), flags=rpq.RARE_END)
+            except rpq.RPQError as e:
+                assert e.status == rpq.RPQ_EINVAL and "candidate" in str(e), (text, str(e))
+                continue
+            assert st.plan == 1, text
+            assert np.array_equal(bm, want), (text, int(s))
+            used += 1
+            out = rpq.DeviceBuffer(8 * gg.words)
+            gg.single_source(nh, int(s), flags=rpq.RARE_END, out_device_ptr=out.ptr)
+            assert np.array_equal(out.to_host(), want), (text, int(s))
+            out.close()
+    assert used >= 20
+    # automatic choice: the same answers, plan 1 exactly when few candidates
+    gg.set_option("rare_end_max", 300)
+    for text in texts:
+        nfa = R.compile_regex(text, 16)
+        nh = rpq.NFA(nfa)
+        s = int(rng.integers(0, g.num_vertices))
+        bm, st = gg.single_source(nh, s)
+        assert np.array_equal(bm, og.ssr(nfa, s).bitmap), text
+        bm2, st2 = gg.single_source(nh, s, level_cap=64)  # per-level outputs: always forward
+        assert st2.plan == 0 and np.array_equal(bm2, bm)
+    gg.set_option("rare_end_max", 0)
+    with pytest.raises(rpq.RPQError):
+        gg.single_source(rpq.NFA(R.compile_regex(texts[0], 16)), 0, flags=rpq.RARE_END | rpq.COUNTERS)
