@@ -660,6 +660,10 @@ def bench_serve(args):
     g = rpq.Graph(graph)
     if args.max_slots:
         g.set_option("max_slots", args.max_slots)
+    if args.serve_lanes is not None:
+        g.set_option("serve_lanes", args.serve_lanes)
+    if args.large_pairs is not None:
+        g.set_option("large_query_pairs", args.large_pairs)
     handles = [rpq.NFA(a) for a in nfas]
     words = g.words
     out = rpq.DeviceBuffer(8 * words)
@@ -675,11 +679,15 @@ def bench_serve(args):
         k = slot_of.get(i)
         return out.ptr if k is None else keep.ptr + 8 * k * words
 
+    alone = [0]
+
     def served_saturated():
         t = time.perf_counter()
         tickets = [g.submit(h, int(s)) for h, s in zip(handles, srcs)]
+        alone[0] = 0
         for i, tk in enumerate(tickets):
-            g.poll(tk, timeout_us=-1, out_device_ptr=dst(i))
+            _, st = g.poll(tk, timeout_us=-1, out_device_ptr=dst(i))
+            alone[0] += st.batch == 1
         return N / (time.perf_counter() - t)
 
     served_saturated()  # warm-up (engine allocation)
@@ -687,7 +695,8 @@ def bench_serve(args):
     sat_rows = keep.to_host().reshape(-1, words)[:len(sample)].copy()
     rate = 0.8 * qps_sat
     arr = np.cumsum(np.random.default_rng(C.seed(4, 4)).exponential(1.0 / rate, size=N))
-    log("served saturated %.1f q/s -> Poisson arrivals at %.1f q/s" % (qps_sat, rate))
+    log("served saturated %.1f q/s (%d queries through the single-query kernel) -> Poisson arrivals at %.1f q/s"
+        % (qps_sat, alone[0], rate))
     tq = queue.Queue()
     start = time.perf_counter() + 0.05
 
@@ -736,6 +745,7 @@ def bench_serve(args):
     rare_rows = keep.to_host().reshape(-1, words)[:len(sample)].copy()
     g.set_option("rare_end_max", 0)
     slots = g.info("serve_slots")
+    lanes = g.info("serve_lanes")
     g.close()
     out.close()
     keep.close()
@@ -750,11 +760,12 @@ def bench_serve(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": "serve on kg-%d-%d-L1000: %d mixed queries, Poisson arrivals at %.1f q/s"
                    % (graph.num_vertices, graph.num_edges, N, rate),
-                   "states_min": int(states.min()), "states_max": int(states.max()), "slots": slots},
+                   "states_min": int(states.min()), "states_max": int(states.max()), "slots": slots,
+                   "lanes": lanes},
         "served": {"qps": round(N / served_span, 2), "gteps": round(pe.sum() / served_span / 1e9, 4),
                    "latency_ms_p50": round(percentile(lat, 50) * 1e3, 3),
                    "latency_ms_p99": round(percentile(lat, 99) * 1e3, 3),
-                   "saturated_qps": round(qps_sat, 2)},
+                   "saturated_qps": round(qps_sat, 2), "single_query_kernel": int(alone[0])},
         "plain": {"qps": round(N / plain_span, 2), "gteps": round(pe.sum() / plain_span / 1e9, 4),
                   "latency_ms_p50": round(percentile(plat, 50) * 1e3, 3),
                   "latency_ms_p99": round(percentile(plat, 99) * 1e3, 3),
@@ -792,6 +803,8 @@ def main():
                     help="JSON file for the autotuner's choices (reused when present, e.g. so that "
                          "profiler passes run the settings of an earlier timed run)")
     ap.add_argument("--serve-queries", type=int, default=2000, help="serve: queries in the stream")
+    ap.add_argument("--serve-lanes", type=int, default=None, help="serve: single-query executors of the served path")
+    ap.add_argument("--large-pairs", type=int, default=None, help="serve: large_query_pairs of the served path")
     ap.add_argument("--serve-parity", type=int, default=128, help="serve: queries checked against the oracle")
     ap.add_argument("--max-slots", type=int, default=0, help="served path: concurrent queries (0 = library default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",

@@ -330,6 +330,17 @@ rpq_status rpq_multi_source_noalloc(rpq_graph *g, const rpq_nfa *n, const int32_
  * batch = the group size.
  */
 rpq_status rpq_submit(rpq_graph *g, const rpq_nfa *n, int32_t source, rpq_ticket *out);
+/*
+ * rpq_submit with a deadline for the request to start: if it is still queued
+ * deadline_us microseconds after this call (no slot, lane or group took it),
+ * it is dropped and rpq_poll of its ticket returns RPQ_ETIMEDOUT with the
+ * ticket retired (a later poll gives RPQ_ENOTFOUND). A request that has
+ * started runs to completion. deadline_us <= 0: no deadline (rpq_submit).
+ * Unlike a poll whose own wait elapsed (RPQ_ETIMEDOUT, ticket kept), the
+ * message of rpq_last_error() then names the deadline.
+ */
+rpq_status rpq_submit_deadline(rpq_graph *g, const rpq_nfa *n, int32_t source, int64_t deadline_us,
+                               rpq_ticket *out);
 rpq_status rpq_poll(rpq_graph *g, rpq_ticket t, uint64_t *out_bitmap, uint32_t flags, rpq_stats *stats,
                     int64_t timeout_us);
 

@@ -124,10 +124,11 @@ class Graph:
             self._lib.og_free(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # no foreign calls from a half-finalized interpreter (the memory goes
-        # with the process)
-        if not sys.is_finalizing():
+        # with the process); the check is bound at definition, as module
+        # globals may already be gone at exit
+        if not _finalizing():
             self.close()
 
     def num_edges(self, inverse: bool = False) -> int:

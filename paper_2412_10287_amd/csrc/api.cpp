@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 
 using namespace rpq;
 
@@ -26,14 +27,63 @@ rpq_status rpq::fail(rpq_status st, const char *fmt, ...) {
     return st;
 }
 
-// Persistent grids are sized to fill the GPU and wait for each other at grid
-// barriers, so two of them in flight on one device at once could each hold
-// part of the GPU and wait (up to the barrier timeout) for workgroups that
-// cannot start. Every persistent launch of this process holds its device's
-// lock from the launch until its stream has drained it.
-std::mutex &rpq::persistent_mutex(int device) {
-    static std::mutex mus[64];
-    return mus[static_cast<unsigned>(device) & 63u];
+// Persistent grids wait for all of their workgroups at grid barriers, so all
+// of them must be resident at once; two grids in flight on one device that
+// together do not fit could each hold part of the GPU and wait (up to the
+// barrier timeout) for workgroups that cannot start. Every persistent launch
+// of this process therefore takes its workgroups from a per-device budget of
+// two per compute unit, from the launch until its stream has drained it, and
+// waits in arrival order while the budget is short. A workgroup of a kernel
+// that fits at least twice per compute unit (512 threads, so at most 128
+// VGPRs and 80 KB of LDS) costs one unit: any two such workgroups fit on one
+// compute unit together. Other kernels cost two.
+namespace {
+struct Budget {
+    std::mutex mu;
+    std::condition_variable cv;
+    int64_t total = -1;  // units, set at first use
+    int64_t free = 0;
+    uint64_t next = 0, serving = 0;  // arrival tickets
+};
+Budget &budget_of(int device) {
+    static Budget b[64];
+    return b[static_cast<unsigned>(device) & 63u];
+}
+}  // namespace
+
+rpq_status rpq::PersistentHold::acquire(int device, int grid, int blocks_per_cu) {
+    release();
+    Budget &b = budget_of(device);
+    std::unique_lock<std::mutex> lk(b.mu);
+    if (b.total < 0) {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu < 1)
+            return fail(RPQ_EDEVICE, "hipDeviceGetAttribute(multiprocessor count) failed");
+        b.total = 2 * static_cast<int64_t>(ncu);
+        b.free = b.total;
+    }
+    int64_t units = static_cast<int64_t>(grid) * (blocks_per_cu >= 2 ? 1 : 2);
+    units = std::min(units, b.total);
+    const uint64_t me = b.next++;
+    b.cv.wait(lk, [&] { return b.serving == me && b.free >= units; });
+    b.serving++;
+    b.free -= units;
+    b.cv.notify_all();  // the next arrival may fit as well
+    device_ = device;
+    units_ = units;
+    return RPQ_OK;
+}
+
+void rpq::PersistentHold::release() {
+    if (device_ < 0) return;
+    Budget &b = budget_of(device_);
+    {
+        std::lock_guard<std::mutex> lk(b.mu);
+        b.free += units_;
+    }
+    b.cv.notify_all();
+    device_ = -1;
+    units_ = 0;
 }
 
 rpq_status rpq::hip_fail(hipError_t e, const char *what) {
@@ -365,7 +415,16 @@ rpq_status rpq::graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32
     g->gv.nwords = g->nwords;
     g->gv.V = V;
     g->gv.L = L;
-    // single-query state, sized for 4-byte state words
+    return exec_alloc(g);
+}
+
+// The single-query executor's device state (sized for 4-byte state words),
+// its pinned staging, stream and events: everything rpq_single_source needs
+// besides the graph store.
+rpq_status rpq::exec_alloc(rpq_graph *g) {
+    const int32_t V = g->V;
+    const int64_t E = g->E;
+    rpq_status st;
     StateView &sv = g->sv;
     const size_t wbytes = 4 * static_cast<size_t>(V) + 256;
     if ((st = dev_alloc(g, reinterpret_cast<void **>(&sv.P), wbytes, "P")) != RPQ_OK) return st;
@@ -412,6 +471,44 @@ rpq_status rpq::graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32
     return RPQ_OK;
 }
 
+rpq_status rpq::exec_clone(const rpq_graph *g, rpq_graph **out) {
+    *out = nullptr;
+    HIP_TRY(hipSetDevice(g->device));
+    rpq_graph *c = new (std::nothrow) rpq_graph;
+    if (!c) return fail(RPQ_ENOMEM, "out of host memory");
+    c->clone_of = g;
+    c->V = g->V;
+    c->L = g->L;
+    c->E = g->E;
+    c->device = g->device;
+    c->gv = g->gv;
+    c->label_edges = g->label_edges;
+    for (int k = 0; k < 2; k++) {
+        c->label_rows[k] = g->label_rows[k];
+        c->rows[k] = g->rows[k];
+    }
+    c->rbase = g->rbase;
+    c->nwords = g->nwords;
+    exec_sync_options(c, g);
+    const rpq_status st = exec_alloc(c);
+    if (st != RPQ_OK) {
+        destroy(c);
+        return st;
+    }
+    *out = c;
+    return RPQ_OK;
+}
+
+void rpq::exec_sync_options(rpq_graph *c, const rpq_graph *g) {
+    c->pull_alpha = g->pull_alpha;
+    c->pull_beta = g->pull_beta;
+    c->plain_grid = g->plain_grid;
+    c->grid_override = g->grid_override;
+    c->coop_launch = g->coop_launch;
+}
+
+void rpq::exec_free(rpq_graph *c) { destroy(c); }
+
 rpq_status rpq_graph_free(rpq_graph *g) {
     if (!g) return RPQ_OK;
     if (serve_pending(g)) return fail(RPQ_EAGAIN, "rpq_graph_free: tickets are still pending");
@@ -430,6 +527,7 @@ rpq_status rpq_graph_info(const rpq_graph *g, const char *key, int64_t *value) {
     else if (!strcmp(key, "persistent_grid")) *value = g->pgrid[1];
     else if (!strcmp(key, "occupancy_blocks_per_cu")) *value = occupancy_blocks_per_cu(1);
     else if (!strcmp(key, "serve_slots")) *value = serve_slots(const_cast<rpq_graph *>(g));
+    else if (!strcmp(key, "serve_lanes")) *value = serve_lane_count(const_cast<rpq_graph *>(g));
     else return fail(RPQ_ENOTFOUND, "rpq_graph_info: unknown key '%s'", key);
     return RPQ_OK;
 }
@@ -478,6 +576,9 @@ rpq_status rpq_set_option(rpq_graph *g, const char *key, int64_t value) {
         if (value < 0 || value > MAX_BATCH)
             return fail(RPQ_EINVAL, "rpq_set_option: serve_stack_min outside [0, %d]", MAX_BATCH);
         g->serve_stack_min = static_cast<int32_t>(value);
+    } else if (!strcmp(key, "serve_lanes")) {
+        if (value < 0 || value > MAX_LANES) return fail(RPQ_EINVAL, "rpq_set_option: serve_lanes outside [0, %d]", MAX_LANES);
+        g->serve_lanes = static_cast<int32_t>(value);
     } else if (!strcmp(key, "cooperative_launch")) {
         if (value != 0 && value != 1) return fail(RPQ_EINVAL, "rpq_set_option: cooperative_launch must be 0 or 1");
         g->coop_launch = value != 0;
@@ -505,6 +606,7 @@ rpq_status rpq_get_option(const rpq_graph *g, const char *key, int64_t *value) {
     else if (!strcmp(key, "large_query_slots")) *value = g->large_slots;
     else if (!strcmp(key, "serve_stack_min")) *value = g->serve_stack_min;
     else if (!strcmp(key, "rare_end_max")) *value = g->rare_end_max;
+    else if (!strcmp(key, "serve_lanes")) *value = g->serve_lanes;
     else if (!strcmp(key, "cooperative_launch")) *value = g->coop_launch ? 1 : 0;
     else if (!strcmp(key, "grid")) *value = g->grid_override;
     else return fail(RPQ_ENOTFOUND, "rpq_get_option: unknown key '%s'", key);
@@ -692,9 +794,10 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
         p.st.hstat = g->hstat_dev;
         p.st.hserial = g->hserial;
     }
-    std::unique_lock<std::mutex> plk(persistent_mutex(g->device), std::defer_lock);
+    PersistentHold hold;  // released when this call returns, after the synchronisation below
     if (persistent) {
-        plk.lock();  // released when this call returns, after the synchronisation below
+        const rpq_status hs = hold.acquire(g->device, grid_p, occupancy_blocks_per_cu(W));
+        if (hs != RPQ_OK) return hs;
         g->bar_idx ^= 1;  // the next persistent launch uses the barrier this one zeroes
         if (timing) HIP_TRY(hipEventRecord(g->ev[2], s));
         HIP_TRY(launch_persistent(W, p, grid_p, g->coop_launch, s));

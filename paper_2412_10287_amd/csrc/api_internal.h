@@ -20,6 +20,7 @@ namespace rpq {
 constexpr int64_t MAX_EDGES = (1ll << 31) - (1ll << 16);  // distinct edges per direction
 constexpr int32_t MAX_BATCH = 1024;
 constexpr int32_t MAX_SLOTS = 256;
+constexpr int32_t MAX_LANES = 8;
 
 struct Trans {
     int32_t sym, from, to;
@@ -90,6 +91,7 @@ struct rpq_graph {
     int64_t large_pairs = 1 << 21;  // served path: queries above this many reached pairs count as large
     int32_t large_slots = 0;        // concurrent served queries while recent queries are large (0: one at a time, single-query kernel)
     int32_t serve_stack_min = 32;   // waiting served requests of one NFA that run as one stacked group (0 = never)
+    int32_t serve_lanes = 2;        // served path: single-query executors for large-query periods (0 = the scheduler thread runs them one at a time)
     int64_t rare_end_max = 0;       // rare-end plan of rpq_single_source for at most this many candidate endpoints (0 = off)
     int32_t grid_override = 0;
     int32_t plain_grid = 0;  // persistent single-query launch workgroups (0 = one per CU)
@@ -118,12 +120,30 @@ struct rpq_graph {
     // scheduler runs holds mu, and submits must not wait for it)
     std::atomic<rpq::ServeState *> serve{nullptr};
     std::mutex serve_mu;
+    // an executor made by exec_clone: the graph store belongs to this handle
+    const rpq_graph *clone_of = nullptr;
 };
 
 namespace rpq {
 
 rpq_status fail(rpq_status st, const char *fmt, ...);
-std::mutex &persistent_mutex(int device);
+// A persistent grid's share of its device's co-resident workgroups (see
+// api.cpp): acquire() waits until `grid` workgroups of a kernel that fits
+// blocks_per_cu times per compute unit can be resident next to every other
+// persistent grid of this process; the destructor returns them.
+class PersistentHold {
+public:
+    PersistentHold() = default;
+    PersistentHold(const PersistentHold &) = delete;
+    PersistentHold &operator=(const PersistentHold &) = delete;
+    ~PersistentHold() { release(); }
+    rpq_status acquire(int device, int grid, int blocks_per_cu);
+    void release();
+
+private:
+    int device_ = -1;
+    int64_t units_ = 0;
+};
 rpq_status hip_fail(hipError_t e, const char *what);
 size_t build_qconst(const rpq_graph *g, const rpq_nfa *n, uint32_t force, uint32_t counters,
                     std::vector<uint8_t> &buf, int32_t *nsym_out);
@@ -131,6 +151,16 @@ size_t build_qconst_into(const rpq_graph *g, const rpq_nfa *n, uint32_t force, u
                          size_t cap, int32_t *nsym_out);
 QueryView query_view(uint8_t *base, int32_t nsym);
 rpq_status graph_upload(rpq_graph *g, const int64_t *label_ptr, const int32_t *src, const int32_t *dst);
+// The single-query executor's state of a handle whose graph store is set.
+rpq_status exec_alloc(rpq_graph *g);
+// A second single-query executor on g's graph store (its own state arrays,
+// staging, stream and query-constant cache, so that it can run a query while
+// g or another executor runs one). It holds no part of the graph store: free
+// it with exec_free before g. exec_sync_options copies the options of the
+// plain path (pull thresholds, grid, launch kind) from g.
+rpq_status exec_clone(const rpq_graph *g, rpq_graph **out);
+void exec_sync_options(rpq_graph *c, const rpq_graph *g);
+void exec_free(rpq_graph *c);
 // Optional parts of a single-query call: a start set instead of one source
 // (nsrc distinct vertices, already in g->pin_srcset) and the shortest-length
 // output (V int32, device memory).
@@ -161,6 +191,8 @@ void serve_shutdown(rpq_graph *g);
 bool serve_pending(rpq_graph *g);
 // Slots the served path's engine admits queries into (0 before it exists).
 int64_t serve_slots(rpq_graph *g);
+// Lanes the served path has made (0 before its first large-query period).
+int64_t serve_lane_count(rpq_graph *g);
 void batch_free(rpq_graph *g);
 // Clears the outputs of *st and keeps its caller-supplied input fields.
 void stats_reset(rpq_stats *st);

@@ -37,6 +37,8 @@ struct Request {
     std::shared_ptr<const rpq_nfa> nfa; // a copy of the NFA (for a stacked group)
     std::vector<uint8_t> qc;            // query constants (build_qconst layout)
     Clock::time_point submitted;
+    bool has_deadline = false;          // rpq_submit_deadline: must start by `deadline`
+    Clock::time_point deadline;
 };
 
 struct Ticket {
@@ -47,6 +49,8 @@ struct Ticket {
     std::vector<uint64_t> spill; // or the bitmap in host memory (the pool was full)
     bool empty_result = false;   // no start state: the answer is empty
     rpq_stats stats{};
+    bool has_deadline = false;   // a queued request that has not started by `deadline` is dropped
+    Clock::time_point deadline;
 };
 
 struct SlotInfo {
@@ -63,6 +67,7 @@ struct ServeState {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request> pending;
+    size_t pending_deadlines = 0;  // requests in `pending` with a deadline
     std::unordered_map<rpq_ticket, Ticket> tickets;
     std::thread worker;
     bool stop = false;
@@ -106,6 +111,15 @@ struct ServeState {
     uint32_t pool_n = 0;
     std::vector<uint32_t> free_entries;  // guarded by mu
     std::vector<uint32_t> ready;         // finished slots to retire (worker only)
+    // lanes: single-query executors (exec_clone) that run the requests of
+    // large-query periods side by side, one thread each; lane_q holds the
+    // requests handed to them and lanes_busy counts those not finished
+    std::vector<rpq_graph *> lanes;
+    std::vector<std::thread> lane_threads;
+    std::deque<Request> lane_q;
+    std::condition_variable cv_lane;
+    uint32_t lanes_busy = 0;
+    bool lanes_failed = false;  // no lane could be made: run requests in the scheduler thread
     hipStream_t copy_stream = nullptr;   // rpq_poll's copies out of the pool
     std::mutex copy_mu;
     // pinned host staging
@@ -510,6 +524,96 @@ static void run_one(rpq_graph *g, ServeState *ss, Request &r) {
     ss->cv_done.notify_all();
 }
 
+// Drops the queued requests whose deadline has passed: their tickets finish
+// with RPQ_ETIMEDOUT. Called with ss->mu held.
+static void expire_pending(ServeState *ss, Clock::time_point now) {
+    if (ss->pending_deadlines == 0) return;
+    bool any = false;
+    for (auto it = ss->pending.begin(); it != ss->pending.end();) {
+        if (!it->has_deadline || it->deadline > now) {
+            ++it;
+            continue;
+        }
+        auto t = ss->tickets.find(it->id);
+        if (t != ss->tickets.end()) {
+            t->second.state = 2;
+            t->second.status = RPQ_ETIMEDOUT;
+            t->second.error = "served request not started within its deadline";
+        }
+        ss->pending_deadlines--;
+        ss->running--;
+        it = ss->pending.erase(it);
+        any = true;
+    }
+    if (any) ss->cv_done.notify_all();
+}
+
+// Takes the first queued request (its deadline no longer counts).
+static Request take_front(ServeState *ss) {
+    Request r = std::move(ss->pending.front());
+    ss->pending.pop_front();
+    if (r.has_deadline) ss->pending_deadlines--;
+    auto t = ss->tickets.find(r.id);
+    if (t != ss->tickets.end()) {
+        t->second.state = 1;
+        t->second.has_deadline = false;
+    }
+    return r;
+}
+
+// A lane's thread: runs the requests handed to it through its own
+// single-query executor until the served path stops.
+static void lane_main(rpq_graph *g, ServeState *ss, rpq_graph *lane) {
+    (void)hipSetDevice(g->device);
+    while (true) {
+        Request r;
+        {
+            std::unique_lock<std::mutex> lk(ss->mu);
+            ss->cv_lane.wait(lk, [&] { return ss->stop || !ss->lane_q.empty(); });
+            if (ss->lane_q.empty()) return;
+            r = std::move(ss->lane_q.front());
+            ss->lane_q.pop_front();
+        }
+        {
+            std::lock_guard<std::recursive_mutex> glk(g->mu);  // options are set under it
+            exec_sync_options(lane, g);
+            if (ss->lanes.size() > 2 && g->pgrid[1] > 0) {
+                // more lanes than two full grids fit: each gets its share
+                const int share = std::max(1, static_cast<int>(2 * g->pgrid[1] / ss->lanes.size()));
+                lane->plain_grid = lane->plain_grid ? std::min(lane->plain_grid, share) : share;
+            }
+        }
+        run_one(lane, ss, r);
+        {
+            std::lock_guard<std::mutex> lk(ss->mu);
+            ss->lanes_busy--;
+        }
+        ss->cv_work.notify_all();
+    }
+}
+
+// Makes the lanes at their first use (in the scheduler thread). Returns the
+// number of lanes; 0 when none could be made (their memory), after which
+// large requests run in the scheduler thread one at a time.
+static size_t lanes_ready(rpq_graph *g, ServeState *ss) {
+    if (!ss->lanes.empty() || ss->lanes_failed) return ss->lanes.size();
+    const int32_t want = std::max<int32_t>(0, g->serve_lanes);
+    std::vector<rpq_graph *> made;
+    for (int32_t k = 0; k < want; k++) {
+        rpq_graph *c = nullptr;
+        if (exec_clone(g, &c) != RPQ_OK) break;
+        made.push_back(c);
+    }
+    std::lock_guard<std::mutex> lk(ss->mu);
+    if (made.empty()) {
+        ss->lanes_failed = true;
+        return 0;
+    }
+    ss->lanes = made;
+    for (rpq_graph *c : ss->lanes) ss->lane_threads.emplace_back(lane_main, g, ss, c);
+    return ss->lanes.size();
+}
+
 static void fail_all(ServeState *ss, rpq_status st, const std::string &msg) {
     std::lock_guard<std::mutex> lk(ss->mu);
     ss->failed = true;
@@ -521,6 +625,7 @@ static void fail_all(ServeState *ss, rpq_status st, const std::string &msg) {
             kv.second.error = msg;
         }
     ss->pending.clear();
+    ss->pending_deadlines = 0;
     ss->running = 0;
     ss->cv_done.notify_all();
 }
@@ -536,12 +641,18 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
         return;
     }
     std::vector<Request> admit, grp, one;
+    bool make_lanes = false;
     while (true) {
         admit.clear();
         grp.clear();
         one.clear();
+        if (make_lanes) {
+            lanes_ready(g, ss);  // outside ss->mu: it allocates their state
+            make_lanes = false;
+        }
         {
             std::unique_lock<std::mutex> lk(ss->mu);
+            expire_pending(ss, Clock::now());
             // a stacked group: at least serve_stack_min waiting requests of one NFA
             const size_t smin = ss->group_off ? 0 : static_cast<size_t>(std::max<int32_t>(g->serve_stack_min, 0));
             auto group_serial = [&]() -> uint64_t {
@@ -560,20 +671,33 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
             if (large) cap = std::min<size_t>(cap, static_cast<size_t>(g->large_slots));
             auto active = [&] { return static_cast<size_t>(ss->slots) - ss->free_slots.size(); };
             const bool single = large && g->large_slots == 0;
+            // the lanes that run such requests (none: they run in this thread)
+            const size_t nl = ss->lanes.size();
             // work: a level to run, a request and a free slot, a group, or a
-            // request to run alone
+            // request to run through the single-query kernel
             ss->cv_work.wait(lk, [&] {
                 return ss->stop || ss->cur_len > 0 ||
                        (!ss->pending.empty() && !ss->free_slots.empty() && active() < cap) || group_serial() != 0 ||
-                       (single && !ss->pending.empty() && active() == 0);
+                       (single && !ss->pending.empty() && active() == 0 && (nl == 0 || ss->lanes_busy < nl));
             });
             if (ss->stop && ss->pending.empty() && ss->cur_len == 0) break;
             const uint64_t gs = ss->stop ? 0 : group_serial();
             if (!gs && single && ss->cur_len == 0 && active() == 0 && !ss->pending.empty()) {
-                one.push_back(std::move(ss->pending.front()));
-                ss->pending.pop_front();
-                auto t = ss->tickets.find(one.back().id);
-                if (t != ss->tickets.end()) t->second.state = 1;
+                if (nl == 0 && g->serve_lanes > 0 && !ss->lanes_failed) {
+                    make_lanes = true;
+                    continue;
+                }
+                if (nl == 0) {
+                    one.push_back(take_front(ss));
+                } else {
+                    // hand requests to the free lanes
+                    while (!ss->pending.empty() && ss->lanes_busy < nl) {
+                        ss->lane_q.push_back(take_front(ss));
+                        ss->lanes_busy++;
+                    }
+                    ss->cv_lane.notify_all();
+                    continue;
+                }
             } else if (gs) {
                 const size_t maxb = static_cast<size_t>(std::min<int32_t>(g->max_batch, MAX_BATCH));
                 for (auto it = ss->pending.begin(); it != ss->pending.end() && grp.size() < maxb;) {
@@ -583,17 +707,17 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
                     }
                     grp.push_back(std::move(*it));
                     it = ss->pending.erase(it);
+                    if (grp.back().has_deadline) ss->pending_deadlines--;
                     auto t = ss->tickets.find(grp.back().id);
-                    if (t != ss->tickets.end()) t->second.state = 1;
+                    if (t != ss->tickets.end()) {
+                        t->second.state = 1;
+                        t->second.has_deadline = false;
+                    }
                 }
             } else {
                 while (!ss->pending.empty() && admit.size() < ss->free_slots.size() &&
-                       active() + admit.size() < cap) {
-                    admit.push_back(std::move(ss->pending.front()));
-                    ss->pending.pop_front();
-                    auto it = ss->tickets.find(admit.back().id);
-                    if (it != ss->tickets.end()) it->second.state = 1;
-                }
+                       active() + admit.size() < cap)
+                    admit.push_back(take_front(ss));
             }
         }
         if (!one.empty()) {
@@ -609,6 +733,7 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
                 for (size_t i = grp.size(); i-- > 0;) {
                     auto t = ss->tickets.find(grp[i].id);
                     if (t != ss->tickets.end()) t->second.state = 0;
+                    grp[i].has_deadline = false;  // it had started
                     ss->pending.push_front(std::move(grp[i]));
                 }
                 ss->group_off = true;
@@ -641,9 +766,18 @@ void rpq::serve_shutdown(rpq_graph *g) {
         std::lock_guard<std::mutex> lk(ss->mu);
         ss->stop = true;
         ss->pending.clear();
+        ss->pending_deadlines = 0;
     }
     ss->cv_work.notify_all();
     if (ss->worker.joinable()) ss->worker.join();
+    {
+        std::lock_guard<std::mutex> lk(ss->mu);
+        ss->lane_q.clear();
+    }
+    ss->cv_lane.notify_all();
+    for (std::thread &t : ss->lane_threads)
+        if (t.joinable()) t.join();
+    for (rpq_graph *c : ss->lanes) exec_free(c);
     if (ss->stream) (void)hipStreamDestroy(ss->stream);
     if (ss->copy_stream) (void)hipStreamDestroy(ss->copy_stream);
     if (ss->pinned) (void)hipHostFree(ss->pinned);
@@ -659,6 +793,13 @@ int64_t rpq::serve_slots(rpq_graph *g) {
     return static_cast<int64_t>(ss->slots);
 }
 
+int64_t rpq::serve_lane_count(rpq_graph *g) {
+    ServeState *ss = g->serve;
+    if (!ss) return 0;
+    std::lock_guard<std::mutex> lk(ss->mu);
+    return static_cast<int64_t>(ss->lanes.size());
+}
+
 bool rpq::serve_pending(rpq_graph *g) {
     ServeState *ss = g->serve;
     if (!ss) return false;
@@ -669,7 +810,18 @@ bool rpq::serve_pending(rpq_graph *g) {
 }
 
 
+static rpq_status submit(rpq_graph *g, const rpq_nfa *n, int32_t source, int64_t deadline_us, rpq_ticket *out);
+
 rpq_status rpq_submit(rpq_graph *g, const rpq_nfa *n, int32_t source, rpq_ticket *out) {
+    return submit(g, n, source, 0, out);
+}
+
+rpq_status rpq_submit_deadline(rpq_graph *g, const rpq_nfa *n, int32_t source, int64_t deadline_us,
+                               rpq_ticket *out) {
+    return submit(g, n, source, deadline_us, out);
+}
+
+static rpq_status submit(rpq_graph *g, const rpq_nfa *n, int32_t source, int64_t deadline_us, rpq_ticket *out) {
     if (!g || !n || !out) return fail(RPQ_EINVAL, "rpq_submit: NULL argument");
     if (source < 0 || source >= g->V) return fail(RPQ_EINVAL, "rpq_submit: source %d outside [0, %d)", source, g->V);
     Request r;
@@ -681,6 +833,10 @@ rpq_status rpq_submit(rpq_graph *g, const rpq_nfa *n, int32_t source, rpq_ticket
     if (r.nsym > MAX_SYMS || sz > QC_STRIDE)
         return fail(RPQ_EINVAL, "rpq_submit: query uses %d symbols; the limit is %d", r.nsym, MAX_SYMS);
     r.submitted = Clock::now();
+    if (deadline_us > 0) {
+        r.has_deadline = true;
+        r.deadline = r.submitted + std::chrono::microseconds(deadline_us);
+    }
     // no g->mu here: the scheduler holds it while it runs a query through
     // the single-query or stacked path, and a submit must not wait for that
     // (requests queue up while one runs, and can then run as a group)
@@ -695,6 +851,9 @@ rpq_status rpq_submit(rpq_graph *g, const rpq_nfa *n, int32_t source, rpq_ticket
         t.empty_result = true;
         t.stats.batch = 1;
     } else {
+        t.has_deadline = r.has_deadline;
+        t.deadline = r.deadline;
+        if (r.has_deadline) ss->pending_deadlines++;
         ss->pending.push_back(std::move(r));
         ss->running++;
     }
@@ -719,19 +878,31 @@ rpq_status rpq_poll(rpq_graph *g, rpq_ticket t, uint64_t *out_bitmap, uint32_t f
         auto it = ss->tickets.find(t);
         if (it == ss->tickets.end() || it->second.state == 3)
             return fail(RPQ_ENOTFOUND, "rpq_poll: unknown ticket %llu", (unsigned long long)t);
-        auto done = [&] { return it->second.state == 2; };
-        if (!done()) {
+        Ticket &tk = it->second;  // the element stays in place while others are added
+        auto done = [&] { return tk.state == 2; };
+        const Clock::time_point now = Clock::now();
+        const bool bounded = timeout_us >= 0;
+        const Clock::time_point until = now + std::chrono::microseconds(bounded ? timeout_us : 0);
+        while (!done()) {
+            // a queued request whose deadline has passed finishes here
+            if (tk.state == 0 && tk.has_deadline && Clock::now() >= tk.deadline) {
+                expire_pending(ss, Clock::now());
+                continue;
+            }
             if (timeout_us == 0) return RPQ_PENDING;
-            if (timeout_us < 0) ss->cv_done.wait(lk, done);
-            else if (!ss->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done))
+            Clock::time_point wake = bounded ? until : Clock::time_point::max();
+            if (tk.state == 0 && tk.has_deadline && tk.deadline < wake) wake = tk.deadline;
+            if (wake == Clock::time_point::max()) ss->cv_done.wait(lk);
+            else ss->cv_done.wait_until(lk, wake);
+            if (!done() && bounded && Clock::now() >= until && !(tk.state == 0 && tk.has_deadline &&
+                                                                Clock::now() >= tk.deadline))
                 return fail(RPQ_ETIMEDOUT, "rpq_poll: ticket %llu not finished within %lld us", (unsigned long long)t,
                             (long long)timeout_us);
         }
-        Ticket &tk = it->second;
         if (tk.status != RPQ_OK) {
             const rpq_status st = tk.status;
             fail(st, "%s", tk.error.c_str());
-            ss->tickets.erase(it);
+            ss->tickets.erase(t);
             return st;
         }
         tk.state = 3;  // this call collects it

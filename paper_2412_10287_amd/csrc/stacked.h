@@ -54,6 +54,8 @@ struct StackParams {
 // byte; enables the pull direction) or 32.
 hipError_t launch_stacked(int G, int QM, const StackParams &p, int grid, bool cooperative, hipStream_t s);
 int stacked_grid(int G, int QM);
+// Workgroups of the stacked kernel that fit on one compute unit (-1 on error).
+int stacked_blocks_per_cu(int G, int QM);
 // Device address of the fixed scratch array (RPQ_NOALLOC_SCRATCH_BYTES) on
 // the current device.
 hipError_t noalloc_scratch_address(void **ptr);

@@ -529,6 +529,73 @@ __device__ __forceinline__ void unit_append4(const StackParams &p, uint32_t n, u
         sviol(p);
 }
 
+// Dense levels: the target's candidate state set only (no queue append; the
+// queue is built afterwards by st_compact, in vertex order). A plain load
+// first, as in unit_append4; the OR needs no return value.
+template <int G, int QM>
+__device__ __forceinline__ void unit_mark(const StackParams &p, uint32_t n, uint32_t j, const UnitC<QM> &U) {
+    const uint32_t t = group_or<G>(U.tb);
+    if (t && j == 0) {
+        uint32_t *sn = p.sup[(n + 1) & 1];
+        if ((sup_ld<QM>(sn, U.dst) & t) != t) (void)sup_or<QM>(sn, U.dst, t);
+    }
+}
+
+template <int G, int QM>
+__device__ __forceinline__ void unit_mark4(const StackParams &p, uint32_t n, uint32_t j, const UnitC<QM> &U0,
+                                           const UnitC<QM> &U1, const UnitC<QM> &U2, const UnitC<QM> &U3) {
+    uint32_t *sn = p.sup[(n + 1) & 1];
+    const uint32_t t0 = group_or<G>(U0.tb), t1 = group_or<G>(U1.tb);
+    const uint32_t t2 = group_or<G>(U2.tb), t3 = group_or<G>(U3.tb);
+    if (j != 0) return;
+    uint32_t o0 = ~0u, o1 = ~0u, o2 = ~0u, o3 = ~0u;
+    if (t0) o0 = sup_ld<QM>(sn, U0.dst);
+    if (t1) o1 = sup_ld<QM>(sn, U1.dst);
+    if (t2) o2 = sup_ld<QM>(sn, U2.dst);
+    if (t3) o3 = sup_ld<QM>(sn, U3.dst);
+    if ((o0 & t0) != t0) (void)sup_or<QM>(sn, U0.dst, t0);
+    if ((o1 & t1) != t1) (void)sup_or<QM>(sn, U1.dst, t1);
+    if ((o2 & t2) != t2) (void)sup_or<QM>(sn, U2.dst, t2);
+    if ((o3 & t3) != t3) (void)sup_or<QM>(sn, U3.dst, t3);
+}
+
+// Level n+1's queue from its candidate state sets, in vertex order: every
+// workgroup takes a contiguous range of vertices, 8 per thread and step, and
+// reserves its step's queue positions with one atomic. Follows an expansion
+// that marked the sets only (unit_mark4); the next select then reads rows,
+// state sets and rank words of consecutive vertices.
+__device__ __forceinline__ void st_compact(const StackParams &p, uint32_t n) {
+    constexpr uint32_t PER = 8;
+    constexpr uint32_t STEP = BLOCK * PER;
+    const uint32_t V = static_cast<uint32_t>(p.V);
+    const uint32_t *sn = p.sup[(n + 1) & 1];
+    int32_t *qn = p.q[(n + 1) & 1];
+    uint32_t *cnt = &p.rec[(n + 1) % REC_RING].nq;
+    const uint32_t per_wg = (V + gridDim.x - 1) / gridDim.x;
+    const uint32_t chunk = (per_wg + STEP - 1) / STEP * STEP;
+    const uint64_t c0 = static_cast<uint64_t>(blockIdx.x) * chunk;
+    const uint64_t c1 = c0 + chunk < V ? c0 + chunk : V;
+    for (uint64_t b = c0; b < c1; b += STEP) {  // workgroup-uniform
+        const uint64_t v0 = b + static_cast<uint64_t>(threadIdx.x) * PER;
+        uint32_t m = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < PER; k++)
+            if (v0 + k < c1 && ldc(&sn[v0 + k]) != 0u) m |= 1u << k;
+        uint64_t wtot;
+        const uint64_t ex = wave_excl_scan(static_cast<uint64_t>(__popc(m)), wtot);
+        uint32_t wbase = 0;
+        block_reserve<uint32_t>(static_cast<uint32_t>(wtot), false, cnt, wbase);
+        uint32_t pos = wbase + static_cast<uint32_t>(ex);
+        while (m) {
+            const uint32_t k = __ffs(m) - 1;
+            m &= m - 1;
+            if (pos < V) qn[pos] = static_cast<int32_t>(v0 + k);
+            else sviol(p);
+            pos++;
+        }
+    }
+}
+
 // Edge-balanced pull of long rows: when every lane of the wave works on the
 // same target row, OR the candidate words of each source word j over the
 // wave and leave them in lanes 0..G-1, so a hub's row costs one atomic per
@@ -555,7 +622,7 @@ __device__ __forceinline__ void wave_merge(UnitC<QM> &U) {
 // OR, and the first writer of sup_next[w] appends w to the next queue. Four
 // units per thread are gathered before any is scattered (QM <= 8), so their
 // loads overlap.
-template <int G, int QM, bool PULL>
+template <int G, int QM, bool PULL, bool MARK>
 __device__ __forceinline__ void expand_range(const StackParams &p, uint32_t n, const StLds &L, uint32_t cnt, uint64_t ubase,
                              uint64_t uend, uint32_t ns) {
     const uint32_t tid = threadIdx.x;
@@ -581,7 +648,8 @@ __device__ __forceinline__ void expand_range(const StackParams &p, uint32_t n, c
             unit_scatter<G, QM>(p, n, j, U1);
             unit_scatter<G, QM>(p, n, j, U2);
             unit_scatter<G, QM>(p, n, j, U3);
-            unit_append4<G, QM>(p, n, j, U0, U1, U2, U3);
+            if constexpr (MARK) unit_mark4<G, QM>(p, n, j, U0, U1, U2, U3);
+            else unit_append4<G, QM>(p, n, j, U0, U1, U2, U3);
         }
     } else {
         for (uint64_t ub = ubase; ub < uend; ub += BLOCK) {
@@ -590,13 +658,14 @@ __device__ __forceinline__ void expand_range(const StackParams &p, uint32_t n, c
             uint32_t lo[1];
             item_search<G, 1>(L, cnt, us, uend, lo);
             unit_gather<G, QM, PULL>(p, n, L, lo[0], us[0], uend, ns, U0);
-            unit_append<G, QM>(p, n, j, U0);
+            if constexpr (MARK) unit_mark<G, QM>(p, n, j, U0);
+            else unit_append<G, QM>(p, n, j, U0);
         }
     }
 }
 
 // Items [0, nitems) with `T` edges (packed in sel) -> units spread over the grid.
-template <int G, int QM, bool PULL>
+template <int G, int QM, bool PULL, bool MARK = false>
 __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, StLds &L, uint64_t sel, uint32_t ns,
                                              uint32_t bid, uint32_t nblk) {
     const uint32_t nitems = static_cast<uint32_t>(sel >> 32);
@@ -623,7 +692,7 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, S
         per = (per + 63) & ~63ull;
         const uint64_t b0 = static_cast<uint64_t>(bid) * per;
         const uint64_t b1 = b0 + per < units ? b0 + per : units;
-        if (b0 < b1) expand_range<G, QM, PULL>(p, n, L, nitems, b0, b1, ns);
+        if (b0 < b1) expand_range<G, QM, PULL, MARK>(p, n, L, nitems, b0, b1, ns);
         __syncthreads();
         return;
     }
@@ -653,7 +722,7 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, S
         __syncthreads();
         const uint64_t u0 = static_cast<uint64_t>(tile) * TILE + static_cast<uint64_t>(part) * part_units;
         const uint64_t u1 = u0 + part_units < units ? u0 + part_units : units;
-        if (u0 < u1) expand_range<G, QM, PULL>(p, n, L, cnt, u0, u1, ns);
+        if (u0 < u1) expand_range<G, QM, PULL, MARK>(p, n, L, cnt, u0, u1, ns);
         __syncthreads();
     }
 }
@@ -904,6 +973,9 @@ __device__ __forceinline__ void st_record(const StackParams &p, uint32_t n, uint
 // expansion units run in workgroup 0 alone, with workgroup barriers in place
 // of grid barriers, while the other workgroups wait at one grid barrier.
 constexpr uint32_t ST_SOLO_MAX_UNITS = 4 * TILE;  // expansion units of a small level
+// push levels with at least V / ST_SWEEP_DIV edges build the next queue in
+// vertex order (st_compact) instead of appending while they expand
+constexpr uint32_t ST_SWEEP_DIV = 16;
 constexpr uint32_t ST_SOLO_MAX_RUN = 2048;        // levels per run (the waiting barrier times out after 5 s)
 
 __device__ __forceinline__ void st_solo_sync() {
@@ -1011,7 +1083,16 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
         const uint32_t mode = st_decide<QM>(p, n, prev);
         if (blockIdx.x == 0 && threadIdx.x == 0) st_record(p, n, mode);
         if (mode == 0) {
-            expand_items<G, QM, false>(p, n, L, ld_acq(&R.sel), ~0u, blockIdx.x, gridDim.x);
+            const uint64_t sel = ld_acq(&R.sel);
+            if ((sel & 0xffffffffull) >= V / ST_SWEEP_DIV) {
+                // a large level: mark the candidates' state sets, then queue
+                // them in vertex order
+                expand_items<G, QM, false, true>(p, n, L, sel, ~0u, blockIdx.x, gridDim.x);
+                if (!grid_barrier(bar, bc)) return;
+                st_compact(p, n);
+            } else {
+                expand_items<G, QM, false>(p, n, L, sel, ~0u, blockIdx.x, gridDim.x);
+            }
             if (!grid_barrier(bar, bc)) return;
             npush++;
         } else {
@@ -1049,10 +1130,11 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
     }
 }
 
-// The grid is sized to be resident on an otherwise idle GPU and the process
-// runs one persistent grid per device at a time, so an ordinary launch
-// suffices; hipLaunchCooperativeKernel (which also guarantees residency
-// against other processes) is the option.
+// The grid is sized to be resident on an otherwise idle GPU, and every
+// persistent grid of the process takes its workgroups from a per-device
+// budget of co-resident workgroups before it is launched, so an ordinary
+// launch suffices; hipLaunchCooperativeKernel (which also guarantees
+// residency against other processes) is the option.
 template <int G, int QM>
 static hipError_t launch_g(const StackParams &p, int grid, bool cooperative, hipStream_t s) {
     StackParams a = p;
@@ -1101,14 +1183,20 @@ static __device__ __align__(256) uint8_t scratch[RPQ_NOALLOC_SCRATCH_BYTES];
 
 hipError_t noalloc_scratch_address(void **ptr) { return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch)); }
 
-int stacked_grid(int G, int QM) {
-    int dev = 0, ncu = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+int stacked_blocks_per_cu(int G, int QM) {
+    int per = 0;
     hipError_t e = hipSuccess;
     RPQ_STACKED_DISPATCH(G, QM, (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stacked<GG, 8>, BLOCK, 0)),
                          (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stacked<GG, 32>, BLOCK, 0)));
-    if (e != hipSuccess || per < 1) return 0;
+    return e == hipSuccess ? per : -1;
+}
+
+int stacked_grid(int G, int QM) {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const int per = stacked_blocks_per_cu(G, QM);
+    if (per < 1) return 0;
     return ncu * (per < PERSISTENT_BLOCKS_PER_CU ? per : PERSISTENT_BLOCKS_PER_CU);
 }
 

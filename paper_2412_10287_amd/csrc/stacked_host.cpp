@@ -254,9 +254,13 @@ rpq_status rpq::stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         const int grid = g->grid_override ? std::min(g->grid_override, full) : full;
         if (grid <= 0) return fail(RPQ_EDEVICE, "%s: no co-resident grid for the stacked kernel", who);
         BT(launch_fill(reinterpret_cast<uint32_t *>(p.bar), sizeof(GridBarrier) / 4, 0, s));
-        // one persistent grid per device at a time (released after the
-        // synchronisation below, at the end of this batch)
-        std::unique_lock<std::mutex> plk(persistent_mutex(g->device));
+        // the grid's share of the device's co-resident workgroups (returned
+        // after the synchronisation below, at the end of this batch)
+        PersistentHold hold;
+        {
+            const rpq_status hs = hold.acquire(g->device, grid, stacked_blocks_per_cu(G, QM));
+            if (hs != RPQ_OK) return hs;
+        }
         BT(hipEventRecord(g->ev[2], s));
         BT(launch_stacked(G, QM, p, grid, g->coop_launch, s));
         BT(hipEventRecord(g->ev[3], s));

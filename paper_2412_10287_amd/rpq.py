@@ -37,7 +37,7 @@ OUT_DEVICE, COUNTERS, KERNEL_TIMING, FORCE_PUSH, FORCE_PULL, HOST_LOOP, GRAPH_LE
 EXPORTS = ("rpq_bitmap_words", "rpq_graph_load", "rpq_graph_free", "rpq_graph_info", "rpq_set_option",
            "rpq_get_option", "rpq_nfa_load", "rpq_nfa_free", "rpq_single_source", "rpq_single_destination",
            "rpq_single_source_lengths", "rpq_source_set", "rpq_multi_source", "rpq_multi_source_noalloc",
-           "rpq_submit", "rpq_poll",
+           "rpq_submit", "rpq_submit_deadline", "rpq_poll",
            "rpq_autotune", "rpq_last_error")
 
 TUNE_PLAIN, TUNE_STACKED = 0, 1
@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH):
         "rpq_multi_source": (ctypes.c_int, [P, P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
         "rpq_multi_source_noalloc": (ctypes.c_int, [P, P, P, i32, P, u32, ctypes.POINTER(rpq_stats)]),
         "rpq_submit": (ctypes.c_int, [P, P, i32, ctypes.POINTER(u64)]),
+        "rpq_submit_deadline": (ctypes.c_int, [P, P, i32, i64, ctypes.POINTER(u64)]),
         "rpq_poll": (ctypes.c_int, [P, u64, P, u32, ctypes.POINTER(rpq_stats), i64]),
         "rpq_autotune": (ctypes.c_int, [P, i32, P, P, i32, ctypes.POINTER(rpq_tuning)]),
         "rpq_last_error": (ctypes.c_char_p, []),
@@ -186,8 +187,9 @@ class DeviceBuffer:
             _hip.hipFree(ctypes.c_void_p(self.ptr))
             self.ptr = None
 
-    def __del__(self):
-        if not sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals may be gone at exit)
+        if not _finalizing():
             self.close()
 
 
@@ -298,8 +300,9 @@ class NFA:
             lib.rpq_nfa_free(self.h)
             self.h = None
 
-    def __del__(self):
-        if not sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals may be gone at exit)
+        if not _finalizing():
             self.close()
 
 
@@ -332,8 +335,9 @@ class Graph:
         check(lib.rpq_graph_free(self.h))
         self.h = None
 
-    def __del__(self):
-        if not sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals may be gone at exit)
+        if not _finalizing():
             self.close()
 
     def info(self, key: str) -> int:
@@ -438,9 +442,14 @@ class Graph:
         return "V%d-L%d-E%d-R%d-%d" % (self.num_vertices, self.num_labels, self.info("num_edges"),
                                        self.info("rows_out"), self.info("rows_in"))
 
-    def submit(self, nfa: NFA, source: int) -> int:
+    def submit(self, nfa: NFA, source: int, deadline_us: Optional[int] = None) -> int:
+        """Queues a query; with deadline_us, rpq_submit_deadline (dropped with
+        RPQ_ETIMEDOUT if it has not started that many microseconds later)."""
         t = ctypes.c_uint64()
-        check(lib.rpq_submit(self.h, nfa.h, int(source), ctypes.byref(t)))
+        if deadline_us is None:
+            check(lib.rpq_submit(self.h, nfa.h, int(source), ctypes.byref(t)))
+        else:
+            check(lib.rpq_submit_deadline(self.h, nfa.h, int(source), int(deadline_us), ctypes.byref(t)))
         self._tickets.add(t.value)
         return t.value
 
@@ -455,6 +464,9 @@ class Graph:
             bm = np.empty(self.words, dtype=np.uint64)
             ptr, fl = _p(bm), 0
         r = lib.rpq_poll(self.h, ctypes.c_uint64(ticket), ptr, fl, ctypes.byref(st), int(timeout_us))
+        if r == RPQ_ETIMEDOUT and b"deadline" in (lib.rpq_last_error() or b""):
+            self._tickets.discard(ticket)  # dropped by its start deadline: retired
+            check(r)
         if r in (RPQ_PENDING, RPQ_ETIMEDOUT):
             return None
         self._tickets.discard(ticket)

@@ -1,8 +1,10 @@
 """Persistent launches from several graph handles at once: threads query two
 handles (plain single-source and stacked multi-source calls, whose grids fill
 the GPU and wait at grid barriers) concurrently; the launches of one process
-are serialized per device, so none waits for workgroups another grid holds,
-and every answer is the oracle's."""
+take their workgroups from a per-device budget of co-resident workgroups
+(grids that fit together run side by side, the others wait), so none waits
+at a barrier for workgroups another grid holds, and every answer is the
+oracle's."""
 import threading
 
 import numpy as np

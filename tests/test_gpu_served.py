@@ -204,15 +204,19 @@ def test_same_nfa_requests_run_as_stacked_groups(rpq):
     assert grouped > 0
 
 
-def test_large_queries_run_alone(rpq):
+@pytest.mark.parametrize("lanes", [0, 2, 3])
+def test_large_queries_run_alone(rpq, lanes):
     # threshold 0: after the first answer every query counts as large, and
-    # with large_query_slots 0 the rest run one at a time with the
-    # single-query kernel; answers and level counts are unchanged
+    # with large_query_slots 0 the rest run through the single-query kernel:
+    # one at a time in the scheduler thread (lanes 0), or on `lanes`
+    # executors side by side, each with its own state (three lanes share
+    # the co-resident workgroups); answers and level counts are unchanged
     w = C.rmat_workload(scale=13, edge_factor=16, num_labels=8, n_per_template=4)
     og = oracle.Graph(w.graph)
     gg = rpq.Graph(w.graph)
     gg.set_option("large_query_pairs", 0)
     gg.set_option("large_query_slots", 0)
+    gg.set_option("serve_lanes", lanes)
     nh = [rpq.NFA(n) for n in w.nfas]
     for rnd in range(2):
         res = _poll_all(gg, _submit_all(gg, nh, w.sources))
@@ -222,6 +226,45 @@ def test_large_queries_run_alone(rpq):
             assert st.levels == r.levels and st.visited_pairs == int(r.level_counts.sum()), (rnd, text)
         if rnd == 1:
             assert all(st.batch == 1 for _, st in res)
+    assert gg.info("serve_lanes") == lanes
+    gg.close()
+
+
+def test_lanes_with_plain_calls_and_pull(rpq):
+    # lanes run while the same handle answers plain calls from another
+    # thread (three persistent grids in flight), with the pull direction on
+    w = C.rmat_workload(scale=14, edge_factor=16, num_labels=8, n_per_template=3)
+    og = oracle.Graph(w.graph)
+    want = [og.ssr(n, int(s)).bitmap for n, s in zip(w.nfas, w.sources)]
+    gg = rpq.Graph(w.graph)
+    gg.set_option("large_query_pairs", 0)
+    gg.set_option("large_query_slots", 0)
+    gg.set_option("serve_lanes", 2)
+    gg.set_option("pull_alpha", 2)
+    nh = [rpq.NFA(n) for n in w.nfas]
+    errors = []
+
+    def plain():
+        try:
+            for _ in range(3):
+                for h, s, b in zip(nh, w.sources, want):
+                    bm, _ = gg.single_source(h, int(s))
+                    if not np.array_equal(bm, b):
+                        errors.append(("plain", int(s)))
+        except Exception as e:  # reported below
+            errors.append(repr(e))
+
+    th = threading.Thread(target=plain)
+    th.start()
+    for rnd in range(3):
+        res = _poll_all(gg, _submit_all(gg, nh, w.sources))
+        for i, (bm, _) in enumerate(res):
+            if not np.array_equal(bm, want[i]):
+                errors.append(("served", rnd, i))
+    th.join(timeout=240)
+    assert not th.is_alive()
+    assert not errors, errors[:5]
+    gg.close()
 
 
 def test_memory_budget_admission(rpq):
@@ -255,4 +298,39 @@ def test_memory_budget_admission(rpq):
         t = gg.submit(nh, int(w.sources[0]))
         gg.poll(t, timeout_us=30_000_000)
     assert e.value.status in (rpq.RPQ_ENOMEM, rpq.RPQ_EDEVICE) and "budget" in str(e.value)
+    gg.close()
+
+
+def test_submit_deadline(rpq):
+    # one slot, so requests queue behind each other: with a 1 us deadline to
+    # start, queued requests are dropped (RPQ_ETIMEDOUT, ticket retired) and
+    # the ones that started return the oracle's answer; with a long deadline
+    # every request completes
+    w = C.rmat_workload(scale=14, edge_factor=16, num_labels=8, n_per_template=4)
+    og = oracle.Graph(w.graph)
+    want = [og.ssr(n, int(s)).bitmap for n, s in zip(w.nfas, w.sources)]
+    gg = rpq.Graph(w.graph)
+    gg.set_option("max_slots", 1)
+    gg.set_option("serve_stack_min", 0)
+    nh = [rpq.NFA(n) for n in w.nfas]
+    tickets = [gg.submit(h, int(s), deadline_us=1) for h, s in zip(nh, w.sources)]
+    expired = done = 0
+    for i, t in enumerate(tickets):
+        try:
+            r = gg.poll(t, timeout_us=30_000_000)
+        except rpq.RPQError as e:
+            assert e.status == rpq.RPQ_ETIMEDOUT and "deadline" in str(e), str(e)
+            expired += 1
+            with pytest.raises(rpq.RPQError) as e2:
+                gg.poll(t, timeout_us=0)
+            assert e2.value.status == rpq.RPQ_ENOTFOUND
+            continue
+        assert r is not None and np.array_equal(r[0], want[i]), i
+        done += 1
+    print("expired", expired, "done", done)
+    assert expired >= 1 and expired + done == len(tickets)
+    tickets = [gg.submit(h, int(s), deadline_us=60_000_000) for h, s in zip(nh, w.sources)]
+    for i, t in enumerate(tickets):
+        r = gg.poll(t, timeout_us=60_000_000)
+        assert r is not None and np.array_equal(r[0], want[i]), i
     gg.close()
