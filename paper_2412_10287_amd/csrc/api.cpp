@@ -2,6 +2,7 @@
 // runtime behind them: graph upload, per-query NFA tables, the single-query
 // executor (one persistent launch, or a host-driven level loop).
 #include "api_internal.h"
+#include "trace.h"
 
 #include <stdarg.h>
 #include <stdio.h>
@@ -326,6 +327,7 @@ static void destroy(rpq_graph *g) {
 
 rpq_status rpq_graph_load(int32_t V, int32_t L, const int64_t *label_ptr, const int32_t *src,
                           const int32_t *dst, rpq_graph **out) {
+    TraceRange tr_("rpq_graph_load");
     if (!out) return fail(RPQ_EINVAL, "rpq_graph_load: out is NULL");
     *out = nullptr;
     if (V < 1) return fail(RPQ_EINVAL, "rpq_graph_load: num_vertices < 1");
@@ -553,6 +555,10 @@ rpq_status rpq_set_option(rpq_graph *g, const char *key, int64_t value) {
     } else if (!strcmp(key, "stacked_beta")) {
         if (value < 1) return fail(RPQ_EINVAL, "rpq_set_option: stacked_beta < 1");
         g->stack_beta = static_cast<double>(value);
+    } else if (!strcmp(key, "stacked_handoff_edges")) {
+        if (value < 0 || value > (int64_t(1) << 40))
+            return fail(RPQ_EINVAL, "rpq_set_option: stacked_handoff_edges outside [0, 2^40]");
+        g->stack_handoff = value;
     } else if (!strcmp(key, "max_batch")) {
         if (value < 1 || value > MAX_BATCH) return fail(RPQ_EINVAL, "rpq_set_option: max_batch outside [1, %d]", MAX_BATCH);
         g->max_batch = static_cast<int32_t>(value);
@@ -599,6 +605,7 @@ rpq_status rpq_get_option(const rpq_graph *g, const char *key, int64_t *value) {
     else if (!strcmp(key, "persistent_grid")) *value = g->plain_grid;
     else if (!strcmp(key, "stacked_alpha")) *value = static_cast<int64_t>(g->stack_alpha);
     else if (!strcmp(key, "stacked_beta")) *value = static_cast<int64_t>(g->stack_beta);
+    else if (!strcmp(key, "stacked_handoff_edges")) *value = g->stack_handoff;
     else if (!strcmp(key, "max_batch")) *value = g->max_batch;
     else if (!strcmp(key, "mem_budget")) *value = g->mem_budget;
     else if (!strcmp(key, "max_slots")) *value = g->max_slots;
@@ -674,6 +681,7 @@ static rpq_status run_graph_levels(rpq_graph *g, Params &p, int W, bool has_star
         // means the device words are wrong
         const uint64_t cap = (static_cast<uint64_t>(MAX_STATES) * static_cast<uint64_t>(g->V)) / GRAPH_LEVELS_PER_REPLAY + 2;
         for (uint64_t r = 0;; r++) {
+            TraceRange tr_("replay of levels from %lld", static_cast<long long>(r * GRAPH_LEVELS_PER_REPLAY));
             HIP_TRY(hipGraphLaunch(ex, s));
             HIP_TRY(hipMemcpyAsync(gc, g->gctl, 16, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
@@ -812,6 +820,7 @@ rpq_status rpq::run_single(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
         uint32_t *nq_host = reinterpret_cast<uint32_t *>(g->pinned + g->qconst_cap);
         nlev = (n->smask != 0) ? 1u : 0u;
         for (uint32_t lev = 0; nlev > lev; lev++) {
+            TraceRange tr_("level %lld", static_cast<long long>(lev));
             HIP_TRY(launch_select(W, p, lev, grid, s));
             if (timing) HIP_TRY(hipEventRecord(g->ev[2], s));
             HIP_TRY(launch_expand(W, p, lev, grid, s));
@@ -1006,6 +1015,7 @@ static rpq_status rare_end(rpq_graph *g, const rpq_nfa *n, int32_t source, uint6
 
 rpq_status rpq_single_source(rpq_graph *g, const rpq_nfa *n, int32_t source, uint64_t *out_bitmap,
                              uint32_t flags, rpq_stats *stats) {
+    TraceRange tr_("rpq_single_source");
     if (!g || !n || !out_bitmap) return fail(RPQ_EINVAL, "rpq_single_source: NULL argument");
     if (source < 0 || source >= g->V)
         return fail(RPQ_EINVAL, "rpq_single_source: source %d outside [0, %d)", source, g->V);
@@ -1043,6 +1053,7 @@ static void reverse_nfa(const rpq_nfa *n, rpq_nfa &rev) {
 
 rpq_status rpq_single_destination(rpq_graph *g, const rpq_nfa *n, int32_t target, uint64_t *out_bitmap,
                                   uint32_t flags, rpq_stats *stats) {
+    TraceRange tr_("rpq_single_destination");
     if (!g || !n || !out_bitmap) return fail(RPQ_EINVAL, "rpq_single_destination: NULL argument");
     if (target < 0 || target >= g->V)
         return fail(RPQ_EINVAL, "rpq_single_destination: target %d outside [0, %d)", target, g->V);
@@ -1061,6 +1072,7 @@ rpq_status rpq_single_destination(rpq_graph *g, const rpq_nfa *n, int32_t target
 // select (by the FIFO-level invariant of App. A that level is the length).
 rpq_status rpq_single_source_lengths(rpq_graph *g, const rpq_nfa *n, int32_t source, int32_t *out_lengths,
                                      uint32_t flags, rpq_stats *stats) {
+    TraceRange tr_("rpq_single_source_lengths");
     if (!g || !n || !out_lengths) return fail(RPQ_EINVAL, "rpq_single_source_lengths: NULL argument");
     if (source < 0 || source >= g->V)
         return fail(RPQ_EINVAL, "rpq_single_source_lengths: source %d outside [0, %d)", source, g->V);
@@ -1090,6 +1102,7 @@ rpq_status rpq_single_source_lengths(rpq_graph *g, const rpq_nfa *n, int32_t sou
 // single-source answers.
 rpq_status rpq_source_set(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
                           uint64_t *out_bitmap, uint32_t flags, rpq_stats *stats) {
+    TraceRange tr_("rpq_source_set");
     if (!g || !n || !sources || !out_bitmap) return fail(RPQ_EINVAL, "rpq_source_set: NULL argument");
     if (n_sources < 1) return fail(RPQ_EINVAL, "rpq_source_set: n_sources < 1");
     for (int32_t i = 0; i < n_sources; i++)

@@ -85,6 +85,7 @@ struct rpq_graph {
     double pull_beta = 24.0;
     double stack_alpha = 0.0;  // the same thresholds for the stacked multi-source path (push only until tuned)
     double stack_beta = 24.0;
+    int64_t stack_handoff = 1 << 20;  // push levels of rpq_multi_source with this many edges (and V/16) run as phase kernels (0 = never)
     int32_t max_batch = 256;
     int64_t mem_budget = 0;  // 0 = a quarter of the free device memory at first use
     int32_t max_slots = 128;

@@ -12,6 +12,7 @@
 #include <mutex>
 
 #include "api_internal.h"
+#include "trace.h"
 #include "stacked.h"
 
 using namespace rpq;
@@ -55,6 +56,7 @@ rpq_status setup(DevScratch &d) {
 
 rpq_status rpq_multi_source_noalloc(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
                                     uint64_t *out_bitmaps, uint32_t flags, rpq_stats *stats) {
+    TraceRange tr_("rpq_multi_source_noalloc");
     if (!g) return fail(RPQ_EINVAL, "rpq_multi_source_noalloc: NULL argument");
     if (g->device < 0 || g->device >= MAX_DEVICES)
         return fail(RPQ_EINVAL, "rpq_multi_source_noalloc: device %d beyond the %d supported", g->device, MAX_DEVICES);

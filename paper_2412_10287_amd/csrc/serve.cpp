@@ -21,6 +21,7 @@
 #include <unordered_map>
 
 #include "api_internal.h"
+#include "trace.h"
 #include "multi.h"
 
 using namespace rpq;
@@ -265,6 +266,7 @@ static rpq_status retire(rpq_graph *g, ServeState *ss);
 // One scheduler iteration with the lock released. Returns a failure status
 // for a device error (the engine then stops and fails every ticket).
 static rpq_status engine_step(rpq_graph *g, ServeState *ss, std::vector<Request> &admit) {
+    TraceRange tr_("served slot level %lld", static_cast<long long>(ss->level));
     MultiParams &p = ss->mp;
     hipStream_t s = ss->stream;
     const uint32_t parity = ss->level & 1;
@@ -407,6 +409,7 @@ static rpq_status retire(rpq_graph *g, ServeState *ss) {
 // each answer then moves to a result-pool entry or, when none is free, to
 // host memory. Called by the worker thread without ss->mu held.
 static rpq_status run_group(rpq_graph *g, ServeState *ss, std::vector<Request> &grp) {
+    TraceRange tr_("served stacked group of %lld", static_cast<long long>(grp.size()));
     const int32_t B = static_cast<int32_t>(grp.size());
     const size_t nw = static_cast<size_t>(g->nwords);
     if (!ss->gout) {
@@ -470,6 +473,7 @@ static rpq_status run_group(rpq_graph *g, ServeState *ss, std::vector<Request> &
 // answer written straight into a result-pool entry or, when none is free,
 // into host memory. Called by the worker thread without ss->mu held.
 static void run_one(rpq_graph *g, ServeState *ss, Request &r) {
+    TraceRange tr_("served query %lld", static_cast<long long>(r.id));
     const size_t nw = static_cast<size_t>(g->nwords);
     uint32_t entry = ~0u;
     {

@@ -48,11 +48,41 @@ struct StackParams {
     uint64_t item_cap, tile_cap;
     int64_t nwords;
     int32_t B, Q, V;
+    // Hand-off of large push levels to the phase kernels (k_st_expand,
+    // k_st_compact, k_st_select): a launch of k_stacked stops before the
+    // expansion of a push level with at least handoff_edges edges (0 = never)
+    // and leaves its place in hand[]; a launch with hand[HAND_RESUME] set
+    // continues at level hand[HAND_LEVEL], whose select is done.
+    uint32_t *hand;
+    uint64_t handoff_edges;
+};
+
+// Push levels with at least V / ST_SWEEP_DIV edges build the next queue in
+// vertex order (st_compact) instead of appending while they expand.
+constexpr uint32_t ST_SWEEP_DIV = 16;
+
+// hand[] words (HAND_WORDS of them)
+enum {
+    HAND_EXIT = 0,    // out: 0 finished (final phase done), 1 stopped before a large push level
+    HAND_LEVEL = 1,   // out: that level; in: the level to resume at
+    HAND_RESUME = 2,  // in: 1 = resume (skip the start pairs, keep counters and statistics)
+    HAND_NPUSH = 3,   // in/out: push levels so far
+    HAND_NPULL = 4,   // in/out: pull levels so far
+    HAND_LAST_LO = 5, // in: |M| of the last selected level (low, high words), for the level count
+    HAND_LAST_HI = 6,
+    HAND_WORDS = 16
 };
 
 // QM is the state bound the kernel is compiled for: 8 (every state set fits a
 // byte; enables the pull direction) or 32.
 hipError_t launch_stacked(int G, int QM, const StackParams &p, int grid, bool cooperative, hipStream_t s);
+// Phase kernels for large push levels (no grid barrier: ordinary launches of
+// as many workgroups as fit): the expansion of level n that marks the
+// candidates' state sets (record: also write level n's statistics record),
+// the vertex-ordered queue of level n + 1, and the select phase of level n.
+hipError_t launch_st_expand(int G, int QM, const StackParams &p, uint32_t n, bool record, hipStream_t s);
+hipError_t launch_st_compact(const StackParams &p, uint32_t n, hipStream_t s);
+hipError_t launch_st_select(int G, int QM, const StackParams &p, uint32_t n, hipStream_t s);
 int stacked_grid(int G, int QM);
 // Workgroups of the stacked kernel that fit on one compute unit (-1 on error).
 int stacked_blocks_per_cu(int G, int QM);

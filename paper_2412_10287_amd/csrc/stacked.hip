@@ -973,9 +973,6 @@ __device__ __forceinline__ void st_record(const StackParams &p, uint32_t n, uint
 // expansion units run in workgroup 0 alone, with workgroup barriers in place
 // of grid barriers, while the other workgroups wait at one grid barrier.
 constexpr uint32_t ST_SOLO_MAX_UNITS = 4 * TILE;  // expansion units of a small level
-// push levels with at least V / ST_SWEEP_DIV edges build the next queue in
-// vertex order (st_compact) instead of appending while they expand
-constexpr uint32_t ST_SWEEP_DIV = 16;
 constexpr uint32_t ST_SOLO_MAX_RUN = 2048;        // levels per run (the waiting barrier times out after 5 s)
 
 __device__ __forceinline__ void st_solo_sync() {
@@ -1015,6 +1012,12 @@ __device__ __forceinline__ void st_solo_levels(const StackParams &p, uint32_t n,
     }
 }
 
+// Writes the work counters this workgroup kept (threads 3..8, see st_select).
+__device__ __forceinline__ void st_flush_counters(const StackParams &p, uint64_t cacc) {
+    if (threadIdx.x >= 3 && threadIdx.x < 3 + ST_NCNT && cacc)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[threadIdx.x - 3]), static_cast<unsigned long long>(cacc));
+}
+
 template <int G, int QM>
 __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
     __shared__ StLds L;
@@ -1022,7 +1025,10 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
     GridBarrier *bar = p.bar;
     BarCtx bc;
     if (!barrier_register(bar, bc)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // a launch that continues after the phase kernels (every workgroup reads
+    // the same words: the host wrote them before the launch)
+    const bool resume = p.hand && ldc(&p.hand[HAND_RESUME]) != 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !resume) {
         rec_clear(p.rec[0]);
         for (int i = 0; i < 4; i++) p.status[i] = 0;
         for (int i = 0; i < ST_NCNT; i++) p.cnt[i] = 0;
@@ -1032,7 +1038,7 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
     // as candidates that level 0's select adds to P
     const QHeader &h = *s_qv.h;
     const uint32_t V = static_cast<uint32_t>(p.V);
-    for (uint32_t i = gthread(); i < static_cast<uint32_t>(p.B); i += gthreads()) {
+    for (uint32_t i = resume ? ~0u : gthread(); i < static_cast<uint32_t>(p.B); i += gthreads()) {
         const uint32_t s = static_cast<uint32_t>(p.sources[i]);
         if (s >= V) {
             sviol(p);
@@ -1056,11 +1062,21 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
     if (!grid_barrier(bar, bc)) return;
     uint32_t n = 0, npush = 0, npull = 0, prev = 0, solo_at = ~0u;
     uint64_t last_pairs = 0, cacc = 0;
+    bool resumed = false;  // level n's select was made by the phase kernels
+    if (resume) {
+        n = ldc(&p.hand[HAND_LEVEL]);
+        npush = ldc(&p.hand[HAND_NPUSH]);
+        npull = ldc(&p.hand[HAND_NPULL]);
+        last_pairs = static_cast<uint64_t>(ldc(&p.hand[HAND_LAST_LO])) |
+                     (static_cast<uint64_t>(ldc(&p.hand[HAND_LAST_HI])) << 32);
+        resumed = true;
+    }
     while (true) {
         const uint32_t nq = ld_acq(&p.rec[n % REC_RING].nq);
         if (nq == 0) break;
-        bool selected = false;
-        if (nq <= BLOCK / G && n != solo_at) {
+        bool selected = resumed;
+        resumed = false;
+        if (!selected && nq <= BLOCK / G && n != solo_at) {
             // a run of small levels in workgroup 0; the rest wait here
             solo_at = n;
             if (blockIdx.x == 0) st_solo_levels<G, QM>(p, n, L, prev, npush, cacc);
@@ -1082,6 +1098,19 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
         last_pairs = ld_acq(&R.pairs);
         const uint32_t mode = st_decide<QM>(p, n, prev);
         if (blockIdx.x == 0 && threadIdx.x == 0) st_record(p, n, mode);
+        if (mode == 0 && p.handoff_edges && (ld_acq(&R.sel) & 0xffffffffull) >= p.handoff_edges &&
+            (ld_acq(&R.sel) & 0xffffffffull) >= V / ST_SWEEP_DIV) {
+            // a large push level: the phase kernels take over from here (the
+            // same decision in every workgroup: all read R after the barrier)
+            st_flush_counters(p, cacc);
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                p.hand[HAND_EXIT] = 1;
+                p.hand[HAND_LEVEL] = n;
+                p.hand[HAND_NPUSH] = npush;
+                p.hand[HAND_NPULL] = npull;
+            }
+            return;
+        }
         if (mode == 0) {
             const uint64_t sel = ld_acq(&R.sel);
             if ((sel & 0xffffffffull) >= V / ST_SWEEP_DIV) {
@@ -1118,8 +1147,7 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
         n++;
     }
     // this workgroup's share of the work counters (threads 3..8)
-    if (threadIdx.x >= 3 && threadIdx.x < 3 + ST_NCNT && cacc)
-        atomicAdd(reinterpret_cast<unsigned long long *>(&p.cnt[threadIdx.x - 3]), static_cast<unsigned long long>(cacc));
+    st_flush_counters(p, cacc);
     // the last level may have found only visited pairs
     const uint32_t levels = (n > 0 && last_pairs == 0) ? n - 1 : n;
     st_final<G, QM>(p, n, levels);
@@ -1127,7 +1155,31 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
         p.status[0] = levels;
         p.status[1] = npush;
         p.status[2] = npull;
+        if (p.hand) p.hand[HAND_EXIT] = 0;
     }
+}
+
+// ------------------------------------------------------------ phase kernels
+// Large push levels outside the persistent launch: each phase is a kernel of
+// its own, so each gets the registers it needs alone (the expansion fits 128
+// VGPRs, two 512-thread workgroups per CU, where the persistent kernel, which
+// holds every phase, takes one), and kernel boundaries order the phases.
+template <int G, int QM>
+__global__ __launch_bounds__(BLOCK) void k_st_expand(StackParams p, uint32_t n, uint32_t record) {
+    __shared__ StLds L;
+    st_qv_setup(p.qv);
+    if (record && blockIdx.x == 0 && threadIdx.x == 0) st_record(p, n, 0);
+    expand_items<G, QM, false, true>(p, n, L, ld_acq(&p.rec[n % REC_RING].sel), ~0u, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_st_compact(StackParams p, uint32_t n) { st_compact(p, n); }
+
+template <int G, int QM>
+__global__ __launch_bounds__(BLOCK) void k_st_select(StackParams p, uint32_t n) {
+    st_qv_setup(p.qv);
+    uint64_t cacc = 0;
+    st_select<G, QM>(p, n, blockIdx.x, gridDim.x, cacc);
+    st_flush_counters(p, cacc);
 }
 
 // The grid is sized to be resident on an otherwise idle GPU, and every
@@ -1171,6 +1223,47 @@ hipError_t launch_stacked(int G, int QM, const StackParams &p, int grid, bool co
     RPQ_STACKED_DISPATCH(G, QM, (e = launch_g<GG, 8>(p, grid, cooperative, s)),
                          (e = launch_g<GG, 32>(p, grid, cooperative, s)));
     return e;
+}
+
+// Workgroups for a phase kernel: as many as fit the GPU at once.
+static int phase_grid(const void *kernel) {
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, BLOCK, 0) != hipSuccess || per < 1) per = 1;
+    return ncu * per;
+}
+
+template <int G, int QM>
+static hipError_t st_expand_g(const StackParams &p, uint32_t n, bool record, hipStream_t s) {
+    static const int grid = phase_grid(reinterpret_cast<const void *>(&k_st_expand<G, QM>));
+    hipLaunchKernelGGL((k_st_expand<G, QM>), dim3(grid), dim3(BLOCK), 0, s, p, n, record ? 1u : 0u);
+    return hipGetLastError();
+}
+
+template <int G, int QM>
+static hipError_t st_select_g(const StackParams &p, uint32_t n, hipStream_t s) {
+    static const int grid = phase_grid(reinterpret_cast<const void *>(&k_st_select<G, QM>));
+    hipLaunchKernelGGL((k_st_select<G, QM>), dim3(grid), dim3(BLOCK), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_st_expand(int G, int QM, const StackParams &p, uint32_t n, bool record, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    RPQ_STACKED_DISPATCH(G, QM, (e = st_expand_g<GG, 8>(p, n, record, s)), (e = st_expand_g<GG, 32>(p, n, record, s)));
+    return e;
+}
+
+hipError_t launch_st_select(int G, int QM, const StackParams &p, uint32_t n, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    RPQ_STACKED_DISPATCH(G, QM, (e = st_select_g<GG, 8>(p, n, s)), (e = st_select_g<GG, 32>(p, n, s)));
+    return e;
+}
+
+hipError_t launch_st_compact(const StackParams &p, uint32_t n, hipStream_t s) {
+    static const int grid = phase_grid(reinterpret_cast<const void *>(&k_st_compact));
+    hipLaunchKernelGGL(k_st_compact, dim3(grid), dim3(BLOCK), 0, s, p, n);
+    return hipGetLastError();
 }
 
 // The fixed device array behind rpq_multi_source_noalloc, in the module of

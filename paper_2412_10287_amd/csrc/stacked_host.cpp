@@ -5,6 +5,7 @@
 #include <algorithm>
 
 #include "api_internal.h"
+#include "trace.h"
 #include "stacked.h"
 
 using namespace rpq;
@@ -84,6 +85,7 @@ static rpq_status batch_prepare(rpq_graph *g, int32_t Q, int G, int32_t B, hipSt
     if ((st = balloc(b, reinterpret_cast<void **>(&p.bar), sizeof(GridBarrier), "barrier")) != RPQ_OK) return st;
     if ((st = balloc(b, reinterpret_cast<void **>(&p.status), 64, "status")) != RPQ_OK) return st;
     if ((st = balloc(b, reinterpret_cast<void **>(&p.cnt), 64, "counters")) != RPQ_OK) return st;
+    if ((st = balloc(b, reinterpret_cast<void **>(&p.hand), 4 * HAND_WORDS, "hand-off words")) != RPQ_OK) return st;
     if ((st = balloc(b, reinterpret_cast<void **>(&p.lvl), 8 * LVL_STRIDE * (LVL_COUNT_CAP + 1), "lvl")) != RPQ_OK)
         return st;
     if ((st = balloc(b, reinterpret_cast<void **>(&b->sources), 4 * static_cast<size_t>(MAX_BATCH), "sources")) !=
@@ -135,6 +137,7 @@ size_t rpq::stacked_arena_layout(const rpq_graph *g, int32_t Q, int G, int32_t B
     q.bar = static_cast<GridBarrier *>(take(sizeof(GridBarrier)));
     q.status = static_cast<uint32_t *>(take(64));
     q.cnt = static_cast<uint64_t *>(take(64));
+    q.hand = static_cast<uint32_t *>(take(4 * HAND_WORDS));
     q.lvl = static_cast<uint64_t *>(take(8 * LVL_STRIDE * (LVL_COUNT_CAP + 1)));
     uint8_t *qc = static_cast<uint8_t *>(take(g->qconst_cap));
     int32_t *sv = static_cast<int32_t *>(take(4 * static_cast<size_t>(MAX_BATCH)));
@@ -153,6 +156,66 @@ size_t rpq::stacked_arena_layout(const rpq_graph *g, int32_t Q, int G, int32_t B
 // arena (ar != nullptr), from the arena alone: then nothing is allocated,
 // the arena's arrays are cleared before each batch, and the host staging is
 // the graph handle's pinned buffer.
+// After a launch of the stacked kernel that may stop before a large push
+// level: runs such levels with the phase kernels (expansion that marks the
+// candidate state sets, vertex-ordered queue, select of the next level), one
+// host check per level, and relaunches the persistent kernel where a level
+// is small, pulls, or the traversal ends (its final phase runs there). The
+// persistent grid keeps its share of the co-resident workgroups throughout
+// (the caller holds it). `stage` is 128 bytes of pinned host memory.
+static rpq_status st_handoff_loop(rpq_graph *g, StackParams &p, int G, int QM, int grid, const QHeader *qh,
+                                  uint8_t *stage, hipStream_t s, const char *who) {
+    uint32_t *hw = reinterpret_cast<uint32_t *>(stage);          // hand words (64 bytes)
+    uint64_t *rw = reinterpret_cast<uint64_t *>(stage + 64);     // level records' fields
+    const uint64_t big = std::max<uint64_t>(p.handoff_edges, static_cast<uint64_t>(g->V) / ST_SWEEP_DIV);
+    // levels are bounded by |Q| |V| (App. A); more hand-offs mean a fault
+    const uint64_t cap = static_cast<uint64_t>(MAX_STATES) * static_cast<uint64_t>(g->V) + 2;
+    for (uint64_t round = 0;; round++) {
+        BT(hipMemcpyAsync(hw, p.hand, 4 * HAND_WORDS, hipMemcpyDeviceToHost, s));
+        BT(hipStreamSynchronize(s));
+        if (hw[HAND_EXIT] != 1) return RPQ_OK;  // finished, or aborted (the caller's status check reports it)
+        if (round > cap) return fail(RPQ_EDEVICE, "%s: the level loop did not terminate", who);
+        uint32_t lev = hw[HAND_LEVEL], npush = hw[HAND_NPUSH];
+        const uint32_t npull = hw[HAND_NPULL];
+        bool record = false;  // the persistent kernel recorded the first level
+        uint64_t last = 0;
+        while (true) {
+            BT(launch_st_expand(G, QM, p, lev, record, s));
+            BT(launch_st_compact(p, lev, s));
+            BT(launch_st_select(G, QM, p, lev + 1, s));
+            npush++;
+            const LevelRec *rn = &p.rec[(lev + 1) % REC_RING];
+            const LevelRec *rc = &p.rec[lev % REC_RING];
+            BT(hipMemcpyAsync(&rw[0], &rn->nq, 4, hipMemcpyDeviceToHost, s));
+            BT(hipMemcpyAsync(&rw[1], &rn->sel, 8, hipMemcpyDeviceToHost, s));
+            BT(hipMemcpyAsync(&rw[2], &rc->pairs, 8, hipMemcpyDeviceToHost, s));
+            BT(hipStreamSynchronize(s));
+            const uint32_t nq = static_cast<uint32_t>(rw[0]);
+            const uint64_t edges = rw[1] & 0xffffffffull;
+            last = rw[2];
+            lev++;
+            // the direction the persistent kernel would take after a push
+            // level (st_decide with prev = push)
+            const bool pull = QM <= 8 && qh->force != 1 &&
+                              (qh->force == 2 || (qh->alpha > 0.f && static_cast<double>(edges) * qh->alpha >
+                                                                          static_cast<double>(qh->e_rel)));
+            if (nq == 0 || edges < big || pull || lev > cap) break;
+            record = true;
+        }
+        // the persistent kernel continues at level lev, whose select is done
+        hw[HAND_EXIT] = 0;
+        hw[HAND_LEVEL] = lev;
+        hw[HAND_RESUME] = 1;
+        hw[HAND_NPUSH] = npush;
+        hw[HAND_NPULL] = npull;
+        hw[HAND_LAST_LO] = static_cast<uint32_t>(last);
+        hw[HAND_LAST_HI] = static_cast<uint32_t>(last >> 32);
+        BT(hipMemcpyAsync(p.hand, hw, 4 * HAND_WORDS, hipMemcpyHostToDevice, s));
+        BT(launch_fill(reinterpret_cast<uint32_t *>(p.bar), sizeof(GridBarrier) / 4, 0, s));
+        BT(launch_stacked(G, QM, p, grid, g->coop_launch, s));
+    }
+}
+
 rpq_status rpq::stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
                             uint64_t *out_bitmaps, uint32_t flags, rpq_stats *stats, const char *who,
                             const StackArena *ar, int32_t probe) {
@@ -190,7 +253,7 @@ rpq_status rpq::stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
                         "%s: %d sources of %d states on %d vertices need %zu bytes of scratch; the limit is %zu", who,
                         B0, n->Q, g->V, need, ar->bytes);
         pin = g->pinned;
-        lvl_room = (g->pinned_cap - g->qconst_cap - 4096 - 128) / (8 * LVL_STRIDE);
+        lvl_room = (g->pinned_cap - g->qconst_cap - 4096 - 256) / (8 * LVL_STRIDE);
         qsz = build_qconst_into(g, n, force, (flags & RPQ_COUNTERS) ? 1u : 0u, pin, g->qconst_cap, &nsym);
     } else {
         qsz = build_qconst(g, n, force, (flags & RPQ_COUNTERS) ? 1u : 0u, qbuf, &nsym);
@@ -211,6 +274,7 @@ rpq_status rpq::stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
     const uint64_t *lvl_rec = nullptr;
     uint32_t lvl_nrec = 0, lvl_levels = 0;
     for (int32_t b0 = 0; b0 < n_sources; b0 += maxb) {
+        TraceRange tr_("stacked batch from source %lld", static_cast<long long>(b0));
         const int32_t B = std::min(maxb, n_sources - b0);
         int G = 1;
         while (G * 64 < B) G *= 2;
@@ -261,8 +325,20 @@ rpq_status rpq::stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
             const rpq_status hs = hold.acquire(g->device, grid, stacked_blocks_per_cu(G, QM));
             if (hs != RPQ_OK) return hs;
         }
+        // large push levels go to the phase kernels (not with a probe, whose
+        // traversals are small by construction)
+        p.handoff_edges = probe < 0 ? static_cast<uint64_t>(g->stack_handoff) : 0;
+        BT(launch_fill(p.hand, HAND_WORDS, 0, s));
         BT(hipEventRecord(g->ev[2], s));
         BT(launch_stacked(G, QM, p, grid, g->coop_launch, s));
+        if (p.handoff_edges) {
+            const QHeader *qh = reinterpret_cast<const QHeader *>(pin);  // the query constants staged above
+            const rpq_status hs = st_handoff_loop(g, p, G, QM, grid, qh, pin + g->qconst_cap + 4096 + 128, s, who);
+            if (hs != RPQ_OK) {
+                if (!ar) batch_free(g);
+                return hs;
+            }
+        }
         BT(hipEventRecord(g->ev[3], s));
         uint32_t *hst = reinterpret_cast<uint32_t *>(pin + g->qconst_cap + 4 * 1024);
         uint64_t *hcnt = reinterpret_cast<uint64_t *>(pin + g->qconst_cap + 4 * 1024 + 64);
@@ -307,7 +383,7 @@ rpq_status rpq::stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
         uint32_t nrec = std::min<uint32_t>(hst[0] + 1, LVL_COUNT_CAP);
         if (ar) {
             nrec = std::min<uint32_t>(nrec, static_cast<uint32_t>(lvl_room));
-            uint64_t *dst = reinterpret_cast<uint64_t *>(pin + g->qconst_cap + 4096 + 128);
+            uint64_t *dst = reinterpret_cast<uint64_t *>(pin + g->qconst_cap + 4096 + 256);
             BT(hipMemcpy(dst, p.lvl, 8 * LVL_STRIDE * static_cast<size_t>(nrec), hipMemcpyDeviceToHost));
             lvl_rec = dst;
         } else {
@@ -344,5 +420,6 @@ rpq_status rpq::stacked_run(rpq_graph *g, const rpq_nfa *n, const int32_t *sourc
 
 rpq_status rpq_multi_source(rpq_graph *g, const rpq_nfa *n, const int32_t *sources, int32_t n_sources,
                             uint64_t *out_bitmaps, uint32_t flags, rpq_stats *stats) {
+    TraceRange tr_("rpq_multi_source");
     return stacked_run(g, n, sources, n_sources, out_bitmaps, flags, stats, "rpq_multi_source", nullptr);
 }

@@ -113,3 +113,14 @@ def test_tuning_cache_roundtrip(rpq, tmp_path):
     g3 = FakeGraph()
     autotune.tune(g3, rpq.TUNE_STACKED, [], [], cache=cache)  # another path: measured again
     assert g3.tuned == 1 and g3.options == {}
+
+
+def test_library_links_roctx(rpq):
+    # the named host ranges (one per C-ABI call, per host-driven level, per
+    # stacked batch and served step) come from the roctx library
+    import shutil
+    import subprocess
+    if not shutil.which("readelf"):
+        pytest.skip("no readelf")
+    out = subprocess.run(["readelf", "-d", rpq.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    assert "librocprofiler-sdk-roctx" in out

@@ -178,6 +178,34 @@ def test_repeat_and_device_output(rpq):
     assert np.array_equal(out.to_host().reshape(len(srcs), gg.words)[:5], first[:5])
 
 
+@pytest.mark.parametrize("B", [5, 130, 1000])
+def test_phase_kernel_handoff(rpq, B):
+    # push levels with at least stacked_handoff_edges edges (and V/16) run as
+    # separate phase kernels, and the persistent kernel resumes after them:
+    # threshold 1 hands off every level of at least V/16 edges. Answers,
+    # level counts and |P| against the oracle, for both thresholds, an
+    # automaton of more than 8 states, and the allocation-free entry point
+    g = G.rmat(12, 8, 6, 1.1, 31)
+    gg = rpq.Graph(g)
+    og = oracle.Graph(g)
+    rng = np.random.default_rng(B)
+    srcs = rng.integers(0, g.num_vertices, size=B)
+    gg.set_option("max_batch", 1024)
+    wide = R.glushkov(R.random_ast(rng, 14, lambda r: r.integers(0, 6), 0.3), 6)
+    for thr in (1, 0):
+        gg.set_option("stacked_handoff_edges", thr)
+        for nfa in (R.compile_regex("(0|^1)* 2 3*", 6), wide):
+            for name, fl in STACK_MODES.items():
+                print("B", B, "threshold", thr, nfa.text, name, flush=True)
+                _check(rpq, gg, og, nfa, srcs, fl)
+    gg.set_option("stacked_handoff_edges", 1)
+    nfa = R.compile_regex("(0|^1)* 2 3*", 6)
+    a, sa = gg.multi_source_noalloc(rpq.NFA(nfa), [int(x) for x in srcs[:256]], level_cap=64)
+    for i, s in enumerate(srcs[:256]):
+        assert np.array_equal(a[i], og.ssr(nfa, int(s)).bitmap), i
+    gg.close()
+
+
 def test_batched_counters(rpq):
     # the stacked call's work counters with RPQ_COUNTERS follow the batched
     # model, recomputed here from each source's oracle distances: scans over
@@ -204,9 +232,13 @@ def test_batched_counters(rpq):
             scans, scanned, active, byt, upd = (int(x) for x in want)
             pe = sum(int(r.product_edges) for r in res)
             for name, fl in STACK_MODES.items():
-                print(nfa.text, B, maxb, name, flush=True)
-                bms, st = gg.multi_source(rpq.NFA(nfa), srcs, flags=fl | rpq.COUNTERS)
-                for i, r in enumerate(res):
-                    assert np.array_equal(bms[i], r.bitmap), (nfa.text, B, name, i)
-                got = (st.scans, st.scanned_edges, st.active, st.alg_bytes, st.updates, st.product_edges)
-                assert got == (scans, scanned, active, byt, upd, pe), (nfa.text, B, maxb, name, got)
+                # with the phase kernels on every large level (threshold 1)
+                # and without (0): the counters add up the same
+                for thr in (1, 0):
+                    print(nfa.text, B, maxb, name, thr, flush=True)
+                    gg.set_option("stacked_handoff_edges", thr)
+                    bms, st = gg.multi_source(rpq.NFA(nfa), srcs, flags=fl | rpq.COUNTERS)
+                    for i, r in enumerate(res):
+                        assert np.array_equal(bms[i], r.bitmap), (nfa.text, B, name, i)
+                    got = (st.scans, st.scanned_edges, st.active, st.alg_bytes, st.updates, st.product_edges)
+                    assert got == (scans, scanned, active, byt, upd, pe), (nfa.text, B, maxb, name, thr, got)
