@@ -34,6 +34,10 @@
 namespace rpq {
 
 constexpr uint32_t PULL_LIGHT_ROW = 128;  // longer pull rows are processed edge-balanced
+// Row lookups a select lane issues together: two keep the select phase
+// kernel within 128 VGPRs (two workgroups per CU; with four it needs 141
+// and gets one, and a large kg level's select took 4.9 ms instead of 3.0).
+constexpr int ST_SYM_BATCH = 2;
 
 // The query's tables for every phase of the stacked kernel: a copy in LDS
 // when the block fits, else the global block.
@@ -279,22 +283,22 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
             for (int k = 0; k < SYM_WORDS; k++) Rs.w[k] &= PAT << j;
         }
         while (true) {
-            uint32_t us[SYM_BATCH], tu[SYM_BATCH], beg[SYM_BATCH], len[SYM_BATCH];
-            RankWordD rw[SYM_BATCH];
+            uint32_t us[ST_SYM_BATCH], tu[ST_SYM_BATCH], beg[ST_SYM_BATCH], len[ST_SYM_BATCH];
+            RankWordD rw[ST_SYM_BATCH];
 #pragma unroll
-            for (int jj = 0; jj < SYM_BATCH; jj++) us[jj] = symbol_pop(Rs);
+            for (int jj = 0; jj < ST_SYM_BATCH; jj++) us[jj] = symbol_pop(Rs);
             bool more = false;
 #pragma unroll
             for (int k = 0; k < SYM_WORDS; k++) more = more || Rs.w[k] != 0;
 #pragma unroll
-            for (int jj = 0; jj < SYM_BATCH; jj++) {
+            for (int jj = 0; jj < ST_SYM_BATCH; jj++) {
                 const uint32_t u = us[jj];
                 tu[jj] = (S && u < nsym) ? succ_of(qv.succ, u, S) : 0u;
                 if (tu[jj]) rw[jj] = g.rankw[qv.push_w[u] + (w >> 6)];
             }
             uint32_t cnt = 0, tot = 0;
 #pragma unroll
-            for (int jj = 0; jj < SYM_BATCH; jj++) {
+            for (int jj = 0; jj < ST_SYM_BATCH; jj++) {
                 const uint32_t u = us[jj];
                 len[jj] = 0;
                 uint32_t e;
@@ -337,7 +341,7 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
                 uint32_t eb = static_cast<uint32_t>(mine);
                 c_edges += tot;
 #pragma unroll
-                for (int jj = 0; jj < SYM_BATCH; jj++) {
+                for (int jj = 0; jj < ST_SYM_BATCH; jj++) {
                     if (!len[jj]) continue;
                     put_item<G>(p, idx, eb, beg[jj], len[jj], w, us[jj], S);
                     idx++;

@@ -27,7 +27,7 @@ def test_source_hash_is_stable_and_follows_the_sources():
         for f in files:
             assert os.path.exists(os.path.join(ROOT, "paper_2412_10287_amd", "csrc", f)), f
     # the two kernels share headers but not their main sources
-    assert bench.source_sha("rpq::k_persistent<1>") != bench.source_sha("rpq::k_stacked<4, 8>")
+    assert bench.source_sha("rpq::k_persistent<1>") != bench.source_sha(bench.STACKED_PASS)
 
 
 def test_traffic_summaries_name_their_kernel_and_sources():
