@@ -23,7 +23,9 @@
  *    word (v >> 6) (least significant bit first); pad bits are zero.
  *  - Handles are owned by the library until the matching *_free call.
  *  - Calls on one graph handle are serialized internally; different graph
- *    handles may be used from different threads.
+ *    handles may be used from different threads. Persistent launches of the
+ *    process on one GPU run side by side while their grids fit together (a
+ *    per-device budget of co-resident workgroups) and wait otherwise.
  */
 #ifndef RPQ_H
 #define RPQ_H
@@ -152,7 +154,9 @@ rpq_status rpq_graph_load(int32_t num_vertices, int32_t num_labels, const int64_
 rpq_status rpq_graph_free(rpq_graph *g);
 /* Graph facts: "num_vertices", "num_labels", "num_edges" (distinct), "device_bytes";
    "serve_slots": queries the served path holds at once, as its memory budget
-   allowed when it started (0 before the first rpq_submit has been admitted). */
+   allowed when it started (0 before the first rpq_submit has been admitted);
+   "serve_lanes": single-query executors the served path has made (0 before
+   it needed one). */
 rpq_status rpq_graph_info(const rpq_graph *g, const char *key, int64_t *value);
 
 /*
@@ -198,9 +202,20 @@ rpq_status rpq_graph_info(const rpq_graph *g, const char *key, int64_t *value);
  *                at most large_query_slots run in slots at once (the state
  *                arrays of many large queries thrash the caches, and a few
  *                of them already fill the GPU); with large_query_slots 0
- *                (the default) such periods run one request at a time with
- *                the single-query kernel once the slots have drained (the
- *                most efficient path per edge for large queries).
+ *                (the default) such periods run requests through the
+ *                single-query kernel once the slots have drained (the most
+ *                efficient path per edge for large queries), on the lanes.
+ *  "serve_lanes" single-query executors of the served path (default 2,
+ *                at most 8; 0 = the scheduler thread runs such requests one
+ *                at a time). Each has its own state arrays, stream and
+ *                constant cache on the handle's graph store, and a thread.
+ *  "serve_promote_pairs"  a query in a slot whose reached pairs pass this
+ *                many moves to a lane and starts over there (default 0 =
+ *                never; large-query periods apply instead).
+ *  "stacked_handoff_edges"  rpq_multi_source runs push levels of at least
+ *                this many edges (and V/16) as separate phase kernels with
+ *                more waves per CU than the persistent kernel (default
+ *                2^20; 0 = never). The answers are the same.
  * Errors: RPQ_ENOTFOUND for an unknown key, RPQ_EINVAL for a bad value.
  */
 rpq_status rpq_set_option(rpq_graph *g, const char *key, int64_t value);

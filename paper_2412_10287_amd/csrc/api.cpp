@@ -582,6 +582,9 @@ rpq_status rpq_set_option(rpq_graph *g, const char *key, int64_t value) {
         if (value < 0 || value > MAX_BATCH)
             return fail(RPQ_EINVAL, "rpq_set_option: serve_stack_min outside [0, %d]", MAX_BATCH);
         g->serve_stack_min = static_cast<int32_t>(value);
+    } else if (!strcmp(key, "serve_promote_pairs")) {
+        if (value < 0) return fail(RPQ_EINVAL, "rpq_set_option: serve_promote_pairs < 0");
+        g->serve_promote_pairs = value;
     } else if (!strcmp(key, "serve_lanes")) {
         if (value < 0 || value > MAX_LANES) return fail(RPQ_EINVAL, "rpq_set_option: serve_lanes outside [0, %d]", MAX_LANES);
         g->serve_lanes = static_cast<int32_t>(value);
@@ -614,6 +617,7 @@ rpq_status rpq_get_option(const rpq_graph *g, const char *key, int64_t *value) {
     else if (!strcmp(key, "serve_stack_min")) *value = g->serve_stack_min;
     else if (!strcmp(key, "rare_end_max")) *value = g->rare_end_max;
     else if (!strcmp(key, "serve_lanes")) *value = g->serve_lanes;
+    else if (!strcmp(key, "serve_promote_pairs")) *value = g->serve_promote_pairs;
     else if (!strcmp(key, "cooperative_launch")) *value = g->coop_launch ? 1 : 0;
     else if (!strcmp(key, "grid")) *value = g->grid_override;
     else return fail(RPQ_ENOTFOUND, "rpq_get_option: unknown key '%s'", key);

@@ -36,6 +36,8 @@ struct MultiParams {
     uint32_t *it_slot;       // items: slot
     uint32_t *tile_first;    // first item of each push tile
     uint64_t *out;           // result pool: 3 * slots bitmaps of nwords words (the last slots stage spills)
+    uint32_t *dead;          // per slot: non-zero = the query moved to a lane; its entries yield nothing
+                             // (the select drops its candidate words) until the slot is admitted again
     uint64_t swords;         // 32-bit words per slot array
     uint64_t item_cap, tile_cap, queue_cap;
     uint32_t slots;

@@ -37,6 +37,7 @@ __global__ void k_multi_admit(MultiParams p, uint32_t parity, uint32_t n, const 
     if (threadIdx.x != 0) return;
     const uint32_t sm = reinterpret_cast<const QHeader *>(stage + off)->smask;
     p.pairs[s * PAIRS_STRIDE] = 0;
+    p.dead[s] = 0;
     if (!sm) return;
     // M_0 = Q_S x {source} as a candidate: the next select adds it to P
     p.M[parity][s * p.swords + v] = sm;
@@ -89,7 +90,9 @@ __global__ __launch_bounds__(BLOCK) void k_multi_select(MultiParams p, uint32_t 
                 const uint64_t at = s * p.swords + v;
                 const uint32_t c = Mc[at];
                 const uint32_t pv = p.P[at];
-                S = c & ~pv;
+                // a slot whose query moved to a lane: its candidates are
+                // dropped, so its frontier ends here
+                S = p.dead[s] ? 0u : (c & ~pv);
                 if (S) p.P[at] = pv | S;
                 if (S != c) Mc[at] = S;
                 qv = slot_view(p, s);

@@ -62,6 +62,8 @@ struct SlotInfo {
     bool finished = false;  // frontier empty; waiting for a result-pool entry
     uint32_t levels = 0;
     uint64_t pairs = 0;
+    bool dead = false;      // moved to a lane (its reached pairs passed serve_promote_pairs)
+    Request req;            // the request, kept for a move to a lane
 };
 
 struct ServeState {
@@ -121,6 +123,7 @@ struct ServeState {
     std::condition_variable cv_lane;
     uint32_t lanes_busy = 0;
     bool lanes_failed = false;  // no lane could be made: run requests in the scheduler thread
+    uint32_t *h_one = nullptr;           // pinned word 1: the value a slot's dead flag is set to
     hipStream_t copy_stream = nullptr;   // rpq_poll's copies out of the pool
     std::mutex copy_mu;
     // pinned host staging
@@ -211,12 +214,13 @@ static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
     SA(p.tile_first, 4 * p.tile_cap);
     ss->pool_n = 2 * slots;
     SA(p.out, 8 * g->nwords * (ss->pool_n + slots));
+    SA(p.dead, 4 * static_cast<size_t>(slots));
     ss->stage_bytes = ADMIT_TABLE_BYTES + QC_STRIDE * static_cast<size_t>(slots);
     SA(ss->d_stage, ss->stage_bytes);
     SA(ss->d_copy_done, 64);
 #undef SA
     const size_t ctl_b = (multi_ctl_bytes(slots) + 63) & ~static_cast<size_t>(63);
-    ss->pinned_bytes = ss->stage_bytes + ctl_b + 8 * slots + 256;
+    ss->pinned_bytes = ss->stage_bytes + ctl_b + 8 * slots + 256 + 64;
     if ((e = hipHostMalloc(reinterpret_cast<void **>(&ss->pinned), ss->pinned_bytes, hipHostMallocDefault)) != hipSuccess)
         return fail(RPQ_ENOMEM, "served path: hipHostMalloc: %s", hipGetErrorString(e));
     uint8_t *hp = ss->pinned;
@@ -228,6 +232,8 @@ static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
     hp += 8 * slots;
     ss->h_copy_flag = reinterpret_cast<volatile uint32_t *>(hp);
     *ss->h_copy_flag = 0;
+    ss->h_one = reinterpret_cast<uint32_t *>(hp + 256);
+    *ss->h_one = 1;
     {
         uint8_t *dp = nullptr;
         if ((e = hipHostGetDevicePointer(reinterpret_cast<void **>(&dp), ss->pinned, 0)) != hipSuccess)
@@ -242,6 +248,7 @@ static rpq_status engine_init(rpq_graph *g, ServeState *ss) {
     for (uint32_t *a : {p.P, p.M[0], p.M[1]})
         if ((e = launch_fill(a, swords * slots, 0, ss->stream)) != hipSuccess) return hip_fail(e, "fill");
     if ((e = launch_fill(p.ctl, multi_ctl_bytes(slots) / 4, 0, ss->stream)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_fill(p.dead, slots, 0, ss->stream)) != hipSuccess) return hip_fail(e, "fill");
     if ((e = launch_fill(ss->d_copy_done, 16, 0, ss->stream)) != hipSuccess) return hip_fail(e, "fill");
     if ((e = launch_fill(reinterpret_cast<uint32_t *>(p.sel), 4, 0, ss->stream)) != hipSuccess)
         return hip_fail(e, "fill");
@@ -289,6 +296,7 @@ static rpq_status engine_step(rpq_graph *g, ServeState *ss, std::vector<Request>
             table[4 * k + 3] = static_cast<uint32_t>(r.qc.size());
             off += (r.qc.size() + 15) & ~static_cast<size_t>(15);
             k++;
+            ss->slot[sl].req = std::move(r);
         }
         ST(hipMemcpyAsync(ss->d_stage, ss->h_stage, off, hipMemcpyHostToDevice, s));
         ST(multi_admit(p, parity, k, ss->d_stage, s));
@@ -313,7 +321,13 @@ static rpq_status engine_step(rpq_graph *g, ServeState *ss, std::vector<Request>
     const uint64_t *h_pairs = reinterpret_cast<const uint64_t *>(ss->h_ctl + multi_pairs_offset(ss->slots));
     if (h_status) return fail(RPQ_EDEVICE, "served path: internal invariant violated %u times", h_status);
     const uint32_t next_len = *reinterpret_cast<const uint32_t *>(ss->h_ctl + CTL_QLEN + (parity ^ 1) * CTL_LINE);
-    // 3. queries whose next frontier is empty are finished
+    // 3. queries whose next frontier is empty are finished; a query whose
+    //    reached pairs passed serve_promote_pairs moves to a lane: its slot's
+    //    candidates are dropped from the next select on (the flag goes up
+    //    on this stream, ahead of the next level), its frontier ends there,
+    //    and retire() hands the request to the lanes instead of answering
+    const uint64_t promote = (g->serve_promote_pairs > 0 && !ss->lanes.empty())
+                                 ? static_cast<uint64_t>(g->serve_promote_pairs) : 0;
     for (uint32_t sl = 0; sl < ss->slots; sl++) {
         SlotInfo &si = ss->slot[sl];
         if (si.ticket && !si.finished && h_cnt[sl] == 0) {
@@ -321,6 +335,9 @@ static rpq_status engine_step(rpq_graph *g, ServeState *ss, std::vector<Request>
             si.levels = ss->level - si.admit_level + 1;
             si.pairs = h_pairs[sl * PAIRS_STRIDE];
             ss->ready.push_back(sl);
+        } else if (si.ticket && !si.finished && !si.dead && promote && h_pairs[sl * PAIRS_STRIDE] > promote) {
+            si.dead = true;
+            ST(hipMemcpyAsync(p.dead + sl, ss->h_one, 4, hipMemcpyHostToDevice, s));
         }
     }
     ss->prev_len = ss->cur_len;
@@ -343,7 +360,10 @@ static rpq_status retire(rpq_graph *g, ServeState *ss) {
         std::lock_guard<std::mutex> lk(ss->mu);
         for (uint32_t f = 0; f < nfin; f++) {
             ss->h_fin[2 * f] = ss->ready[f];
-            if (!ss->free_entries.empty()) {
+            if (ss->slot[ss->ready[f]].dead) {
+                // extracted only to clear the slot: a staging entry, not copied out
+                ss->h_fin[2 * f + 1] = ss->pool_n + nspill++;
+            } else if (!ss->free_entries.empty()) {
                 ss->h_fin[2 * f + 1] = ss->free_entries.back();
                 ss->free_entries.pop_back();
             } else {
@@ -362,6 +382,10 @@ static rpq_status retire(rpq_graph *g, ServeState *ss) {
     for (uint32_t f = 0, k = 0; f < nfin; f++) {
         const uint32_t entry = ss->h_fin[2 * f + 1];
         if (entry < ss->pool_n) continue;
+        if (ss->slot[ss->h_fin[2 * f]].dead) {
+            k++;
+            continue;
+        }
         spilled[k].resize(static_cast<size_t>(g->nwords));
         ST(hipMemcpy(spilled[k].data(), p.out + static_cast<size_t>(entry) * g->nwords, 8 * static_cast<size_t>(g->nwords),
                      hipMemcpyDeviceToHost));
@@ -375,6 +399,16 @@ static rpq_status retire(rpq_graph *g, ServeState *ss) {
         const bool spill = entry >= ss->pool_n;
         SlotInfo &si = ss->slot[sl];
         auto it = ss->tickets.find(si.ticket);
+        if (si.dead) {
+            // the request runs again on a lane from its start (answered there)
+            if (spill) k++;
+            ss->lane_q.push_front(std::move(si.req));
+            ss->lanes_busy++;
+            ss->cv_lane.notify_one();
+            si = SlotInfo{};
+            ss->free_slots.push_back(sl);
+            continue;
+        }
         if (it != ss->tickets.end()) {
             Ticket &t = it->second;
             if (spill) t.spill.swap(spilled[k]);
@@ -646,6 +680,9 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
     }
     std::vector<Request> admit, grp, one;
     bool make_lanes = false;
+    // with promotion, the lanes exist from the start: large queries move
+    // there from their slots while the slots go on with the rest
+    if (g->serve_promote_pairs > 0 && g->serve_lanes > 0) lanes_ready(g, ss);
     while (true) {
         admit.clear();
         grp.clear();
@@ -670,7 +707,8 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
             // queries are large; with large_query_slots 0, large-query
             // periods run one request at a time through the single-query
             // kernel once the slots have drained
-            const bool large = ss->size_n && ss->size_avg > static_cast<double>(g->large_pairs);
+            const bool promoting = g->serve_promote_pairs > 0 && !ss->lanes.empty();
+            const bool large = !promoting && ss->size_n && ss->size_avg > static_cast<double>(g->large_pairs);
             size_t cap = ss->slots;
             if (large) cap = std::min<size_t>(cap, static_cast<size_t>(g->large_slots));
             auto active = [&] { return static_cast<size_t>(ss->slots) - ss->free_slots.size(); };

@@ -167,6 +167,7 @@ def test_large_query_cap(rpq):
     gg = rpq.Graph(w.graph)
     gg.set_option("large_query_pairs", 0)
     gg.set_option("large_query_slots", 2)
+    gg.set_option("serve_promote_pairs", 0)  # the large-period cap, not promotion
     assert gg.get_option("large_query_slots") == 2
     nh = [rpq.NFA(n) for n in w.nfas]
     for rnd in range(2):
@@ -217,6 +218,7 @@ def test_large_queries_run_alone(rpq, lanes):
     gg.set_option("large_query_pairs", 0)
     gg.set_option("large_query_slots", 0)
     gg.set_option("serve_lanes", lanes)
+    gg.set_option("serve_promote_pairs", 0)  # large periods, not promotion
     nh = [rpq.NFA(n) for n in w.nfas]
     for rnd in range(2):
         res = _poll_all(gg, _submit_all(gg, nh, w.sources))
@@ -231,14 +233,15 @@ def test_large_queries_run_alone(rpq, lanes):
 
 
 def test_lanes_with_plain_calls_and_pull(rpq):
-    # lanes run while the same handle answers plain calls from another
-    # thread (three persistent grids in flight), with the pull direction on
+    # every served query moves from its slot to a lane after its first level
+    # (promotion threshold 1 pair) while the same handle answers plain calls
+    # from another thread (up to three persistent grids wanting the GPU),
+    # with the pull direction on
     w = C.rmat_workload(scale=14, edge_factor=16, num_labels=8, n_per_template=3)
     og = oracle.Graph(w.graph)
     want = [og.ssr(n, int(s)).bitmap for n, s in zip(w.nfas, w.sources)]
     gg = rpq.Graph(w.graph)
-    gg.set_option("large_query_pairs", 0)
-    gg.set_option("large_query_slots", 0)
+    gg.set_option("serve_promote_pairs", 1)
     gg.set_option("serve_lanes", 2)
     gg.set_option("pull_alpha", 2)
     nh = [rpq.NFA(n) for n in w.nfas]
@@ -333,4 +336,30 @@ def test_submit_deadline(rpq):
     for i, t in enumerate(tickets):
         r = gg.poll(t, timeout_us=60_000_000)
         assert r is not None and np.array_equal(r[0], want[i]), i
+    gg.close()
+
+
+@pytest.mark.parametrize("threshold", [1, 2000, 0])
+def test_promotion_to_lanes(rpq, threshold):
+    # a slot query whose reached pairs pass serve_promote_pairs moves to a
+    # lane and starts over there; answers, level counts and |P| stay the
+    # oracle's, and promoted answers carry batch 1 (threshold 0: never)
+    w = C.rmat_workload(scale=13, edge_factor=16, num_labels=8, n_per_template=4)
+    og = oracle.Graph(w.graph)
+    gg = rpq.Graph(w.graph)
+    gg.set_option("serve_promote_pairs", threshold)
+    gg.set_option("serve_stack_min", 0)
+    nh = [rpq.NFA(n) for n in w.nfas]
+    for rnd in range(2):
+        res = _poll_all(gg, _submit_all(gg, nh, w.sources))
+        alone = 0
+        for (bm, st), n, s, text in zip(res, w.nfas, w.sources, w.queries):
+            r = og.ssr(n, int(s))
+            assert np.array_equal(bm, r.bitmap), (threshold, rnd, text)
+            assert st.levels == r.levels and st.visited_pairs == int(r.level_counts.sum()), (threshold, text)
+            alone += st.batch == 1
+        print("threshold", threshold, "round", rnd, "promoted", alone, "of", len(res))
+        if threshold == 1:
+            assert alone >= len(res) // 2
+    assert gg.info("serve_lanes") == (2 if threshold else 0)
     gg.close()
