@@ -38,6 +38,14 @@ constexpr uint32_t PULL_LIGHT_ROW = 128;  // longer pull rows are processed edge
 // kernel within 128 VGPRs (two workgroups per CU; with four it needs 141
 // and gets one, and a large kg level's select took 4.9 ms instead of 3.0).
 constexpr int ST_SYM_BATCH = 2;
+// The expansion phase kernel: units per thread and step, and the waves per
+// SIMD its registers are fitted to (six: three 512-thread workgroups per CU,
+// 80 VGPRs). Two units per thread fit without spills up to G = 4, one beyond;
+// at two workgroups per CU with four units per thread a large kg level's
+// expansion took 14.5 ms, at three with two 12.5 ms.
+template <int G>
+constexpr int st_expand_upt() { return G <= 4 ? 2 : 1; }
+constexpr int ST_EXPAND_WAVES = 6;
 
 // The query's tables for every phase of the stacked kernel: a copy in LDS
 // when the block fits, else the global block.
@@ -132,10 +140,15 @@ __device__ __forceinline__ uint64_t group_or64(uint64_t x) {
     return x;
 }
 
-// LDS copy of the work items one workgroup is processing.
-struct StLds {
-    uint32_t eb[TILE + 1], beg[TILE + 1], v[TILE + 1], u[TILE + 1], s[TILE + 1];
+// LDS copy of the work items one workgroup is processing: at most CAP of
+// them (a tile of TILE edges holds at most TILE / G + 1 items of G-word
+// units; the persistent kernel keeps room for the G = 1 case).
+template <uint32_t CAP>
+struct StLdsN {
+    static constexpr uint32_t cap = CAP;
+    uint32_t eb[CAP], beg[CAP], v[CAP], u[CAP], s[CAP];
 };
+using StLds = StLdsN<TILE + 1>;
 
 // Records item idx: `len` edges numbered from eb (both reserved by the caller
 // with one atomic on a word that counts items in its high half and edges in
@@ -388,8 +401,8 @@ struct UnitC {
 // edge. The halving steps depend on cnt alone (the same in every lane), so
 // they run as one uniform loop of ceil(log2(cnt)) steps for all K units; a
 // unit past uend searches for the range's last unit, and its caller drops it.
-template <int G, int K>
-__device__ __forceinline__ void item_search(const StLds &L, uint32_t cnt, const uint64_t (&unit)[K], uint64_t uend,
+template <int G, int K, class LT>
+__device__ __forceinline__ void item_search(const LT &L, uint32_t cnt, const uint64_t (&unit)[K], uint64_t uend,
                                             uint32_t (&lo)[K]) {
     uint32_t t[K];
 #pragma unroll
@@ -406,8 +419,8 @@ __device__ __forceinline__ void item_search(const StLds &L, uint32_t cnt, const 
     }
 }
 
-template <int G, int QM, bool PULL>
-__device__ __forceinline__ void unit_gather(const StackParams &p, uint32_t n, const StLds &L, uint32_t lo,
+template <int G, int QM, bool PULL, class LT>
+__device__ __forceinline__ void unit_gather(const StackParams &p, uint32_t n, const LT &L, uint32_t lo,
                                             uint64_t unit, uint64_t uend, uint32_t ns, UnitC<QM> &U) {
     const uint32_t V = static_cast<uint32_t>(p.V);
     const uint32_t j = static_cast<uint32_t>(unit % G);
@@ -623,37 +636,42 @@ __device__ __forceinline__ void wave_merge(UnitC<QM> &U) {
 // Pull (long rows): the item is (w, u) with the reverse neighbour v on the
 // edge; only states in sup[v] & L.s (predecessors of the wanted states) count.
 // Either way the candidate bits already in P are dropped before the atomic
-// OR, and the first writer of sup_next[w] appends w to the next queue. Four
+// OR, and the first writer of sup_next[w] appends w to the next queue. UPT
 // units per thread are gathered before any is scattered (QM <= 8), so their
-// loads overlap.
-template <int G, int QM, bool PULL, bool MARK>
-__device__ __forceinline__ void expand_range(const StackParams &p, uint32_t n, const StLds &L, uint32_t cnt, uint64_t ubase,
-                             uint64_t uend, uint32_t ns) {
+// loads overlap; fewer units per thread take fewer registers and leave room
+// for more waves.
+template <int G, int QM, bool PULL, bool MARK, int UPT, class LT>
+__device__ __forceinline__ void expand_range(const StackParams &p, uint32_t n, const LT &L, uint32_t cnt, uint64_t ubase,
+                                             uint64_t uend, uint32_t ns) {
     const uint32_t tid = threadIdx.x;
     const uint32_t j = tid % G;
     if constexpr (QM <= 8) {
-        static_assert(TILE == 4 * BLOCK, "four units per thread and step");
-        for (uint64_t ub = ubase; ub < uend; ub += TILE) {
-            UnitC<QM> U0, U1, U2, U3;
-            const uint64_t us[4] = {ub + tid, ub + BLOCK + tid, ub + 2 * BLOCK + tid, ub + 3 * BLOCK + tid};
-            uint32_t lo[4];
-            item_search<G, 4>(L, cnt, us, uend, lo);
-            unit_gather<G, QM, PULL>(p, n, L, lo[0], us[0], uend, ns, U0);
-            unit_gather<G, QM, PULL>(p, n, L, lo[1], us[1], uend, ns, U1);
-            unit_gather<G, QM, PULL>(p, n, L, lo[2], us[2], uend, ns, U2);
-            unit_gather<G, QM, PULL>(p, n, L, lo[3], us[3], uend, ns, U3);
+        static_assert(TILE % (UPT * BLOCK) == 0, "a tile is whole steps of the workgroup");
+        for (uint64_t ub = ubase; ub < uend; ub += UPT * BLOCK) {
+            UnitC<QM> U[UPT];
+            uint64_t us[UPT];
+#pragma unroll
+            for (int k = 0; k < UPT; k++) us[k] = ub + static_cast<uint64_t>(k) * BLOCK + tid;
+            uint32_t lo[UPT];
+            item_search<G, UPT>(L, cnt, us, uend, lo);
+#pragma unroll
+            for (int k = 0; k < UPT; k++) unit_gather<G, QM, PULL>(p, n, L, lo[k], us[k], uend, ns, U[k]);
             if constexpr (PULL) {
-                wave_merge<G, QM>(U0);
-                wave_merge<G, QM>(U1);
-                wave_merge<G, QM>(U2);
-                wave_merge<G, QM>(U3);
+#pragma unroll
+                for (int k = 0; k < UPT; k++) wave_merge<G, QM>(U[k]);
             }
-            unit_scatter<G, QM>(p, n, j, U0);
-            unit_scatter<G, QM>(p, n, j, U1);
-            unit_scatter<G, QM>(p, n, j, U2);
-            unit_scatter<G, QM>(p, n, j, U3);
-            if constexpr (MARK) unit_mark4<G, QM>(p, n, j, U0, U1, U2, U3);
-            else unit_append4<G, QM>(p, n, j, U0, U1, U2, U3);
+#pragma unroll
+            for (int k = 0; k < UPT; k++) unit_scatter<G, QM>(p, n, j, U[k]);
+            if constexpr (UPT == 4) {
+                if constexpr (MARK) unit_mark4<G, QM>(p, n, j, U[0], U[1], U[2], U[3]);
+                else unit_append4<G, QM>(p, n, j, U[0], U[1], U[2], U[3]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < UPT; k++) {
+                    if constexpr (MARK) unit_mark<G, QM>(p, n, j, U[k]);
+                    else unit_append<G, QM>(p, n, j, U[k]);
+                }
+            }
         }
     } else {
         for (uint64_t ub = ubase; ub < uend; ub += BLOCK) {
@@ -669,9 +687,11 @@ __device__ __forceinline__ void expand_range(const StackParams &p, uint32_t n, c
 }
 
 // Items [0, nitems) with `T` edges (packed in sel) -> units spread over the grid.
-template <int G, int QM, bool PULL, bool MARK = false>
-__device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, StLds &L, uint64_t sel, uint32_t ns,
+template <int G, int QM, bool PULL, bool MARK = false, int UPT = 4, class LT = StLds>
+__device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, LT &L, uint64_t sel, uint32_t ns,
                                              uint32_t bid, uint32_t nblk) {
+    constexpr uint32_t TE = TILE / G;
+    static_assert(LT::cap >= TE + 1, "room for the items of one tile");
     const uint32_t nitems = static_cast<uint32_t>(sel >> 32);
     const uint32_t T = static_cast<uint32_t>(sel);
     if (T == 0 || nitems == 0) return;
@@ -681,7 +701,7 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, S
     }
     const uint64_t units = static_cast<uint64_t>(T) * G;
     const uint32_t tid = threadIdx.x;
-    if (nitems <= TILE) {
+    if (nitems < LT::cap) {
         // few items: every workgroup stages all of them and takes an even,
         // wave-aligned share of the units, so small levels use the whole chip
         for (uint32_t x = tid; x < nitems; x += BLOCK) {
@@ -696,11 +716,10 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, S
         per = (per + 63) & ~63ull;
         const uint64_t b0 = static_cast<uint64_t>(bid) * per;
         const uint64_t b1 = b0 + per < units ? b0 + per : units;
-        if (b0 < b1) expand_range<G, QM, PULL, MARK>(p, n, L, nitems, b0, b1, ns);
+        if (b0 < b1) expand_range<G, QM, PULL, MARK, UPT>(p, n, L, nitems, b0, b1, ns);
         __syncthreads();
         return;
     }
-    constexpr uint32_t TE = TILE / G;
     const uint32_t ntiles = (T + TE - 1) / TE;
     // fewer tiles than workgroups: split each tile into parts of at least a
     // wave's worth of units, so the level still spreads over the grid
@@ -726,7 +745,7 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, S
         __syncthreads();
         const uint64_t u0 = static_cast<uint64_t>(tile) * TILE + static_cast<uint64_t>(part) * part_units;
         const uint64_t u1 = u0 + part_units < units ? u0 + part_units : units;
-        if (u0 < u1) expand_range<G, QM, PULL, MARK>(p, n, L, cnt, u0, u1, ns);
+        if (u0 < u1) expand_range<G, QM, PULL, MARK, UPT>(p, n, L, cnt, u0, u1, ns);
         __syncthreads();
     }
 }
@@ -885,9 +904,10 @@ __device__ __forceinline__ uint32_t st_decide(const StackParams &p, uint32_t n, 
 }
 
 // --------------------------------------------------------------- extract
-// Result: source b reaches v iff some final state's row at v has bit b. One
-// wavefront per (64-vertex block, word): 64 ballots transpose the block into
-// one output word per source. P and the last frontier are reset.
+// Result: source b reaches v iff some final state's row at v has bit b. A
+// wavefront holds 64 consecutive vertices, one per lane, and 64 ballots
+// transpose each source word of the block into one output word per source.
+// P and the last frontier are reset.
 template <int G, int QM>
 __device__ __forceinline__ void st_final(const StackParams &p, uint32_t nexit, uint32_t levels) {
     const uint32_t V = static_cast<uint32_t>(p.V);
@@ -932,29 +952,92 @@ __device__ __forceinline__ void st_final(const StackParams &p, uint32_t nexit, u
         }
         p.out[threadIdx.x] = f & word_full(p.B, threadIdx.x);
     }
+    if constexpr (QM * G <= 32) {
+        // a wave takes KC consecutive 64-vertex blocks and every source word
+        // of them: each lane loads its vertex's whole row (all loads in
+        // flight together), and lane i of the wave then stores KC
+        // consecutive output words of source j*64 + i for every word j
+        constexpr uint32_t NW = QM * G;
+        constexpr uint32_t KC = 16 / G;
+        const uint32_t QG = Q * G;
+        const uint64_t nchunks = (nwords + KC - 1) / KC;
+        for (uint64_t c = gthread() >> 6; c < nchunks; c += gthreads() >> 6) {
+            uint64_t mine[G][KC];
+#pragma unroll
+            for (uint32_t kk = 0; kk < KC; kk++) {
+                const uint64_t k = c * KC + kk;
+                const uint64_t v = k * 64 + lane;
+                uint64_t f[G];
+#pragma unroll
+                for (int j = 0; j < G; j++) f[j] = 0;
+                if (v < V && !(probing && v == p.probe)) {
+                    const uint64_t r0 = rowi<G>(p, static_cast<uint32_t>(v), 0);
+                    uint64_t x[NW];
+#pragma unroll
+                    for (uint32_t w = 0; w < NW; w++) x[w] = w < QG ? ldc(&p.P[r0 + w]) : 0ull;
+#pragma unroll
+                    for (uint32_t w = 0; w < NW; w++) {
+                        if (x[w]) {
+                            if (fm >> (w / G) & 1u) f[w % G] |= x[w];
+                            p.P[r0 + w] = 0;
+                            p.M[0][r0 + w] = 0;
+                            p.M[1][r0 + w] = 0;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < G; j++) {
+                    uint64_t t = 0;
+                    if (!probing) {  // uniform: the probe is a launch parameter
+                        for (uint32_t i = 0; i < 64; i++) {
+                            const uint64_t bl = __ballot((f[j] >> i) & 1ull);
+                            if (lane == i) t = bl;
+                        }
+                    }
+                    mine[j][kk] = t;
+                }
+            }
+            if (probing) continue;
+#pragma unroll
+            for (int j = 0; j < G; j++) {
+                const uint32_t src = j * 64 + lane;
+                if (src >= B) continue;
+#pragma unroll
+                for (uint32_t kk = 0; kk < KC; kk++) {
+                    const uint64_t k = c * KC + kk;
+                    if (k < nwords) p.out[static_cast<uint64_t>(src) * nwords + k] = mine[j][kk];
+                }
+            }
+        }
+        return;
+    }
     for (uint64_t gw = gthread() >> 6; gw < total; gw += gthreads() >> 6) {
         const uint64_t k = gw / G;
         const uint32_t j = static_cast<uint32_t>(gw % G);
         const uint64_t v = k * 64 + lane;
         uint64_t f = 0;
         if (v < V && !(probing && v == p.probe)) {
+            const uint64_t r0 = rowi<G>(p, static_cast<uint32_t>(v), 0) + j;
             for (uint32_t q = 0; q < Q; q++) {
-                const uint64_t idx = rowi<G>(p, static_cast<uint32_t>(v), q) + j;
-                const uint64_t x = ldc(&p.P[idx]);
+                const uint64_t x = ldc(&p.P[r0 + q * G]);
                 if (x) {
                     if (fm >> q & 1u) f |= x;
-                    p.P[idx] = 0;
-                    p.M[0][idx] = 0;
-                    p.M[1][idx] = 0;
+                    p.P[r0 + q * G] = 0;
+                    p.M[0][r0 + q * G] = 0;
+                    p.M[1][r0 + q * G] = 0;
                 }
             }
         }
         if (probing) continue;  // uniform: the probe is a launch parameter
+        // transpose: lane i keeps the word of source j*64 + i (bit l = vertex
+        // 64k + l) and the wave stores all of them with one instruction
+        uint64_t mine = 0;
         for (uint32_t i = 0; i < 64; i++) {
             const uint64_t b = __ballot((f >> i) & 1ull);
-            const uint32_t src = j * 64 + i;
-            if (lane == 0 && src < B) p.out[static_cast<uint64_t>(src) * nwords + k] = b;
+            if (lane == i) mine = b;
         }
+        const uint32_t src = j * 64 + lane;
+        if (src < B) p.out[static_cast<uint64_t>(src) * nwords + k] = mine;
     }
 }
 
@@ -1169,11 +1252,12 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
 // VGPRs, two 512-thread workgroups per CU, where the persistent kernel, which
 // holds every phase, takes one), and kernel boundaries order the phases.
 template <int G, int QM>
-__global__ __launch_bounds__(BLOCK) void k_st_expand(StackParams p, uint32_t n, uint32_t record) {
-    __shared__ StLds L;
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ST_EXPAND_WAVES))) void k_st_expand(StackParams p, uint32_t n, uint32_t record) {
+    __shared__ StLdsN<TILE / G + 1> L;
     st_qv_setup(p.qv);
     if (record && blockIdx.x == 0 && threadIdx.x == 0) st_record(p, n, 0);
-    expand_items<G, QM, false, true>(p, n, L, ld_acq(&p.rec[n % REC_RING].sel), ~0u, blockIdx.x, gridDim.x);
+    expand_items<G, QM, false, true, st_expand_upt<G>()>(p, n, L, ld_acq(&p.rec[n % REC_RING].sel), ~0u, blockIdx.x,
+                                                   gridDim.x);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_st_compact(StackParams p, uint32_t n) { st_compact(p, n); }
