@@ -82,7 +82,7 @@ hipError_t launch_stacked(int G, int QM, const StackParams &p, int grid, bool co
 // the vertex-ordered queue of level n + 1, and the select phase of level n.
 hipError_t launch_st_expand(int G, int QM, const StackParams &p, uint32_t n, bool record, hipStream_t s);
 hipError_t launch_st_compact(const StackParams &p, uint32_t n, hipStream_t s);
-hipError_t launch_st_select(int G, int QM, const StackParams &p, uint32_t n, hipStream_t s);
+hipError_t launch_st_select(int G, int QM, const StackParams &p, uint32_t n, bool counters, hipStream_t s);
 int stacked_grid(int G, int QM);
 // Workgroups of the stacked kernel that fit on one compute unit (-1 on error).
 int stacked_blocks_per_cu(int G, int QM);

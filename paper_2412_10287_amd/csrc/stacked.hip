@@ -38,14 +38,19 @@ constexpr uint32_t PULL_LIGHT_ROW = 128;  // longer pull rows are processed edge
 // kernel within 128 VGPRs (two workgroups per CU; with four it needs 141
 // and gets one, and a large kg level's select took 4.9 ms instead of 3.0).
 constexpr int ST_SYM_BATCH = 2;
-// The expansion phase kernel: units per thread and step, and the waves per
-// SIMD its registers are fitted to (six: three 512-thread workgroups per CU,
-// 80 VGPRs). Two units per thread fit without spills up to G = 4, one beyond;
-// at two workgroups per CU with four units per thread a large kg level's
-// expansion took 14.5 ms, at three with two 12.5 ms.
+// The expansion phase kernel: units per thread and step, threads per
+// workgroup, and the waves per SIMD its registers are fitted to (none of
+// these spill). More resident waves hide more of the gathers' and atomics'
+// latency: on a large kg level (G = 4) the expansion took 14.5 ms at two
+// 512-thread workgroups per CU with four units per thread, 12.5 ms at three
+// with two units, and 11.2 ms at seven 256-thread workgroups with one unit
+// (69 VGPRs; the 22.6 KB of LDS per workgroup allows seven).
 template <int G>
-constexpr int st_expand_upt() { return G <= 4 ? 2 : 1; }
-constexpr int ST_EXPAND_WAVES = 6;
+constexpr int st_expand_upt() { return G <= 2 ? 2 : 1; }
+template <int G>
+constexpr int st_expand_threads() { return G <= 2 ? BLOCK : BLOCK / 2; }
+template <int G>
+constexpr int st_expand_waves() { return G <= 2 ? 6 : 7; }
 
 // The query's tables for every phase of the stacked kernel: a copy in LDS
 // when the block fits, else the global block.
@@ -175,7 +180,9 @@ __device__ __forceinline__ void put_item(const StackParams &p, uint32_t idx, uin
 }
 
 // ------------------------------------------------------------------ select
-template <int G, int QM>
+// COUNT = false leaves out the work counters and the update count (a launch
+// without RPQ_COUNTERS), which frees the registers they take.
+template <int G, int QM, bool COUNT = true>
 __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint32_t bid, uint32_t nblk, uint64_t &cacc) {
     const GraphView &g = p.g;
     const QueryView &qv = s_qv;
@@ -222,7 +229,7 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
     const uint32_t nsym = qv.h->nsym;
     uint64_t pairs = 0, upd = 0, c_scans = 0, c_edges = 0, c_wb = 0, c_pe = 0;
     uint32_t nfront = 0, su = 0;
-    const bool counters = qv.h->counters != 0;
+    const bool counters = COUNT && qv.h->counters != 0;
     // workgroup-uniform loop: item reservations are made per workgroup
     for (uint32_t bbase = bid * GPB; bbase < nq; bbase += nblk * GPB) {
         const uint32_t i = bbase + threadIdx.x / G;
@@ -255,7 +262,8 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
                     nzm |= 1u << k;
                     pk[k] = static_cast<uint32_t>(__popcll(nb));
                     pairs += pk[k];
-                    halves += (static_cast<uint32_t>(nb) != 0u) + (static_cast<uint32_t>(nb >> 32) != 0u);
+                    if constexpr (COUNT)
+                        halves += (static_cast<uint32_t>(nb) != 0u) + (static_cast<uint32_t>(nb >> 32) != 0u);
                 }
                 if (nb != c) Mc[idx] = nb;
             }
@@ -278,9 +286,11 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
         }
         // nonzero source words per state over the group (for the work counter)
         uint32_t nzc[QM];
-        const uint64_t gmask = ((1ull << G) - 1ull) << (grp * G);
+        if constexpr (COUNT) {
+            const uint64_t gmask = ((1ull << G) - 1ull) << (grp * G);
 #pragma unroll
-        for (int k = 0; k < QM; k++) nzc[k] = static_cast<uint32_t>(__popcll(__ballot((nzm >> k) & 1u) & gmask));
+            for (int k = 0; k < QM; k++) nzc[k] = static_cast<uint32_t>(__popcll(__ballot((nzm >> k) & 1u) & gmask));
+        }
         // items: the small NFA factor first (succ_u of the state set), then
         // the neighbour range of the u-row at w. Only the symbols with a
         // transition out of S can give an item; lane j of the group looks up
@@ -315,30 +325,33 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
                 const uint32_t u = us[jj];
                 len[jj] = 0;
                 uint32_t e;
-                c_scans += tu[jj] != 0u;
+                if constexpr (COUNT) c_scans += tu[jj] != 0u;
                 if (tu[jj] && row_range(g, rw[jj], qv.push_r[u], w, beg[jj], e)) {
                     if (e > beg[jj] && e <= g.ncol) len[jj] = e - beg[jj];
                     else if (e != beg[jj]) sviol(p);
                 }
                 if (len[jj]) {
-                    // (edge, transition, word) updates this item carries and,
-                    // with the counters, its product edges: |succ_u(q)| per
-                    // pair (q, source) of the frontier, per edge
-                    const uint32_t *su_tab = qv.succ + u * MAX_STATES;
-                    uint32_t c = 0;
-                    uint64_t pe = 0;
+                    if constexpr (COUNT) {
+                        // (edge, transition, word) updates this item carries
+                        // and, with the counters, its product edges:
+                        // |succ_u(q)| per pair (q, source) of the frontier,
+                        // per edge
+                        const uint32_t *su_tab = qv.succ + u * MAX_STATES;
+                        uint32_t c = 0;
+                        uint64_t pe = 0;
 #pragma unroll
-                    for (int k = 0; k < QM; k++) {
-                        if ((S >> k) & 1u) {
-                            const uint32_t ns = static_cast<uint32_t>(__popc(su_tab[k]));
-                            c += ns * nzc[k];
-                            pe += static_cast<uint64_t>(ns) * pk[k];
+                        for (int k = 0; k < QM; k++) {
+                            if ((S >> k) & 1u) {
+                                const uint32_t ns = static_cast<uint32_t>(__popc(su_tab[k]));
+                                c += ns * nzc[k];
+                                pe += static_cast<uint64_t>(ns) * pk[k];
+                            }
                         }
-                    }
-                    upd += static_cast<uint64_t>(c) * len[jj];
-                    if (counters) {
-                        c_pe += pe * len[jj];
-                        c_wb += static_cast<uint64_t>(Wv) * len[jj];
+                        upd += static_cast<uint64_t>(c) * len[jj];
+                        if (counters) {
+                            c_pe += pe * len[jj];
+                            c_wb += static_cast<uint64_t>(Wv) * len[jj];
+                        }
                     }
                     cnt++;
                     tot += len[jj];
@@ -352,7 +365,7 @@ __device__ __forceinline__ void st_select(const StackParams &p, uint32_t n, uint
                 const uint64_t mine = wbase + ex;
                 uint32_t idx = static_cast<uint32_t>(mine >> 32);
                 uint32_t eb = static_cast<uint32_t>(mine);
-                c_edges += tot;
+                if constexpr (COUNT) c_edges += tot;
 #pragma unroll
                 for (int jj = 0; jj < ST_SYM_BATCH; jj++) {
                     if (!len[jj]) continue;
@@ -640,18 +653,18 @@ __device__ __forceinline__ void wave_merge(UnitC<QM> &U) {
 // units per thread are gathered before any is scattered (QM <= 8), so their
 // loads overlap; fewer units per thread take fewer registers and leave room
 // for more waves.
-template <int G, int QM, bool PULL, bool MARK, int UPT, class LT>
+template <int G, int QM, bool PULL, bool MARK, int UPT, int NT, class LT>
 __device__ __forceinline__ void expand_range(const StackParams &p, uint32_t n, const LT &L, uint32_t cnt, uint64_t ubase,
                                              uint64_t uend, uint32_t ns) {
     const uint32_t tid = threadIdx.x;
     const uint32_t j = tid % G;
     if constexpr (QM <= 8) {
-        static_assert(TILE % (UPT * BLOCK) == 0, "a tile is whole steps of the workgroup");
-        for (uint64_t ub = ubase; ub < uend; ub += UPT * BLOCK) {
+        static_assert(TILE % (UPT * NT) == 0, "a tile is whole steps of the workgroup");
+        for (uint64_t ub = ubase; ub < uend; ub += UPT * NT) {
             UnitC<QM> U[UPT];
             uint64_t us[UPT];
 #pragma unroll
-            for (int k = 0; k < UPT; k++) us[k] = ub + static_cast<uint64_t>(k) * BLOCK + tid;
+            for (int k = 0; k < UPT; k++) us[k] = ub + static_cast<uint64_t>(k) * NT + tid;
             uint32_t lo[UPT];
             item_search<G, UPT>(L, cnt, us, uend, lo);
 #pragma unroll
@@ -674,7 +687,7 @@ __device__ __forceinline__ void expand_range(const StackParams &p, uint32_t n, c
             }
         }
     } else {
-        for (uint64_t ub = ubase; ub < uend; ub += BLOCK) {
+        for (uint64_t ub = ubase; ub < uend; ub += NT) {
             UnitC<QM> U0;
             const uint64_t us[1] = {ub + tid};
             uint32_t lo[1];
@@ -687,7 +700,7 @@ __device__ __forceinline__ void expand_range(const StackParams &p, uint32_t n, c
 }
 
 // Items [0, nitems) with `T` edges (packed in sel) -> units spread over the grid.
-template <int G, int QM, bool PULL, bool MARK = false, int UPT = 4, class LT = StLds>
+template <int G, int QM, bool PULL, bool MARK = false, int UPT = 4, int NT = BLOCK, class LT = StLds>
 __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, LT &L, uint64_t sel, uint32_t ns,
                                              uint32_t bid, uint32_t nblk) {
     constexpr uint32_t TE = TILE / G;
@@ -704,7 +717,7 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, L
     if (nitems < LT::cap) {
         // few items: every workgroup stages all of them and takes an even,
         // wave-aligned share of the units, so small levels use the whole chip
-        for (uint32_t x = tid; x < nitems; x += BLOCK) {
+        for (uint32_t x = tid; x < nitems; x += NT) {
             L.eb[x] = ldc(&p.it_ebase[x]);
             L.beg[x] = ldc(&p.it_beg[x]);
             L.v[x] = ldc(&p.it_v[x]);
@@ -716,7 +729,7 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, L
         per = (per + 63) & ~63ull;
         const uint64_t b0 = static_cast<uint64_t>(bid) * per;
         const uint64_t b1 = b0 + per < units ? b0 + per : units;
-        if (b0 < b1) expand_range<G, QM, PULL, MARK, UPT>(p, n, L, nitems, b0, b1, ns);
+        if (b0 < b1) expand_range<G, QM, PULL, MARK, UPT, NT>(p, n, L, nitems, b0, b1, ns);
         __syncthreads();
         return;
     }
@@ -735,7 +748,7 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, L
             i0 = i1 = 0;
         }
         const uint32_t cnt = i1 - i0 + 1;
-        for (uint32_t x = tid; x < cnt; x += BLOCK) {
+        for (uint32_t x = tid; x < cnt; x += NT) {
             L.eb[x] = ldc(&p.it_ebase[i0 + x]);
             L.beg[x] = ldc(&p.it_beg[i0 + x]);
             L.v[x] = ldc(&p.it_v[i0 + x]);
@@ -745,7 +758,7 @@ __device__ __forceinline__ void expand_items(const StackParams &p, uint32_t n, L
         __syncthreads();
         const uint64_t u0 = static_cast<uint64_t>(tile) * TILE + static_cast<uint64_t>(part) * part_units;
         const uint64_t u1 = u0 + part_units < units ? u0 + part_units : units;
-        if (u0 < u1) expand_range<G, QM, PULL, MARK, UPT>(p, n, L, cnt, u0, u1, ns);
+        if (u0 < u1) expand_range<G, QM, PULL, MARK, UPT, NT>(p, n, L, cnt, u0, u1, ns);
         __syncthreads();
     }
 }
@@ -1252,22 +1265,23 @@ __global__ __launch_bounds__(BLOCK) void k_stacked(StackParams p) {
 // VGPRs, two 512-thread workgroups per CU, where the persistent kernel, which
 // holds every phase, takes one), and kernel boundaries order the phases.
 template <int G, int QM>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ST_EXPAND_WAVES))) void k_st_expand(StackParams p, uint32_t n, uint32_t record) {
+__global__ __launch_bounds__(st_expand_threads<G>()) __attribute__((amdgpu_waves_per_eu(st_expand_waves<G>())))
+void k_st_expand(StackParams p, uint32_t n, uint32_t record) {
     __shared__ StLdsN<TILE / G + 1> L;
     st_qv_setup(p.qv);
     if (record && blockIdx.x == 0 && threadIdx.x == 0) st_record(p, n, 0);
-    expand_items<G, QM, false, true, st_expand_upt<G>()>(p, n, L, ld_acq(&p.rec[n % REC_RING].sel), ~0u, blockIdx.x,
+    expand_items<G, QM, false, true, st_expand_upt<G>(), st_expand_threads<G>()>(p, n, L, ld_acq(&p.rec[n % REC_RING].sel), ~0u, blockIdx.x,
                                                    gridDim.x);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_st_compact(StackParams p, uint32_t n) { st_compact(p, n); }
 
-template <int G, int QM>
+template <int G, int QM, bool COUNT>
 __global__ __launch_bounds__(BLOCK) void k_st_select(StackParams p, uint32_t n) {
     st_qv_setup(p.qv);
     uint64_t cacc = 0;
-    st_select<G, QM>(p, n, blockIdx.x, gridDim.x, cacc);
-    st_flush_counters(p, cacc);
+    st_select<G, QM, COUNT>(p, n, blockIdx.x, gridDim.x, cacc);
+    if constexpr (COUNT) st_flush_counters(p, cacc);
 }
 
 // The grid is sized to be resident on an otherwise idle GPU, and every
@@ -1314,25 +1328,26 @@ hipError_t launch_stacked(int G, int QM, const StackParams &p, int grid, bool co
 }
 
 // Workgroups for a phase kernel: as many as fit the GPU at once.
-static int phase_grid(const void *kernel) {
+static int phase_grid(const void *kernel, int threads = BLOCK) {
     int dev = 0, ncu = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, BLOCK, 0) != hipSuccess || per < 1) per = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1) per = 1;
     return ncu * per;
 }
 
 template <int G, int QM>
 static hipError_t st_expand_g(const StackParams &p, uint32_t n, bool record, hipStream_t s) {
-    static const int grid = phase_grid(reinterpret_cast<const void *>(&k_st_expand<G, QM>));
-    hipLaunchKernelGGL((k_st_expand<G, QM>), dim3(grid), dim3(BLOCK), 0, s, p, n, record ? 1u : 0u);
+    constexpr int NT = st_expand_threads<G>();
+    static const int grid = phase_grid(reinterpret_cast<const void *>(&k_st_expand<G, QM>), NT);
+    hipLaunchKernelGGL((k_st_expand<G, QM>), dim3(grid), dim3(NT), 0, s, p, n, record ? 1u : 0u);
     return hipGetLastError();
 }
 
-template <int G, int QM>
+template <int G, int QM, bool COUNT>
 static hipError_t st_select_g(const StackParams &p, uint32_t n, hipStream_t s) {
-    static const int grid = phase_grid(reinterpret_cast<const void *>(&k_st_select<G, QM>));
-    hipLaunchKernelGGL((k_st_select<G, QM>), dim3(grid), dim3(BLOCK), 0, s, p, n);
+    static const int grid = phase_grid(reinterpret_cast<const void *>(&k_st_select<G, QM, COUNT>));
+    hipLaunchKernelGGL((k_st_select<G, QM, COUNT>), dim3(grid), dim3(BLOCK), 0, s, p, n);
     return hipGetLastError();
 }
 
@@ -1342,9 +1357,12 @@ hipError_t launch_st_expand(int G, int QM, const StackParams &p, uint32_t n, boo
     return e;
 }
 
-hipError_t launch_st_select(int G, int QM, const StackParams &p, uint32_t n, hipStream_t s) {
+hipError_t launch_st_select(int G, int QM, const StackParams &p, uint32_t n, bool counters, hipStream_t s) {
     hipError_t e = hipSuccess;
-    RPQ_STACKED_DISPATCH(G, QM, (e = st_select_g<GG, 8>(p, n, s)), (e = st_select_g<GG, 32>(p, n, s)));
+    if (counters)
+        RPQ_STACKED_DISPATCH(G, QM, (e = st_select_g<GG, 8, true>(p, n, s)), (e = st_select_g<GG, 32, true>(p, n, s)))
+    else
+        RPQ_STACKED_DISPATCH(G, QM, (e = st_select_g<GG, 8, false>(p, n, s)), (e = st_select_g<GG, 32, false>(p, n, s)))
     return e;
 }
 

@@ -182,7 +182,7 @@ static rpq_status st_handoff_loop(rpq_graph *g, StackParams &p, int G, int QM, i
         while (true) {
             BT(launch_st_expand(G, QM, p, lev, record, s));
             BT(launch_st_compact(p, lev, s));
-            BT(launch_st_select(G, QM, p, lev + 1, s));
+            BT(launch_st_select(G, QM, p, lev + 1, qh->counters != 0, s));
             npush++;
             const LevelRec *rn = &p.rec[(lev + 1) % REC_RING];
             const LevelRec *rc = &p.rec[lev % REC_RING];
