@@ -367,7 +367,10 @@ rpq_status rpq_poll(rpq_graph *g, rpq_ticket t, uint64_t *out_bitmap, uint32_t f
  *    launch: one per CU, or a half, quarter or eighth of that) and the
  *    direction thresholds "pull_alpha" / "pull_beta".
  *  RPQ_TUNE_STACKED: nfas[0] from all n_queries sources through
- *    rpq_multi_source; tunes "stacked_alpha" / "stacked_beta".
+ *    rpq_multi_source; tunes "stacked_alpha" / "stacked_beta", then, with
+ *    the best of those, "stacked_handoff_edges" in {0 (no phase kernels),
+ *    2^20, 2^22, 2^24} (levels below V/16 edges stay in the persistent
+ *    kernel whatever the threshold).
  * Candidates: alpha in {0 (push only), 1, 2, 4, 8, 16, 64} x beta in
  * {4, 24, 128}. The time of a setting is the summed device time (HIP events)
  * of the sample after one warm-up pass with the handle's previous settings.
@@ -383,6 +386,7 @@ typedef struct {
     double best_ms;      /* device time of the sample with the chosen setting */
     double default_ms;   /* device time with the settings the handle had before */
     int32_t candidates;  /* settings timed */
+    int64_t handoff_edges; /* stacked: "stacked_handoff_edges" chosen; plain: 0 */
 } rpq_tuning;
 rpq_status rpq_autotune(rpq_graph *g, int32_t path, const rpq_nfa *const *nfas, const int32_t *sources,
                         int32_t n_queries, rpq_tuning *out);

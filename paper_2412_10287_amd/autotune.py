@@ -32,6 +32,8 @@ def apply(graph: "rpq.Graph", path: int, chosen: dict):
         graph.set_option(grid_key, int(chosen["grid"]))
     graph.set_option(a_key, int(chosen["alpha"]))
     graph.set_option(b_key, int(chosen["beta"]))
+    if path == rpq.TUNE_STACKED and "handoff_edges" in chosen:
+        graph.set_option("stacked_handoff_edges", int(chosen["handoff_edges"]))
 
 
 def tune(graph: "rpq.Graph", path: int, nfas: Sequence["rpq.NFA"], sources: Sequence[int],

@@ -9,6 +9,7 @@
 // formulations at a fixed constant (Sec. 5.1); on the GPU the best switch
 // point depends on the graph's degree skew and the queries' label mix, so it
 // is measured.
+#include <stddef.h>
 #include <string.h>
 
 #include <algorithm>
@@ -18,11 +19,15 @@
 
 using namespace rpq;
 
+// the Python binding mirrors this layout field by field
+static_assert(offsetof(rpq_tuning, handoff_edges) == 48 && sizeof(rpq_tuning) == 56, "rpq_tuning layout");
+
 namespace {
 
 struct Setting {
     int32_t grid;
     double alpha, beta;
+    int64_t handoff;  // stacked: phase-kernel hand-off threshold
 };
 
 rpq_status time_plain(rpq_graph *g, const rpq_nfa *const *nfas, const int32_t *src, int32_t n, double *ms) {
@@ -71,18 +76,19 @@ rpq_status rpq_autotune(rpq_graph *g, int32_t path, const rpq_nfa *const *nfas, 
         for (int32_t d : {2, 4, 8})
             if (full / d >= 16) grids[ng++] = full / d;
     }
-    for (int32_t gi = 0; gi < ng; gi++)
-        for (double a : alphas) {
-            if (a == 0.0) {
-                cand.push_back({grids[gi], 0.0, 24.0});
-                continue;
-            }
-            for (double b : betas) cand.push_back({grids[gi], a, b});
-        }
     // saved settings (restored on failure), and the time with them
     const int32_t grid0 = g->plain_grid;
     const double a0 = path == RPQ_TUNE_PLAIN ? g->pull_alpha : g->stack_alpha;
     const double b0 = path == RPQ_TUNE_PLAIN ? g->pull_beta : g->stack_beta;
+    const int64_t h0 = g->stack_handoff;
+    for (int32_t gi = 0; gi < ng; gi++)
+        for (double a : alphas) {
+            if (a == 0.0) {
+                cand.push_back({grids[gi], 0.0, 24.0, h0});
+                continue;
+            }
+            for (double b : betas) cand.push_back({grids[gi], a, b, h0});
+        }
     auto apply = [&](const Setting &s) {
         if (path == RPQ_TUNE_PLAIN) {
             g->plain_grid = s.grid;
@@ -91,6 +97,7 @@ rpq_status rpq_autotune(rpq_graph *g, int32_t path, const rpq_nfa *const *nfas, 
         } else {
             g->stack_alpha = s.alpha;
             g->stack_beta = s.beta;
+            g->stack_handoff = s.handoff;
         }
     };
     uint64_t *dout = nullptr;
@@ -105,27 +112,43 @@ rpq_status rpq_autotune(rpq_graph *g, int32_t path, const rpq_nfa *const *nfas, 
     };
     rpq_status st;
     double def_ms = 0.0, best_ms = 0.0;
-    Setting best{grid0, a0, b0};
+    Setting best{grid0, a0, b0, h0};
     // warm-up with the saved settings, then their time
     if ((st = measure(&def_ms)) == RPQ_OK) st = measure(&def_ms);
     best_ms = def_ms;
-    for (size_t k = 0; st == RPQ_OK && k < cand.size(); k++) {
-        apply(cand[k]);
+    auto try_setting = [&](const Setting &c) {
+        apply(c);
         double ms = 0.0;
         st = measure(&ms);
         if (st == RPQ_OK && ms < best_ms) {
             best_ms = ms;
-            best = cand[k];
+            best = c;
+        }
+    };
+    for (size_t k = 0; st == RPQ_OK && k < cand.size(); k++) try_setting(cand[k]);
+    size_t ncand = cand.size();
+    // stacked, second stage: the hand-off threshold under the best
+    // direction thresholds (the two interact little: pull levels never
+    // leave the persistent kernel)
+    if (path == RPQ_TUNE_STACKED) {
+        const Setting base = best;  // the first stage's choice (threshold h0)
+        for (int64_t h : {int64_t{0}, int64_t{1} << 20, int64_t{1} << 22, int64_t{1} << 24}) {
+            if (st != RPQ_OK || h == base.handoff) continue;
+            Setting c = base;
+            c.handoff = h;
+            try_setting(c);
+            ncand++;
         }
     }
     if (dout) (void)hipFree(dout);
-    apply(st == RPQ_OK ? best : Setting{grid0, a0, b0});
+    apply(st == RPQ_OK ? best : Setting{grid0, a0, b0, h0});
     if (st != RPQ_OK) return st;
     out->grid = best.grid;
     out->alpha = static_cast<int64_t>(best.alpha);
     out->beta = static_cast<int64_t>(best.beta);
     out->best_ms = best_ms;
     out->default_ms = def_ms;
-    out->candidates = static_cast<int32_t>(cand.size());
+    out->candidates = static_cast<int32_t>(ncand);
+    out->handoff_edges = path == RPQ_TUNE_STACKED ? best.handoff : 0;
     return RPQ_OK;
 }

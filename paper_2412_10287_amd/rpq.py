@@ -45,7 +45,8 @@ TUNE_PLAIN, TUNE_STACKED = 0, 1
 
 class rpq_tuning(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_int64), ("alpha", ctypes.c_int64), ("beta", ctypes.c_int64),
-                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double), ("candidates", ctypes.c_int32)]
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double), ("candidates", ctypes.c_int32),
+                ("handoff_edges", ctypes.c_int64)]
 
 
 class rpq_stats(ctypes.Structure):

@@ -111,8 +111,16 @@ def test_tuning_cache_roundtrip(rpq, tmp_path):
     assert r2["cached"] and g2.tuned == 0
     assert g2.options == {"persistent_grid": 64, "pull_alpha": 4, "pull_beta": 24}
     g3 = FakeGraph()
+    g3.autotune = lambda path, nfas, sources: {"grid": 0, "alpha": 0, "beta": 24, "best_ms": 1.0, "default_ms": 1.5,
+                                               "candidates": 22, "handoff_edges": 1 << 22}
     autotune.tune(g3, rpq.TUNE_STACKED, [], [], cache=cache)  # another path: measured again
-    assert g3.tuned == 1 and g3.options == {}
+    assert g3.options == {}
+    g4 = FakeGraph()
+    r4 = autotune.tune(g4, rpq.TUNE_STACKED, [], [], cache=cache)
+    assert r4["cached"] and g4.tuned == 0
+    assert g4.options == {"stacked_alpha": 0, "stacked_beta": 24, "stacked_handoff_edges": 1 << 22}
+    # the C struct and its ctypes mirror agree on the new field's place
+    assert rpq.rpq_tuning.handoff_edges.offset == 48 and ctypes.sizeof(rpq.rpq_tuning) == 56
 
 
 def test_library_links_roctx(rpq):

@@ -359,6 +359,10 @@ def test_autotune_keeps_answers(rpq):
         assert np.array_equal(bm, og.ssr(n, s).bitmap)
     rec = gg.autotune(rpq.TUNE_STACKED, nh[:1], srcs * 3)
     assert gg.get_option("stacked_alpha") == rec["alpha"]
+    # the second stage times the hand-off thresholds other than the kept one
+    assert rec["candidates"] == 19 + 3 and rec["handoff_edges"] in (0, 1 << 20, 1 << 22, 1 << 24)
+    assert gg.get_option("stacked_handoff_edges") == rec["handoff_edges"]
+    assert rec["best_ms"] <= rec["default_ms"] + 1e-9
     bms, _ = gg.multi_source(nh[0], srcs * 3)
     for i, s in enumerate(srcs * 3):
         assert np.array_equal(bms[i], og.ssr(w.nfas[0], s).bitmap)
