@@ -965,6 +965,84 @@ __device__ __forceinline__ void st_final(const StackParams &p, uint32_t nexit, u
         }
         p.out[threadIdx.x] = f & word_full(p.B, threadIdx.x);
     }
+    if constexpr (G <= 4) {
+        // A wave takes KC consecutive 64-vertex blocks. The rows of a block
+        // are one contiguous range of P, read 64 consecutive words per load
+        // (four whole lines, where a load of one word per vertex touches 64
+        // lines); set words are cleared with the same pattern, and the
+        // words of final states are ORed into the wave's LDS columns F[j],
+        // one word per vertex. Lane l then holds vertex l's result words,
+        // and 64 ballots per word j transpose them into one output word per
+        // source; lane i stores KC consecutive words of source j*64 + i.
+        constexpr uint32_t KC = 16 / G;
+        __shared__ uint64_t s_f[BLOCK / 64][G][64];
+        uint64_t(*F)[64] = s_f[threadIdx.x >> 6];
+        const uint32_t QG = Q * G;
+        const uint64_t nchunks = (nwords + KC - 1) / KC;
+        for (uint64_t c = gthread() >> 6; c < nchunks; c += gthreads() >> 6) {  // wave-uniform
+            uint64_t mine[G][KC];
+#pragma unroll
+            for (uint32_t kk = 0; kk < KC; kk++) {
+                const uint64_t v0 = (c * KC + kk) * 64;
+#pragma unroll
+                for (int j = 0; j < G; j++) F[j][lane] = 0;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                if (v0 < V) {
+                    const uint32_t nv = V - v0 < 64 ? static_cast<uint32_t>(V - v0) : 64u;
+                    const uint32_t words = nv * QG;
+                    const uint64_t base = v0 * QG;  // rowi(v0, 0)
+                    for (uint32_t i0 = 0; i0 < words; i0 += 4 * 64) {
+                        uint64_t x[4];
+#pragma unroll
+                        for (uint32_t r = 0; r < 4; r++) {
+                            const uint32_t i = i0 + r * 64 + lane;
+                            x[r] = i < words ? ldc(&p.P[base + i]) : 0ull;
+                        }
+#pragma unroll
+                        for (uint32_t r = 0; r < 4; r++) {
+                            if (!x[r]) continue;
+                            const uint32_t i = i0 + r * 64 + lane;
+                            const uint32_t vl = i / QG;
+                            const uint32_t rem = i - vl * QG;
+                            if (probing && v0 + vl == p.probe) continue;
+                            p.P[base + i] = 0;
+                            p.M[0][base + i] = 0;
+                            p.M[1][base + i] = 0;
+                            if (fm >> (rem / G) & 1u)
+                                atomicOr(reinterpret_cast<unsigned long long *>(&F[rem % G][vl]),
+                                         static_cast<unsigned long long>(x[r]));
+                        }
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+                for (int j = 0; j < G; j++) {
+                    const uint64_t f = F[j][lane];
+                    uint64_t t = 0;
+                    if (!probing) {  // uniform: the probe is a launch parameter
+                        for (uint32_t i = 0; i < 64; i++) {
+                            const uint64_t bl = __ballot((f >> i) & 1ull);
+                            if (lane == i) t = bl;
+                        }
+                    }
+                    mine[j][kk] = t;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // F is read before the next block clears it
+            }
+            if (probing) continue;
+#pragma unroll
+            for (int j = 0; j < G; j++) {
+                const uint32_t src = j * 64 + lane;
+                if (src >= B) continue;
+#pragma unroll
+                for (uint32_t kk = 0; kk < KC; kk++) {
+                    const uint64_t k = c * KC + kk;
+                    if (k < nwords) p.out[static_cast<uint64_t>(src) * nwords + k] = mine[j][kk];
+                }
+            }
+        }
+        return;
+    }
     if constexpr (QM * G <= 32) {
         // a wave takes KC consecutive 64-vertex blocks and every source word
         // of them: each lane loads its vertex's whole row (all loads in
