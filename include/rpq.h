@@ -196,6 +196,14 @@ rpq_status rpq_graph_info(const rpq_graph *g, const char *key, int64_t *value);
  *                outputs, counters, or direction and level-driver flags.
  *  "serve_stack_min"  waiting served requests of one NFA handle that run as
  *                one stacked group (default 32; 0 = never).
+ *  "serve_group_wait_us"  while at least serve_stack_min / 2 (and two)
+ *                waiting requests share an NFA handle and the last request
+ *                arrived less than this long ago, waiting requests are not
+ *                admitted to slots, and a stacked group short of max_batch
+ *                does not start unless its oldest request has waited 25
+ *                times as long, so that a burst of one NFA's requests
+ *                gathers into one group (default 200; 0 = at once; at most
+ *                10^6).
  *  "large_query_pairs", "large_query_slots"  while the moving average of
  *                the reached (state, vertex) pairs of recently finished
  *                served queries exceeds large_query_pairs (default 2^21),

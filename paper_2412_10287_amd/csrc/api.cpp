@@ -582,6 +582,10 @@ rpq_status rpq_set_option(rpq_graph *g, const char *key, int64_t value) {
         if (value < 0 || value > MAX_BATCH)
             return fail(RPQ_EINVAL, "rpq_set_option: serve_stack_min outside [0, %d]", MAX_BATCH);
         g->serve_stack_min = static_cast<int32_t>(value);
+    } else if (!strcmp(key, "serve_group_wait_us")) {
+        if (value < 0 || value > 1000000)
+            return fail(RPQ_EINVAL, "rpq_set_option: serve_group_wait_us outside [0, 10^6]");
+        g->serve_group_wait_us = value;
     } else if (!strcmp(key, "serve_promote_pairs")) {
         if (value < 0) return fail(RPQ_EINVAL, "rpq_set_option: serve_promote_pairs < 0");
         g->serve_promote_pairs = value;
@@ -615,6 +619,7 @@ rpq_status rpq_get_option(const rpq_graph *g, const char *key, int64_t *value) {
     else if (!strcmp(key, "large_query_pairs")) *value = g->large_pairs;
     else if (!strcmp(key, "large_query_slots")) *value = g->large_slots;
     else if (!strcmp(key, "serve_stack_min")) *value = g->serve_stack_min;
+    else if (!strcmp(key, "serve_group_wait_us")) *value = g->serve_group_wait_us;
     else if (!strcmp(key, "rare_end_max")) *value = g->rare_end_max;
     else if (!strcmp(key, "serve_lanes")) *value = g->serve_lanes;
     else if (!strcmp(key, "serve_promote_pairs")) *value = g->serve_promote_pairs;

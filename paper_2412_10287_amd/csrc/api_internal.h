@@ -92,6 +92,7 @@ struct rpq_graph {
     int64_t large_pairs = 1 << 21;  // served path: queries above this many reached pairs count as large
     int32_t large_slots = 0;        // concurrent served queries while recent queries are large (0: one at a time, single-query kernel)
     int32_t serve_stack_min = 32;   // waiting served requests of one NFA that run as one stacked group (0 = never)
+    int64_t serve_group_wait_us = 200;  // served path: a burst of one NFA's requests waits this long for more before slots take it (0 = never)
     int32_t serve_lanes = 2;        // served path: single-query executors for large queries (0 = none)
     int64_t serve_promote_pairs = 0;  // served path: a slot query that reaches more pairs moves to a lane (0 = never)
     int64_t rare_end_max = 0;       // rare-end plan of rpq_single_source for at most this many candidate endpoints (0 = off)

@@ -71,6 +71,7 @@ struct ServeState {
     std::condition_variable cv_work, cv_done;
     std::deque<Request> pending;
     size_t pending_deadlines = 0;  // requests in `pending` with a deadline
+    Clock::time_point last_submit{};  // arrival of the latest request (guarded by mu)
     std::unordered_map<rpq_ticket, Ticket> tickets;
     std::thread worker;
     bool stop = false;
@@ -703,6 +704,37 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
                     if (++cnt[r.serial] >= smin) return r.serial;
                 return 0;
             };
+            // a burst of one NFA's requests (half a group or more waiting,
+            // the last one recent) is held back from the slots for a short
+            // while, and a group short of max_batch waits as long for more
+            // of its requests, so that the burst gathers into one group
+            const auto gwait = std::chrono::microseconds(smin ? std::max<int64_t>(g->serve_group_wait_us, 0) : 0);
+            const size_t maxb = static_cast<size_t>(std::min<int32_t>(g->max_batch, MAX_BATCH));
+            // (a group also starts once its oldest request has waited 25
+            // windows, so a steady trickle of one NFA's requests is not held
+            // until max_batch of them have come)
+            auto group_ready = [&]() -> uint64_t {
+                const uint64_t gsr = group_serial();
+                const Clock::time_point now = Clock::now();
+                if (!gsr || gwait.count() == 0 || now - ss->last_submit >= gwait) return gsr;
+                size_t c = 0;
+                Clock::time_point oldest = now;
+                for (const Request &r : ss->pending)
+                    if (r.serial == gsr) {
+                        c++;
+                        oldest = std::min(oldest, r.submitted);
+                    }
+                return c >= maxb || now - oldest >= 25 * gwait ? gsr : 0;
+            };
+            const size_t hmin = std::max<size_t>(2, smin / 2);
+            auto holding = [&]() -> bool {
+                if (gwait.count() == 0 || ss->pending.size() < hmin || Clock::now() - ss->last_submit >= gwait)
+                    return false;
+                std::unordered_map<uint64_t, size_t> cnt;
+                for (const Request &r : ss->pending)
+                    if (++cnt[r.serial] >= hmin) return true;
+                return false;
+            };
             // concurrency: every slot, or large_query_slots while recent
             // queries are large; with large_query_slots 0, large-query
             // periods run one request at a time through the single-query
@@ -717,13 +749,22 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
             const size_t nl = ss->lanes.size();
             // work: a level to run, a request and a free slot, a group, or a
             // request to run through the single-query kernel
-            ss->cv_work.wait(lk, [&] {
+            auto ready = [&] {
                 return ss->stop || ss->cur_len > 0 ||
-                       (!ss->pending.empty() && !ss->free_slots.empty() && active() < cap) || group_serial() != 0 ||
+                       (!ss->pending.empty() && !ss->free_slots.empty() && active() < cap && !holding()) ||
+                       group_ready() != 0 ||
                        (single && !ss->pending.empty() && active() == 0 && (nl == 0 || ss->lanes_busy < nl));
-            });
+            };
+            while (!ready()) {
+                // a held burst is looked at again when its window closes
+                const Clock::time_point until = ss->last_submit + gwait;
+                if (gwait.count() > 0 && !ss->pending.empty() && Clock::now() < until)
+                    ss->cv_work.wait_until(lk, until);
+                else
+                    ss->cv_work.wait(lk);
+            }
             if (ss->stop && ss->pending.empty() && ss->cur_len == 0) break;
-            const uint64_t gs = ss->stop ? 0 : group_serial();
+            const uint64_t gs = ss->stop ? 0 : group_ready();
             if (!gs && single && ss->cur_len == 0 && active() == 0 && !ss->pending.empty()) {
                 if (nl == 0 && g->serve_lanes > 0 && !ss->lanes_failed) {
                     make_lanes = true;
@@ -741,7 +782,6 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
                     continue;
                 }
             } else if (gs) {
-                const size_t maxb = static_cast<size_t>(std::min<int32_t>(g->max_batch, MAX_BATCH));
                 for (auto it = ss->pending.begin(); it != ss->pending.end() && grp.size() < maxb;) {
                     if (it->serial != gs) {
                         ++it;
@@ -756,7 +796,7 @@ static void worker_main(rpq_graph *g, ServeState *ss) {
                         t->second.has_deadline = false;
                     }
                 }
-            } else {
+            } else if (!holding()) {
                 while (!ss->pending.empty() && admit.size() < ss->free_slots.size() &&
                        active() + admit.size() < cap)
                     admit.push_back(take_front(ss));
@@ -896,6 +936,7 @@ static rpq_status submit(rpq_graph *g, const rpq_nfa *n, int32_t source, int64_t
         t.has_deadline = r.has_deadline;
         t.deadline = r.deadline;
         if (r.has_deadline) ss->pending_deadlines++;
+        ss->last_submit = r.submitted;
         ss->pending.push_back(std::move(r));
         ss->running++;
     }
