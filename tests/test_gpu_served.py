@@ -205,6 +205,36 @@ def test_same_nfa_requests_run_as_stacked_groups(rpq):
     assert grouped > 0
 
 
+def test_burst_gathers_into_one_group(rpq):
+    # a burst of one NFA's requests waits for the rest of the burst (the
+    # serve_group_wait_us window, here long enough for Python's submits) and
+    # runs as one stacked group of max_batch; with the window off the slots
+    # may take the first requests; every answer equals the oracle's
+    w = C.rmat_workload(scale=13, edge_factor=16, num_labels=8, n_per_template=1)
+    og = oracle.Graph(w.graph)
+    gg = rpq.Graph(w.graph)
+    for bad in (-1, 1_000_001):
+        with pytest.raises(rpq.RPQError) as e:
+            gg.set_option("serve_group_wait_us", bad)
+        assert e.value.status == rpq.RPQ_EINVAL
+    gg.set_option("serve_group_wait_us", 200_000)
+    assert gg.get_option("serve_group_wait_us") == 200_000
+    gg.set_option("max_batch", 64)
+    nh = rpq.NFA(w.nfas[0])
+    srcs = [int(x) for x in np.random.default_rng(12).integers(0, w.graph.num_vertices, size=64)]
+    for window in (200_000, 0):
+        gg.set_option("serve_group_wait_us", window)
+        tickets = [(gg.submit(nh, s), s) for s in srcs]
+        batches = []
+        for t, s in tickets:
+            bm, st = gg.poll(t, timeout_us=60_000_000)
+            assert np.array_equal(bm, og.ssr(w.nfas[0], s).bitmap), (window, s)
+            batches.append(st.batch)
+        print("window", window, "batches", sorted(set(batches)), flush=True)
+        if window:
+            assert all(b == 64 for b in batches)
+
+
 @pytest.mark.parametrize("lanes", [0, 2, 3])
 def test_large_queries_run_alone(rpq, lanes):
     # threshold 0: after the first answer every query counts as large, and
